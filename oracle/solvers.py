@@ -1,0 +1,130 @@
+"""Oracle: the iterative methods of Sect. 2.4 on the Schur complement (FP64, CPU).
+
+Test infrastructure only: the HIP library never imports this module.
+
+Each solver takes ``apply``, a callable for the matrix (normally
+``WilsonClover.schur``), and plain numpy vectors, and follows the paper's
+algorithm in its order and notation.  Readings of points the paper leaves open:
+
+* Richardson (Alg. 4): omega is an input.  The algorithm's
+  omega = delta / |lambda_max| is formed by the caller from
+  ``power_iteration``; the returned value is the final iterate x^(n), which the
+  listing leaves unnamed.
+* Power iteration (Sect. 2.4.4 says a few steps suffice): gamma_5-hermiticity
+  pairs the eigenvalues of D_S as (lambda, conj(lambda)), so the iteration
+  cannot settle on one eigenvector; the estimate is the geometric mean growth
+  (|A^N v0| / |v0|)^(1/N), which tends to |lambda_max|.
+* GMRES (Alg. 2): standard Arnoldi, v_1 = r/beta and v_{k+1} = w / h_{k+1,k}
+  (the listing's v_k = r / h_{k,k-1} is read this way), h_{jk} = v_j^H w with
+  modified Gram-Schmidt in the listing's order, least squares by a dense
+  ``lstsq`` at every step.  A cycle ends early when the least-squares residual
+  falls to the absolute target or on breakdown h_{k+1,k} <= 1e-14 beta;
+  convergence is declared only on the recomputed residual at the restart (the
+  listing's line "check convergence via beta").
+* Flexible GMRES: the same with a right preconditioner z_k = M v_k and the
+  update x += Z_k y_k.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def vnorm(v):
+    return float(np.sqrt(np.sum(np.abs(v) ** 2)))
+
+
+def vdot(a, b):
+    """a^H b over all entries."""
+    return complex(np.vdot(a.ravel(), b.ravel()))
+
+
+def richardson(apply, b, x0, n: int, omega: float):
+    """Alg. 4: n sweeps of x <- x + omega (b - A x) from x0."""
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for _ in range(n):
+        r = b - apply(x)
+        x = x + omega * r
+    return x
+
+
+def power_iteration(apply, v0, n: int):
+    """|lambda_max| estimate (|A^n v0| / |v0|)^(1/n), normalising every step."""
+    v = np.array(v0, dtype=np.complex128, copy=True)
+    nv = vnorm(v)
+    v = v / nv
+    log_growth = 0.0
+    for _ in range(n):
+        w = apply(v)
+        g = vnorm(w)
+        log_growth += np.log(g)
+        v = w / g
+    return float(np.exp(log_growth / n))
+
+
+class GmresResult:
+    def __init__(self, x, converged, cycles, iters, history):
+        self.x = x
+        self.converged = converged
+        self.cycles = cycles
+        self.iters = iters
+        self.history = history  # residual estimate after every Arnoldi step
+
+
+def gmres(apply, b, x0, m: int, max_cycles: int, tol_abs: float, precond=None,
+          breakdown: float = 1e-14):
+    """Restarted GMRES(n = max_cycles, m) of Alg. 2 (flexible if precond is given).
+
+    Stops when the true residual |b - A x| at a restart is <= tol_abs.
+    """
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    history = []
+    iters = 0
+    for cycle in range(max_cycles + 1):
+        r = b - apply(x)
+        beta = vnorm(r)
+        if beta <= tol_abs:
+            return GmresResult(x, True, cycle, iters, history)
+        if cycle == max_cycles:
+            break
+        V = [r / beta]
+        Z = []
+        H = np.zeros((m + 1, m), dtype=np.complex128)
+        g = np.zeros(m + 1, dtype=np.complex128)
+        g[0] = beta
+        k_used = 0
+        y = None
+        for k in range(m):
+            z = V[k] if precond is None else precond(V[k])
+            Z.append(z)
+            w = apply(z)
+            for j in range(k + 1):
+                H[j, k] = vdot(V[j], w)
+                w = w - H[j, k] * V[j]
+            H[k + 1, k] = vnorm(w)
+            iters += 1
+            k_used = k + 1
+            y, *_ = np.linalg.lstsq(H[:k + 2, :k + 1], g[:k + 2], rcond=None)
+            est = vnorm(g[:k + 2] - H[:k + 2, :k + 1] @ y)
+            history.append(est)
+            if est <= tol_abs or H[k + 1, k].real <= breakdown * beta:
+                break
+            V.append(w / H[k + 1, k])
+        basis = Z if precond is not None else V
+        for j in range(k_used):
+            x = x + y[j] * basis[j]
+    return GmresResult(x, False, max_cycles, iters, history)
+
+
+def oe_solve(op, b, m: int, max_cycles: int, tol: float, precond=None):
+    """Odd-even solve of D x = b: eq. 2's prepare, GMRES on the Schur complement
+    to |b~_e - D_S x_e| <= tol |b|, reconstruct.  Returns (x, GmresResult)."""
+    bt = op.prepare(b)
+    res = gmres(op.schur, bt, np.zeros_like(bt), m, max_cycles, tol * vnorm(b), precond)
+    return op.reconstruct(res.x, b), res
+
+
+def richardson_preconditioner(apply, nsweeps: int, omega: float):
+    """M v = nsweeps Richardson sweeps on A z = v from z = 0 (Alg. 4)."""
+    def M(v):
+        return richardson(apply, v, np.zeros_like(v), nsweeps, omega)
+    return M

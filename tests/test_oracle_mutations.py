@@ -1,0 +1,87 @@
+"""The pins have teeth: plausible mistakes planted in the oracle (on the CPU) must
+make at least one pin fail.  Each mutant is patched in with monkeypatch and the
+pin is expected to raise AssertionError."""
+import numpy as np
+import pytest
+
+import test_oracle_pins as pins
+from oracle import dirac
+
+
+def _hop_swapped_projectors(lat, U, psi, adjoint=False):
+    # mistake: (1 + gamma) on the forward hop, (1 - gamma) on the backward hop
+    return _orig_hop(lat, U, psi, adjoint=not adjoint)
+
+
+def _hop_undaggered_backward(lat, U, psi, adjoint=False):
+    # mistake: U_mu(x - mu) instead of U_mu(x - mu)^H on the backward hop
+    out = np.zeros_like(psi)
+    for mu in range(4):
+        fw = dirac._colour(U[..., mu, :, :], lat.fwd(psi, mu))
+        out += fw - dirac._spin(dirac.GAMMA[mu], fw)
+        bw = lat.bwd(dirac._colour(np.swapaxes(U[..., mu, :, :], -1, -2), psi), mu)
+        out += bw + dirac._spin(dirac.GAMMA[mu], bw)
+    return 0.5 * out
+
+
+def _hop_no_half(lat, U, psi, adjoint=False):
+    return 2.0 * _orig_hop(lat, U, psi, adjoint)
+
+
+def _hop_axes_swapped(lat, U, psi, adjoint=False):
+    # mistake: the link of direction mu paired with the shift along the next axis
+    Us = U[..., [1, 0, 2, 3], :, :]
+    return _orig_hop(lat, Us, psi, adjoint)
+
+
+def _field_strength_quarter(lat, U):
+    return {k: 2.0 * v for k, v in _orig_fs(lat, U).items()}
+
+
+def _field_strength_reversed(lat, U):
+    return {k: -v for k, v in _orig_fs(lat, U).items()}
+
+
+def _field_strength_one_leaf(lat, U):
+    out = {}
+    for mu in range(4):
+        for nu in range(mu + 1, 4):
+            Um, Un = U[..., mu, :, :], U[..., nu, :, :]
+            S = lat.shift
+            Q = 4 * Um @ S(Un, {mu: 1}) @ dirac.dag(S(Um, {nu: 1})) @ dirac.dag(Un)
+            out[(mu, nu)] = (Q - dirac.dag(Q)) / 8.0
+    return out
+
+
+_orig_hop = dirac.hopping
+_orig_fs = dirac.field_strength
+
+
+@pytest.mark.parametrize("mutant,pin", [
+    (_hop_swapped_projectors, lambda: pins.test_free_field_full_operator((1, 5, 7, 4))),
+    (_hop_undaggered_backward, pins.test_pure_gauge),
+    (_hop_undaggered_backward, pins.test_gamma5_hermiticity),
+    (_hop_no_half, lambda: pins.test_free_field_schur((2, 5, 3, 7))),
+    (_hop_axes_swapped, pins.test_gauge_covariance),
+    (_hop_axes_swapped, pins.test_pure_gauge),
+])
+def test_hopping_mutants_caught(monkeypatch, mutant, pin):
+    monkeypatch.setattr(dirac, "hopping", mutant)
+    with pytest.raises(AssertionError):
+        pin()
+
+
+@pytest.mark.parametrize("mutant", [_field_strength_quarter, _field_strength_reversed])
+def test_clover_normalisation_mutants_caught(monkeypatch, mutant):
+    monkeypatch.setattr(dirac, "field_strength", mutant)
+    with pytest.raises(AssertionError):
+        pins.test_constant_abelian_clover(1)
+
+
+def test_single_leaf_clover_caught(monkeypatch):
+    # four times one leaf still agrees on a constant field; the leaf average
+    # over a varying abelian field tells them apart
+    monkeypatch.setattr(dirac, "field_strength", _field_strength_one_leaf)
+    pins.test_constant_abelian_clover(1)
+    with pytest.raises(AssertionError):
+        pins.test_abelian_field_clover_leaf_average()

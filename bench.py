@@ -1,0 +1,244 @@
+"""Benchmark of the odd-even Wilson-clover hot path on one MI355X.
+
+A step is one pass of the path over one batch of synthetic input on the large
+single-GPU lattice 48^3 x 96 (eps 0.5, c_sw 1.2, m0 -0.25, t antiperiodic):
+one FP32 Schur apply y_e = D_S x_e (eq. 3) and 20 FP32 Richardson sweeps
+(Alg. 4) with omega = 0.8 / |lambda_max(D_S)|.  Inputs are resident in HBM before
+the timed region.  Reported:
+
+  value          FP32 Schur-apply GB/s: algorithmic bytes of one apply (every
+                 field touched once per kernel: 2208 B per even site) / apply time
+  sweeps_per_s   FP32 Richardson sweeps per second
+  roofline       the dominant stencil kernel's algorithmic bytes per launch / its
+                 mean HIP-event duration, against 8 TB/s
+  mixed_vs_fp64  time to |b - D x| / |b| <= 1e-10 on 16^3 x 32 (eps 0.5, c_sw 1.0,
+                 m0 -0.2, Gaussian b) for FP64 GMRES(50) and for the same solver
+                 with the operator and Richardson preconditioner in FP32
+  cpu_baseline   the FP64 NumPy oracle on the host, on a bounded sample
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "Schur apply GB/s (% HBM peak) + smoother sweeps/s, mixed vs FP64 at 1e-10 resid"
+HBM_PEAK_GBS = 8000.0
+LARGE = dict(dims=(48, 48, 48, 96), eps=0.5, c_sw=1.2, m0=-0.25, seed_gauge=301, seed_vec=302)
+MIXED = dict(dims=(16, 16, 16, 32), eps=0.5, c_sw=1.0, m0=-0.2, seed_gauge=201, seed_vec=202)
+SWEEPS = 20
+BYTES_APPLY_F32 = 2208    # per even site, FP32 links/spinors/clover, every field once per kernel
+BYTES_APPLY_F64 = 4416
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def cpu_baseline(budget_s: float = 12.0):
+    """Time the FP64 oracle's Schur apply on the host on a 16^3 x 32 sample."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle.dirac import Lattice, WilsonClover
+    from paper_2407_08092_amd import synth
+
+    dims = MIXED["dims"]
+    with threadpool_limits(1):
+        lat = Lattice(dims)
+        op = WilsonClover(lat, synth.gauge_field(dims, MIXED["eps"], MIXED["seed_gauge"]), MIXED["c_sw"], MIXED["m0"])
+        x = synth.gaussian_complex((lat.Vh, 12), MIXED["seed_vec"])
+        n, t0 = 0, time.perf_counter()
+        while True:
+            x = op.schur(x) / 4.0
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        dt = (time.perf_counter() - t0) / n
+    gbs = BYTES_APPLY_F64 * lat.Vh / dt / 1e9
+    return {"value": round(gbs, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"{n} FP64 Schur applies on 16^3x32 (V/2 = {lat.Vh}), algorithmic FP64 bytes "
+                      f"({BYTES_APPLY_F64} B/even site) / mean time {dt * 1e3:.1f} ms; numpy single thread",
+            "host_cores_available": len(os.sched_getaffinity(0))}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is single-GPU; "
+              f"multi-GPU sharding is design only)", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None if args.no_cpu else cpu_baseline()
+    if cpu:
+        log(f"cpu baseline {cpu['value']} GB/s")
+
+    import torch
+
+    from paper_2407_08092_amd import api, synth
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    cfg = LARGE
+    dims = cfg["dims"]
+    t0 = time.time()
+    lat = api.create_lattice(dims, device=dev)
+    U = synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev)
+    api.set_gauge(lat, U)
+    del U
+    torch.cuda.empty_cache()
+    api.set_clover(lat, cfg["c_sw"], cfg["m0"])
+    vh = lat.Vh
+    g = synth.gaussian_complex((2, 12, vh), cfg["seed_vec"])
+    x64 = torch.from_numpy(g[0]).to(dev)
+    b64 = torch.from_numpy(g[1]).to(dev)
+    del g
+    lam = api.estimate_lambda_max(lat, 50, x64)
+    omega = 0.8 / lam
+    x32 = x64.to(torch.complex64)
+    b32 = b64.to(torch.complex64)
+    y32 = torch.empty_like(x32)
+    xs = torch.empty_like(x32)
+    log(f"set-up {time.time() - t0:.1f} s, |lambda_max| = {lam:.4f}, omega = {omega:.4f}")
+
+    stream = torch.cuda.current_stream(dev)
+
+    def step(ev=None):
+        if ev is not None:
+            ev[0].record(stream)
+        api.apply_schur(lat, x32, y32)
+        if ev is not None:
+            ev[1].record(stream)
+        xs.zero_()
+        api.richardson_smooth(lat, xs, b32, SWEEPS, omega)
+        if ev is not None:
+            ev[2].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    api.profile_begin(lat)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t_start
+    prof = api.profile_end(lat)
+    t_apply = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps  # ms
+    t_sweeps = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
+    gbs = BYTES_APPLY_F32 * vh / (t_apply * 1e-3) / 1e9
+    sweeps_per_s = SWEEPS / (t_sweeps * 1e-3)
+    ms_per_step = t_wall / args.steps * 1e3
+    log(f"FP32 apply {t_apply:.3f} ms = {gbs:.0f} GB/s; {sweeps_per_s:.1f} sweeps/s")
+
+    # dominant kernel of the timed region
+    name, st = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    ach = st["bytes_per_launch"] / (st["mean_ms"] * 1e-3) / 1e9
+    roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": st["bytes_per_launch"], "mean_ms": round(st["mean_ms"], 4),
+            "launches": st["launches"],
+            "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
+                                "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
+                            for k, v in prof.items()}}
+
+    # FP64 apply and sweeps on the same lattice (context)
+    y64 = torch.empty_like(x64)
+    for _ in range(2):
+        api.apply_schur(lat, x64, y64)
+    torch.cuda.synchronize()
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    n64 = max(3, args.steps // 4)
+    e0.record(stream)
+    for _ in range(n64):
+        api.apply_schur(lat, x64, y64)
+    e1.record(stream)
+    xs64 = torch.zeros_like(x64)
+    api.richardson_smooth(lat, xs64, b64, SWEEPS, omega)
+    e2.record(stream)
+    torch.cuda.synchronize()
+    t64 = e0.elapsed_time(e1) / n64
+    fp64 = {"apply_ms": round(t64, 4), "apply_GBs": round(BYTES_APPLY_F64 * vh / (t64 * 1e-3) / 1e9, 1),
+            "sweeps_per_s": round(SWEEPS / (e1.elapsed_time(e2) * 1e-3), 1)}
+    del y64, xs64, x64, b64
+    api.destroy_lattice(lat)
+    del lat
+    torch.cuda.empty_cache()
+
+    mixed = None
+    if not args.no_solve:
+        mixed = mixed_vs_fp64(api, synth, torch, dev)
+
+    out = {
+        "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "odd-even Wilson-clover 48^3x96, eps 0.5, c_sw 1.2, m0 -0.25, t antiperiodic: "
+                               "FP32 Schur apply + 20 FP32 Richardson sweeps per step",
+                   "dims": list(dims), "even_sites": vh, "sweeps_per_step": SWEEPS, "omega": round(omega, 6)},
+        "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "schur_apply_ms": round(t_apply, 4),
+        "sweeps_per_s": round(sweeps_per_s, 1),
+        "fp64": fp64,
+        "mixed_vs_fp64": mixed,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def mixed_vs_fp64(api, synth, torch, dev):
+    cfg = MIXED
+    dims = cfg["dims"]
+    lat = api.create_lattice(dims, device=dev)
+    api.set_gauge(lat, synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev))
+    api.set_clover(lat, cfg["c_sw"], cfg["m0"])
+    b = torch.from_numpy(synth.gaussian_spinor(dims, cfg["seed_vec"])).to(dev)
+    v0 = torch.from_numpy(synth.gaussian_complex((12, lat.Vh), cfg["seed_vec"] + 1)).to(dev)
+    omega = 0.8 / api.estimate_lambda_max(lat, 50, v0)
+    runs = {}
+    variants = {
+        "fp64_gmres50": dict(inner_prec=api.DDQ_F64, smoother_sweeps=0),
+        "fp64_gmres50_rich4": dict(inner_prec=api.DDQ_F64, smoother_sweeps=4),
+        "mixed_gmres50": dict(inner_prec=api.DDQ_F32, smoother_sweeps=0),
+        "mixed_gmres50_rich4": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4),
+    }
+    for name, kw in variants.items():
+        best = None
+        for _ in range(2):  # first call warms up and sizes the basis
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x, info, ok = api.oe_gmres_solve(lat, b, m=50, max_cycles=200, tol=1e-10, omega=omega, **kw)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        runs[name] = {"time_s": round(best, 4), "converged": bool(ok), "cycles": info["cycles"],
+                      "iters": info["iters"], "applies_f64": info["applies_f64"], "applies_f32": info["applies_lo"],
+                      "relres": info["true_relres"]}
+        log(f"{name}: {runs[name]}")
+    fp64_best = min(v["time_s"] for k, v in runs.items() if k.startswith("fp64") and v["converged"])
+    mixed_best = min(v["time_s"] for k, v in runs.items() if k.startswith("mixed") and v["converged"])
+    api.destroy_lattice(lat)
+    return {"workload": "16^3x32, eps 0.5, c_sw 1.0, m0 -0.2, Gaussian b, tol 1e-10 (|b~_e - D_S x_e| / |b|)",
+            "runs": runs, "fp64_best_s": fp64_best, "mixed_best_s": mixed_best,
+            "speedup": round(fp64_best / mixed_best, 3)}
+
+
+if __name__ == "__main__":
+    main()

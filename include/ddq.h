@@ -1,0 +1,195 @@
+/*
+ * ddq.h -- C ABI of the odd-even Wilson-clover library for AMD Instinct MI355X (gfx950).
+ *
+ * The library applies and inverts the odd-even preconditioned Wilson-clover
+ * Dirac operator of arXiv:2407.08092: the Schur complement
+ *     D_S = D_ee - D_eo D_oo^-1 D_oe                                    (eq. 3)
+ * of the even-first block form of D x = b                              (eq. 1),
+ * its factorised inverse                                               (eq. 2),
+ * the Richardson smoother of Alg. 4 and the restarted GMRES of Alg. 2 run on D_S.
+ *
+ * Operator (the paper names it in Sect. 2.3 but does not write it out; these are
+ * the library's conventions):
+ *   D psi(x) = A(x) psi(x) - H psi(x),
+ *   H psi(x) = 1/2 sum_mu [(1 - g_mu) U_mu(x) psi(x+mu) + (1 + g_mu) U_mu(x-mu)^H psi(x-mu)],
+ *   A(x)     = (4 + m0) + (i c_sw / 4) sum_{mu != nu} sigma_munu F_munu(x),
+ *   F_munu   = (Q_munu - Q_munu^H) / 8, Q_munu = sum of the four plaquette leaves at x,
+ * chiral gamma basis (g_k = [[0, -i s_k], [i s_k, 0]], g_4 = [[0, 1], [1, 0]],
+ * g_5 = diag(1, 1, -1, -1)), so A(x) is two Hermitian 6x6 blocks (Sect. 2.4.5).
+ * Periodic in x, y, z; antiperiodic in t when requested (a hop across the t
+ * boundary carries -1).  A site is even when x+y+z+t is even (Sect. 2.4.5).
+ *
+ * Layouts (all complex numbers are (re, im) pairs of the stated real type):
+ *   gauge links   U[t][z][y][x][mu][a][b]                      complex128
+ *   full vector   psi[t][z][y][x][spin 4][colour 3]            complex128 or complex64
+ *   parity vector v[rhs][sc][i]: sc = 3*spin + colour (12 rows), i = checkerboard
+ *                 index of the site within its parity = (lexicographic index
+ *                 x + Lx*(y + Ly*(z + Lz*t))) >> 1.  Row stride = V/2 elements,
+ *                 right-hand-side stride = 12*V/2 elements.  complex128 for
+ *                 DDQ_F64, complex64 for DDQ_F32.
+ *   clover export A[i][block 2][6][6] complex128, block 0 acting on spins 0,1 and
+ *                 block 1 on spins 2,3, index 3*spin' + colour inside a block.
+ *
+ * Ownership: every field pointer is a device pointer owned by the caller, except
+ * the gauge input of ddq_set_gauge, which may be a host pointer.  The library owns
+ * its packed copies of links and clover blocks and its work buffers; it allocates
+ * them in ddq_create_lattice / ddq_set_gauge / ddq_set_clover and, for GMRES
+ * bases, on the first solve that needs a larger basis; ddq_destroy_lattice frees
+ * them.  Apply and smooth calls allocate nothing.
+ *
+ * Streams: every call enqueues its work on the lattice's stream and returns
+ * without waiting, except ddq_set_clover, ddq_get_clover, ddq_estimate_lambda_max
+ * and ddq_oe_gmres_solve, which synchronise that stream.  One thread at a time
+ * per lattice handle.
+ *
+ * Errors: every call returns a ddq_status; no exception crosses the ABI.  On an
+ * error ddq_last_error() returns a message for the calling thread.
+ */
+#ifndef DDQ_H
+#define DDQ_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ddq_lattice ddq_lattice;
+
+/* Arithmetic of a call.  DDQ_F64: complex128 vectors, FP64 links and clover.
+ * DDQ_F32: complex64 vectors, FP32 links and clover (blocks inverted in FP64,
+ * then rounded). */
+enum ddq_prec { DDQ_F64 = 0, DDQ_F32 = 1 };
+
+enum ddq_status {
+  DDQ_OK = 0,
+  DDQ_NOT_CONVERGED = 1,   /* solver stopped at max_cycles; x holds the last iterate */
+  DDQ_ERR_ARG = -1,        /* bad argument (odd extent, null pointer, bad precision ...) */
+  DDQ_ERR_STATE = -2,      /* call out of order (apply before set_gauge / set_clover) */
+  DDQ_ERR_HIP = -3,        /* a HIP runtime call failed */
+  DDQ_ERR_OOM = -4,        /* device allocation failed */
+  DDQ_ERR_NOT_PD = -5,     /* a 6x6 clover block is not positive definite */
+  DDQ_ERR_NONFINITE = -6   /* NaN or Inf met in a residual norm */
+};
+
+/* storage_flags of ddq_set_gauge: which link precisions to materialise. */
+enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2 };
+
+/* Lattice of extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2, with
+ * V = Lx*Ly*Lz*Lt < 2^31.  t_antiperiodic != 0 selects antiperiodic t.
+ * hip_stream: a hipStream_t (NULL = the null stream). */
+int ddq_create_lattice(const int dims[4], int t_antiperiodic, void* hip_stream,
+                       ddq_lattice** out);
+int ddq_destroy_lattice(ddq_lattice* lat);
+int ddq_set_stream(ddq_lattice* lat, void* hip_stream);
+/* volume V and half volume V/2 */
+int ddq_lattice_size(const ddq_lattice* lat, int64_t* volume, int64_t* half_volume);
+
+/* Gauge links U (canonical layout, SU(3), complex128; host pointer when
+ * U_on_device == 0).  Packs them into the library's per-parity layout in the
+ * precisions selected by storage_flags.  Invalidates the clover term. */
+int ddq_set_gauge(ddq_lattice* lat, const void* U, int U_on_device, unsigned storage_flags);
+
+/* Builds the clover blocks A(x) on the GPU in FP64 (Sect. 2.3 operator), keeps
+ * A_ee and inverts every odd-site 6x6 block by Cholesky in FP64 (Sect. 2.4.5:
+ * storing D_oo^-1 is cheap); then rounds to every stored link precision.
+ * Returns DDQ_ERR_NOT_PD if a block is not positive definite. */
+int ddq_set_clover(ddq_lattice* lat, double c_sw, double m0);
+
+/* Exports A_ee and A_oo^-1 (FP64) in the clover export layout; device pointers,
+ * each V/2 * 72 complex128. Either may be NULL. */
+int ddq_get_clover(ddq_lattice* lat, void* A_ee, void* A_oo_inv);
+
+/* Full vector <-> parity vector (parity 0 = even, 1 = odd), nrhs right-hand
+ * sides, vectors complex128 (DDQ_F64) or complex64 (DDQ_F32). */
+int ddq_pack_parity(ddq_lattice* lat, int prec, int nrhs, int parity,
+                    const void* full, void* v);
+int ddq_unpack_parity(ddq_lattice* lat, int prec, int nrhs, int parity,
+                      const void* v, void* full);
+
+/* y_e = D_S x_e (eq. 3), or D_S^H x_e = g_5 D_S g_5 x_e when dagger != 0, for
+ * nrhs parity vectors.  x_e and y_e must not overlap. */
+int ddq_apply_schur(ddq_lattice* lat, int prec, int nrhs, const void* x_e, void* y_e,
+                    int dagger);
+
+/* Alg. 4 on D_S: nsweeps times x_e <- x_e + omega (b_e - D_S x_e), in place
+ * (x_e: in x^(0), out x^(n)).  omega is used as given; Alg. 4's
+ * omega = delta / |lambda_max| is formed by the caller (see
+ * ddq_estimate_lambda_max). */
+int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const void* b_e,
+                          int nsweeps, double omega);
+
+/* |lambda_max(D_S)| by power iteration in FP64 (Sect. 2.4.4):
+ * out = (|D_S^iters v0| / |v0|)^(1/iters).  v0: FP64 parity vector (device,
+ * not modified).  Synchronises the stream. */
+int ddq_estimate_lambda_max(ddq_lattice* lat, int iters, const void* v0, double* out);
+
+/* eq. 2, FP64: bt_e = b_e - D_eo D_oo^-1 b_o (b: full vector, bt_e: parity
+ * vector) and x = (x_e, D_oo^-1 (b_o - D_oe x_e)) (x: full vector). */
+int ddq_oe_prepare(ddq_lattice* lat, int nrhs, const void* b, void* bt_e);
+int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* b, void* x);
+
+/* Restarted GMRES(m) of Alg. 2 on D_S with eq. 2 around it.
+ *   m            cycle length (1 <= m <= 128)
+ *   max_cycles   restarts before giving up (DDQ_NOT_CONVERGED)
+ *   tol          stop when |b~_e - D_S x_e| <= tol * |b| (b the full right-hand
+ *                side); the same as the full residual |b - D x| in exact arithmetic
+ *   inner_prec   DDQ_F64: every operator apply in FP64.  DDQ_F32: inside a cycle
+ *                the operator and the smoother run in FP32 on FP64 Arnoldi
+ *                vectors (iterative refinement: the residual at every restart,
+ *                the orthogonalisation and the update are FP64)
+ *   smoother_sweeps  nu > 0: right preconditioner z = M v of nu Richardson
+ *                sweeps from zero (flexible GMRES); 0: none
+ *   omega        Richardson weight of the preconditioner
+ *   inner_reduction  a cycle ends once its residual estimate has fallen by
+ *                this factor (0 = automatic: 0 for FP64, 1e-5 for FP32)
+ * x: full vector, in the initial guess, out the solution; b: full vector;
+ * both complex128.  info (may be NULL) receives counts and the final residual
+ * (FP64, recomputed).  Synchronises the stream. */
+typedef struct {
+  int m;
+  int max_cycles;
+  double tol;
+  int inner_prec;
+  int smoother_sweeps;
+  double omega;
+  double inner_reduction;
+} ddq_gmres_params;
+
+typedef struct {
+  int cycles;            /* restarts performed */
+  int iters;             /* Arnoldi steps */
+  int applies_f64;       /* D_S applications in FP64 (smoother sweeps included) */
+  int applies_lo;        /* D_S applications in FP32 (smoother sweeps included) */
+  double true_relres;    /* |b~_e - D_S x_e| / |b|, FP64, after the last update */
+  double t_total_ms;     /* wall time of the call */
+} ddq_solve_info;
+
+int ddq_oe_gmres_solve(ddq_lattice* lat, void* x, const void* b,
+                       const ddq_gmres_params* params, ddq_solve_info* info);
+
+/* Per-kernel timing of the stencil kernels.  Between ddq_profile_begin and
+ * ddq_profile_end every stencil launch on the lattice's stream is bracketed by
+ * two HIP events on that stream.  ddq_profile_end synchronises the stream and
+ * fills up to max_entries records, one per kernel variant, with the launch count,
+ * the summed event time and the kernel's algorithmic bytes per launch (every
+ * field touched once per launch: links, clover blocks and spinors; the roofline
+ * numerator).  *n_out receives the number of variants seen. */
+typedef struct {
+  char name[40];
+  int launches;
+  double total_ms;
+  double bytes_per_launch;
+} ddq_kernel_stats;
+
+int ddq_profile_begin(ddq_lattice* lat);
+int ddq_profile_end(ddq_lattice* lat, ddq_kernel_stats* out, int max_entries, int* n_out);
+
+/* Thread-local message of the last error (empty string if none). */
+const char* ddq_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DDQ_H */

@@ -1,0 +1,253 @@
+"""Python binding of the C ABI in include/ddq.h: same names, torch tensors for
+device memory and streams, argument marshalling only.  Every step of the path
+runs in the HIP library; nothing here computes.
+
+Tensor layouts (see include/ddq.h):
+  gauge links   complex128 [Lt, Lz, Ly, Lx, 4, 3, 3]
+  full vector   complex128 / complex64 [Lt, Lz, Ly, Lx, 4, 3]   (or [nrhs, ...])
+  parity vector complex128 / complex64 [12, V/2]                  (or [nrhs, 12, V/2])
+The arithmetic of a call follows the dtype: complex128 -> FP64, complex64 -> FP32.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import DDQ_F32, DDQ_F64, DDQ_STORE_F32, DDQ_STORE_F64, DDQError, GmresParams, SolveInfo, check, lib
+
+__all__ = [
+    "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
+    "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
+    "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
+    "DDQ_F64", "DDQ_F32",
+]
+
+
+def _prec(t: torch.Tensor) -> int:
+    if t.dtype == torch.complex128:
+        return DDQ_F64
+    if t.dtype == torch.complex64:
+        return DDQ_F32
+    raise TypeError(f"expected complex128 or complex64, got {t.dtype}")
+
+
+def _dev(t: torch.Tensor, name: str) -> C.c_void_p:
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+class Lattice:
+    """Handle of a ddq_lattice; owns nothing on the Python side but the handle."""
+
+    def __init__(self, handle: C.c_void_p, dims, t_antiperiodic: bool, device: torch.device):
+        self.handle = handle
+        self.dims = tuple(dims)
+        self.t_antiperiodic = t_antiperiodic
+        self.device = device
+        V, Vh = C.c_int64(), C.c_int64()
+        check(lib().ddq_lattice_size(handle, C.byref(V), C.byref(Vh)), "ddq_lattice_size")
+        self.V, self.Vh = V.value, Vh.value
+        self._stream = None
+
+    def sync_stream(self):
+        """Enqueue the next calls on torch's current stream of the lattice's device."""
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        if s != self._stream:
+            check(lib().ddq_set_stream(self.handle, C.c_void_p(s)), "ddq_set_stream")
+            self._stream = s
+
+    @property
+    def full_shape(self):
+        lx, ly, lz, lt = self.dims
+        return (lt, lz, ly, lx, 4, 3)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h is not None and _lib._lib is not None:
+            try:
+                _lib._lib.ddq_destroy_lattice(h)
+            except Exception:  # pragma: no cover
+                pass
+            self.handle = None
+
+
+def create_lattice(dims, t_antiperiodic: bool = True, device=None) -> Lattice:
+    dims = [int(d) for d in dims]
+    device = torch.device("cuda", torch.cuda.current_device()) if device is None else torch.device(device)
+    arr = (C.c_int * 4)(*dims)
+    h = C.c_void_p()
+    with torch.cuda.device(device):
+        s = torch.cuda.current_stream(device).cuda_stream
+        check(lib().ddq_create_lattice(arr, int(bool(t_antiperiodic)), C.c_void_p(s), C.byref(h)),
+              "ddq_create_lattice")
+    lat = Lattice(h, dims, t_antiperiodic, device)
+    lat._stream = s
+    return lat
+
+
+def destroy_lattice(lat: Lattice) -> None:
+    if lat.handle is not None:
+        check(lib().ddq_destroy_lattice(lat.handle), "ddq_destroy_lattice")
+        lat.handle = None
+
+
+def set_gauge(lat: Lattice, U: torch.Tensor, store=(DDQ_F64, DDQ_F32)) -> None:
+    if U.dtype != torch.complex128 or tuple(U.shape) != lat.full_shape[:4] + (4, 3, 3):
+        raise ValueError(f"U must be complex128 of shape {lat.full_shape[:4] + (4, 3, 3)}")
+    U = U.contiguous()
+    flags = (DDQ_STORE_F64 if DDQ_F64 in store else 0) | (DDQ_STORE_F32 if DDQ_F32 in store else 0)
+    lat.sync_stream()
+    check(lib().ddq_set_gauge(lat.handle, C.c_void_p(U.data_ptr()), int(U.is_cuda), flags), "ddq_set_gauge")
+    if not U.is_cuda:
+        torch.cuda.current_stream(lat.device).synchronize()
+
+
+def set_clover(lat: Lattice, c_sw: float, m0: float) -> None:
+    lat.sync_stream()
+    check(lib().ddq_set_clover(lat.handle, float(c_sw), float(m0)), "ddq_set_clover")
+
+
+def get_clover(lat: Lattice):
+    """(A_ee, A_oo^-1) as complex128 device tensors [V/2, 2, 6, 6]."""
+    a = torch.empty((lat.Vh, 2, 6, 6), dtype=torch.complex128, device=lat.device)
+    b = torch.empty_like(a)
+    lat.sync_stream()
+    check(lib().ddq_get_clover(lat.handle, _dev(a, "A_ee"), _dev(b, "A_oo_inv")), "ddq_get_clover")
+    return a, b
+
+
+def parity_vector(lat: Lattice, nrhs=None, dtype=torch.complex128) -> torch.Tensor:
+    shape = (12, lat.Vh) if nrhs is None else (nrhs, 12, lat.Vh)
+    return torch.empty(shape, dtype=dtype, device=lat.device)
+
+
+def _nrhs_parity(lat, v):
+    if v.dim() == 2 and tuple(v.shape) == (12, lat.Vh):
+        return 1
+    if v.dim() == 3 and tuple(v.shape[1:]) == (12, lat.Vh):
+        return v.shape[0]
+    raise ValueError(f"parity vector must be [12, {lat.Vh}] or [nrhs, 12, {lat.Vh}], got {tuple(v.shape)}")
+
+
+def _nrhs_full(lat, f):
+    if tuple(f.shape) == lat.full_shape:
+        return 1
+    if f.dim() == 7 and tuple(f.shape[1:]) == lat.full_shape:
+        return f.shape[0]
+    raise ValueError(f"full vector must be {lat.full_shape} or [nrhs, ...], got {tuple(f.shape)}")
+
+
+def pack_parity(lat: Lattice, full: torch.Tensor, parity: int, out: torch.Tensor = None) -> torch.Tensor:
+    n = _nrhs_full(lat, full)
+    if out is None:
+        out = parity_vector(lat, None if full.dim() == 6 else n, full.dtype)
+    lat.sync_stream()
+    check(lib().ddq_pack_parity(lat.handle, _prec(full), n, int(parity), _dev(full, "full"), _dev(out, "v")),
+          "ddq_pack_parity")
+    return out
+
+
+def unpack_parity(lat: Lattice, v: torch.Tensor, parity: int, out: torch.Tensor = None) -> torch.Tensor:
+    n = _nrhs_parity(lat, v)
+    if out is None:
+        shape = lat.full_shape if v.dim() == 2 else (n,) + lat.full_shape
+        out = torch.zeros(shape, dtype=v.dtype, device=lat.device)
+    lat.sync_stream()
+    check(lib().ddq_unpack_parity(lat.handle, _prec(v), n, int(parity), _dev(v, "v"), _dev(out, "full")),
+          "ddq_unpack_parity")
+    return out
+
+
+def apply_schur(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor = None, dagger: bool = False) -> torch.Tensor:
+    """y_e = D_S x_e (eq. 3), or D_S^H x_e with dagger."""
+    n = _nrhs_parity(lat, x_e)
+    if y_e is None:
+        y_e = torch.empty_like(x_e)
+    lat.sync_stream()
+    check(lib().ddq_apply_schur(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(y_e, "y_e"), int(bool(dagger))),
+          "ddq_apply_schur")
+    return y_e
+
+
+def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweeps: int, omega: float) -> torch.Tensor:
+    """Alg. 4 on D_S, in place on x_e."""
+    n = _nrhs_parity(lat, x_e)
+    if b_e.dtype != x_e.dtype or b_e.shape != x_e.shape:
+        raise ValueError("x_e and b_e must match in dtype and shape")
+    lat.sync_stream()
+    check(lib().ddq_richardson_smooth(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(b_e, "b_e"),
+                                      int(nsweeps), float(omega)), "ddq_richardson_smooth")
+    return x_e
+
+
+def estimate_lambda_max(lat: Lattice, iters: int, v0: torch.Tensor) -> float:
+    if v0.dtype != torch.complex128:
+        raise TypeError("v0 must be complex128")
+    _nrhs_parity(lat, v0)
+    out = C.c_double()
+    lat.sync_stream()
+    check(lib().ddq_estimate_lambda_max(lat.handle, int(iters), _dev(v0, "v0"), C.byref(out)),
+          "ddq_estimate_lambda_max")
+    return out.value
+
+
+def oe_prepare(lat: Lattice, b: torch.Tensor) -> torch.Tensor:
+    n = _nrhs_full(lat, b)
+    if b.dtype != torch.complex128:
+        raise TypeError("b must be complex128")
+    bt = parity_vector(lat, None if b.dim() == 6 else n)
+    lat.sync_stream()
+    check(lib().ddq_oe_prepare(lat.handle, n, _dev(b, "b"), _dev(bt, "bt_e")), "ddq_oe_prepare")
+    return bt
+
+
+def oe_reconstruct(lat: Lattice, x_e: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    n = _nrhs_full(lat, b)
+    if b.dtype != torch.complex128 or x_e.dtype != torch.complex128:
+        raise TypeError("x_e and b must be complex128")
+    x = torch.empty_like(b)
+    lat.sync_stream()
+    check(lib().ddq_oe_reconstruct(lat.handle, n, _dev(x_e, "x_e"), _dev(b, "b"), _dev(x, "x")),
+          "ddq_oe_reconstruct")
+    return x
+
+
+def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
+                   tol: float = 1e-10, inner_prec: int = DDQ_F64, smoother_sweeps: int = 0, omega: float = 0.0,
+                   inner_reduction: float = 0.0):
+    """Odd-even GMRES(m) of Alg. 2 with eq. 2 around it.  Returns (x, info, converged)."""
+    if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
+        raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
+                    float(inner_reduction))
+    info = SolveInfo()
+    lat.sync_stream()
+    st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
+               "ddq_oe_gmres_solve", allow=(0, 1))
+    return x, info.as_dict(), st == 0
+
+
+def profile_begin(lat: Lattice) -> None:
+    """Start bracketing every stencil launch with HIP events on the lattice's stream."""
+    lat.sync_stream()
+    check(lib().ddq_profile_begin(lat.handle), "ddq_profile_begin")
+
+
+def profile_end(lat: Lattice):
+    """Stop profiling; per kernel variant: launches, total and mean event time,
+    algorithmic bytes per launch."""
+    arr = (_lib.KernelStats * 64)()
+    n = C.c_int()
+    check(lib().ddq_profile_end(lat.handle, arr, 64, C.byref(n)), "ddq_profile_end")
+    out = {}
+    for k in range(min(n.value, 64)):
+        e = arr[k]
+        out[e.name.decode()] = {"launches": e.launches, "total_ms": e.total_ms,
+                                "mean_ms": e.total_ms / max(e.launches, 1), "bytes_per_launch": e.bytes_per_launch}
+    return out

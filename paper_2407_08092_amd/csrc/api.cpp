@@ -1,0 +1,781 @@
+// api.cpp -- the C ABI (include/ddq.h): lattice handles, set-up, operator
+// applications, Richardson smoothing, power iteration, eq. 2 prepare /
+// reconstruct and the restarted (flexible, mixed-precision) GMRES of Alg. 2.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ddq.h"
+#include "ddq_internal.h"
+
+using namespace ddq;
+using cd = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return fail(DDQ_ERR_HIP, std::string(#expr) + " failed: " + hipGetErrorString(e_)); \
+  } while (0)
+
+#define CHK(expr)            \
+  do {                       \
+    int r_ = (expr);         \
+    if (r_ < 0) return r_;   \
+  } while (0)
+
+int dalloc(void** p, size_t bytes) {
+  *p = nullptr;
+  if (bytes == 0) return DDQ_OK;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(e == hipErrorOutOfMemory ? DDQ_ERR_OOM : DDQ_ERR_HIP,
+                "hipMalloc of " + std::to_string(bytes) + " bytes failed: " + hipGetErrorString(e));
+  }
+  return DDQ_OK;
+}
+
+void dfree(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+// a device buffer that only grows
+struct Grow {
+  void* p = nullptr;
+  size_t bytes = 0;
+  int ensure(size_t need) {
+    if (need <= bytes) return DDQ_OK;
+    dfree(p);
+    bytes = 0;
+    int r = dalloc(&p, need);
+    if (r == DDQ_OK) bytes = need;
+    return r;
+  }
+  void release() {
+    dfree(p);
+    bytes = 0;
+  }
+};
+
+}  // namespace
+
+struct ddq_lattice {
+  int dims[4];
+  int anti;
+  int64_t V, Vh;
+  Geo geo;
+  hipStream_t stream;
+  // canonical FP64 links kept on the device for the clover build
+  void* U = nullptr;
+  bool have_gauge = false;
+  unsigned store = 0;
+  void* links[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
+  void* clov[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [prec][0: A_ee, 1: A_oo^-1]
+  bool have_clover = false;
+  // work buffers
+  Grow tmp[2];        // u_o per precision
+  Grow scratch64;     // FP64 parity vectors
+  Grow scratch32;     // FP32 parity vectors
+  Grow partial;       // reduction partials
+  Grow small;         // device scalars: h (2 x 256 complex), norms
+  double* host = nullptr;  // pinned host mirror of `small`
+  size_t host_bytes = 0;
+  int nbx = 0;        // workgroups of the reduction kernels
+
+  // per-kernel timing (ddq_profile_begin / ddq_profile_end)
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev;          // pairs: start 2k, stop 2k+1
+  std::vector<int> ev_kind;            // kind of pair k
+  int ev_used = 0;
+  std::vector<std::string> kind_name;
+  std::vector<double> kind_ms, kind_bytes;
+  std::vector<int> kind_n;
+
+  long long nvec() const { return 12LL * Vh; }  // complex elements of one parity vector
+};
+
+namespace {
+
+int check_lat(const ddq_lattice* L) {
+  if (!L) return fail(DDQ_ERR_ARG, "null lattice handle");
+  return DDQ_OK;
+}
+
+int check_prec(int prec) {
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "precision must be DDQ_F64 or DDQ_F32");
+  return DDQ_OK;
+}
+
+int check_ready(const ddq_lattice* L, int prec) {
+  CHK(check_lat(L));
+  CHK(check_prec(prec));
+  if (!L->have_gauge) return fail(DDQ_ERR_STATE, "ddq_set_gauge has not been called");
+  if (!L->links[prec][0]) return fail(DDQ_ERR_STATE, "links not stored in the requested precision");
+  if (!L->have_clover) return fail(DDQ_ERR_STATE, "ddq_set_clover has not been called");
+  return DDQ_OK;
+}
+
+size_t elem_bytes(int prec) { return prec == DDQ_F64 ? 16 : 8; }
+
+int ensure_host(ddq_lattice* L, size_t bytes) {
+  if (bytes <= L->host_bytes) return DDQ_OK;
+  if (L->host) (void)hipHostFree(L->host);
+  L->host = nullptr;
+  L->host_bytes = 0;
+  HIPCHK(hipHostMalloc((void**)&L->host, bytes, hipHostMallocDefault));
+  L->host_bytes = bytes;
+  return DDQ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// operator building blocks
+// ---------------------------------------------------------------------------
+// algorithmic bytes of one stencil launch: every field touched once
+double hop_bytes(const ddq_lattice* L, int prec, int mode, int nrhs) {
+  // complex numbers per site: spinor rows (12 each) per right-hand side, 72 link
+  // entries (8 directions x 9), 36 clover pairs (2 blocks x 18 slots)
+  int spin = 0;
+  bool clover = true;
+  switch (mode) {
+    case M_HOP_CLINV: spin = 2; break;            // in, out
+    case M_RECON: spin = 3; break;                // in, b, out
+    case M_APPLY: spin = 3; break;                // in, x, out
+    case M_RICH: spin = 4; break;                 // in, x, b, out
+    case M_RESID: spin = 4; break;                // in, x, b, out
+    case M_PREP: spin = 3; clover = false; break; // in, b, out
+  }
+  const double per_site = (double)(12 * spin * nrhs + 72 + (clover ? 36 : 0)) * (prec == DDQ_F64 ? 16 : 8);
+  return per_site * (double)L->Vh;
+}
+
+const char* mode_name(int mode) {
+  static const char* n[] = {"hop_clinv", "hop_recon", "hop_apply", "hop_richardson", "hop_resid", "hop_prep"};
+  return n[mode];
+}
+
+int prof_flush(ddq_lattice* L) {
+  if (L->ev_used == 0) return DDQ_OK;
+  HIPCHK(hipEventSynchronize(L->ev[2 * (L->ev_used - 1) + 1]));
+  for (int k = 0; k < L->ev_used; ++k) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, L->ev[2 * k], L->ev[2 * k + 1]));
+    L->kind_ms[L->ev_kind[k]] += ms;
+    L->kind_n[L->ev_kind[k]] += 1;
+  }
+  L->ev_used = 0;
+  return DDQ_OK;
+}
+
+// launch a stencil kernel, bracketed by events while profiling
+template <typename R>
+hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
+  if (!L->prof_on) return launch_hop<R>(a, mode, dag, nrhs, L->stream);
+  const int prec = sizeof(R) == 8 ? DDQ_F64 : DDQ_F32;
+  std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : "_f32") + (dag ? "_dag" : "") +
+                     (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
+  int kind = -1;
+  for (size_t k = 0; k < L->kind_name.size(); ++k)
+    if (L->kind_name[k] == name) kind = (int)k;
+  if (kind < 0) {
+    kind = (int)L->kind_name.size();
+    L->kind_name.push_back(name);
+    L->kind_ms.push_back(0.0);
+    L->kind_n.push_back(0);
+    L->kind_bytes.push_back(hop_bytes(L, prec, mode, nrhs));
+  }
+  if (L->ev_used * 2 == (int)L->ev.size()) {
+    if (L->ev.size() < 2048) {
+      hipEvent_t e0, e1;
+      hipError_t e = hipEventCreate(&e0);
+      if (e != hipSuccess) return e;
+      e = hipEventCreate(&e1);
+      if (e != hipSuccess) return e;
+      L->ev.push_back(e0);
+      L->ev.push_back(e1);
+      L->ev_kind.push_back(0);
+    } else if (prof_flush(L) != DDQ_OK) {
+      return hipErrorUnknown;
+    }
+  }
+  const int k = L->ev_used++;
+  L->ev_kind[k] = kind;
+  hipError_t e = hipEventRecord(L->ev[2 * k], L->stream);
+  if (e != hipSuccess) return e;
+  e = launch_hop<R>(a, mode, dag, nrhs, L->stream);
+  if (e != hipSuccess) return e;
+  return hipEventRecord(L->ev[2 * k + 1], L->stream);
+}
+
+template <typename R>
+HopArgs<R> hop_args(const ddq_lattice* L, int prec, int p_out) {
+  HopArgs<R> a{};
+  a.g = L->geo;
+  a.p_out = p_out;
+  a.links = (const pair<R>*)L->links[prec][p_out];
+  a.clov = (const pair<R>*)L->clov[prec][p_out];
+  a.rhs_stride = L->nvec();
+  return a;
+}
+
+// u_o = A_oo^-1 H_oe x_e  (kernel A)
+template <typename R>
+hipError_t kernel_A(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, pair<R>* u, bool dag) {
+  HopArgs<R> a = hop_args<R>(L, prec, 1);
+  a.in = x;
+  a.out = u;
+  return run_hop<R>(L, a, M_HOP_CLINV, dag, nrhs);
+}
+
+// even-side kernel B in one of its modes
+template <typename R>
+hipError_t kernel_B(ddq_lattice* L, int prec, int nrhs, int mode, const pair<R>* u, const pair<R>* x,
+                    const pair<R>* b, pair<R>* out, R omega, bool dag) {
+  HopArgs<R> a = hop_args<R>(L, prec, 0);
+  a.in = u;
+  a.x = x;
+  a.b = b;
+  a.out = out;
+  a.omega = omega;
+  return run_hop<R>(L, a, mode, dag, nrhs);
+}
+
+template <typename R>
+int schur(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, pair<R>* y, bool dag) {
+  pair<R>* u = (pair<R>*)L->tmp[prec].p;
+  HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, dag));
+  HIPCHK(kernel_B<R>(L, prec, nrhs, M_APPLY, u, x, nullptr, y, R(0), dag));
+  return DDQ_OK;
+}
+
+template <typename R>
+int resid(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, const pair<R>* b, pair<R>* r) {
+  pair<R>* u = (pair<R>*)L->tmp[prec].p;
+  HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, false));
+  HIPCHK(kernel_B<R>(L, prec, nrhs, M_RESID, u, x, b, r, R(0), false));
+  return DDQ_OK;
+}
+
+template <typename R>
+int sweeps(ddq_lattice* L, int prec, int nrhs, pair<R>* x, const pair<R>* b, int n, R omega) {
+  pair<R>* u = (pair<R>*)L->tmp[prec].p;
+  for (int k = 0; k < n; ++k) {
+    HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, false));
+    HIPCHK(kernel_B<R>(L, prec, nrhs, M_RICH, u, x, b, x, omega, false));
+  }
+  return DDQ_OK;
+}
+
+int ensure_tmp(ddq_lattice* L, int prec, int nrhs) {
+  return L->tmp[prec].ensure((size_t)nrhs * L->nvec() * elem_bytes(prec));
+}
+
+// |v|^2 of n complex128 elements into device scalar dst
+int norm2_dev(ddq_lattice* L, const d2_t* v, long long n, double* dst) {
+  HIPCHK(launch_norm2_partial(v, n, (double*)L->partial.p, L->nbx, L->stream));
+  HIPCHK(launch_reduce_real((const double*)L->partial.p, L->nbx, dst, L->stream));
+  return DDQ_OK;
+}
+
+int fetch(ddq_lattice* L, const void* dev, size_t bytes) {
+  CHK(ensure_host(L, bytes));
+  HIPCHK(hipMemcpyAsync(L->host, dev, bytes, hipMemcpyDeviceToHost, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return DDQ_OK;
+}
+
+int norm_host(ddq_lattice* L, const d2_t* v, long long n, double* out) {
+  double* d = (double*)L->small.p;
+  CHK(norm2_dev(L, v, n, d));
+  CHK(fetch(L, d, sizeof(double)));
+  *out = std::sqrt(L->host[0]);
+  return DDQ_OK;
+}
+
+// eq. 2: b~_e = b_e - D_eo D_oo^-1 b_o = b_e + H_eo (A_oo^-1 b_o); bo: work vector(s)
+int prepare_impl(ddq_lattice* L, int nrhs, const d2_t* b, d2_t* bt_e, d2_t* bo) {
+  CHK(ensure_tmp(L, DDQ_F64, nrhs));
+  d2_t* u = (d2_t*)L->tmp[DDQ_F64].p;
+  HIPCHK(launch_pack_parity<double>(L->geo, 1, nrhs, b, bo, L->stream));
+  HIPCHK(launch_clover_only<double>(L->geo, nrhs, (const d2_t*)L->clov[DDQ_F64][1], bo, u, L->stream));
+  HIPCHK(launch_pack_parity<double>(L->geo, 0, nrhs, b, bt_e, L->stream));
+  HIPCHK(kernel_B<double>(L, DDQ_F64, nrhs, M_PREP, u, nullptr, bt_e, bt_e, 0.0, false));
+  return DDQ_OK;
+}
+
+// eq. 2: x_o = D_oo^-1 (b_o - D_oe x_e) = A_oo^-1 (b_o + H_oe x_e); bo, xo: work vectors
+int reconstruct_impl(ddq_lattice* L, int nrhs, const d2_t* x_e, const d2_t* b, d2_t* x, d2_t* bo, d2_t* xo) {
+  HIPCHK(launch_pack_parity<double>(L->geo, 1, nrhs, b, bo, L->stream));
+  HopArgs<double> a = hop_args<double>(L, DDQ_F64, 1);
+  a.in = x_e;
+  a.b = bo;
+  a.out = xo;
+  HIPCHK(run_hop<double>(L, a, M_RECON, false, nrhs));
+  HIPCHK(launch_unpack_parity<double>(L->geo, 0, nrhs, x_e, x, L->stream));
+  HIPCHK(launch_unpack_parity<double>(L->geo, 1, nrhs, xo, x, L->stream));
+  return DDQ_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* ddq_last_error(void) { return g_err.c_str(); }
+
+int ddq_create_lattice(const int dims[4], int t_antiperiodic, void* hip_stream, ddq_lattice** out) {
+  if (!out) return fail(DDQ_ERR_ARG, "out is null");
+  *out = nullptr;
+  if (!dims) return fail(DDQ_ERR_ARG, "dims is null");
+  long long V = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (dims[k] < 2 || (dims[k] & 1))
+      return fail(DDQ_ERR_ARG, "every extent must be even and >= 2 (got " + std::to_string(dims[k]) + ")");
+    V *= dims[k];
+  }
+  if (V >= (1LL << 31)) return fail(DDQ_ERR_ARG, "volume must be below 2^31 sites");
+  ddq_lattice* L = new ddq_lattice();
+  for (int k = 0; k < 4; ++k) L->dims[k] = dims[k];
+  L->anti = t_antiperiodic ? 1 : 0;
+  L->V = V;
+  L->Vh = V / 2;
+  Geo& g = L->geo;
+  for (int k = 0; k < 4; ++k) g.L[k] = dims[k];
+  g.Lxh = dims[0] / 2;
+  g.Vh = (int)L->Vh;
+  g.sY = g.Lxh;
+  g.sZ = g.Lxh * dims[1];
+  g.sT = g.Lxh * dims[1] * dims[2];
+  g.antiperiodic = L->anti;
+  L->stream = (hipStream_t)hip_stream;
+  long long nb = (L->nvec() + 255) / 256;
+  L->nbx = (int)(nb > 1024 ? 1024 : nb);
+  int r = L->partial.ensure((size_t)L->nbx * 256 * sizeof(d2_t));
+  if (r == DDQ_OK) r = L->small.ensure(4096 * sizeof(double));
+  if (r == DDQ_OK) r = ensure_host(L, 4096 * sizeof(double));
+  if (r != DDQ_OK) {
+    ddq_destroy_lattice(L);
+    return r;
+  }
+  *out = L;
+  return DDQ_OK;
+}
+
+int ddq_destroy_lattice(ddq_lattice* L) {
+  if (!L) return DDQ_OK;
+  dfree(L->U);
+  for (int p = 0; p < 2; ++p)
+    for (int q = 0; q < 2; ++q) {
+      dfree(L->links[p][q]);
+      dfree(L->clov[p][q]);
+    }
+  L->tmp[0].release();
+  L->tmp[1].release();
+  L->scratch64.release();
+  L->scratch32.release();
+  L->partial.release();
+  L->small.release();
+  if (L->host) (void)hipHostFree(L->host);
+  for (hipEvent_t e : L->ev) (void)hipEventDestroy(e);
+  delete L;
+  return DDQ_OK;
+}
+
+int ddq_set_stream(ddq_lattice* L, void* hip_stream) {
+  CHK(check_lat(L));
+  L->stream = (hipStream_t)hip_stream;
+  return DDQ_OK;
+}
+
+int ddq_lattice_size(const ddq_lattice* L, int64_t* volume, int64_t* half_volume) {
+  CHK(check_lat(L));
+  if (volume) *volume = L->V;
+  if (half_volume) *half_volume = L->Vh;
+  return DDQ_OK;
+}
+
+int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned storage_flags) {
+  CHK(check_lat(L));
+  if (!U) return fail(DDQ_ERR_ARG, "U is null");
+  if (storage_flags == 0) storage_flags = DDQ_STORE_F64 | DDQ_STORE_F32;
+  if (storage_flags & ~(unsigned)(DDQ_STORE_F64 | DDQ_STORE_F32))
+    return fail(DDQ_ERR_ARG, "unknown storage flag");
+  L->have_gauge = false;
+  L->have_clover = false;
+  const size_t ubytes = (size_t)L->V * 4 * 9 * 16;
+  if (!L->U) CHK(dalloc(&L->U, ubytes));
+  HIPCHK(hipMemcpyAsync(L->U, U, ubytes, U_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                        L->stream));
+  const size_t n = (size_t)8 * 9 * L->Vh;  // complex entries per parity
+  for (int q = 0; q < 2; ++q)
+    if (!L->links[DDQ_F64][q]) CHK(dalloc(&L->links[DDQ_F64][q], n * 16));
+  HIPCHK(launch_pack_gauge_f64(L->geo, (const d2_t*)L->U, (d2_t*)L->links[DDQ_F64][0],
+                               (d2_t*)L->links[DDQ_F64][1], L->stream));
+  if (storage_flags & DDQ_STORE_F32) {
+    for (int q = 0; q < 2; ++q) {
+      if (!L->links[DDQ_F32][q]) CHK(dalloc(&L->links[DDQ_F32][q], n * 8));
+      HIPCHK(launch_links_to_f32((const d2_t*)L->links[DDQ_F64][q], (f2_t*)L->links[DDQ_F32][q], (long long)n,
+                                 L->stream));
+    }
+  } else {
+    for (int q = 0; q < 2; ++q) dfree(L->links[DDQ_F32][q]);
+  }
+  L->store = storage_flags | DDQ_STORE_F64;
+  L->have_gauge = true;
+  return DDQ_OK;
+}
+
+int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
+  CHK(check_lat(L));
+  if (!L->have_gauge) return fail(DDQ_ERR_STATE, "ddq_set_gauge has not been called");
+  if (!std::isfinite(c_sw) || !std::isfinite(m0)) return fail(DDQ_ERR_ARG, "c_sw and m0 must be finite");
+  L->have_clover = false;
+  const size_t n = (size_t)2 * 18 * L->Vh;  // (re, im) slots per parity
+  for (int q = 0; q < 2; ++q)
+    if (!L->clov[DDQ_F64][q]) CHK(dalloc(&L->clov[DDQ_F64][q], n * 16));
+  int* flag = (int*)L->small.p;
+  HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), L->stream));
+  HIPCHK(launch_clover_build(L->geo, (const d2_t*)L->U, c_sw, m0, (d2_t*)L->clov[DDQ_F64][0],
+                             (d2_t*)L->clov[DDQ_F64][1], flag, L->stream));
+  CHK(fetch(L, flag, sizeof(int)));
+  int notpd = ((int*)L->host)[0];
+  if (notpd) return fail(DDQ_ERR_NOT_PD, "a 6x6 clover block is not positive definite");
+  if (L->links[DDQ_F32][0]) {
+    for (int q = 0; q < 2; ++q) {
+      if (!L->clov[DDQ_F32][q]) CHK(dalloc(&L->clov[DDQ_F32][q], n * 8));
+      HIPCHK(launch_links_to_f32((const d2_t*)L->clov[DDQ_F64][q], (f2_t*)L->clov[DDQ_F32][q], (long long)n,
+                                 L->stream));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(L->stream));
+  L->have_clover = true;
+  return DDQ_OK;
+}
+
+int ddq_get_clover(ddq_lattice* L, void* A_ee, void* A_oo_inv) {
+  CHK(check_ready(L, DDQ_F64));
+  if (A_ee) HIPCHK(launch_clover_export(L->geo, (const d2_t*)L->clov[DDQ_F64][0], (d2_t*)A_ee, L->stream));
+  if (A_oo_inv)
+    HIPCHK(launch_clover_export(L->geo, (const d2_t*)L->clov[DDQ_F64][1], (d2_t*)A_oo_inv, L->stream));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return DDQ_OK;
+}
+
+int ddq_pack_parity(ddq_lattice* L, int prec, int nrhs, int parity, const void* full, void* v) {
+  CHK(check_lat(L));
+  CHK(check_prec(prec));
+  if (nrhs < 1 || (parity != 0 && parity != 1) || !full || !v) return fail(DDQ_ERR_ARG, "bad pack arguments");
+  if (prec == DDQ_F64)
+    HIPCHK(launch_pack_parity<double>(L->geo, parity, nrhs, (const d2_t*)full, (d2_t*)v, L->stream));
+  else
+    HIPCHK(launch_pack_parity<float>(L->geo, parity, nrhs, (const f2_t*)full, (f2_t*)v, L->stream));
+  return DDQ_OK;
+}
+
+int ddq_unpack_parity(ddq_lattice* L, int prec, int nrhs, int parity, const void* v, void* full) {
+  CHK(check_lat(L));
+  CHK(check_prec(prec));
+  if (nrhs < 1 || (parity != 0 && parity != 1) || !full || !v) return fail(DDQ_ERR_ARG, "bad unpack arguments");
+  if (prec == DDQ_F64)
+    HIPCHK(launch_unpack_parity<double>(L->geo, parity, nrhs, (const d2_t*)v, (d2_t*)full, L->stream));
+  else
+    HIPCHK(launch_unpack_parity<float>(L->geo, parity, nrhs, (const f2_t*)v, (f2_t*)full, L->stream));
+  return DDQ_OK;
+}
+
+int ddq_apply_schur(ddq_lattice* L, int prec, int nrhs, const void* x_e, void* y_e, int dagger) {
+  CHK(check_ready(L, prec));
+  if (nrhs < 1 || !x_e || !y_e) return fail(DDQ_ERR_ARG, "bad apply arguments");
+  if (x_e == y_e) return fail(DDQ_ERR_ARG, "x_e and y_e must not overlap");
+  CHK(ensure_tmp(L, prec, nrhs));
+  if (prec == DDQ_F64) return schur<double>(L, prec, nrhs, (const d2_t*)x_e, (d2_t*)y_e, dagger != 0);
+  return schur<float>(L, prec, nrhs, (const f2_t*)x_e, (f2_t*)y_e, dagger != 0);
+}
+
+int ddq_richardson_smooth(ddq_lattice* L, int prec, int nrhs, void* x_e, const void* b_e, int nsweeps,
+                          double omega) {
+  CHK(check_ready(L, prec));
+  if (nrhs < 1 || !x_e || !b_e || nsweeps < 0) return fail(DDQ_ERR_ARG, "bad smoother arguments");
+  if (x_e == b_e) return fail(DDQ_ERR_ARG, "x_e and b_e must not overlap");
+  CHK(ensure_tmp(L, prec, nrhs));
+  if (prec == DDQ_F64) return sweeps<double>(L, prec, nrhs, (d2_t*)x_e, (const d2_t*)b_e, nsweeps, omega);
+  return sweeps<float>(L, prec, nrhs, (f2_t*)x_e, (const f2_t*)b_e, nsweeps, (float)omega);
+}
+
+int ddq_estimate_lambda_max(ddq_lattice* L, int iters, const void* v0, double* out) {
+  CHK(check_ready(L, DDQ_F64));
+  if (iters < 1 || !v0 || !out) return fail(DDQ_ERR_ARG, "bad power-iteration arguments");
+  if (iters > 4000) return fail(DDQ_ERR_ARG, "at most 4000 power iterations");
+  CHK(ensure_tmp(L, DDQ_F64, 1));
+  const long long n = L->nvec();
+  CHK(L->scratch64.ensure(2 * (size_t)n * 16));
+  d2_t* v = (d2_t*)L->scratch64.p;
+  d2_t* w = v + n;
+  double* nrm = (double*)L->small.p;  // nrm[0] = |v0|^2, nrm[1 + k] = |D_S v_k|^2
+  CHK(norm2_dev(L, (const d2_t*)v0, n, nrm));
+  HIPCHK(launch_scale_dev(v, (const d2_t*)v0, nrm, n, L->stream));
+  for (int k = 0; k < iters; ++k) {
+    CHK(schur<double>(L, DDQ_F64, 1, v, w, false));
+    CHK(norm2_dev(L, w, n, nrm + 1 + k));
+    HIPCHK(launch_scale_dev(v, w, nrm + 1 + k, n, L->stream));
+  }
+  CHK(fetch(L, nrm, (size_t)(iters + 1) * sizeof(double)));
+  double lg = 0.0;
+  for (int k = 0; k < iters; ++k) lg += 0.5 * std::log(L->host[1 + k]);
+  if (!(L->host[0] > 0.0)) return fail(DDQ_ERR_ARG, "v0 is zero");
+  if (!std::isfinite(lg)) return fail(DDQ_ERR_NONFINITE, "power iteration produced a non-finite norm");
+  *out = std::exp(lg / iters);
+  return DDQ_OK;
+}
+
+int ddq_oe_prepare(ddq_lattice* L, int nrhs, const void* b, void* bt_e) {
+  CHK(check_ready(L, DDQ_F64));
+  if (nrhs < 1 || !b || !bt_e) return fail(DDQ_ERR_ARG, "bad prepare arguments");
+  if (b == bt_e) return fail(DDQ_ERR_ARG, "b and bt_e must not overlap");
+  CHK(L->scratch64.ensure((size_t)nrhs * L->nvec() * 16));
+  return prepare_impl(L, nrhs, (const d2_t*)b, (d2_t*)bt_e, (d2_t*)L->scratch64.p);
+}
+
+int ddq_oe_reconstruct(ddq_lattice* L, int nrhs, const void* x_e, const void* b, void* x) {
+  CHK(check_ready(L, DDQ_F64));
+  if (nrhs < 1 || !x_e || !b || !x) return fail(DDQ_ERR_ARG, "bad reconstruct arguments");
+  if (x == b || x == x_e) return fail(DDQ_ERR_ARG, "x must not overlap b or x_e");
+  const size_t nb = (size_t)nrhs * L->nvec();
+  CHK(L->scratch64.ensure(2 * nb * 16));
+  d2_t* bo = (d2_t*)L->scratch64.p;
+  return reconstruct_impl(L, nrhs, (const d2_t*)x_e, (const d2_t*)b, (d2_t*)x, bo, bo + nb);
+}
+
+int ddq_profile_begin(ddq_lattice* L) {
+  CHK(check_lat(L));
+  L->prof_on = true;
+  L->ev_used = 0;
+  L->kind_name.clear();
+  L->kind_ms.clear();
+  L->kind_n.clear();
+  L->kind_bytes.clear();
+  return DDQ_OK;
+}
+
+int ddq_profile_end(ddq_lattice* L, ddq_kernel_stats* out, int max_entries, int* n_out) {
+  CHK(check_lat(L));
+  if (!L->prof_on) return fail(DDQ_ERR_STATE, "ddq_profile_begin has not been called");
+  CHK(prof_flush(L));
+  L->prof_on = false;
+  const int n = (int)L->kind_name.size();
+  if (n_out) *n_out = n;
+  for (int k = 0; k < n && k < max_entries && out; ++k) {
+    std::memset(out[k].name, 0, sizeof(out[k].name));
+    std::strncpy(out[k].name, L->kind_name[k].c_str(), sizeof(out[k].name) - 1);
+    out[k].launches = L->kind_n[k];
+    out[k].total_ms = L->kind_ms[k];
+    out[k].bytes_per_launch = L->kind_bytes[k];
+  }
+  return DDQ_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// GMRES(m) of Alg. 2 on D_S, flexible and mixed precision
+// ===========================================================================
+namespace {
+
+struct Givens {
+  double c;
+  cd s;
+};
+
+// rotate (a, b) -> (r, 0) with G = [[c, s], [-conj(s), c]], c real
+Givens make_givens(cd a, cd b) {
+  double na = std::abs(a), nb = std::abs(b);
+  if (nb == 0.0) return {1.0, 0.0};
+  if (na == 0.0) return {0.0, std::conj(b) / nb};
+  double rho = std::hypot(na, nb);
+  return {na / rho, (a / na) * std::conj(b) / rho};
+}
+
+}  // namespace
+
+extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
+                                  ddq_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  CHK(check_ready(L, DDQ_F64));
+  if (!x || !b || !P) return fail(DDQ_ERR_ARG, "x, b and params must be non-null");
+  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
+  const int m = P->m;
+  if (m < 1 || m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
+  if (P->max_cycles < 0 || !(P->tol >= 0.0) || P->smoother_sweeps < 0)
+    return fail(DDQ_ERR_ARG, "bad max_cycles, tol or smoother_sweeps");
+  CHK(check_prec(P->inner_prec));
+  const bool lo = P->inner_prec == DDQ_F32;
+  if (lo) CHK(check_ready(L, DDQ_F32));
+  const int nu = P->smoother_sweeps;
+  const bool flexible = nu > 0 || lo;
+  const double red = P->inner_reduction > 0.0 ? P->inner_reduction : (lo ? 1e-5 : 0.0);
+  const long long n = L->nvec();
+  const size_t vb = (size_t)n * 16;
+
+  // FP64 work: bt, xe, w, V[0..m], Z[0..m-1]
+  const size_t nv64 = 3 + (size_t)(m + 1) + (flexible ? (size_t)m : 0);
+  CHK(L->scratch64.ensure(nv64 * vb));
+  CHK(ensure_tmp(L, DDQ_F64, 1));
+  d2_t* base = (d2_t*)L->scratch64.p;
+  d2_t* bt = base;
+  d2_t* xe = base + n;
+  d2_t* w = base + 2 * n;
+  d2_t* V = base + 3 * n;
+  d2_t* Z = flexible ? V + (size_t)(m + 1) * n : nullptr;
+  // FP32 work: b32, x32, w32
+  f2_t *b32 = nullptr, *x32 = nullptr, *w32 = nullptr;
+  if (lo) {
+    CHK(L->scratch32.ensure(3 * (size_t)n * 8));
+    CHK(ensure_tmp(L, DDQ_F32, 1));
+    b32 = (f2_t*)L->scratch32.p;
+    x32 = b32 + n;
+    w32 = b32 + 2 * n;
+  }
+  d2_t* hdev = (d2_t*)L->small.p;          // [0, 128): first pass, [128, 256): second pass
+  double* ndev = (double*)(hdev + 256);    // |w|^2
+  CHK(ensure_host(L, 4096 * sizeof(double)));
+
+  int applies64 = 0, applies_lo = 0, iters = 0, cycles = 0;
+  // |b| of the full right-hand side (2 parities: 2n complex numbers)
+  double bnorm;
+  CHK(norm_host(L, (const d2_t*)b, 2 * n, &bnorm));
+  if (!std::isfinite(bnorm)) return fail(DDQ_ERR_NONFINITE, "right-hand side is not finite");
+  const double target = P->tol * bnorm;
+
+  // eq. 2: b~_e, initial x_e from the even half of x
+  CHK(prepare_impl(L, 1, (const d2_t*)b, bt, w));
+  HIPCHK(launch_pack_parity<double>(L->geo, 0, 1, (const d2_t*)x, xe, L->stream));
+
+  std::vector<cd> Hcol(m + 2), g(m + 2), y(m + 1);
+  std::vector<std::vector<cd>> R(m, std::vector<cd>(m + 1));
+  std::vector<Givens> rot(m);
+  int status = DDQ_NOT_CONVERGED;
+  double beta = 0.0;
+
+  for (cycles = 0;; ++cycles) {
+    // r = b~ - D_S x (FP64), the iterative-refinement residual
+    CHK(resid<double>(L, DDQ_F64, 1, xe, bt, V));
+    ++applies64;
+    CHK(norm_host(L, V, n, &beta));
+    if (!std::isfinite(beta)) return fail(DDQ_ERR_NONFINITE, "residual norm is not finite");
+    if (beta <= target) {
+      status = DDQ_OK;
+      break;
+    }
+    if (cycles == P->max_cycles) break;
+    HIPCHK(launch_scale(V, V, 1.0 / beta, n, L->stream));
+    std::fill(g.begin(), g.end(), cd(0.0));
+    g[0] = beta;
+    const double cycle_target = std::max(target, red * beta);
+    int k_used = 0;
+    for (int k = 0; k < m; ++k) {
+      d2_t* vk = V + (size_t)k * n;
+      d2_t* zk = flexible ? Z + (size_t)k * n : vk;
+      // z_k = M v_k, w = D_S z_k
+      if (lo) {
+        if (nu > 0) {
+          HIPCHK(launch_to_f32(b32, vk, n, L->stream));
+          HIPCHK(launch_scale_f32(x32, b32, (float)P->omega, n, L->stream));  // first sweep from 0
+          CHK(sweeps<float>(L, DDQ_F32, 1, x32, b32, nu - 1, (float)P->omega));
+          applies_lo += nu - 1;
+        } else {
+          HIPCHK(launch_to_f32(x32, vk, n, L->stream));
+        }
+        HIPCHK(launch_to_f64(zk, x32, n, L->stream));
+        CHK(schur<float>(L, DDQ_F32, 1, x32, w32, false));
+        ++applies_lo;
+        HIPCHK(launch_to_f64(w, w32, n, L->stream));
+      } else {
+        if (nu > 0) {
+          HIPCHK(launch_scale(zk, vk, P->omega, n, L->stream));
+          CHK(sweeps<double>(L, DDQ_F64, 1, zk, vk, nu - 1, P->omega));
+          applies64 += nu - 1;
+        }
+        CHK(schur<double>(L, DDQ_F64, 1, zk, w, false));
+        ++applies64;
+      }
+      // classical Gram-Schmidt, twice: h = V^H w, w -= V h
+      const int kk = k + 1;
+      for (int pass = 0; pass < 2; ++pass) {
+        d2_t* h = hdev + pass * 128;
+        HIPCHK(launch_dot_partial(V, n, kk, w, n, (d2_t*)L->partial.p, L->nbx, L->stream));
+        HIPCHK(launch_reduce_partial((const d2_t*)L->partial.p, L->nbx, kk, h, L->stream));
+        HIPCHK(launch_update(w, V, n, kk, h, -1.0, n, L->stream));
+      }
+      CHK(norm2_dev(L, w, n, ndev));
+      CHK(fetch(L, hdev, 256 * sizeof(d2_t) + sizeof(double)));
+      const double* hh = L->host;
+      for (int j = 0; j < kk; ++j) Hcol[j] = cd(hh[2 * j] + hh[256 + 2 * j], hh[2 * j + 1] + hh[256 + 2 * j + 1]);
+      const double hn = std::sqrt(hh[512]);
+      if (!std::isfinite(hn)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
+      Hcol[kk] = hn;
+      // apply the previous rotations, then a new one
+      for (int j = 0; j < k; ++j) {
+        cd t = rot[j].c * Hcol[j] + rot[j].s * Hcol[j + 1];
+        Hcol[j + 1] = -std::conj(rot[j].s) * Hcol[j] + rot[j].c * Hcol[j + 1];
+        Hcol[j] = t;
+      }
+      rot[k] = make_givens(Hcol[k], Hcol[kk]);
+      Hcol[k] = rot[k].c * Hcol[k] + rot[k].s * Hcol[kk];
+      Hcol[kk] = 0.0;
+      g[kk] = -std::conj(rot[k].s) * g[k];
+      g[k] = rot[k].c * g[k];
+      for (int j = 0; j <= k; ++j) R[k][j] = Hcol[j];
+      ++iters;
+      k_used = kk;
+      const double est = std::abs(g[kk]);
+      if (est <= cycle_target || hn <= 1e-14 * beta) break;
+      HIPCHK(launch_scale(V + (size_t)kk * n, w, 1.0 / hn, n, L->stream));
+    }
+    // y = R^-1 g, x_e += Z y (or V y)
+    for (int j = k_used - 1; j >= 0; --j) {
+      cd s = g[j];
+      for (int q = j + 1; q < k_used; ++q) s -= R[q][j] * y[q];
+      y[j] = s / R[j][j];
+    }
+    double* yh = L->host;
+    for (int j = 0; j < k_used; ++j) {
+      yh[2 * j] = y[j].real();
+      yh[2 * j + 1] = y[j].imag();
+    }
+    d2_t* ydev = hdev;
+    HIPCHK(hipMemcpyAsync(ydev, yh, (size_t)k_used * sizeof(d2_t), hipMemcpyHostToDevice, L->stream));
+    HIPCHK(launch_update(xe, flexible ? Z : V, n, k_used, ydev, 1.0, n, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));  // yh is reused next cycle
+  }
+  CHK(reconstruct_impl(L, 1, xe, (const d2_t*)b, (d2_t*)x, w, V));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  if (info) {
+    info->cycles = cycles;
+    info->iters = iters;
+    info->applies_f64 = applies64;
+    info->applies_lo = applies_lo;
+    info->true_relres = bnorm > 0 ? beta / bnorm : 0.0;
+    info->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status == DDQ_NOT_CONVERGED) g_err = "GMRES stopped at max_cycles";
+  return status;
+}

@@ -1,0 +1,314 @@
+// ddq_device.h -- device-side building blocks of the odd-even Wilson-clover kernels.
+//
+// Conventions are those of include/ddq.h: chiral gamma basis, hopping term
+// H = 1/2 sum_mu [(1 - g_mu) U_mu(x) T_+mu + (1 + g_mu) U_mu(x-mu)^H T_-mu], clover
+// blocks as two Hermitian 6x6 matrices per site (Sect. 2.4.5).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddq {
+
+// ---------------------------------------------------------------------------
+// complex arithmetic on (re, im) pairs
+// ---------------------------------------------------------------------------
+template <typename R> struct cpx { R r, i; };
+
+// native two-element vectors: one 16-byte (FP64) or 8-byte (FP32) access per complex
+typedef double d2_t __attribute__((ext_vector_type(2)));
+typedef float f2_t __attribute__((ext_vector_type(2)));
+template <typename R> struct pair_t;
+template <> struct pair_t<double> { using type = d2_t; };
+template <> struct pair_t<float> { using type = f2_t; };
+template <typename R> using pair = typename pair_t<R>::type;
+
+template <typename R> __device__ __forceinline__ cpx<R> mk(R r, R i) { return {r, i}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator+(cpx<R> a, cpx<R> b) { return {a.r + b.r, a.i + b.i}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator-(cpx<R> a, cpx<R> b) { return {a.r - b.r, a.i - b.i}; }
+template <typename R> __device__ __forceinline__ cpx<R> operator*(cpx<R> a, cpx<R> b) {
+  return {a.r * b.r - a.i * b.i, a.r * b.i + a.i * b.r};
+}
+template <typename R> __device__ __forceinline__ cpx<R> operator*(R s, cpx<R> a) { return {s * a.r, s * a.i}; }
+template <typename R> __device__ __forceinline__ cpx<R> conj(cpx<R> a) { return {a.r, -a.i}; }
+// conj(a) * b
+template <typename R> __device__ __forceinline__ cpx<R> cmul_conj(cpx<R> a, cpx<R> b) {
+  return {a.r * b.r + a.i * b.i, a.r * b.i - a.i * b.r};
+}
+template <typename R> __device__ __forceinline__ cpx<R> times_i(cpx<R> a) { return {-a.i, a.r}; }
+template <typename R> __device__ __forceinline__ cpx<R> times_minus_i(cpx<R> a) { return {a.i, -a.r}; }
+// acc += a * b
+template <typename R> __device__ __forceinline__ void cfma(cpx<R>& acc, cpx<R> a, cpx<R> b) {
+  acc.r = fma(a.r, b.r, acc.r);
+  acc.r = fma(-a.i, b.i, acc.r);
+  acc.i = fma(a.r, b.i, acc.i);
+  acc.i = fma(a.i, b.r, acc.i);
+}
+// acc += conj(a) * b
+template <typename R> __device__ __forceinline__ void cfma_conj(cpx<R>& acc, cpx<R> a, cpx<R> b) {
+  acc.r = fma(a.r, b.r, acc.r);
+  acc.r = fma(a.i, b.i, acc.r);
+  acc.i = fma(a.r, b.i, acc.i);
+  acc.i = fma(-a.i, b.r, acc.i);
+}
+
+// Row-strided fields through raw buffer descriptors.  A field is `nrows` rows of
+// V/2 (re, im) pairs.  The descriptor (base, byte size) lives in SGPRs, the row
+// offset goes into the scalar soffset operand and the lane's site into one 32-bit
+// VGPR offset, so a twelve-row spinor gather costs one VGPR of address, not
+// twelve 64-bit addresses.  Reads past the descriptor's size return zero instead
+// of faulting.  Every offset stays below 4 GiB: one descriptor never spans more
+// than one spinor, one link direction or one clover block pair.
+typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+constexpr int BUF_DWORD3 = 0x00020000;  // gfx9-family raw buffer format word
+
+template <typename R>
+struct Rows {
+  __amdgpu_buffer_rsrc_t rsrc;
+  uint32_t row_bytes;
+};
+
+template <typename R>
+__device__ __forceinline__ Rows<R> rows(const pair<R>* base, int nrows, int vh) {
+  Rows<R> r;
+  const uint32_t rb = (uint32_t)vh * (uint32_t)sizeof(pair<R>);
+  r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(rb * (uint32_t)nrows), BUF_DWORD3);
+  r.row_bytes = rb;
+  return r;
+}
+
+template <typename R> __device__ __forceinline__ uint32_t byte_off(int i) {
+  return (uint32_t)i * (uint32_t)sizeof(pair<R>);
+}
+
+template <typename R>
+__device__ __forceinline__ cpx<R> bload(const Rows<R>& r, int row, uint32_t off) {
+  if constexpr (sizeof(R) == 8) {
+    u4_t v = __builtin_amdgcn_raw_buffer_load_b128(r.rsrc, (int)off, (int)(row * r.row_bytes), 0);
+    d2_t d = __builtin_bit_cast(d2_t, v);
+    return {d.x, d.y};
+  } else {
+    u2_t v = __builtin_amdgcn_raw_buffer_load_b64(r.rsrc, (int)off, (int)(row * r.row_bytes), 0);
+    f2_t f = __builtin_bit_cast(f2_t, v);
+    return {f.x, f.y};
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ void bstore(const Rows<R>& r, int row, uint32_t off, cpx<R> a) {
+  if constexpr (sizeof(R) == 8) {
+    d2_t d;
+    d.x = a.r;
+    d.y = a.i;
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, d), r.rsrc, (int)off,
+                                           (int)(row * r.row_bytes), 0);
+  } else {
+    f2_t f;
+    f.x = a.r;
+    f.y = a.i;
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, f), r.rsrc, (int)off,
+                                          (int)(row * r.row_bytes), 0);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// geometry of one parity: checkerboard index i <-> coordinates
+// ---------------------------------------------------------------------------
+struct Geo {
+  int L[4];      // Lx, Ly, Lz, Lt
+  int Lxh;       // Lx / 2
+  int Vh;        // V / 2
+  int sY, sZ, sT;  // checkerboard strides of y, z, t: Lxh, Lxh*Ly, Lxh*Ly*Lz
+  int antiperiodic;
+};
+
+struct Site {
+  int i, x, y, z, t;
+};
+
+// coordinates of checkerboard site i of parity p
+__device__ __forceinline__ Site decode(const Geo& g, int i, int p) {
+  Site s;
+  s.i = i;
+  int xh = i % g.Lxh;
+  int r = i / g.Lxh;
+  s.y = r % g.L[1];
+  r /= g.L[1];
+  s.z = r % g.L[2];
+  s.t = r / g.L[2];
+  s.x = 2 * xh + ((p + s.y + s.z + s.t) & 1);
+  return s;
+}
+
+// XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the
+// eight XCDs; renumber them so that every XCD walks one contiguous range of sites
+// and the neighbour reuse in y and z stays inside that XCD's L2.
+__device__ __forceinline__ int xcd_block(int nblocks_padded) {
+  int b = blockIdx.x;
+  int per = nblocks_padded >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// spinors: 4 spins x 3 colours
+// ---------------------------------------------------------------------------
+template <typename R> struct Spinor { cpx<R> c[4][3]; };
+template <typename R> struct Half { cpx<R> c[2][3]; };
+
+template <typename R> __device__ __forceinline__ void zero(Spinor<R>& s) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s.c[a][b] = {R(0), R(0)};
+}
+
+// spinor at checkerboard site i of a parity vector (12 rows)
+template <typename R>
+__device__ __forceinline__ Spinor<R> load_spinor(const Rows<R>& v, int i) {
+  Spinor<R> s;
+  const uint32_t off = byte_off<R>(i);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) s.c[a][b] = bload<R>(v, 3 * a + b, off);
+  return s;
+}
+template <typename R>
+__device__ __forceinline__ void store_spinor(const Rows<R>& v, int i, const Spinor<R>& s) {
+  const uint32_t off = byte_off<R>(i);
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) bstore<R>(v, 3 * a + b, off, s.c[a][b]);
+}
+
+// Spin projection (1 + sg * g_mu) psi in the chiral basis.  With
+// g_mu = [[0, B], [B^H, 0]] (B_1 = -i s1, B_2 = -i s2, B_3 = -i s3, B_4 = 1) the
+// projected spinor is (h, sg * B^H h) with h = psi_up + sg * B psi_dn, so only
+// the two-spin h goes through the SU(3) multiply.
+template <int MU, typename R>
+__device__ __forceinline__ Half<R> project(const Spinor<R>& p, R sg) {
+  Half<R> h;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    cpx<R> b0, b1;  // B psi_dn
+    if (MU == 0) {        // B = [[0, -i], [-i, 0]]
+      b0 = times_minus_i(p.c[3][c]);
+      b1 = times_minus_i(p.c[2][c]);
+    } else if (MU == 1) { // B = [[0, -1], [1, 0]]
+      b0 = {-p.c[3][c].r, -p.c[3][c].i};
+      b1 = p.c[2][c];
+    } else if (MU == 2) { // B = [[-i, 0], [0, i]]
+      b0 = times_minus_i(p.c[2][c]);
+      b1 = times_i(p.c[3][c]);
+    } else {              // B = 1
+      b0 = p.c[2][c];
+      b1 = p.c[3][c];
+    }
+    h.c[0][c] = p.c[0][c] + sg * b0;
+    h.c[1][c] = p.c[1][c] + sg * b1;
+  }
+  return h;
+}
+
+// acc += f * (h, sg * B^H h): reconstruct the lower spins of a projected spinor
+template <int MU, typename R>
+__device__ __forceinline__ void accumulate(Spinor<R>& acc, const Half<R>& h, R sg) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    acc.c[0][c] = acc.c[0][c] + h.c[0][c];
+    acc.c[1][c] = acc.c[1][c] + h.c[1][c];
+    cpx<R> d0, d1;  // B^H h
+    if (MU == 0) {        // B^H = [[0, i], [i, 0]]
+      d0 = times_i(h.c[1][c]);
+      d1 = times_i(h.c[0][c]);
+    } else if (MU == 1) { // B^H = [[0, 1], [-1, 0]]
+      d0 = h.c[1][c];
+      d1 = {-h.c[0][c].r, -h.c[0][c].i};
+    } else if (MU == 2) { // B^H = [[i, 0], [0, -i]]
+      d0 = times_i(h.c[0][c]);
+      d1 = times_minus_i(h.c[1][c]);
+    } else {
+      d0 = h.c[0][c];
+      d1 = h.c[1][c];
+    }
+    acc.c[2][c] = acc.c[2][c] + sg * d0;
+    acc.c[3][c] = acc.c[3][c] + sg * d1;
+  }
+}
+
+// U h for a 3x3 link stored as 9 rows (row-major entries)
+template <typename R>
+__device__ __forceinline__ Half<R> link_mul(const Rows<R>& U, int i, const Half<R>& h) {
+  cpx<R> u[9];
+  const uint32_t off = byte_off<R>(i);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = bload<R>(U, e, off);
+  Half<R> o;
+#pragma unroll
+  for (int s = 0; s < 2; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      cpx<R> acc = u[3 * a] * h.c[s][0];
+      cfma(acc, u[3 * a + 1], h.c[s][1]);
+      cfma(acc, u[3 * a + 2], h.c[s][2]);
+      o.c[s][a] = acc;
+    }
+  return o;
+}
+
+// ---------------------------------------------------------------------------
+// clover blocks: Hermitian 6x6, 18 (re, im) slots per block:
+//   slots 0..2  diagonal pairs (d0, d1), (d2, d3), (d4, d5)
+//   slots 3..17 upper triangle a_jk, j < k, row-major ((0,1), (0,2), ..., (4,5))
+// layout [block 2][slot 18][i] with row stride vh.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int tri_slot(int j, int k) {  // j < k
+  return 3 + j * 5 - (j * (j - 1)) / 2 + (k - j - 1);
+}
+
+// C: the clover field (36 rows: block 0 slots 0..17, block 1 slots 18..35)
+template <typename R>
+__device__ __forceinline__ void clover_block_mul(const Rows<R>& C, int blk, int i, const cpx<R> in[6],
+                                                 cpx<R> out[6]) {
+  cpx<R> a[15];
+  R d[6];
+  const uint32_t off = byte_off<R>(i);
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    cpx<R> dd = bload<R>(C, 18 * blk + k, off);
+    d[2 * k] = dd.r;
+    d[2 * k + 1] = dd.i;
+  }
+#pragma unroll
+  for (int k = 0; k < 15; ++k) a[k] = bload<R>(C, 18 * blk + 3 + k, off);
+#pragma unroll
+  for (int j = 0; j < 6; ++j) out[j] = d[j] * in[j];
+#pragma unroll
+  for (int j = 0; j < 6; ++j)
+#pragma unroll
+    for (int k = j + 1; k < 6; ++k) {
+      cpx<R> ajk = a[tri_slot(j, k) - 3];
+      cfma(out[j], ajk, in[k]);
+      cfma_conj(out[k], ajk, in[j]);
+    }
+}
+
+// out = A psi for the two blocks of a site (block 0: spins 0,1; block 1: spins 2,3)
+template <typename R>
+__device__ __forceinline__ Spinor<R> clover_mul(const Rows<R>& C, int i, const Spinor<R>& p) {
+  Spinor<R> o;
+#pragma unroll
+  for (int b = 0; b < 2; ++b) {
+    cpx<R> in[6], out[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) in[k] = p.c[2 * b + k / 3][k % 3];
+    clover_block_mul<R>(C, b, i, in, out);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) o.c[2 * b + k / 3][k % 3] = out[k];
+  }
+  return o;
+}
+
+}  // namespace ddq

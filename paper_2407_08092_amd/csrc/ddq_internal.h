@@ -1,0 +1,81 @@
+// ddq_internal.h -- host-side declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "ddq_device.h"
+
+namespace ddq {
+
+// Epilogue of the hopping kernel.  The kernel computes h = H_{p, 1-p} in at every
+// site of parity p (H restricted to rows of parity p, columns of parity 1-p) and
+// then, with C the site's stored clover block (A_ee on even sites, A_oo^-1 on odd):
+enum HopMode {
+  M_HOP_CLINV = 0,  // out = C h                      u_o = A_oo^-1 H_oe x_e   (kernel A)
+  M_RECON = 1,      // out = C (b + h)                x_o = A_oo^-1 (b_o + H_oe x_e)
+  M_APPLY = 2,      // out = C x - h                  y_e = A_ee x_e - H_eo u_o (kernel B)
+  M_RICH = 3,       // out = x + w (b - C x + h)      Richardson sweep, in place
+  M_RESID = 4,      // out = b - C x + h              r = b - D_S x
+  M_PREP = 5,       // out = b + h                    b~_e = b_e + H_eo u_o
+  M_NMODES = 6
+};
+
+template <typename R>
+struct HopArgs {
+  Geo g;
+  int p_out;                 // parity of the output sites
+  const pair<R>* in;         // hopping input, parity 1 - p_out
+  const pair<R>* links;      // [8 dirs][9][vh], parity p_out: U_mu(x) then U_mu(x-mu)^H
+  const pair<R>* clov;       // [2 blocks][18 slots][vh], parity p_out
+  const pair<R>* x;          // own-parity vector (APPLY, RICH, RESID)
+  const pair<R>* b;          // own-parity right-hand side (RECON, RICH, RESID, PREP)
+  pair<R>* out;
+  R omega;
+  int nblk;                  // workgroups along x, padded to a multiple of 8
+  long long rhs_stride;      // elements between right-hand sides (blockIdx.y)
+};
+
+constexpr int HOP_BLOCK = 256;
+
+template <typename R>
+hipError_t launch_hop(const HopArgs<R>& a, int mode, bool dagger, int nrhs, hipStream_t s);
+
+// out = C v for every site of one parity (C = that parity's stored clover blocks)
+template <typename R>
+hipError_t launch_clover_only(const Geo& g, int nrhs, const pair<R>* clov, const pair<R>* v, pair<R>* out,
+                              hipStream_t s);
+
+// FP64 vector kernels (complex128 vectors of n elements)
+hipError_t launch_dot_partial(const d2_t* V, long long vstride, int k, const d2_t* w, long long n,
+                              d2_t* partial, int nbx, hipStream_t s);
+hipError_t launch_reduce_partial(const d2_t* partial, int nbx, int k, d2_t* out, hipStream_t s);
+hipError_t launch_update(d2_t* w, const d2_t* V, long long vstride, int k, const d2_t* h,
+                         double sign, long long n, hipStream_t s);
+hipError_t launch_norm2_partial(const d2_t* w, long long n, double* partial, int nbx, hipStream_t s);
+hipError_t launch_reduce_real(const double* partial, int nbx, double* out, hipStream_t s);
+hipError_t launch_scale(d2_t* out, const d2_t* in, double a, long long n, hipStream_t s);
+hipError_t launch_scale_dev(d2_t* out, const d2_t* in, const double* inv_norm_dev, long long n,
+                            hipStream_t s);
+hipError_t launch_axpy(d2_t* y, double ar, double ai, const d2_t* x, long long n, hipStream_t s);
+hipError_t launch_copy(d2_t* y, const d2_t* x, long long n, hipStream_t s);
+hipError_t launch_to_f32(f2_t* y, const d2_t* x, long long n, hipStream_t s);
+hipError_t launch_to_f64(d2_t* y, const f2_t* x, long long n, hipStream_t s);
+hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStream_t s);
+
+// field kernels
+hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_even, d2_t* out_odd,
+                                 hipStream_t s);
+hipError_t launch_links_to_f32(const d2_t* in, f2_t* out, long long n, hipStream_t s);
+hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0,
+                               d2_t* clov_even, d2_t* clov_odd_inv, int* notpd, hipStream_t s);
+hipError_t launch_clover_export(const Geo& g, const d2_t* packed, d2_t* dense, hipStream_t s);
+template <typename R>
+hipError_t launch_pack_parity(const Geo& g, int parity, int nrhs, const pair<R>* full, pair<R>* v,
+                              hipStream_t s);
+template <typename R>
+hipError_t launch_unpack_parity(const Geo& g, int parity, int nrhs, const pair<R>* v, pair<R>* full,
+                                hipStream_t s);
+
+}  // namespace ddq

@@ -1,0 +1,397 @@
+// fields.hip -- set-up kernels: gauge packing, clover blocks and their inverses,
+// parity packing of vectors.
+#include "ddq_internal.h"
+
+namespace ddq {
+
+// lexicographic index of coordinates (x, y, z, t)
+__device__ __forceinline__ long long lex(const Geo& g, int x, int y, int z, int t) {
+  return x + (long long)g.L[0] * (y + (long long)g.L[1] * (z + (long long)g.L[2] * t));
+}
+
+__device__ __forceinline__ void coords_shift(const Geo& g, int c[4], int mu, int step) {
+  c[mu] += step;
+  if (c[mu] < 0) c[mu] += g.L[mu];
+  if (c[mu] >= g.L[mu]) c[mu] -= g.L[mu];
+}
+
+// ---------------------------------------------------------------------------
+// gauge packing: per parity p and site i, dirs 0..3 = U_mu(x), dirs 4..7 = U_mu(x-mu)^H
+// ---------------------------------------------------------------------------
+__global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict__ out_e,
+                             d2_t* __restrict__ out_o) {
+  const int vh = g.Vh;
+  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 2LL * vh) return;
+  const int p = (int)(tid / vh);
+  const int i = (int)(tid % vh);
+  Site s = decode(g, i, p);
+  d2_t* out = p == 0 ? out_e : out_o;
+  const long long n = lex(g, s.x, s.y, s.z, s.t);
+  for (int mu = 0; mu < 4; ++mu) {
+    const d2_t* u = U + (n * 4 + mu) * 9;
+    for (int e = 0; e < 9; ++e) out[(size_t)(mu * 9 + e) * vh + i] = u[e];
+    int c[4] = {s.x, s.y, s.z, s.t};
+    coords_shift(g, c, mu, -1);
+    const long long nb = lex(g, c[0], c[1], c[2], c[3]);
+    const d2_t* ub = U + (nb * 4 + mu) * 9;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        d2_t v = ub[3 * b + a];
+        v.y = -v.y;
+        out[(size_t)((4 + mu) * 9 + 3 * a + b) * vh + i] = v;
+      }
+  }
+}
+
+hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_e, d2_t* out_o, hipStream_t s) {
+  long long n = 2LL * g.Vh;
+  int blocks = (int)((n + 255) / 256);
+  hipLaunchKernelGGL(k_pack_gauge, dim3(blocks), dim3(256), 0, s, g, U, out_e, out_o);
+  return hipGetLastError();
+}
+
+__global__ void k_d2_to_f2(const d2_t* __restrict__ in, f2_t* __restrict__ out, long long n) {
+  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (; k < n; k += stride) {
+    d2_t v = in[k];
+    f2_t w;
+    w.x = (float)v.x;
+    w.y = (float)v.y;
+    out[k] = w;
+  }
+}
+
+hipError_t launch_links_to_f32(const d2_t* in, f2_t* out, long long n, hipStream_t s) {
+  int blocks = (int)((n + 255) / 256);
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_d2_to_f2, dim3(blocks), dim3(256), 0, s, in, out, n);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// clover blocks
+// ---------------------------------------------------------------------------
+struct M3 {
+  cpx<double> a[3][3];
+};
+
+__device__ __forceinline__ M3 load_link(const Geo& g, const d2_t* U, const int c[4], int mu) {
+  const long long n = lex(g, c[0], c[1], c[2], c[3]);
+  const d2_t* u = U + (n * 4 + mu) * 9;
+  M3 m;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      d2_t v = u[3 * a + b];
+      m.a[a][b] = {v.x, v.y};
+    }
+  return m;
+}
+
+__device__ __forceinline__ M3 mul(const M3& A, const M3& B) {
+  M3 C;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cpx<double> s = A.a[a][0] * B.a[0][b];
+      cfma(s, A.a[a][1], B.a[1][b]);
+      cfma(s, A.a[a][2], B.a[2][b]);
+      C.a[a][b] = s;
+    }
+  return C;
+}
+
+__device__ __forceinline__ M3 dagger(const M3& A) {
+  M3 C;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) C.a[a][b] = conj(A.a[b][a]);
+  return C;
+}
+
+// Q_munu(x): the four counter-clockwise leaves of the mu-nu plane that touch x
+__device__ M3 clover_leaves(const Geo& g, const d2_t* U, const int x[4], int mu, int nu) {
+  int c[4];
+  M3 Q;
+  // leaf 1: U_mu(x) U_nu(x+mu) U_mu(x+nu)^H U_nu(x)^H
+  {
+    M3 a = load_link(g, U, x, mu);
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, mu, 1);
+    M3 b = load_link(g, U, c, nu);
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, nu, 1);
+    M3 d = dagger(load_link(g, U, c, mu));
+    M3 e = dagger(load_link(g, U, x, nu));
+    Q = mul(mul(mul(a, b), d), e);
+  }
+  // leaf 2: U_nu(x) U_mu(x-mu+nu)^H U_nu(x-mu)^H U_mu(x-mu)
+  {
+    M3 a = load_link(g, U, x, nu);
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, mu, -1);
+    coords_shift(g, c, nu, 1);
+    M3 b = dagger(load_link(g, U, c, mu));
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, mu, -1);
+    M3 d = dagger(load_link(g, U, c, nu));
+    M3 e = load_link(g, U, c, mu);
+    M3 L = mul(mul(mul(a, b), d), e);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q.a[i][j] = Q.a[i][j] + L.a[i][j];
+  }
+  // leaf 3: U_mu(x-mu)^H U_nu(x-mu-nu)^H U_mu(x-mu-nu) U_nu(x-nu)
+  {
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, mu, -1);
+    M3 a = dagger(load_link(g, U, c, mu));
+    coords_shift(g, c, nu, -1);
+    M3 b = dagger(load_link(g, U, c, nu));
+    M3 d = load_link(g, U, c, mu);
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, nu, -1);
+    M3 e = load_link(g, U, c, nu);
+    M3 L = mul(mul(mul(a, b), d), e);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q.a[i][j] = Q.a[i][j] + L.a[i][j];
+  }
+  // leaf 4: U_nu(x-nu)^H U_mu(x-nu) U_nu(x+mu-nu) U_mu(x)^H
+  {
+    for (int k = 0; k < 4; ++k) c[k] = x[k];
+    coords_shift(g, c, nu, -1);
+    M3 a = dagger(load_link(g, U, c, nu));
+    M3 b = load_link(g, U, c, mu);
+    coords_shift(g, c, mu, 1);
+    M3 d = load_link(g, U, c, nu);
+    M3 e = dagger(load_link(g, U, x, mu));
+    M3 L = mul(mul(mul(a, b), d), e);
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) Q.a[i][j] = Q.a[i][j] + L.a[i][j];
+  }
+  return Q;
+}
+
+// F = (Q - Q^H) / 8
+__device__ __forceinline__ M3 field_from_leaves(const M3& Q) {
+  M3 F;
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 3; ++b) {
+      cpx<double> q = Q.a[a][b], qt = conj(Q.a[b][a]);
+      F.a[a][b] = {(q.r - qt.r) * 0.125, (q.i - qt.i) * 0.125};
+    }
+  return F;
+}
+
+// write a Hermitian 6x6 block (full matrix M) into the packed 18-slot format
+__device__ __forceinline__ void store_packed(d2_t* C, int i, int vh, const cpx<double> M[6][6]) {
+  for (int k = 0; k < 3; ++k) {
+    d2_t v;
+    v.x = M[2 * k][2 * k].r;
+    v.y = M[2 * k + 1][2 * k + 1].r;
+    C[(size_t)k * vh + i] = v;
+  }
+  for (int j = 0; j < 6; ++j)
+    for (int k = j + 1; k < 6; ++k) {
+      d2_t v;
+      v.x = M[j][k].r;
+      v.y = M[j][k].i;
+      C[(size_t)tri_slot(j, k) * vh + i] = v;
+    }
+}
+
+// In-place inverse of a Hermitian positive-definite 6x6 matrix by Cholesky
+// A = L L^H; returns false if a pivot is not positive.
+__device__ bool hpd_inverse6(cpx<double> A[6][6]) {
+  cpx<double> L[6][6];
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) L[j][k] = {0.0, 0.0};
+  for (int j = 0; j < 6; ++j) {
+    double d = A[j][j].r;
+    for (int k = 0; k < j; ++k) d -= L[j][k].r * L[j][k].r + L[j][k].i * L[j][k].i;
+    if (!(d > 0.0)) return false;
+    double ljj = sqrt(d);
+    L[j][j] = {ljj, 0.0};
+    for (int r = j + 1; r < 6; ++r) {
+      cpx<double> s = A[r][j];
+      for (int k = 0; k < j; ++k) {
+        cpx<double> t = L[r][k] * conj(L[j][k]);
+        s = s - t;
+      }
+      L[r][j] = {s.r / ljj, s.i / ljj};
+    }
+  }
+  // Linv = L^-1 (lower triangular), column by column by forward substitution
+  cpx<double> Li[6][6];
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) Li[j][k] = {0.0, 0.0};
+  for (int c = 0; c < 6; ++c) {
+    Li[c][c] = {1.0 / L[c][c].r, 0.0};
+    for (int r = c + 1; r < 6; ++r) {
+      cpx<double> s = {0.0, 0.0};
+      for (int k = c; k < r; ++k) cfma(s, L[r][k], Li[k][c]);
+      Li[r][c] = {-s.r / L[r][r].r, -s.i / L[r][r].r};
+    }
+  }
+  // A^-1 = Li^H Li
+  for (int j = 0; j < 6; ++j)
+    for (int k = 0; k < 6; ++k) {
+      cpx<double> s = {0.0, 0.0};
+      for (int r = (j > k ? j : k); r < 6; ++r) cfma_conj(s, Li[r][j], Li[r][k]);
+      A[j][k] = s;
+    }
+  return true;
+}
+
+// Per site: A_+- = (4 + m0) 1_6 + (i c_sw / 2) sum_l s_l (x) E_l^+-,
+// E_l^+- = +-F_{l t} - F_{jk}, (l, j, k) cyclic over (x, y, z).  This is the
+// chiral-basis form of (4 + m0) + (i c_sw / 4) sum sigma_munu F_munu:
+// sigma_{l t} = diag(s_l, -s_l) and sigma_{jk} = -diag(s_l, s_l).
+__global__ void k_clover_build(Geo g, const d2_t* __restrict__ U, double c_sw, double m0,
+                               d2_t* __restrict__ cl_e, d2_t* __restrict__ cl_o_inv, int* notpd) {
+  const int vh = g.Vh;
+  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 2LL * vh) return;
+  const int p = (int)(tid / vh);
+  const int i = (int)(tid % vh);
+  Site s = decode(g, i, p);
+  const int x[4] = {s.x, s.y, s.z, s.t};
+  // the six F_munu, indexed by (mu, nu) with mu < nu
+  M3 Fxt = field_from_leaves(clover_leaves(g, U, x, 0, 3));
+  M3 Fyt = field_from_leaves(clover_leaves(g, U, x, 1, 3));
+  M3 Fzt = field_from_leaves(clover_leaves(g, U, x, 2, 3));
+  M3 Fyz = field_from_leaves(clover_leaves(g, U, x, 1, 2));
+  M3 Fzx;  // F_zx = -F_xz
+  {
+    M3 Fxz = field_from_leaves(clover_leaves(g, U, x, 0, 2));
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) Fzx.a[a][b] = {-Fxz.a[a][b].r, -Fxz.a[a][b].i};
+  }
+  M3 Fxy = field_from_leaves(clover_leaves(g, U, x, 0, 1));
+  const double h = 0.5 * c_sw;
+  for (int blk = 0; blk < 2; ++blk) {
+    const double sg = blk == 0 ? 1.0 : -1.0;
+    cpx<double> E[3][3][3];  // E_l
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        E[0][a][b] = sg * Fxt.a[a][b] - Fyz.a[a][b];
+        E[1][a][b] = sg * Fyt.a[a][b] - Fzx.a[a][b];
+        E[2][a][b] = sg * Fzt.a[a][b] - Fxy.a[a][b];
+      }
+    // M = (i h) [s1 (x) E0 + s2 (x) E1 + s3 (x) E2] + (4 + m0)
+    cpx<double> M[6][6];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        cpx<double> e0 = E[0][a][b], e1 = E[1][a][b], e2 = E[2][a][b];
+        // spin blocks of s1 e0 + s2 e1 + s3 e2: [[e2, e0 - i e1], [e0 + i e1, -e2]]
+        cpx<double> b00 = e2, b11 = {-e2.r, -e2.i};
+        cpx<double> b01 = e0 - times_i(e1), b10 = e0 + times_i(e1);
+        M[a][b] = h * times_i(b00);
+        M[a][3 + b] = h * times_i(b01);
+        M[3 + a][b] = h * times_i(b10);
+        M[3 + a][3 + b] = h * times_i(b11);
+      }
+    for (int k = 0; k < 6; ++k) M[k][k].r += 4.0 + m0;
+    if (p == 0) {
+      store_packed(cl_e + (size_t)blk * 18 * vh, i, vh, M);
+    } else {
+      if (!hpd_inverse6(M)) {
+        *notpd = 1;
+        for (int j = 0; j < 6; ++j)
+          for (int k = 0; k < 6; ++k) M[j][k] = {0.0, 0.0};
+      }
+      store_packed(cl_o_inv + (size_t)blk * 18 * vh, i, vh, M);
+    }
+  }
+}
+
+hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0, d2_t* cl_e,
+                               d2_t* cl_o_inv, int* notpd, hipStream_t s) {
+  long long n = 2LL * g.Vh;
+  int blocks = (int)((n + 127) / 128);
+  hipLaunchKernelGGL(k_clover_build, dim3(blocks), dim3(128), 0, s, g, U, c_sw, m0, cl_e, cl_o_inv,
+                     notpd);
+  return hipGetLastError();
+}
+
+// packed [2][18][vh] -> dense [vh][2][6][6]
+__global__ void k_clover_export(Geo g, const d2_t* __restrict__ P, d2_t* __restrict__ D) {
+  const int vh = g.Vh;
+  long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (tid >= 2LL * vh) return;
+  const int blk = (int)(tid / vh);
+  const int i = (int)(tid % vh);
+  const d2_t* C = P + (size_t)blk * 18 * vh;
+  d2_t* out = D + ((size_t)i * 2 + blk) * 36;
+  for (int k = 0; k < 3; ++k) {
+    d2_t d = C[(size_t)k * vh + i];
+    d2_t a, b;
+    a.x = d.x; a.y = 0.0;
+    b.x = d.y; b.y = 0.0;
+    out[(2 * k) * 6 + 2 * k] = a;
+    out[(2 * k + 1) * 6 + 2 * k + 1] = b;
+  }
+  for (int j = 0; j < 6; ++j)
+    for (int k = j + 1; k < 6; ++k) {
+      d2_t v = C[(size_t)tri_slot(j, k) * vh + i];
+      out[j * 6 + k] = v;
+      v.y = -v.y;
+      out[k * 6 + j] = v;
+    }
+}
+
+hipError_t launch_clover_export(const Geo& g, const d2_t* packed, d2_t* dense, hipStream_t s) {
+  long long n = 2LL * g.Vh;
+  hipLaunchKernelGGL(k_clover_export, dim3((int)((n + 255) / 256)), dim3(256), 0, s, g, packed, dense);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// parity packing of vectors: full [n][12] <-> parity [12][vh]
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void k_pack_parity(Geo g, int parity, const pair<R>* __restrict__ full, pair<R>* __restrict__ v) {
+  const int vh = g.Vh;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vh) return;
+  const size_t r = blockIdx.y;
+  Site s = decode(g, i, parity);
+  const long long n = lex(g, s.x, s.y, s.z, s.t);
+  const pair<R>* src = full + r * (size_t)2 * vh * 12 + n * 12;
+  pair<R>* dst = v + r * (size_t)vh * 12;
+  for (int k = 0; k < 12; ++k) dst[(size_t)k * vh + i] = src[k];
+}
+
+template <typename R>
+__global__ void k_unpack_parity(Geo g, int parity, const pair<R>* __restrict__ v, pair<R>* __restrict__ full) {
+  const int vh = g.Vh;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= vh) return;
+  const size_t r = blockIdx.y;
+  Site s = decode(g, i, parity);
+  const long long n = lex(g, s.x, s.y, s.z, s.t);
+  pair<R>* dst = full + r * (size_t)2 * vh * 12 + n * 12;
+  const pair<R>* src = v + r * (size_t)vh * 12;
+  for (int k = 0; k < 12; ++k) dst[k] = src[(size_t)k * vh + i];
+}
+
+template <typename R>
+hipError_t launch_pack_parity(const Geo& g, int parity, int nrhs, const pair<R>* full, pair<R>* v,
+                              hipStream_t s) {
+  dim3 grid((g.Vh + 255) / 256, nrhs);
+  hipLaunchKernelGGL((k_pack_parity<R>), grid, dim3(256), 0, s, g, parity, full, v);
+  return hipGetLastError();
+}
+
+template <typename R>
+hipError_t launch_unpack_parity(const Geo& g, int parity, int nrhs, const pair<R>* v, pair<R>* full,
+                                hipStream_t s) {
+  dim3 grid((g.Vh + 255) / 256, nrhs);
+  hipLaunchKernelGGL((k_unpack_parity<R>), grid, dim3(256), 0, s, g, parity, v, full);
+  return hipGetLastError();
+}
+
+template hipError_t launch_pack_parity<double>(const Geo&, int, int, const d2_t*, d2_t*, hipStream_t);
+template hipError_t launch_pack_parity<float>(const Geo&, int, int, const f2_t*, f2_t*, hipStream_t);
+template hipError_t launch_unpack_parity<double>(const Geo&, int, int, const d2_t*, d2_t*, hipStream_t);
+template hipError_t launch_unpack_parity<float>(const Geo&, int, int, const f2_t*, f2_t*, hipStream_t);
+
+}  // namespace ddq

@@ -91,11 +91,12 @@ def gauge_field(dims, eps: float, seed: int, device=None):
     return _expi(su3_coefficients(dims, seed), eps, device=device)
 
 
-def random_su3_sites(dims, seed: int, eps: float = 3.0) -> np.ndarray:
-    """One random SU(3) matrix per site, shape (Lt, Lz, Ly, Lx, 3, 3)."""
+def random_su3_sites(dims, seed: int, eps: float = 3.0, device=None):
+    """One random SU(3) matrix per site, shape (Lt, Lz, Ly, Lx, 3, 3) (numpy, or a
+    torch tensor on `device`)."""
     rng = np.random.default_rng(seed)
     a = rng.standard_normal(field_shape(dims) + (8,))
-    return _expi(a, eps)
+    return _expi(a, eps, device=device)
 
 
 def gaussian_complex(shape, seed: int) -> np.ndarray:

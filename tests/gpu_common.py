@@ -1,0 +1,45 @@
+"""Shared set-up for the GPU parity tests: the same seeded inputs go to the oracle
+and, through the C ABI, to the HIP library.  Layout changes between the oracle's
+[V/2, 12] parity vectors and the ABI's [12, V/2] are done here, in test code."""
+import numpy as np
+import torch
+
+from oracle.dirac import Lattice, WilsonClover
+from paper_2407_08092_amd import api, synth
+
+
+def to_dev(v_np, dtype=torch.complex128):
+    """oracle parity vector [V/2, 12] (or [n, V/2, 12]) -> ABI layout on the GPU."""
+    t = torch.from_numpy(np.ascontiguousarray(np.swapaxes(v_np, -1, -2)))
+    return t.to(device="cuda", dtype=dtype).contiguous()
+
+
+def to_host(t):
+    """ABI parity vector -> oracle layout (complex128 numpy)."""
+    return np.ascontiguousarray(np.swapaxes(t.detach().to(torch.complex128).cpu().numpy(), -1, -2))
+
+
+class Case:
+    """One lattice with its oracle operator and its GPU twin."""
+
+    def __init__(self, dims, eps, c_sw, m0, seed, antiperiodic=True):
+        self.dims = tuple(dims)
+        self.olat = Lattice(dims, antiperiodic)
+        self.U = synth.gauge_field(dims, eps, seed)
+        self.op = WilsonClover(self.olat, self.U, c_sw, m0)
+        self.lat = api.create_lattice(dims, antiperiodic)
+        api.set_gauge(self.lat, torch.from_numpy(self.U).cuda())
+        api.set_clover(self.lat, c_sw, m0)
+
+    def vec(self, seed, n=None):
+        shape = (self.olat.Vh, 12) if n is None else (n, self.olat.Vh, 12)
+        return synth.gaussian_complex(shape, seed)
+
+    def full(self, seed):
+        return synth.gaussian_spinor(self.dims, seed)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))

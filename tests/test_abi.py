@@ -1,0 +1,71 @@
+"""The C-ABI library loads, exports every symbol include/ddq.h declares, and
+rejects bad arguments on the host before touching the GPU (CPU only)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2407_08092_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ddq.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(ddq_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("ddq_create_lattice", "ddq_set_gauge", "ddq_set_clover", "ddq_apply_schur",
+                     "ddq_richardson_smooth", "ddq_oe_gmres_solve", "ddq_oe_prepare", "ddq_oe_reconstruct"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_every_symbol():
+    assert set(declared_functions()) == set(_lib._SIGNATURES)
+
+
+@pytest.mark.parametrize("dims", [(4, 5, 4, 4), (0, 4, 4, 4), (4, 4, 4, 1), (4, 4, -2, 4)])
+def test_bad_extents_rejected_on_host(dims):
+    L = _lib.lib()
+    h = C.c_void_p()
+    arr = (C.c_int * 4)(*dims)
+    st = L.ddq_create_lattice(arr, 1, None, C.byref(h))
+    assert st == -1
+    assert h.value is None
+    assert b"even" in L.ddq_last_error()
+
+
+def test_null_arguments_rejected_on_host():
+    L = _lib.lib()
+    assert L.ddq_create_lattice(None, 1, None, None) == -1
+    assert L.ddq_apply_schur(None, 0, 1, None, None, 0) == -1
+    assert L.ddq_destroy_lattice(None) == 0
+    assert L.ddq_set_clover(None, 1.0, 0.0) == -1
+
+
+def test_too_large_volume_rejected():
+    L = _lib.lib()
+    h = C.c_void_p()
+    arr = (C.c_int * 4)(2048, 2048, 2048, 2)
+    assert L.ddq_create_lattice(arr, 1, None, C.byref(h)) == -1
+
+
+def test_no_cpu_fallback_in_product_package():
+    # the product package never imports the oracle
+    pkg = os.path.join(ROOT, "paper_2407_08092_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".cpp", ".hip", ".h")):
+                src = open(os.path.join(dirpath, f)).read()
+                assert "import oracle" not in src and "from oracle" not in src, f

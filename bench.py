@@ -39,6 +39,38 @@ BYTES_APPLY_F32 = 2208    # per even site, FP32 links/spinors/clover, every fiel
 BYTES_APPLY_F64 = 4416
 
 
+MODE_CODE = {"clinv": 0, "recon": 1, "apply": 2, "richardson": 3, "resid": 4, "prep": 5}
+KERNEL_SOURCES = ("paper_2407_08092_amd/csrc/hop.hip", "paper_2407_08092_amd/csrc/ddq_device.h",
+                  "paper_2407_08092_amd/csrc/ddq_internal.h")
+PROFILE = "profiles/hop_kernels_48x96.md"
+
+
+def measured_traffic(kernel_name: str):
+    """HBM traffic per launch of a stencil kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a copy kernel), or None when
+    the kernel sources changed since the counters were taken."""
+    import hashlib
+
+    h = hashlib.sha1()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    cur = h.hexdigest()[:16]
+    parts = kernel_name.split("_")  # hop_<mode>_<f32|f64>[...]
+    if len(parts) < 3 or parts[1] not in MODE_CODE:
+        return None
+    key = ("float" if parts[2] == "f32" else "double") + f":{MODE_CODE[parts[1]]}"
+    try:
+        lines = open(os.path.join(ROOT, PROFILE)).read().splitlines()
+    except OSError:
+        return None
+    for ln in lines:
+        f = ln.split()
+        if len(f) == 4 and f[0] == "traffic_bytes_per_launch" and f[1] == key and f[3] == cur:
+            return float(f[2])
+    return None
+
+
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
@@ -150,8 +182,10 @@ def main():
     # dominant kernel of the timed region
     name, st = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     ach = st["bytes_per_launch"] / (st["mean_ms"] * 1e-3) / 1e9
+    traffic = measured_traffic(name)
     roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "traffic_over_algorithmic": round(traffic / st["bytes_per_launch"], 3) if traffic else None,
             "bytes_per_launch": st["bytes_per_launch"], "mean_ms": round(st["mean_ms"], 4),
             "launches": st["launches"],
             "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
@@ -181,6 +215,9 @@ def main():
     del lat
     torch.cuda.empty_cache()
 
+    stream_gbs = stream_probe(api, torch, dev)
+    log(f"stream copy {stream_gbs:.0f} GB/s")
+
     mixed = None
     if not args.no_solve:
         mixed = mixed_vs_fp64(api, synth, torch, dev)
@@ -193,6 +230,8 @@ def main():
                                "FP32 Schur apply + 20 FP32 Richardson sweeps per step",
                    "dims": list(dims), "even_sites": vh, "sweeps_per_step": SWEEPS, "omega": round(omega, 6)},
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
+        "stream_copy_GBs": round(stream_gbs, 1),
+        "pct_of_stream_copy": round(100 * gbs / stream_gbs, 2),
         "schur_apply_ms": round(t_apply, 4),
         "sweeps_per_s": round(sweeps_per_s, 1),
         "fp64": fp64,
@@ -201,6 +240,26 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def stream_probe(api, torch, dev, nbytes=4 << 30, reps=5):
+    """Attainable HBM bandwidth: the library's STREAM-style copy of 4 GiB,
+    (read + write bytes) / time."""
+    src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1)
+    api.stream_copy(dst, src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        api.stream_copy(dst, src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
 def mixed_vs_fp64(api, synth, torch, dev):

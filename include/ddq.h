@@ -168,6 +168,24 @@ typedef struct {
 int ddq_oe_gmres_solve(ddq_lattice* lat, void* x, const void* b,
                        const ddq_gmres_params* params, ddq_solve_info* info);
 
+/* Backward pass of y_e = D_S(U) x_e (pattern: differentiation).
+ * ddq_backward_apply: grad_x_e = D_S^H grad_y_e = g5 D_S g5 grad_y_e (the adjoint
+ *   apply; the same as ddq_apply_schur with dagger = 1).
+ * ddq_backward_link_force: for L = Re(chi_e^H D_S(U) phi_e) (chi_e the upstream
+ *   gradient of y_e), the derivative with respect to every link, FP64:
+ *     G  complex128 [t][z][y][x][mu][3][3]: dL = Re tr(G^H dU) (torch's convention
+ *        for the gradient of a real function of complex U), or NULL;
+ *     F  double [t][z][y][x][mu][8]: F_a = dL/de for U -> exp(i e T_a) U,
+ *        T_a = lambda_a / 2, i.e. F_a = -Im tr(T_a U G^H), or NULL.
+ *   Both the hopping term and the clover term (its leaves and the inverse A_oo^-1)
+ *   are differentiated.  accumulate != 0 adds to G / F instead of overwriting.
+ *   chi_e, phi_e: FP64 parity vectors.  Needs the canonical links set by
+ *   ddq_set_gauge and the clover of ddq_set_clover.  Work buffers (two parity
+ *   vectors and V x 54 complex128 insertions) grow on first use. */
+int ddq_backward_apply(ddq_lattice* lat, int prec, int nrhs, const void* grad_y_e, void* grad_x_e);
+int ddq_backward_link_force(ddq_lattice* lat, const void* chi_e, const void* phi_e, void* G, void* F,
+                            int accumulate);
+
 /* Per-kernel timing of the stencil kernels.  Between ddq_profile_begin and
  * ddq_profile_end every stencil launch on the lattice's stream is bracketed by
  * two HIP events on that stream.  ddq_profile_end synchronises the stream and
@@ -184,6 +202,11 @@ typedef struct {
 
 int ddq_profile_begin(ddq_lattice* lat);
 int ddq_profile_end(ddq_lattice* lat, ddq_kernel_stats* out, int max_entries, int* n_out);
+
+/* STREAM-style device copy of `bytes` (a multiple of 16) from src to dst on
+ * hip_stream: the attainable-bandwidth probe reported next to the HBM peak.
+ * dst and src are device pointers, 16-byte aligned, not overlapping. */
+int ddq_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
 
 /* Thread-local message of the last error (empty string if none). */
 const char* ddq_last_error(void);

@@ -9,7 +9,8 @@ import ctypes as C
 import os
 
 PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(PKG, "libddq.so")
+# DDQ_LIBRARY selects an alternative build of the same library (tuning runs)
+LIB_PATH = os.environ.get("DDQ_LIBRARY") or os.path.join(PKG, "libddq.so")
 
 DDQ_F64, DDQ_F32 = 0, 1
 DDQ_STORE_F64, DDQ_STORE_F32 = 1, 2
@@ -60,6 +61,9 @@ _SIGNATURES = {
     "ddq_oe_prepare": [_P, C.c_int, _P, _P],
     "ddq_oe_reconstruct": [_P, C.c_int, _P, _P, _P],
     "ddq_oe_gmres_solve": [_P, _P, _P, C.POINTER(GmresParams), C.POINTER(SolveInfo)],
+    "ddq_backward_apply": [_P, C.c_int, C.c_int, _P, _P],
+    "ddq_backward_link_force": [_P, _P, _P, _P, _P, C.c_int],
+    "ddq_stream_copy": [_P, _P, C.c_int64, _P],
     "ddq_profile_begin": [_P],
     "ddq_profile_end": [_P, C.POINTER(KernelStats), C.c_int, C.POINTER(C.c_int)],
     "ddq_last_error": [],

@@ -21,6 +21,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
+    "stream_copy", "backward_apply", "backward_link_force",
     "DDQ_F64", "DDQ_F32",
 ]
 
@@ -251,3 +252,47 @@ def profile_end(lat: Lattice):
         out[e.name.decode()] = {"launches": e.launches, "total_ms": e.total_ms,
                                 "mean_ms": e.total_ms / max(e.launches, 1), "bytes_per_launch": e.bytes_per_launch}
     return out
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
+    """Device copy through the library's STREAM-style kernel on torch's current stream."""
+    nb = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() < nb:
+        raise ValueError("dst too small")
+    s = torch.cuda.current_stream(src.device).cuda_stream
+    check(lib().ddq_stream_copy(_dev(dst, "dst"), _dev(src, "src"), nb, C.c_void_p(s)), "ddq_stream_copy")
+
+
+def backward_apply(lat: Lattice, grad_y_e: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    """grad_x_e = D_S^H grad_y_e (the adjoint apply)."""
+    n = _nrhs_parity(lat, grad_y_e)
+    if out is None:
+        out = torch.empty_like(grad_y_e)
+    lat.sync_stream()
+    check(lib().ddq_backward_apply(lat.handle, _prec(grad_y_e), n, _dev(grad_y_e, "grad_y_e"), _dev(out, "grad_x_e")),
+          "ddq_backward_apply")
+    return out
+
+
+def backward_link_force(lat: Lattice, chi_e: torch.Tensor, phi_e: torch.Tensor, want_G: bool = True,
+                        want_F: bool = False, G: torch.Tensor = None, F: torch.Tensor = None):
+    """Derivative of L = Re(chi_e^H D_S(U) phi_e) with respect to the links: G (torch's
+    complex-gradient convention, [Lt, Lz, Ly, Lx, 4, 3, 3]) and/or the su(3) force F
+    ([Lt, Lz, Ly, Lx, 4, 8]).  Passing G / F accumulates into them."""
+    if chi_e.dtype != torch.complex128 or phi_e.dtype != torch.complex128:
+        raise TypeError("chi_e and phi_e must be complex128")
+    if _nrhs_parity(lat, chi_e) != 1 or _nrhs_parity(lat, phi_e) != 1:
+        raise ValueError("one right-hand side")
+    acc = G is not None or F is not None
+    if acc and ((want_G and G is None) or (want_F and F is None)):
+        raise ValueError("pass every requested output when accumulating")
+    shp = lat.full_shape[:4] + (4,)
+    if want_G and G is None:
+        G = torch.empty(shp + (3, 3), dtype=torch.complex128, device=lat.device)
+    if want_F and F is None:
+        F = torch.empty(shp + (8,), dtype=torch.float64, device=lat.device)
+    lat.sync_stream()
+    check(lib().ddq_backward_link_force(lat.handle, _dev(chi_e, "chi_e"), _dev(phi_e, "phi_e"),
+                                        _dev(G, "G") if want_G else None, _dev(F, "F") if want_F else None,
+                                        int(acc)), "ddq_backward_link_force")
+    return G, F

@@ -89,7 +89,9 @@ struct ddq_lattice {
   void* links[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
   void* clov[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [prec][0: A_ee, 1: A_oo^-1]
   bool have_clover = false;
+  double c_sw = 0.0, m0 = 0.0;
   // work buffers
+  Grow force_ws;      // force: psi_o, lambda_o, insertions
   Grow tmp[2];        // u_o per precision
   Grow scratch64;     // FP64 parity vectors
   Grow scratch32;     // FP32 parity vectors
@@ -391,6 +393,7 @@ int ddq_destroy_lattice(ddq_lattice* L) {
   L->tmp[1].release();
   L->scratch64.release();
   L->scratch32.release();
+  L->force_ws.release();
   L->partial.release();
   L->small.release();
   if (L->host) (void)hipHostFree(L->host);
@@ -424,9 +427,12 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   if (!L->U) CHK(dalloc(&L->U, ubytes));
   HIPCHK(hipMemcpyAsync(L->U, U, ubytes, U_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
                         L->stream));
-  const size_t n = (size_t)8 * 9 * L->Vh;  // complex entries per parity
+  const size_t n = (size_t)8 * 9 * field_vh((int)L->Vh);  // complex entries per parity
   for (int q = 0; q < 2; ++q)
-    if (!L->links[DDQ_F64][q]) CHK(dalloc(&L->links[DDQ_F64][q], n * 16));
+    if (!L->links[DDQ_F64][q]) {
+      CHK(dalloc(&L->links[DDQ_F64][q], n * 16));
+      HIPCHK(hipMemsetAsync(L->links[DDQ_F64][q], 0, n * 16, L->stream));  // block padding
+    }
   HIPCHK(launch_pack_gauge_f64(L->geo, (const d2_t*)L->U, (d2_t*)L->links[DDQ_F64][0],
                                (d2_t*)L->links[DDQ_F64][1], L->stream));
   if (storage_flags & DDQ_STORE_F32) {
@@ -448,9 +454,12 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
   if (!L->have_gauge) return fail(DDQ_ERR_STATE, "ddq_set_gauge has not been called");
   if (!std::isfinite(c_sw) || !std::isfinite(m0)) return fail(DDQ_ERR_ARG, "c_sw and m0 must be finite");
   L->have_clover = false;
-  const size_t n = (size_t)2 * 18 * L->Vh;  // (re, im) slots per parity
+  const size_t n = (size_t)36 * field_vh((int)L->Vh);  // (re, im) slots per parity
   for (int q = 0; q < 2; ++q)
-    if (!L->clov[DDQ_F64][q]) CHK(dalloc(&L->clov[DDQ_F64][q], n * 16));
+    if (!L->clov[DDQ_F64][q]) {
+      CHK(dalloc(&L->clov[DDQ_F64][q], n * 16));
+      HIPCHK(hipMemsetAsync(L->clov[DDQ_F64][q], 0, n * 16, L->stream));  // block padding
+    }
   int* flag = (int*)L->small.p;
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), L->stream));
   HIPCHK(launch_clover_build(L->geo, (const d2_t*)L->U, c_sw, m0, (d2_t*)L->clov[DDQ_F64][0],
@@ -466,6 +475,8 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
     }
   }
   HIPCHK(hipStreamSynchronize(L->stream));
+  L->c_sw = c_sw;
+  L->m0 = m0;
   L->have_clover = true;
   return DDQ_OK;
 }
@@ -562,6 +573,38 @@ int ddq_oe_reconstruct(ddq_lattice* L, int nrhs, const void* x_e, const void* b,
   CHK(L->scratch64.ensure(2 * nb * 16));
   d2_t* bo = (d2_t*)L->scratch64.p;
   return reconstruct_impl(L, nrhs, (const d2_t*)x_e, (const d2_t*)b, (d2_t*)x, bo, bo + nb);
+}
+
+int ddq_backward_apply(ddq_lattice* L, int prec, int nrhs, const void* grad_y_e, void* grad_x_e) {
+  return ddq_apply_schur(L, prec, nrhs, grad_y_e, grad_x_e, 1);
+}
+
+int ddq_backward_link_force(ddq_lattice* L, const void* chi_e, const void* phi_e, void* G, void* F,
+                            int accumulate) {
+  CHK(check_ready(L, DDQ_F64));
+  if (!chi_e || !phi_e) return fail(DDQ_ERR_ARG, "chi_e and phi_e must be non-null");
+  if (!G && !F) return DDQ_OK;
+  const long long n = L->nvec();
+  const size_t need = (size_t)(2 * n + L->V * 54) * 16;
+  CHK(L->force_ws.ensure(need));
+  CHK(ensure_tmp(L, DDQ_F64, 1));
+  d2_t* psi = (d2_t*)L->force_ws.p;
+  d2_t* lam = psi + n;
+  d2_t* W = lam + n;
+  // psi_o = A_oo^-1 H_oe phi_e ;  lambda_o = A_oo^-1 (H^H)_oe chi_e  (kernel A, plain and dagger)
+  HIPCHK(kernel_A<double>(L, DDQ_F64, 1, (const d2_t*)phi_e, psi, false));
+  HIPCHK(kernel_A<double>(L, DDQ_F64, 1, (const d2_t*)chi_e, lam, true));
+  HIPCHK(launch_force(L->geo, (const d2_t*)L->U, (const d2_t*)chi_e, lam, (const d2_t*)phi_e, psi, L->c_sw, W,
+                      (d2_t*)G, (double*)F, accumulate, L->stream));
+  return DDQ_OK;
+}
+
+int ddq_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {
+  if (!dst || !src || bytes < 0 || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15))
+    return fail(DDQ_ERR_ARG, "stream copy needs 16-byte aligned pointers and a multiple of 16 bytes");
+  if (bytes == 0) return DDQ_OK;
+  HIPCHK(launch_stream_copy(dst, src, bytes, (hipStream_t)hip_stream));
+  return DDQ_OK;
 }
 
 int ddq_profile_begin(ddq_lattice* L) {

@@ -269,4 +269,20 @@ hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStr
   return hipGetLastError();
 }
 
+// STREAM-style copy with 16-byte accesses, one element per thread: the
+// attainable-bandwidth probe and the calibration kernel for the traffic counters
+__global__ void __launch_bounds__(RB) k_stream_copy(u4_t* __restrict__ dst, const u4_t* __restrict__ src,
+                                                    long long n16) {
+  const long long e = (long long)blockIdx.x * RB + threadIdx.x;
+  if (e < n16) dst[e] = src[e];
+}
+
+hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s) {
+  const long long n16 = bytes / 16;
+  const long long blocks = (n16 + RB - 1) / RB;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(RB), 0, s, (u4_t*)dst, (const u4_t*)src, n16);
+  return hipGetLastError();
+}
+
 }  // namespace ddq

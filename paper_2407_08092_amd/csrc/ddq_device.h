@@ -59,6 +59,17 @@ template <typename R> __device__ __forceinline__ void cfma_conj(cpx<R>& acc, cpx
 // twelve 64-bit addresses.  Reads past the descriptor's size return zero instead
 // of faulting.  Every offset stays below 4 GiB: one descriptor never spans more
 // than one spinor, one link direction or one clover block pair.
+// cache-policy bits of the streamed (read-once) link and clover loads: 2 = nt
+// (non-temporal), which keeps them from evicting the neighbour spinor rows that
+// eight sites reuse (measured +12% on the 48^3 x 96 stencil)
+#ifndef DDQ_STREAM_AUX
+#define DDQ_STREAM_AUX 2
+#endif
+// cache-policy bits of the spinor loads (reused by the eight neighbours)
+#ifndef DDQ_SPINOR_AUX
+#define DDQ_SPINOR_AUX 0
+#endif
+
 typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
 constexpr int BUF_DWORD3 = 0x00020000;  // gfx9-family raw buffer format word
@@ -82,14 +93,47 @@ template <typename R> __device__ __forceinline__ uint32_t byte_off(int i) {
   return (uint32_t)i * (uint32_t)sizeof(pair<R>);
 }
 
+// Link and clover fields (read once per kernel) are stored in blocks of
+// DDQ_FIELD_BLOCK sites: all rows of one block are contiguous, so one wavefront's
+// nine link entries (or 36 clover slots) are a single contiguous run of memory
+// instead of rows V/2 elements apart.  0 selects plain rows.
+#ifndef DDQ_FIELD_BLOCK
+#define DDQ_FIELD_BLOCK 64
+#endif
+__host__ __device__ __forceinline__ int field_vh(int vh) {
+  return DDQ_FIELD_BLOCK ? ((vh + DDQ_FIELD_BLOCK - 1) / DDQ_FIELD_BLOCK) * DDQ_FIELD_BLOCK : vh;
+}
+// element index of (row, site i) in an nrows-row link or clover field
+__host__ __device__ __forceinline__ size_t fidx(int row, int i, int nrows, int vh) {
+  if (DDQ_FIELD_BLOCK)
+    return ((size_t)(i / DDQ_FIELD_BLOCK) * nrows + row) * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK);
+  return (size_t)row * vh + i;
+}
+// descriptor and lane offset of a link or clover field
 template <typename R>
+__device__ __forceinline__ Rows<R> frows(const pair<R>* base, int nrows, int vh) {
+  if (!DDQ_FIELD_BLOCK) return rows<R>(base, nrows, vh);
+  Rows<R> r;
+  const uint32_t total = (uint32_t)field_vh(vh) * (uint32_t)nrows * (uint32_t)sizeof(pair<R>);
+  r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)total, BUF_DWORD3);
+  r.row_bytes = DDQ_FIELD_BLOCK * (uint32_t)sizeof(pair<R>);
+  return r;
+}
+template <typename R> __device__ __forceinline__ uint32_t foff(int i, int nrows) {
+  if (!DDQ_FIELD_BLOCK) return byte_off<R>(i);
+  return (uint32_t)((i / DDQ_FIELD_BLOCK) * nrows * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK)) *
+         (uint32_t)sizeof(pair<R>);
+}
+
+// AUX: cache-policy bits of the load (0 = default)
+template <typename R, int AUX = 0>
 __device__ __forceinline__ cpx<R> bload(const Rows<R>& r, int row, uint32_t off) {
   if constexpr (sizeof(R) == 8) {
-    u4_t v = __builtin_amdgcn_raw_buffer_load_b128(r.rsrc, (int)off, (int)(row * r.row_bytes), 0);
+    u4_t v = __builtin_amdgcn_raw_buffer_load_b128(r.rsrc, (int)off, (int)(row * r.row_bytes), AUX);
     d2_t d = __builtin_bit_cast(d2_t, v);
     return {d.x, d.y};
   } else {
-    u2_t v = __builtin_amdgcn_raw_buffer_load_b64(r.rsrc, (int)off, (int)(row * r.row_bytes), 0);
+    u2_t v = __builtin_amdgcn_raw_buffer_load_b64(r.rsrc, (int)off, (int)(row * r.row_bytes), AUX);
     f2_t f = __builtin_bit_cast(f2_t, v);
     return {f.x, f.y};
   }
@@ -144,8 +188,27 @@ __device__ __forceinline__ Site decode(const Geo& g, int i, int p) {
 // XCD-aware workgroup order: the dispatcher deals workgroups round-robin over the
 // eight XCDs; renumber them so that every XCD walks one contiguous range of sites
 // and the neighbour reuse in y and z stays inside that XCD's L2.
+// Renumbering workgroups so that each XCD walks one contiguous range measured
+// slower on the 48^3 x 96 stencil (4.06 vs 4.71 TB/s): with the dispatcher's own
+// round-robin order all XCDs work on neighbouring sites at once and share the
+// neighbour rows through the Infinity Cache.  Kept as an option.
+#ifndef DDQ_XCD_REMAP
+#define DDQ_XCD_REMAP 0
+#endif
+// Chunked order: the dispatcher deals workgroups round-robin over the 8 XCDs;
+// with DDQ_XCD_CHUNK = C each XCD instead receives C consecutive workgroups of
+// every group of 8 C, so block-boundary neighbours share an L2.
+#ifndef DDQ_XCD_CHUNK
+#define DDQ_XCD_CHUNK 0
+#endif
 __device__ __forceinline__ int xcd_block(int nblocks_padded) {
   int b = blockIdx.x;
+  if (DDQ_XCD_CHUNK > 0) {
+    const int C = DDQ_XCD_CHUNK;
+    const int grp = b / (8 * C), r = b % (8 * C);
+    return grp * 8 * C + (r % 8) * C + r / 8;
+  }
+  if (!DDQ_XCD_REMAP) return b;
   int per = nblocks_padded >> 3;
   return (b & 7) * per + (b >> 3);
 }
@@ -171,7 +234,7 @@ __device__ __forceinline__ Spinor<R> load_spinor(const Rows<R>& v, int i) {
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) s.c[a][b] = bload<R>(v, 3 * a + b, off);
+    for (int b = 0; b < 3; ++b) s.c[a][b] = bload<R, DDQ_SPINOR_AUX>(v, 3 * a + b, off);
   return s;
 }
 template <typename R>
@@ -238,21 +301,29 @@ __device__ __forceinline__ void accumulate(Spinor<R>& acc, const Half<R>& h, R s
   }
 }
 
-// U h for a 3x3 link stored as 9 rows (row-major entries)
+
+// a 3x3 link, 9 row-major entries stored as 9 rows
+template <typename R> struct Link { cpx<R> u[9]; };
+
 template <typename R>
-__device__ __forceinline__ Half<R> link_mul(const Rows<R>& U, int i, const Half<R>& h) {
-  cpx<R> u[9];
-  const uint32_t off = byte_off<R>(i);
+__device__ __forceinline__ Link<R> load_link(const Rows<R>& U, uint32_t off) {
+  Link<R> l;
 #pragma unroll
-  for (int e = 0; e < 9; ++e) u[e] = bload<R>(U, e, off);
+  for (int e = 0; e < 9; ++e) l.u[e] = bload<R, DDQ_STREAM_AUX>(U, e, off);
+  return l;
+}
+
+// U h on both spins of a half spinor
+template <typename R>
+__device__ __forceinline__ Half<R> link_mul(const Link<R>& U, const Half<R>& h) {
   Half<R> o;
 #pragma unroll
   for (int s = 0; s < 2; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      cpx<R> acc = u[3 * a] * h.c[s][0];
-      cfma(acc, u[3 * a + 1], h.c[s][1]);
-      cfma(acc, u[3 * a + 2], h.c[s][2]);
+      cpx<R> acc = U.u[3 * a] * h.c[s][0];
+      cfma(acc, U.u[3 * a + 1], h.c[s][1]);
+      cfma(acc, U.u[3 * a + 2], h.c[s][2]);
       o.c[s][a] = acc;
     }
   return o;
@@ -270,19 +341,18 @@ __host__ __device__ constexpr int tri_slot(int j, int k) {  // j < k
 
 // C: the clover field (36 rows: block 0 slots 0..17, block 1 slots 18..35)
 template <typename R>
-__device__ __forceinline__ void clover_block_mul(const Rows<R>& C, int blk, int i, const cpx<R> in[6],
+__device__ __forceinline__ void clover_block_mul(const Rows<R>& C, int blk, uint32_t off, const cpx<R> in[6],
                                                  cpx<R> out[6]) {
   cpx<R> a[15];
   R d[6];
-  const uint32_t off = byte_off<R>(i);
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    cpx<R> dd = bload<R>(C, 18 * blk + k, off);
+    cpx<R> dd = bload<R, DDQ_STREAM_AUX>(C, 18 * blk + k, off);
     d[2 * k] = dd.r;
     d[2 * k + 1] = dd.i;
   }
 #pragma unroll
-  for (int k = 0; k < 15; ++k) a[k] = bload<R>(C, 18 * blk + 3 + k, off);
+  for (int k = 0; k < 15; ++k) a[k] = bload<R, DDQ_STREAM_AUX>(C, 18 * blk + 3 + k, off);
 #pragma unroll
   for (int j = 0; j < 6; ++j) out[j] = d[j] * in[j];
 #pragma unroll
@@ -296,15 +366,16 @@ __device__ __forceinline__ void clover_block_mul(const Rows<R>& C, int blk, int 
 }
 
 // out = A psi for the two blocks of a site (block 0: spins 0,1; block 1: spins 2,3)
+// C: clover field descriptor (frows, 36 rows); off: the site's lane offset foff(i, 36)
 template <typename R>
-__device__ __forceinline__ Spinor<R> clover_mul(const Rows<R>& C, int i, const Spinor<R>& p) {
+__device__ __forceinline__ Spinor<R> clover_mul(const Rows<R>& C, uint32_t off, const Spinor<R>& p) {
   Spinor<R> o;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
     cpx<R> in[6], out[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) in[k] = p.c[2 * b + k / 3][k % 3];
-    clover_block_mul<R>(C, b, i, in, out);
+    clover_block_mul<R>(C, b, off, in, out);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o.c[2 * b + k / 3][k % 3] = out[k];
   }

@@ -37,7 +37,10 @@ struct HopArgs {
   long long rhs_stride;      // elements between right-hand sides (blockIdx.y)
 };
 
-constexpr int HOP_BLOCK = 256;
+#ifndef DDQ_HOP_BLOCK
+#define DDQ_HOP_BLOCK 256
+#endif
+constexpr int HOP_BLOCK = DDQ_HOP_BLOCK;
 
 template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a, int mode, bool dagger, int nrhs, hipStream_t s);
@@ -63,6 +66,13 @@ hipError_t launch_copy(d2_t* y, const d2_t* x, long long n, hipStream_t s);
 hipError_t launch_to_f32(f2_t* y, const d2_t* x, long long n, hipStream_t s);
 hipError_t launch_to_f64(d2_t* y, const f2_t* x, long long n, hipStream_t s);
 hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStream_t s);
+
+hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s);
+
+// link force: insertions W (V x 54 complex) then per-link G (V x 4 x 9 complex) / F (V x 4 x 8)
+hipError_t launch_force(const Geo& g, const d2_t* U, const d2_t* chi_e, const d2_t* lam_o, const d2_t* phi_e,
+                        const d2_t* psi_o, double c_sw, d2_t* W, d2_t* G, double* F, int accumulate,
+                        hipStream_t s);
 
 // field kernels
 hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_even, d2_t* out_odd,

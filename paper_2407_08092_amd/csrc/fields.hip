@@ -30,7 +30,8 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
   const long long n = lex(g, s.x, s.y, s.z, s.t);
   for (int mu = 0; mu < 4; ++mu) {
     const d2_t* u = U + (n * 4 + mu) * 9;
-    for (int e = 0; e < 9; ++e) out[(size_t)(mu * 9 + e) * vh + i] = u[e];
+    const size_t fvh9 = (size_t)9 * field_vh(vh);
+    for (int e = 0; e < 9; ++e) out[mu * fvh9 + fidx(e, i, 9, vh)] = u[e];
     int c[4] = {s.x, s.y, s.z, s.t};
     coords_shift(g, c, mu, -1);
     const long long nb = lex(g, c[0], c[1], c[2], c[3]);
@@ -39,7 +40,7 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
       for (int b = 0; b < 3; ++b) {
         d2_t v = ub[3 * b + a];
         v.y = -v.y;
-        out[(size_t)((4 + mu) * 9 + 3 * a + b) * vh + i] = v;
+        out[(4 + mu) * fvh9 + fidx(3 * a + b, i, 9, vh)] = v;
       }
   }
 }
@@ -182,19 +183,20 @@ __device__ __forceinline__ M3 field_from_leaves(const M3& Q) {
 }
 
 // write a Hermitian 6x6 block (full matrix M) into the packed 18-slot format
-__device__ __forceinline__ void store_packed(d2_t* C, int i, int vh, const cpx<double> M[6][6]) {
+// block blk of site i of a 36-row clover field
+__device__ __forceinline__ void store_packed(d2_t* C, int blk, int i, int vh, const cpx<double> M[6][6]) {
   for (int k = 0; k < 3; ++k) {
     d2_t v;
     v.x = M[2 * k][2 * k].r;
     v.y = M[2 * k + 1][2 * k + 1].r;
-    C[(size_t)k * vh + i] = v;
+    C[fidx(18 * blk + k, i, 36, vh)] = v;
   }
   for (int j = 0; j < 6; ++j)
     for (int k = j + 1; k < 6; ++k) {
       d2_t v;
       v.x = M[j][k].r;
       v.y = M[j][k].i;
-      C[(size_t)tri_slot(j, k) * vh + i] = v;
+      C[fidx(18 * blk + tri_slot(j, k), i, 36, vh)] = v;
     }
 }
 
@@ -291,14 +293,14 @@ __global__ void k_clover_build(Geo g, const d2_t* __restrict__ U, double c_sw, d
       }
     for (int k = 0; k < 6; ++k) M[k][k].r += 4.0 + m0;
     if (p == 0) {
-      store_packed(cl_e + (size_t)blk * 18 * vh, i, vh, M);
+      store_packed(cl_e, blk, i, vh, M);
     } else {
       if (!hpd_inverse6(M)) {
         *notpd = 1;
         for (int j = 0; j < 6; ++j)
           for (int k = 0; k < 6; ++k) M[j][k] = {0.0, 0.0};
       }
-      store_packed(cl_o_inv + (size_t)blk * 18 * vh, i, vh, M);
+      store_packed(cl_o_inv, blk, i, vh, M);
     }
   }
 }
@@ -319,10 +321,9 @@ __global__ void k_clover_export(Geo g, const d2_t* __restrict__ P, d2_t* __restr
   if (tid >= 2LL * vh) return;
   const int blk = (int)(tid / vh);
   const int i = (int)(tid % vh);
-  const d2_t* C = P + (size_t)blk * 18 * vh;
   d2_t* out = D + ((size_t)i * 2 + blk) * 36;
   for (int k = 0; k < 3; ++k) {
-    d2_t d = C[(size_t)k * vh + i];
+    d2_t d = P[fidx(18 * blk + k, i, 36, vh)];
     d2_t a, b;
     a.x = d.x; a.y = 0.0;
     b.x = d.y; b.y = 0.0;
@@ -331,7 +332,7 @@ __global__ void k_clover_export(Geo g, const d2_t* __restrict__ P, d2_t* __restr
   }
   for (int j = 0; j < 6; ++j)
     for (int k = j + 1; k < 6; ++k) {
-      d2_t v = C[(size_t)tri_slot(j, k) * vh + i];
+      d2_t v = P[fidx(18 * blk + tri_slot(j, k), i, 36, vh)];
       out[j * 6 + k] = v;
       v.y = -v.y;
       out[k * 6 + j] = v;

@@ -141,8 +141,8 @@ def main():
     del g
     lam = api.estimate_lambda_max(lat, 50, x64)
     omega = 0.8 / lam
-    x32 = x64.to(torch.complex64)
-    b32 = b64.to(torch.complex64)
+    x32 = api.convert_parity(lat, x64, torch.complex64)
+    b32 = api.convert_parity(lat, b64, torch.complex64)
     y32 = torch.empty_like(x32)
     xs = torch.empty_like(x32)
     log(f"set-up {time.time() - t0:.1f} s, |lambda_max| = {lam:.4f}, omega = {omega:.4f}")

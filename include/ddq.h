@@ -22,11 +22,13 @@
  * Layouts (all complex numbers are (re, im) pairs of the stated real type):
  *   gauge links   U[t][z][y][x][mu][a][b]                      complex128
  *   full vector   psi[t][z][y][x][spin 4][colour 3]            complex128 or complex64
- *   parity vector v[rhs][sc][i]: sc = 3*spin + colour (12 rows), i = checkerboard
+ *   parity vector rows sc = 3*spin + colour (12 rows) at site i = checkerboard
  *                 index of the site within its parity = (lexicographic index
- *                 x + Lx*(y + Ly*(z + Lz*t))) >> 1.  Row stride = V/2 elements,
- *                 right-hand-side stride = 12*V/2 elements.  complex128 for
- *                 DDQ_F64, complex64 for DDQ_F32.
+ *                 x + Lx*(y + Ly*(z + Lz*t))) >> 1; right-hand-side stride
+ *                 12*V/2 complex numbers.
+ *                   DDQ_F64: complex128 v[rhs][sc][i] (row stride V/2).
+ *                   DDQ_F32: complex64 v[rhs][sc/2][i][sc%2]: rows 2k and 2k+1 share
+ *                   one 16-byte element per site, so every access is 16 bytes.
  *   clover export A[i][block 2][6][6] complex128, block 0 acting on spins 0,1 and
  *                 block 1 on spins 2,3, index 3*spin' + colour inside a block.
  *
@@ -106,6 +108,10 @@ int ddq_pack_parity(ddq_lattice* lat, int prec, int nrhs, int parity,
                     const void* full, void* v);
 int ddq_unpack_parity(ddq_lattice* lat, int prec, int nrhs, int parity,
                       const void* v, void* full);
+
+/* Parity vectors between the FP64 and FP32 layouts (rounding to FP32 or exact
+ * widening); equal precisions copy.  src and dst must not overlap. */
+int ddq_convert_parity(ddq_lattice* lat, int nrhs, int src_prec, const void* src, int dst_prec, void* dst);
 
 /* y_e = D_S x_e (eq. 3), or D_S^H x_e = g_5 D_S g_5 x_e when dagger != 0, for
  * nrhs parity vectors.  x_e and y_e must not overlap. */

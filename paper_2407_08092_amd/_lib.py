@@ -55,6 +55,7 @@ _SIGNATURES = {
     "ddq_get_clover": [_P, _P, _P],
     "ddq_pack_parity": [_P, C.c_int, C.c_int, C.c_int, _P, _P],
     "ddq_unpack_parity": [_P, C.c_int, C.c_int, C.c_int, _P, _P],
+    "ddq_convert_parity": [_P, C.c_int, C.c_int, _P, C.c_int, _P],
     "ddq_apply_schur": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_richardson_smooth": [_P, C.c_int, C.c_int, _P, _P, C.c_int, C.c_double],
     "ddq_estimate_lambda_max": [_P, C.c_int, _P, C.POINTER(C.c_double)],

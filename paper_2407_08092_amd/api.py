@@ -5,7 +5,8 @@ runs in the HIP library; nothing here computes.
 Tensor layouts (see include/ddq.h):
   gauge links   complex128 [Lt, Lz, Ly, Lx, 4, 3, 3]
   full vector   complex128 / complex64 [Lt, Lz, Ly, Lx, 4, 3]   (or [nrhs, ...])
-  parity vector complex128 / complex64 [12, V/2]                  (or [nrhs, 12, V/2])
+  parity vector complex128 [12, V/2] (or [nrhs, 12, V/2]);
+                complex64 [6, V/2, 2] (or [nrhs, 6, V/2, 2]): rows 2k, 2k+1 paired per site
 The arithmetic of a call follows the dtype: complex128 -> FP64, complex64 -> FP32.
 """
 from __future__ import annotations
@@ -21,7 +22,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
-    "stream_copy", "backward_apply", "backward_link_force",
+    "stream_copy", "backward_apply", "backward_link_force", "convert_parity",
     "DDQ_F64", "DDQ_F32",
 ]
 
@@ -122,17 +123,34 @@ def get_clover(lat: Lattice):
     return a, b
 
 
+def _parity_shape(lat, dtype):
+    return (12, lat.Vh) if dtype == torch.complex128 else (6, lat.Vh, 2)
+
+
 def parity_vector(lat: Lattice, nrhs=None, dtype=torch.complex128) -> torch.Tensor:
-    shape = (12, lat.Vh) if nrhs is None else (nrhs, 12, lat.Vh)
+    shape = _parity_shape(lat, dtype)
+    if nrhs is not None:
+        shape = (nrhs,) + shape
     return torch.empty(shape, dtype=dtype, device=lat.device)
 
 
 def _nrhs_parity(lat, v):
-    if v.dim() == 2 and tuple(v.shape) == (12, lat.Vh):
+    shp = _parity_shape(lat, v.dtype)
+    if tuple(v.shape) == shp:
         return 1
-    if v.dim() == 3 and tuple(v.shape[1:]) == (12, lat.Vh):
+    if v.dim() == len(shp) + 1 and tuple(v.shape[1:]) == shp:
         return v.shape[0]
-    raise ValueError(f"parity vector must be [12, {lat.Vh}] or [nrhs, 12, {lat.Vh}], got {tuple(v.shape)}")
+    raise ValueError(f"{v.dtype} parity vector must be {shp} or [nrhs, *{shp}], got {tuple(v.shape)}")
+
+
+def convert_parity(lat: Lattice, v: torch.Tensor, dtype) -> torch.Tensor:
+    """Parity vector to another precision (and its layout) through the library."""
+    n = _nrhs_parity(lat, v)
+    out = parity_vector(lat, None if v.dim() == len(_parity_shape(lat, v.dtype)) else n, dtype)
+    lat.sync_stream()
+    check(lib().ddq_convert_parity(lat.handle, n, _prec(v), _dev(v, "src"), _prec(out), _dev(out, "dst")),
+          "ddq_convert_parity")
+    return out
 
 
 def _nrhs_full(lat, f):
@@ -156,7 +174,7 @@ def pack_parity(lat: Lattice, full: torch.Tensor, parity: int, out: torch.Tensor
 def unpack_parity(lat: Lattice, v: torch.Tensor, parity: int, out: torch.Tensor = None) -> torch.Tensor:
     n = _nrhs_parity(lat, v)
     if out is None:
-        shape = lat.full_shape if v.dim() == 2 else (n,) + lat.full_shape
+        shape = lat.full_shape if v.dim() == len(_parity_shape(lat, v.dtype)) else (n,) + lat.full_shape
         out = torch.zeros(shape, dtype=v.dtype, device=lat.device)
     lat.sync_stream()
     check(lib().ddq_unpack_parity(lat.handle, _prec(v), n, int(parity), _dev(v, "v"), _dev(out, "full")),

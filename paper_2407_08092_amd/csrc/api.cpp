@@ -438,8 +438,8 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   if (storage_flags & DDQ_STORE_F32) {
     for (int q = 0; q < 2; ++q) {
       if (!L->links[DDQ_F32][q]) CHK(dalloc(&L->links[DDQ_F32][q], n * 8));
-      HIPCHK(launch_links_to_f32((const d2_t*)L->links[DDQ_F64][q], (f2_t*)L->links[DDQ_F32][q], (long long)n,
-                                 L->stream));
+      HIPCHK(launch_field_to_f32((const d2_t*)L->links[DDQ_F64][q], L->links[DDQ_F32][q], 4, LINK_ROWS,
+                                 (int)L->Vh, L->stream));
     }
   } else {
     for (int q = 0; q < 2; ++q) dfree(L->links[DDQ_F32][q]);
@@ -470,8 +470,8 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
   if (L->links[DDQ_F32][0]) {
     for (int q = 0; q < 2; ++q) {
       if (!L->clov[DDQ_F32][q]) CHK(dalloc(&L->clov[DDQ_F32][q], n * 8));
-      HIPCHK(launch_links_to_f32((const d2_t*)L->clov[DDQ_F64][q], (f2_t*)L->clov[DDQ_F32][q], (long long)n,
-                                 L->stream));
+      HIPCHK(launch_field_to_f32((const d2_t*)L->clov[DDQ_F64][q], L->clov[DDQ_F32][q], 1, CLOVER_ROWS,
+                                 (int)L->Vh, L->stream));
     }
   }
   HIPCHK(hipStreamSynchronize(L->stream));
@@ -573,6 +573,22 @@ int ddq_oe_reconstruct(ddq_lattice* L, int nrhs, const void* x_e, const void* b,
   CHK(L->scratch64.ensure(2 * nb * 16));
   d2_t* bo = (d2_t*)L->scratch64.p;
   return reconstruct_impl(L, nrhs, (const d2_t*)x_e, (const d2_t*)b, (d2_t*)x, bo, bo + nb);
+}
+
+int ddq_convert_parity(ddq_lattice* L, int nrhs, int src_prec, const void* src, int dst_prec, void* dst) {
+  CHK(check_lat(L));
+  CHK(check_prec(src_prec));
+  CHK(check_prec(dst_prec));
+  if (nrhs < 1 || !src || !dst) return fail(DDQ_ERR_ARG, "bad conversion arguments");
+  if (src_prec == dst_prec) {
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)nrhs * L->nvec() * elem_bytes(src_prec), hipMemcpyDeviceToDevice,
+                          L->stream));
+  } else if (src_prec == DDQ_F64) {
+    HIPCHK(launch_parity_to_f32(dst, (const d2_t*)src, nrhs, (int)L->Vh, L->stream));
+  } else {
+    HIPCHK(launch_parity_to_f64((d2_t*)dst, src, nrhs, (int)L->Vh, L->stream));
+  }
+  return DDQ_OK;
 }
 
 int ddq_backward_apply(ddq_lattice* L, int prec, int nrhs, const void* grad_y_e, void* grad_x_e) {
@@ -739,17 +755,17 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
       // z_k = M v_k, w = D_S z_k
       if (lo) {
         if (nu > 0) {
-          HIPCHK(launch_to_f32(b32, vk, n, L->stream));
+          HIPCHK(launch_parity_to_f32(b32, vk, 1, (int)L->Vh, L->stream));
           HIPCHK(launch_scale_f32(x32, b32, (float)P->omega, n, L->stream));  // first sweep from 0
           CHK(sweeps<float>(L, DDQ_F32, 1, x32, b32, nu - 1, (float)P->omega));
           applies_lo += nu - 1;
         } else {
-          HIPCHK(launch_to_f32(x32, vk, n, L->stream));
+          HIPCHK(launch_parity_to_f32(x32, vk, 1, (int)L->Vh, L->stream));
         }
-        HIPCHK(launch_to_f64(zk, x32, n, L->stream));
+        HIPCHK(launch_parity_to_f64(zk, x32, 1, (int)L->Vh, L->stream));
         CHK(schur<float>(L, DDQ_F32, 1, x32, w32, false));
         ++applies_lo;
-        HIPCHK(launch_to_f64(w, w32, n, L->stream));
+        HIPCHK(launch_parity_to_f64(w, w32, 1, (int)L->Vh, L->stream));
       } else {
         if (nu > 0) {
           HIPCHK(launch_scale(zk, vk, P->omega, n, L->stream));

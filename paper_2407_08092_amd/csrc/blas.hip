@@ -222,38 +222,6 @@ hipError_t launch_copy(d2_t* y, const d2_t* x, long long n, hipStream_t s) {
   return hipGetLastError();
 }
 
-__global__ void k_to_f32(f2_t* __restrict__ y, const d2_t* __restrict__ x, long long n) {
-  const long long stride = (long long)gridDim.x * RB;
-  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
-    d2_t a = x[e];
-    f2_t b;
-    b.x = (float)a.x;
-    b.y = (float)a.y;
-    y[e] = b;
-  }
-}
-
-hipError_t launch_to_f32(f2_t* y, const d2_t* x, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(n)), dim3(RB), 0, s, y, x, n);
-  return hipGetLastError();
-}
-
-__global__ void k_to_f64(d2_t* __restrict__ y, const f2_t* __restrict__ x, long long n) {
-  const long long stride = (long long)gridDim.x * RB;
-  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
-    f2_t a = x[e];
-    d2_t b;
-    b.x = (double)a.x;
-    b.y = (double)a.y;
-    y[e] = b;
-  }
-}
-
-hipError_t launch_to_f64(d2_t* y, const f2_t* x, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_to_f64, dim3(grid_for(n)), dim3(RB), 0, s, y, x, n);
-  return hipGetLastError();
-}
-
 __global__ void k_scale_f32(f2_t* __restrict__ y, const f2_t* __restrict__ x, float a, long long n) {
   const long long stride = (long long)gridDim.x * RB;
   for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {

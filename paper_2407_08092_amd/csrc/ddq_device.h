@@ -52,13 +52,16 @@ template <typename R> __device__ __forceinline__ void cfma_conj(cpx<R>& acc, cpx
   acc.i = fma(-a.i, b.r, acc.i);
 }
 
-// Row-strided fields through raw buffer descriptors.  A field is `nrows` rows of
-// V/2 (re, im) pairs.  The descriptor (base, byte size) lives in SGPRs, the row
-// offset goes into the scalar soffset operand and the lane's site into one 32-bit
-// VGPR offset, so a twelve-row spinor gather costs one VGPR of address, not
-// twelve 64-bit addresses.  Reads past the descriptor's size return zero instead
-// of faulting.  Every offset stays below 4 GiB: one descriptor never spans more
-// than one spinor, one link direction or one clover block pair.
+// Every field is stored as rows of 16-byte elements, one per site: an element holds
+// CPE<R> complex numbers (one in FP64, two in FP32), so every load is a 16-byte
+// access per lane.  Logical complex row r of a field lives in element row
+// r / CPE, slot r % CPE.  Fields are read through raw buffer descriptors: the
+// descriptor (base, byte size) lives in SGPRs, the element-row offset in the scalar
+// soffset operand and the lane's site in one 32-bit VGPR offset, so a twelve-row
+// spinor gather costs one VGPR of address.  Reads past the descriptor's size return
+// zero instead of faulting.  Every offset stays below 4 GiB: a descriptor never
+// spans more than one spinor, one link direction or one clover field.
+
 // cache-policy bits of the streamed (read-once) link and clover loads: 2 = nt
 // (non-temporal), which keeps them from evicting the neighbour spinor rows that
 // eight sites reuse (measured +12% on the 48^3 x 96 stencil)
@@ -72,88 +75,104 @@ template <typename R> __device__ __forceinline__ void cfma_conj(cpx<R>& acc, cpx
 
 typedef unsigned int u2_t __attribute__((ext_vector_type(2)));
 typedef unsigned int u4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 constexpr int BUF_DWORD3 = 0x00020000;  // gfx9-family raw buffer format word
 
-template <typename R>
-struct Rows {
+// complex numbers per 16-byte element
+template <typename R> struct cpe_t { static constexpr int value = 16 / (int)sizeof(pair<R>); };
+template <typename R> constexpr int CPE = cpe_t<R>::value;
+
+// complex rows of the three field kinds
+constexpr int SPINOR_ROWS = 12;  // 4 spins x 3 colours
+constexpr int LINK_ROWS = 18;    // per direction mu: U_mu(x) (9 entries), then U_mu(x - mu)^H (9)
+constexpr int CLOVER_ROWS = 36;  // 2 blocks x 18 (re, im) slots
+
+struct Field {
   __amdgpu_buffer_rsrc_t rsrc;
-  uint32_t row_bytes;
+  uint32_t row_bytes;  // bytes between element rows
 };
 
-template <typename R>
-__device__ __forceinline__ Rows<R> rows(const pair<R>* base, int nrows, int vh) {
-  Rows<R> r;
-  const uint32_t rb = (uint32_t)vh * (uint32_t)sizeof(pair<R>);
-  r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(rb * (uint32_t)nrows), BUF_DWORD3);
-  r.row_bytes = rb;
-  return r;
+// parity vector: element rows of V/2 elements each
+__device__ __forceinline__ Field vfield(const void* base, int erows, int vh) {
+  Field f;
+  const uint32_t rb = (uint32_t)vh * 16u;
+  f.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)(rb * (uint32_t)erows), BUF_DWORD3);
+  f.row_bytes = rb;
+  return f;
 }
-
-template <typename R> __device__ __forceinline__ uint32_t byte_off(int i) {
-  return (uint32_t)i * (uint32_t)sizeof(pair<R>);
-}
+__device__ __forceinline__ uint32_t voff(int i) { return (uint32_t)i * 16u; }
 
 // Link and clover fields (read once per kernel) are stored in blocks of
-// DDQ_FIELD_BLOCK sites: all rows of one block are contiguous, so one wavefront's
-// nine link entries (or 36 clover slots) are a single contiguous run of memory
-// instead of rows V/2 elements apart.  0 selects plain rows.
+// DDQ_FIELD_BLOCK sites: all element rows of one block are contiguous, so one
+// wavefront's link (or clover) is a single contiguous run of memory.  0 selects
+// plain rows.
 #ifndef DDQ_FIELD_BLOCK
 #define DDQ_FIELD_BLOCK 64
 #endif
 __host__ __device__ __forceinline__ int field_vh(int vh) {
   return DDQ_FIELD_BLOCK ? ((vh + DDQ_FIELD_BLOCK - 1) / DDQ_FIELD_BLOCK) * DDQ_FIELD_BLOCK : vh;
 }
-// element index of (row, site i) in an nrows-row link or clover field
-__host__ __device__ __forceinline__ size_t fidx(int row, int i, int nrows, int vh) {
+// element index of (element row, site i) in an erows-row blocked field
+__host__ __device__ __forceinline__ size_t fidx(int row, int i, int erows, int vh) {
   if (DDQ_FIELD_BLOCK)
-    return ((size_t)(i / DDQ_FIELD_BLOCK) * nrows + row) * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK);
+    return ((size_t)(i / DDQ_FIELD_BLOCK) * erows + row) * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK);
   return (size_t)row * vh + i;
 }
-// descriptor and lane offset of a link or clover field
-template <typename R>
-__device__ __forceinline__ Rows<R> frows(const pair<R>* base, int nrows, int vh) {
-  if (!DDQ_FIELD_BLOCK) return rows<R>(base, nrows, vh);
-  Rows<R> r;
-  const uint32_t total = (uint32_t)field_vh(vh) * (uint32_t)nrows * (uint32_t)sizeof(pair<R>);
-  r.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)total, BUF_DWORD3);
-  r.row_bytes = DDQ_FIELD_BLOCK * (uint32_t)sizeof(pair<R>);
-  return r;
+__device__ __forceinline__ Field bfield(const void* base, int erows, int vh) {
+  if (!DDQ_FIELD_BLOCK) return vfield(base, erows, vh);
+  Field f;
+  const uint32_t total = (uint32_t)field_vh(vh) * (uint32_t)erows * 16u;
+  f.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)total, BUF_DWORD3);
+  f.row_bytes = DDQ_FIELD_BLOCK * 16u;
+  return f;
 }
-template <typename R> __device__ __forceinline__ uint32_t foff(int i, int nrows) {
-  if (!DDQ_FIELD_BLOCK) return byte_off<R>(i);
-  return (uint32_t)((i / DDQ_FIELD_BLOCK) * nrows * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK)) *
-         (uint32_t)sizeof(pair<R>);
+__device__ __forceinline__ uint32_t boff(int i, int erows) {
+  if (!DDQ_FIELD_BLOCK) return voff(i);
+  return (uint32_t)((i / DDQ_FIELD_BLOCK) * erows * DDQ_FIELD_BLOCK + (i % DDQ_FIELD_BLOCK)) * 16u;
 }
 
-// AUX: cache-policy bits of the load (0 = default)
-template <typename R, int AUX = 0>
-__device__ __forceinline__ cpx<R> bload(const Rows<R>& r, int row, uint32_t off) {
+template <int AUX = 0>
+__device__ __forceinline__ u4_t ld16(const Field& f, int row, uint32_t off) {
+  return __builtin_amdgcn_raw_buffer_load_b128(f.rsrc, (int)off, (int)(row * f.row_bytes), AUX);
+}
+__device__ __forceinline__ void st16(const Field& f, int row, uint32_t off, u4_t v) {
+  __builtin_amdgcn_raw_buffer_store_b128(v, f.rsrc, (int)off, (int)(row * f.row_bytes), 0);
+}
+
+// 16-byte element <-> CPE complex numbers
+template <typename R>
+__device__ __forceinline__ void unpack(u4_t q, cpx<R>* c) {
   if constexpr (sizeof(R) == 8) {
-    u4_t v = __builtin_amdgcn_raw_buffer_load_b128(r.rsrc, (int)off, (int)(row * r.row_bytes), AUX);
-    d2_t d = __builtin_bit_cast(d2_t, v);
-    return {d.x, d.y};
+    d2_t d = __builtin_bit_cast(d2_t, q);
+    c[0] = {d.x, d.y};
   } else {
-    u2_t v = __builtin_amdgcn_raw_buffer_load_b64(r.rsrc, (int)off, (int)(row * r.row_bytes), AUX);
-    f2_t f = __builtin_bit_cast(f2_t, v);
-    return {f.x, f.y};
+    f4_t f = __builtin_bit_cast(f4_t, q);
+    c[0] = {f.x, f.y};
+    c[1] = {f.z, f.w};
   }
 }
-
 template <typename R>
-__device__ __forceinline__ void bstore(const Rows<R>& r, int row, uint32_t off, cpx<R> a) {
+__device__ __forceinline__ u4_t pack(const cpx<R>* c) {
   if constexpr (sizeof(R) == 8) {
     d2_t d;
-    d.x = a.r;
-    d.y = a.i;
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4_t, d), r.rsrc, (int)off,
-                                           (int)(row * r.row_bytes), 0);
+    d.x = c[0].r;
+    d.y = c[0].i;
+    return __builtin_bit_cast(u4_t, d);
   } else {
-    f2_t f;
-    f.x = a.r;
-    f.y = a.i;
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2_t, f), r.rsrc, (int)off,
-                                          (int)(row * r.row_bytes), 0);
+    f4_t f;
+    f.x = c[0].r;
+    f.y = c[0].i;
+    f.z = c[1].r;
+    f.w = c[1].i;
+    return __builtin_bit_cast(u4_t, f);
   }
+}
+
+// complex rows [r0, r0 + n) of a field (n a multiple of CPE, r0 too)
+template <typename R, int AUX = 0>
+__device__ __forceinline__ void load_rows(const Field& f, int r0, int n, uint32_t off, cpx<R>* out) {
+#pragma unroll
+  for (int k = 0; k < n / CPE<R>; ++k) unpack<R>(ld16<AUX>(f, r0 / CPE<R> + k, off), out + k * CPE<R>);
 }
 
 // ---------------------------------------------------------------------------
@@ -226,24 +245,27 @@ template <typename R> __device__ __forceinline__ void zero(Spinor<R>& s) {
     for (int b = 0; b < 3; ++b) s.c[a][b] = {R(0), R(0)};
 }
 
-// spinor at checkerboard site i of a parity vector (12 rows)
+// spinor of a parity vector (12 complex rows) at lane offset off = voff(i)
 template <typename R>
-__device__ __forceinline__ Spinor<R> load_spinor(const Rows<R>& v, int i) {
+__device__ __forceinline__ Spinor<R> load_spinor(const Field& v, uint32_t off) {
+  cpx<R> c[SPINOR_ROWS];
+  load_rows<R, DDQ_SPINOR_AUX>(v, 0, SPINOR_ROWS, off, c);
   Spinor<R> s;
-  const uint32_t off = byte_off<R>(i);
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) s.c[a][b] = bload<R, DDQ_SPINOR_AUX>(v, 3 * a + b, off);
+    for (int b = 0; b < 3; ++b) s.c[a][b] = c[3 * a + b];
   return s;
 }
 template <typename R>
-__device__ __forceinline__ void store_spinor(const Rows<R>& v, int i, const Spinor<R>& s) {
-  const uint32_t off = byte_off<R>(i);
+__device__ __forceinline__ void store_spinor(const Field& v, uint32_t off, const Spinor<R>& s) {
+  cpx<R> c[SPINOR_ROWS];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 3; ++b) bstore<R>(v, 3 * a + b, off, s.c[a][b]);
+    for (int b = 0; b < 3; ++b) c[3 * a + b] = s.c[a][b];
+#pragma unroll
+  for (int k = 0; k < SPINOR_ROWS / CPE<R>; ++k) st16(v, k, off, pack<R>(c + k * CPE<R>));
 }
 
 // Spin projection (1 + sg * g_mu) psi in the chiral basis.  With
@@ -302,15 +324,25 @@ __device__ __forceinline__ void accumulate(Spinor<R>& acc, const Half<R>& h, R s
 }
 
 
-// a 3x3 link, 9 row-major entries stored as 9 rows
+// a 3x3 link, 9 row-major entries
 template <typename R> struct Link { cpx<R> u[9]; };
 
+// one direction's link field: LINK_ROWS complex rows (U_mu(x), then U_mu(x - mu)^H)
 template <typename R>
-__device__ __forceinline__ Link<R> load_link(const Rows<R>& U, uint32_t off) {
+__device__ __forceinline__ Link<R> load_link_half(const Field& U, int half, uint32_t off) {
   Link<R> l;
-#pragma unroll
-  for (int e = 0; e < 9; ++e) l.u[e] = bload<R, DDQ_STREAM_AUX>(U, e, off);
+  load_rows<R, DDQ_STREAM_AUX>(U, 9 * half, 9, off, l.u);  // FP64 only: 9 rows = 9 elements
   return l;
+}
+template <typename R>
+__device__ __forceinline__ void load_link_pair(const Field& U, uint32_t off, Link<R>& fwd, Link<R>& bwd) {
+  cpx<R> c[LINK_ROWS];
+  load_rows<R, DDQ_STREAM_AUX>(U, 0, LINK_ROWS, off, c);
+#pragma unroll
+  for (int e = 0; e < 9; ++e) {
+    fwd.u[e] = c[e];
+    bwd.u[e] = c[9 + e];
+  }
 }
 
 // U h on both spins of a half spinor
@@ -333,49 +365,45 @@ __device__ __forceinline__ Half<R> link_mul(const Link<R>& U, const Half<R>& h) 
 // clover blocks: Hermitian 6x6, 18 (re, im) slots per block:
 //   slots 0..2  diagonal pairs (d0, d1), (d2, d3), (d4, d5)
 //   slots 3..17 upper triangle a_jk, j < k, row-major ((0,1), (0,2), ..., (4,5))
-// layout [block 2][slot 18][i] with row stride vh.
+// a site's clover field has CLOVER_ROWS = 36 complex rows: block 0 slots, then block 1.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int tri_slot(int j, int k) {  // j < k
   return 3 + j * 5 - (j * (j - 1)) / 2 + (k - j - 1);
 }
 
-// C: the clover field (36 rows: block 0 slots 0..17, block 1 slots 18..35)
 template <typename R>
-__device__ __forceinline__ void clover_block_mul(const Rows<R>& C, int blk, uint32_t off, const cpx<R> in[6],
-                                                 cpx<R> out[6]) {
-  cpx<R> a[15];
+__device__ __forceinline__ void clover_block_apply(const cpx<R>* sl, const cpx<R> in[6], cpx<R> out[6]) {
   R d[6];
 #pragma unroll
   for (int k = 0; k < 3; ++k) {
-    cpx<R> dd = bload<R, DDQ_STREAM_AUX>(C, 18 * blk + k, off);
-    d[2 * k] = dd.r;
-    d[2 * k + 1] = dd.i;
+    d[2 * k] = sl[k].r;
+    d[2 * k + 1] = sl[k].i;
   }
-#pragma unroll
-  for (int k = 0; k < 15; ++k) a[k] = bload<R, DDQ_STREAM_AUX>(C, 18 * blk + 3 + k, off);
 #pragma unroll
   for (int j = 0; j < 6; ++j) out[j] = d[j] * in[j];
 #pragma unroll
   for (int j = 0; j < 6; ++j)
 #pragma unroll
     for (int k = j + 1; k < 6; ++k) {
-      cpx<R> ajk = a[tri_slot(j, k) - 3];
+      cpx<R> ajk = sl[tri_slot(j, k)];
       cfma(out[j], ajk, in[k]);
       cfma_conj(out[k], ajk, in[j]);
     }
 }
 
-// out = A psi for the two blocks of a site (block 0: spins 0,1; block 1: spins 2,3)
-// C: clover field descriptor (frows, 36 rows); off: the site's lane offset foff(i, 36)
+// out = A psi for the two blocks of a site (block 0: spins 0,1; block 1: spins 2,3).
+// C: the clover field (bfield, CLOVER_ROWS / CPE element rows); off = boff(i, ...)
 template <typename R>
-__device__ __forceinline__ Spinor<R> clover_mul(const Rows<R>& C, uint32_t off, const Spinor<R>& p) {
+__device__ __forceinline__ Spinor<R> clover_mul(const Field& C, uint32_t off, const Spinor<R>& p) {
   Spinor<R> o;
 #pragma unroll
   for (int b = 0; b < 2; ++b) {
+    cpx<R> sl[18];
+    load_rows<R, DDQ_STREAM_AUX>(C, 18 * b, 18, off, sl);
     cpx<R> in[6], out[6];
 #pragma unroll
     for (int k = 0; k < 6; ++k) in[k] = p.c[2 * b + k / 3][k % 3];
-    clover_block_mul<R>(C, b, off, in, out);
+    clover_block_apply<R>(sl, in, out);
 #pragma unroll
     for (int k = 0; k < 6; ++k) o.c[2 * b + k / 3][k % 3] = out[k];
   }

@@ -27,8 +27,8 @@ struct HopArgs {
   Geo g;
   int p_out;                 // parity of the output sites
   const pair<R>* in;         // hopping input, parity 1 - p_out
-  const pair<R>* links;      // [8 dirs][9][vh], parity p_out: U_mu(x) then U_mu(x-mu)^H
-  const pair<R>* clov;       // [2 blocks][18 slots][vh], parity p_out
+  const pair<R>* links;      // 4 direction fields of LINK_ROWS complex rows, parity p_out
+  const pair<R>* clov;       // clover field of CLOVER_ROWS complex rows, parity p_out
   const pair<R>* x;          // own-parity vector (APPLY, RICH, RESID)
   const pair<R>* b;          // own-parity right-hand side (RECON, RICH, RESID, PREP)
   pair<R>* out;
@@ -63,8 +63,6 @@ hipError_t launch_scale_dev(d2_t* out, const d2_t* in, const double* inv_norm_de
                             hipStream_t s);
 hipError_t launch_axpy(d2_t* y, double ar, double ai, const d2_t* x, long long n, hipStream_t s);
 hipError_t launch_copy(d2_t* y, const d2_t* x, long long n, hipStream_t s);
-hipError_t launch_to_f32(f2_t* y, const d2_t* x, long long n, hipStream_t s);
-hipError_t launch_to_f64(d2_t* y, const f2_t* x, long long n, hipStream_t s);
 hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStream_t s);
 
 hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s);
@@ -77,7 +75,9 @@ hipError_t launch_force(const Geo& g, const d2_t* U, const d2_t* chi_e, const d2
 // field kernels
 hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_even, d2_t* out_odd,
                                  hipStream_t s);
-hipError_t launch_links_to_f32(const d2_t* in, f2_t* out, long long n, hipStream_t s);
+hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows, int vh, hipStream_t s);
+hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s);
+hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0,
                                d2_t* clov_even, d2_t* clov_odd_inv, int* notpd, hipStream_t s);
 hipError_t launch_clover_export(const Geo& g, const d2_t* packed, d2_t* dense, hipStream_t s);

@@ -16,7 +16,8 @@ __device__ __forceinline__ void coords_shift(const Geo& g, int c[4], int mu, int
 }
 
 // ---------------------------------------------------------------------------
-// gauge packing: per parity p and site i, dirs 0..3 = U_mu(x), dirs 4..7 = U_mu(x-mu)^H
+// gauge packing: per parity p, direction mu and site i, complex rows 0..8 = U_mu(x)
+// and rows 9..17 = U_mu(x-mu)^H (FP64: one complex per 16-byte element)
 // ---------------------------------------------------------------------------
 __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict__ out_e,
                              d2_t* __restrict__ out_o) {
@@ -28,10 +29,10 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
   Site s = decode(g, i, p);
   d2_t* out = p == 0 ? out_e : out_o;
   const long long n = lex(g, s.x, s.y, s.z, s.t);
+  const size_t fsz = (size_t)LINK_ROWS * field_vh(vh);  // one direction's link field
   for (int mu = 0; mu < 4; ++mu) {
     const d2_t* u = U + (n * 4 + mu) * 9;
-    const size_t fvh9 = (size_t)9 * field_vh(vh);
-    for (int e = 0; e < 9; ++e) out[mu * fvh9 + fidx(e, i, 9, vh)] = u[e];
+    for (int e = 0; e < 9; ++e) out[mu * fsz + fidx(e, i, LINK_ROWS, vh)] = u[e];
     int c[4] = {s.x, s.y, s.z, s.t};
     coords_shift(g, c, mu, -1);
     const long long nb = lex(g, c[0], c[1], c[2], c[3]);
@@ -40,7 +41,7 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
       for (int b = 0; b < 3; ++b) {
         d2_t v = ub[3 * b + a];
         v.y = -v.y;
-        out[(4 + mu) * fvh9 + fidx(3 * a + b, i, 9, vh)] = v;
+        out[mu * fsz + fidx(9 + 3 * a + b, i, LINK_ROWS, vh)] = v;
       }
   }
 }
@@ -52,22 +53,31 @@ hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_e, d2_t*
   return hipGetLastError();
 }
 
-__global__ void k_d2_to_f2(const d2_t* __restrict__ in, f2_t* __restrict__ out, long long n) {
-  long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long stride = (long long)gridDim.x * blockDim.x;
-  for (; k < n; k += stride) {
-    d2_t v = in[k];
-    f2_t w;
-    w.x = (float)v.x;
-    w.y = (float)v.y;
-    out[k] = w;
-  }
+// FP64 blocked fields (nfields fields of crows complex rows) -> FP32 blocked fields
+// whose 16-byte element e holds complex rows 2e and 2e+1
+__global__ void k_field_to_f32(const d2_t* __restrict__ in, f4_t* __restrict__ out, int nfields, int crows, int vh) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int er = crows / 2;
+  const long long total = (long long)nfields * er * vh;
+  if (tid >= total) return;
+  const int i = (int)(tid % vh);
+  const int e = (int)((tid / vh) % er);
+  const int f = (int)(tid / ((long long)vh * er));
+  const size_t fv = (size_t)field_vh(vh);
+  const d2_t* src = in + (size_t)f * crows * fv;
+  d2_t a = src[fidx(2 * e, i, crows, vh)], b = src[fidx(2 * e + 1, i, crows, vh)];
+  f4_t o;
+  o.x = (float)a.x;
+  o.y = (float)a.y;
+  o.z = (float)b.x;
+  o.w = (float)b.y;
+  out[(size_t)f * er * fv + fidx(e, i, er, vh)] = o;
 }
 
-hipError_t launch_links_to_f32(const d2_t* in, f2_t* out, long long n, hipStream_t s) {
-  int blocks = (int)((n + 255) / 256);
-  if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(k_d2_to_f2, dim3(blocks), dim3(256), 0, s, in, out, n);
+hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows, int vh, hipStream_t s) {
+  const long long total = (long long)nfields * (crows / 2) * vh;
+  hipLaunchKernelGGL(k_field_to_f32, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, in, (f4_t*)out,
+                     nfields, crows, vh);
   return hipGetLastError();
 }
 
@@ -346,7 +356,8 @@ hipError_t launch_clover_export(const Geo& g, const d2_t* packed, d2_t* dense, h
 }
 
 // ---------------------------------------------------------------------------
-// parity packing of vectors: full [n][12] <-> parity [12][vh]
+// parity packing of vectors: full [n][12] <-> parity layout (FP64: [12][vh]
+// complex128; FP32: [6][vh] elements of two complex64, rows 2k and 2k+1)
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ void k_pack_parity(Geo g, int parity, const pair<R>* __restrict__ full, pair<R>* __restrict__ v) {
@@ -358,7 +369,8 @@ __global__ void k_pack_parity(Geo g, int parity, const pair<R>* __restrict__ ful
   const long long n = lex(g, s.x, s.y, s.z, s.t);
   const pair<R>* src = full + r * (size_t)2 * vh * 12 + n * 12;
   pair<R>* dst = v + r * (size_t)vh * 12;
-  for (int k = 0; k < 12; ++k) dst[(size_t)k * vh + i] = src[k];
+  constexpr int C = CPE<R>;
+  for (int k = 0; k < 12; ++k) dst[((size_t)(k / C) * vh + i) * C + (k % C)] = src[k];
 }
 
 template <typename R>
@@ -371,7 +383,8 @@ __global__ void k_unpack_parity(Geo g, int parity, const pair<R>* __restrict__ v
   const long long n = lex(g, s.x, s.y, s.z, s.t);
   pair<R>* dst = full + r * (size_t)2 * vh * 12 + n * 12;
   const pair<R>* src = v + r * (size_t)vh * 12;
-  for (int k = 0; k < 12; ++k) dst[k] = src[(size_t)k * vh + i];
+  constexpr int C = CPE<R>;
+  for (int k = 0; k < 12; ++k) dst[k] = src[((size_t)(k / C) * vh + i) * C + (k % C)];
 }
 
 template <typename R>
@@ -394,5 +407,53 @@ template hipError_t launch_pack_parity<double>(const Geo&, int, int, const d2_t*
 template hipError_t launch_pack_parity<float>(const Geo&, int, int, const f2_t*, f2_t*, hipStream_t);
 template hipError_t launch_unpack_parity<double>(const Geo&, int, int, const d2_t*, d2_t*, hipStream_t);
 template hipError_t launch_unpack_parity<float>(const Geo&, int, int, const f2_t*, f2_t*, hipStream_t);
+
+// FP64 parity vectors [nrhs][12][vh] <-> FP32 parity vectors [nrhs][6][vh][2]
+__global__ void k_parity_to_f32(f4_t* __restrict__ y, const d2_t* __restrict__ x, long long n6, int vh) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;  // (rhs, k, i)
+  if (t >= n6) return;
+  const int i = (int)(t % vh);
+  const long long rk = t / vh;  // rhs * 6 + k
+  const long long rhs = rk / 6;
+  const int k = (int)(rk % 6);
+  const d2_t* xr = x + rhs * 12LL * vh;
+  d2_t a = xr[(size_t)(2 * k) * vh + i], b = xr[(size_t)(2 * k + 1) * vh + i];
+  f4_t o;
+  o.x = (float)a.x;
+  o.y = (float)a.y;
+  o.z = (float)b.x;
+  o.w = (float)b.y;
+  y[t] = o;
+}
+
+__global__ void k_parity_to_f64(d2_t* __restrict__ y, const f4_t* __restrict__ x, long long n6, int vh) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n6) return;
+  const int i = (int)(t % vh);
+  const long long rk = t / vh;
+  const long long rhs = rk / 6;
+  const int k = (int)(rk % 6);
+  d2_t* yr = y + rhs * 12LL * vh;
+  f4_t q = x[t];
+  d2_t a, b;
+  a.x = q.x;
+  a.y = q.y;
+  b.x = q.z;
+  b.y = q.w;
+  yr[(size_t)(2 * k) * vh + i] = a;
+  yr[(size_t)(2 * k + 1) * vh + i] = b;
+}
+
+hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s) {
+  const long long n6 = 6LL * vh * nrhs;
+  hipLaunchKernelGGL(k_parity_to_f32, dim3((unsigned)((n6 + 255) / 256)), dim3(256), 0, s, (f4_t*)y, x, n6, vh);
+  return hipGetLastError();
+}
+
+hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s) {
+  const long long n6 = 6LL * vh * nrhs;
+  hipLaunchKernelGGL(k_parity_to_f64, dim3((unsigned)((n6 + 255) / 256)), dim3(256), 0, s, y, (const f4_t*)x, n6, vh);
+  return hipGetLastError();
+}
 
 }  // namespace ddq

@@ -67,19 +67,18 @@ __device__ __forceinline__ void hop_fence(Spinor<R>& acc) {
 
 template <typename R>
 struct HopCtx {
-  Rows<R> in;
+  Field in;
   const pair<R>* links;
   int vh;
-  uint32_t loff;  // lane offset of the output site in a 9-row link field
+  uint32_t loff;  // lane offset of the output site in a link field
   Nbr nb;
-  R sf, sb;      // projector signs of forward and backward hops
+  R sf, sb;       // projector signs of forward and backward hops
 };
 
-template <int H, typename R>
-__device__ __forceinline__ Link<R> hop_link(const HopCtx<R>& c) {
-  // dirs 0..3: U_mu(x); dirs 4..7: U_mu(x - mu)^H
-  constexpr int dir = (H & 1) ? 4 + (H >> 1) : (H >> 1);
-  return load_link<R>(frows<R>(c.links + (size_t)dir * 9 * field_vh(c.vh), 9, c.vh), c.loff);
+// link field of direction mu (LINK_ROWS complex rows, blocked)
+template <typename R>
+__device__ __forceinline__ Field link_field(const HopCtx<R>& c, int mu) {
+  return bfield(c.links + (size_t)mu * LINK_ROWS * field_vh(c.vh), LINK_ROWS / CPE<R>, c.vh);
 }
 
 // acc += (1 + sg g_mu) U in(neighbour), hop H
@@ -94,21 +93,39 @@ __device__ __forceinline__ void hop_compute(Spinor<R>& acc, const Spinor<R>& p, 
   accumulate<MU, R>(acc, uh, sg);
 }
 
+// Loads of hop H: the neighbour spinor, and the link.  FP64 reads one 9-entry half
+// of a direction's link field per hop; FP32 reads both halves (nine 16-byte
+// elements) at the forward hop and keeps the backward link for the next hop.
 template <int H, typename R>
-__device__ __forceinline__ void hop_steps(Spinor<R>& acc, Spinor<R>& p, Link<R>& u, const HopCtx<R>& c) {
+__device__ __forceinline__ void hop_loads(const HopCtx<R>& c, Spinor<R>& p, Link<R>& u, Link<R>& u_bwd) {
+  p = load_spinor<R>(c.in, voff(c.nb.j[H]));
+  if constexpr (CPE<R> == 1) {
+    u = load_link_half<R>(link_field(c, H >> 1), H & 1, c.loff);
+  } else if constexpr ((H & 1) == 0) {
+    load_link_pair<R>(link_field(c, H >> 1), c.loff, u, u_bwd);
+  } else {
+    u = u_bwd;
+  }
+}
+
+template <int H, typename R>
+__device__ __forceinline__ void hop_steps(Spinor<R>& acc, Spinor<R>& p, Link<R>& u, Link<R>& u_bwd,
+                                          const HopCtx<R>& c) {
   if constexpr (DDQ_PREFETCH && H < 7) {
-    Spinor<R> pn = load_spinor<R>(c.in, c.nb.j[H + 1]);
-    Link<R> un = hop_link<H + 1, R>(c);
+    Spinor<R> pn;
+    Link<R> un, ub = u_bwd;
+    hop_loads<H + 1, R>(c, pn, un, ub);
     hop_compute<H, R>(acc, p, u, c);
     hop_fence<R>(acc);
-    hop_steps<H + 1, R>(acc, pn, un, c);
+    hop_steps<H + 1, R>(acc, pn, un, ub, c);
   } else {
     hop_compute<H, R>(acc, p, u, c);
     hop_fence<R>(acc);
     if constexpr (H < 7) {
-      Spinor<R> pn = load_spinor<R>(c.in, c.nb.j[H + 1]);
-      Link<R> un = hop_link<H + 1, R>(c);
-      hop_steps<H + 1, R>(acc, pn, un, c);
+      Spinor<R> pn;
+      Link<R> un, ub = u_bwd;
+      hop_loads<H + 1, R>(c, pn, un, ub);
+      hop_steps<H + 1, R>(acc, pn, un, ub, c);
     }
   }
 }
@@ -129,15 +146,17 @@ hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
   const int i = xcd_block(a.nblk) * HOP_BLOCK + (int)threadIdx.x;
   if (i >= vh) return;
+  constexpr int SP_E = SPINOR_ROWS / CPE<R>;  // element rows of a spinor
   const size_t roff = (size_t)blockIdx.y * (size_t)a.rhs_stride;
-  const Rows<R> cl = frows<R>(a.clov, 36, vh);
-  const uint32_t coff = foff<R>(i, 36);
+  const Field cl = bfield(a.clov, CLOVER_ROWS / CPE<R>, vh);
+  const uint32_t coff = boff(i, CLOVER_ROWS / CPE<R>);
+  const uint32_t off = voff(i);
   const Site s = decode(a.g, i, a.p_out);
   HopCtx<R> c;
-  c.in = rows<R>(a.in + roff, 12, vh);
+  c.in = vfield(a.in + roff, SP_E, vh);
   c.links = a.links;
   c.vh = vh;
-  c.loff = foff<R>(i, 9);
+  c.loff = boff(i, LINK_ROWS / CPE<R>);
   c.nb = neighbours(a.g, s);
   // D: forward (1 - g), backward (1 + g).  D^H = g5 D g5 flips both projectors.
   c.sf = DAG ? R(1) : R(-1);
@@ -146,60 +165,61 @@ hop_kernel(HopArgs<R> a) {
   Spinor<R> acc;
   zero(acc);
   {
-    Spinor<R> p = load_spinor<R>(c.in, c.nb.j[0]);
-    Link<R> u = hop_link<0, R>(c);
-    hop_steps<0, R>(acc, p, u, c);
+    Spinor<R> p;
+    Link<R> u, ub;
+    hop_loads<0, R>(c, p, u, ub);
+    hop_steps<0, R>(acc, p, u, ub, c);
   }
   // h = 1/2 acc
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc.c[sp][c] = R(0.5) * acc.c[sp][c];
+    for (int cc = 0; cc < 3; ++cc) acc.c[sp][cc] = R(0.5) * acc.c[sp][cc];
 
-  const Rows<R> out = rows<R>(a.out + roff, 12, vh);  // may alias a.x (in-place Richardson)
+  const Field out = vfield(a.out + roff, SP_E, vh);  // may alias a.x (in-place Richardson)
   if constexpr (MODE == M_HOP_CLINV) {
-    store_spinor<R>(out, i, clover_mul<R>(cl, coff, acc));
+    store_spinor<R>(out, off, clover_mul<R>(cl, coff, acc));
   } else if constexpr (MODE == M_RECON) {
-    Spinor<R> bb = load_spinor<R>(rows<R>(a.b + roff, 12, vh), i);
+    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) bb.c[sp][c] = bb.c[sp][c] + acc.c[sp][c];
-    store_spinor<R>(out, i, clover_mul<R>(cl, coff, bb));
+      for (int cc = 0; cc < 3; ++cc) bb.c[sp][cc] = bb.c[sp][cc] + acc.c[sp][cc];
+    store_spinor<R>(out, off, clover_mul<R>(cl, coff, bb));
   } else if constexpr (MODE == M_APPLY) {
-    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(rows<R>(a.x + roff, 12, vh), i));
+    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(vfield(a.x + roff, SP_E, vh), off));
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) cx.c[sp][c] = cx.c[sp][c] - acc.c[sp][c];
-    store_spinor<R>(out, i, cx);
+      for (int cc = 0; cc < 3; ++cc) cx.c[sp][cc] = cx.c[sp][cc] - acc.c[sp][cc];
+    store_spinor<R>(out, off, cx);
   } else if constexpr (MODE == M_RICH) {
-    Spinor<R> xx = load_spinor<R>(rows<R>(a.x + roff, 12, vh), i);
-    Spinor<R> bb = load_spinor<R>(rows<R>(a.b + roff, 12, vh), i);
+    Spinor<R> xx = load_spinor<R>(vfield(a.x + roff, SP_E, vh), off);
+    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
     Spinor<R> cx = clover_mul<R>(cl, coff, xx);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        cpx<R> r = bb.c[sp][c] - cx.c[sp][c] + acc.c[sp][c];
-        xx.c[sp][c] = xx.c[sp][c] + a.omega * r;
+      for (int cc = 0; cc < 3; ++cc) {
+        cpx<R> r = bb.c[sp][cc] - cx.c[sp][cc] + acc.c[sp][cc];
+        xx.c[sp][cc] = xx.c[sp][cc] + a.omega * r;
       }
-    store_spinor<R>(out, i, xx);
+    store_spinor<R>(out, off, xx);
   } else if constexpr (MODE == M_RESID) {
-    Spinor<R> bb = load_spinor<R>(rows<R>(a.b + roff, 12, vh), i);
-    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(rows<R>(a.x + roff, 12, vh), i));
+    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
+    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(vfield(a.x + roff, SP_E, vh), off));
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) bb.c[sp][c] = bb.c[sp][c] - cx.c[sp][c] + acc.c[sp][c];
-    store_spinor<R>(out, i, bb);
+      for (int cc = 0; cc < 3; ++cc) bb.c[sp][cc] = bb.c[sp][cc] - cx.c[sp][cc] + acc.c[sp][cc];
+    store_spinor<R>(out, off, bb);
   } else {  // M_PREP
-    Spinor<R> bb = load_spinor<R>(rows<R>(a.b + roff, 12, vh), i);
+    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) bb.c[sp][c] = bb.c[sp][c] + acc.c[sp][c];
-    store_spinor<R>(out, i, bb);
+      for (int cc = 0; cc < 3; ++cc) bb.c[sp][cc] = bb.c[sp][cc] + acc.c[sp][cc];
+    store_spinor<R>(out, off, bb);
   }
 }
 
@@ -237,8 +257,10 @@ __global__ void __launch_bounds__(HOP_BLOCK) k_clover_only(Geo g, const pair<R>*
   const int i = blockIdx.x * HOP_BLOCK + (int)threadIdx.x;
   if (i >= vh) return;
   const size_t roff = (size_t)blockIdx.y * 12 * (size_t)vh;
-  store_spinor<R>(rows<R>(out + roff, 12, vh), i,
-                  clover_mul<R>(frows<R>(clov, 36, vh), foff<R>(i, 36), load_spinor<R>(rows<R>(v + roff, 12, vh), i)));
+  constexpr int SP_E = SPINOR_ROWS / CPE<R>;
+  store_spinor<R>(vfield(out + roff, SP_E, vh), voff(i),
+                  clover_mul<R>(bfield(clov, CLOVER_ROWS / CPE<R>, vh), boff(i, CLOVER_ROWS / CPE<R>),
+                                load_spinor<R>(vfield(v + roff, SP_E, vh), voff(i))));
 }
 
 template <typename R>

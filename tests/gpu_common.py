@@ -9,14 +9,23 @@ from paper_2407_08092_amd import api, synth
 
 
 def to_dev(v_np, dtype=torch.complex128):
-    """oracle parity vector [V/2, 12] (or [n, V/2, 12]) -> ABI layout on the GPU."""
-    t = torch.from_numpy(np.ascontiguousarray(np.swapaxes(v_np, -1, -2)))
+    """oracle parity vector [V/2, 12] (or [n, V/2, 12]) -> ABI layout on the GPU:
+    complex128 [.., 12, V/2]; complex64 [.., 6, V/2, 2] (rows 2k, 2k+1 paired)."""
+    a = np.swapaxes(v_np, -1, -2)  # [.., 12, Vh]
+    if dtype == torch.complex64:
+        vh = a.shape[-1]
+        a = np.swapaxes(a.reshape(a.shape[:-2] + (6, 2, vh)), -1, -2)  # [.., 6, Vh, 2]
+    t = torch.from_numpy(np.ascontiguousarray(a))
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
 def to_host(t):
-    """ABI parity vector -> oracle layout (complex128 numpy)."""
-    return np.ascontiguousarray(np.swapaxes(t.detach().to(torch.complex128).cpu().numpy(), -1, -2))
+    """ABI parity vector -> oracle layout [.., V/2, 12] (complex128 numpy)."""
+    a = t.detach().cpu().numpy().astype(np.complex128)
+    if t.dtype == torch.complex64:
+        a = np.swapaxes(a, -1, -2)  # [.., 6, 2, Vh]
+        a = a.reshape(a.shape[:-3] + (12, a.shape[-1]))
+    return np.ascontiguousarray(np.swapaxes(a, -1, -2))
 
 
 class Case:

@@ -69,8 +69,8 @@ def test_free_field_schur_fullsize(free_lattice, k):
     expect = plane_even(DIMS, p, np.einsum("st,ta->sa", schur_of_p(p, M0), u), "cuda")
     y = api.apply_schur(free_lattice, psi)
     assert relerr(y, expect) < 1e-12
-    y32 = api.apply_schur(free_lattice, psi.to(torch.complex64))
-    assert relerr(y32.to(torch.complex128), expect) < 1e-5
+    y32 = api.apply_schur(free_lattice, api.convert_parity(free_lattice, psi, torch.complex64))
+    assert relerr(api.convert_parity(free_lattice, y32, torch.complex128), expect) < 1e-5
 
 
 def test_richardson_eigenvector_fullsize(free_lattice):
@@ -84,9 +84,9 @@ def test_richardson_eigenvector_fullsize(free_lattice):
     x = torch.zeros_like(b)
     api.richardson_smooth(free_lattice, x, b, n, omega)
     assert relerr(x, expect) < 1e-12
-    x32 = torch.zeros_like(b, dtype=torch.complex64)
-    api.richardson_smooth(free_lattice, x32, b.to(torch.complex64), n, omega)
-    assert relerr(x32.to(torch.complex128), expect) < 1e-5
+    x32 = api.parity_vector(free_lattice, dtype=torch.complex64).zero_()
+    api.richardson_smooth(free_lattice, x32, api.convert_parity(free_lattice, b, torch.complex64), n, omega)
+    assert relerr(api.convert_parity(free_lattice, x32, torch.complex128), expect) < 1e-5
 
 
 def test_pure_gauge_fullsize():

@@ -110,7 +110,7 @@ def test_richardson_f32(dims):
     lam = solvers.power_iteration(c.op.schur, c.vec(25), 50)
     omega = 0.8 / lam
     ref = solvers.richardson(c.op.schur, b, np.zeros_like(b), 20, omega)
-    xd = torch.zeros((12, c.olat.Vh), dtype=torch.complex64, device="cuda")
+    xd = api.parity_vector(c.lat, dtype=torch.complex64).zero_()
     api.richardson_smooth(c.lat, xd, to_dev(b, torch.complex64), 20, omega)
     torch.cuda.synchronize()
     assert rel(to_host(xd), ref) < 1e-5
@@ -149,10 +149,16 @@ def test_pack_unpack_roundtrip_bitwise(dims):
     api.unpack_parity(c.lat, o, 1, out=g)
     f32 = f.to(torch.complex64)
     e32 = api.pack_parity(c.lat, f32, 0)
+    g32 = api.unpack_parity(c.lat, e32, 0)
     torch.cuda.synchronize()
     assert torch.equal(g, f)
     assert np.array_equal(to_host(e), c.olat.to_parity(c.full(41), 0))
-    assert torch.equal(e32, e.to(torch.complex64))
+    assert torch.equal(e32, api.convert_parity(c.lat, e, torch.complex64))
+    assert torch.equal(e32, to_dev(to_host(e), torch.complex64))
+    even = torch.from_numpy(np.broadcast_to(c.olat.parity == 0, f.shape[:4]).copy()).cuda()[..., None, None]
+    assert torch.equal(g32 * even, f32 * even)
+    # FP32 -> FP64 widening is exact
+    assert torch.equal(api.convert_parity(c.lat, e32, torch.complex128), to_dev(to_host(e32)))
 
 
 def test_power_iteration_matches_oracle():

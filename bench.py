@@ -37,6 +37,7 @@ MIXED = dict(dims=(16, 16, 16, 32), eps=0.5, c_sw=1.0, m0=-0.2, seed_gauge=201, 
 SWEEPS = 20
 BYTES_APPLY_F32 = 2208    # per even site, FP32 links/spinors/clover, every field once per kernel
 BYTES_APPLY_F64 = 4416
+BYTES_APPLY_F32_L12 = 1824  # 12-real FP32 links
 
 
 MODE_CODE = {"clinv": 0, "recon": 1, "apply": 2, "richardson": 3, "resid": 4, "prep": 5}
@@ -56,10 +57,12 @@ def measured_traffic(kernel_name: str):
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     cur = h.hexdigest()[:16]
-    parts = kernel_name.split("_")  # hop_<mode>_<f32|f64>[...]
+    parts = kernel_name.split("_")  # hop_<mode>_<f32|f32l12|f64>[...]
     if len(parts) < 3 or parts[1] not in MODE_CODE:
         return None
-    key = ("float" if parts[2] == "f32" else "double") + f":{MODE_CODE[parts[1]]}"
+    key = ("float" if parts[2].startswith("f32") else "double") + f":{MODE_CODE[parts[1]]}"
+    if parts[2] == "f32l12":
+        key += ":l12"
     try:
         lines = open(os.path.join(ROOT, PROFILE)).read().splitlines()
     except OSError:
@@ -192,6 +195,25 @@ def main():
                                 "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
                             for k, v in prof.items()}}
 
+    # the same FP32 step with 12-real links (third row rebuilt from unitarity)
+    U = synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev)
+    api.set_gauge(lat, U, link12=True)
+    del U
+    torch.cuda.empty_cache()
+    api.set_clover(lat, cfg["c_sw"], cfg["m0"])
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ev12 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        step(ev12[k])
+    torch.cuda.synchronize()
+    t12 = sum(e[0].elapsed_time(e[1]) for e in ev12) / args.steps
+    s12 = sum(e[1].elapsed_time(e[2]) for e in ev12) / args.steps
+    link12 = {"apply_ms": round(t12, 4), "apply_GBs": round(BYTES_APPLY_F32_L12 * vh / (t12 * 1e-3) / 1e9, 1),
+              "bytes_per_even_site": BYTES_APPLY_F32_L12, "sweeps_per_s": round(SWEEPS / (s12 * 1e-3), 1)}
+    log(f"FP32 12-real links: apply {t12:.3f} ms, {link12['sweeps_per_s']} sweeps/s")
+
     # FP64 apply and sweeps on the same lattice (context)
     y64 = torch.empty_like(x64)
     for _ in range(2):
@@ -234,6 +256,7 @@ def main():
         "pct_of_stream_copy": round(100 * gbs / stream_gbs, 2),
         "schur_apply_ms": round(t_apply, 4),
         "sweeps_per_s": round(sweeps_per_s, 1),
+        "fp32_link12": link12,
         "fp64": fp64,
         "mixed_vs_fp64": mixed,
         "roofline": roof,

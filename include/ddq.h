@@ -74,8 +74,12 @@ enum ddq_status {
   DDQ_ERR_NONFINITE = -6   /* NaN or Inf met in a residual norm */
 };
 
-/* storage_flags of ddq_set_gauge: which link precisions to materialise. */
-enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2 };
+/* storage_flags of ddq_set_gauge: which link precisions to materialise.  FP64
+ * links are always kept (the outer residual of the solver uses them).
+ * DDQ_STORE_F32_LINK12 stores the FP32 links as their first two rows only and
+ * rebuilds the third from SU(3) unitarity (row 2 = conj(row 0 x row 1)) inside
+ * the kernels: one third fewer link bytes. */
+enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2, DDQ_STORE_F32_LINK12 = 4 };
 
 /* Lattice of extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2, with
  * V = Lx*Ly*Lz*Lt < 2^31.  t_antiperiodic != 0 selects antiperiodic t.

@@ -13,7 +13,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("DDQ_LIBRARY") or os.path.join(PKG, "libddq.so")
 
 DDQ_F64, DDQ_F32 = 0, 1
-DDQ_STORE_F64, DDQ_STORE_F32 = 1, 2
+DDQ_STORE_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12 = 1, 2, 4
 STATUS = {
     0: "DDQ_OK", 1: "DDQ_NOT_CONVERGED", -1: "DDQ_ERR_ARG", -2: "DDQ_ERR_STATE", -3: "DDQ_ERR_HIP",
     -4: "DDQ_ERR_OOM", -5: "DDQ_ERR_NOT_PD", -6: "DDQ_ERR_NONFINITE",

@@ -16,7 +16,8 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import DDQ_F32, DDQ_F64, DDQ_STORE_F32, DDQ_STORE_F64, DDQError, GmresParams, SolveInfo, check, lib
+from ._lib import (DDQ_F32, DDQ_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12, DDQ_STORE_F64, DDQError, GmresParams,
+                   SolveInfo, check, lib)
 
 __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
@@ -98,11 +99,15 @@ def destroy_lattice(lat: Lattice) -> None:
         lat.handle = None
 
 
-def set_gauge(lat: Lattice, U: torch.Tensor, store=(DDQ_F64, DDQ_F32)) -> None:
+def set_gauge(lat: Lattice, U: torch.Tensor, store=(DDQ_F64, DDQ_F32), link12: bool = False) -> None:
+    """Links U (complex128, canonical).  link12: keep the FP32 links as two rows
+    (third rebuilt from unitarity in the kernels)."""
     if U.dtype != torch.complex128 or tuple(U.shape) != lat.full_shape[:4] + (4, 3, 3):
         raise ValueError(f"U must be complex128 of shape {lat.full_shape[:4] + (4, 3, 3)}")
     U = U.contiguous()
     flags = (DDQ_STORE_F64 if DDQ_F64 in store else 0) | (DDQ_STORE_F32 if DDQ_F32 in store else 0)
+    if link12:
+        flags |= DDQ_STORE_F32_LINK12
     lat.sync_stream()
     check(lib().ddq_set_gauge(lat.handle, C.c_void_p(U.data_ptr()), int(U.is_cuda), flags), "ddq_set_gauge")
     if not U.is_cuda:

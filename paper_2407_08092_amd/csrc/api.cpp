@@ -89,6 +89,7 @@ struct ddq_lattice {
   void* links[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
   void* clov[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [prec][0: A_ee, 1: A_oo^-1]
   bool have_clover = false;
+  bool link12 = false;  // FP32 links stored as their first two rows
   double c_sw = 0.0, m0 = 0.0;
   // work buffers
   Grow force_ws;      // force: psi_o, lambda_o, insertions
@@ -163,7 +164,8 @@ double hop_bytes(const ddq_lattice* L, int prec, int mode, int nrhs) {
     case M_RESID: spin = 4; break;                // in, x, b, out
     case M_PREP: spin = 3; clover = false; break; // in, b, out
   }
-  const double per_site = (double)(12 * spin * nrhs + 72 + (clover ? 36 : 0)) * (prec == DDQ_F64 ? 16 : 8);
+  const int link = (prec == DDQ_F32 && L->link12) ? 48 : 72;
+  const double per_site = (double)(12 * spin * nrhs + link + (clover ? 36 : 0)) * (prec == DDQ_F64 ? 16 : 8);
   return per_site * (double)L->Vh;
 }
 
@@ -190,7 +192,8 @@ template <typename R>
 hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
   if (!L->prof_on) return launch_hop<R>(a, mode, dag, nrhs, L->stream);
   const int prec = sizeof(R) == 8 ? DDQ_F64 : DDQ_F32;
-  std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : "_f32") + (dag ? "_dag" : "") +
+  std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
+                     (dag ? "_dag" : "") +
                      (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
   int kind = -1;
   for (size_t k = 0; k < L->kind_name.size(); ++k)
@@ -233,6 +236,7 @@ HopArgs<R> hop_args(const ddq_lattice* L, int prec, int p_out) {
   a.links = (const pair<R>*)L->links[prec][p_out];
   a.clov = (const pair<R>*)L->clov[prec][p_out];
   a.rhs_stride = L->nvec();
+  a.link12 = (prec == DDQ_F32 && L->link12) ? 1 : 0;
   return a;
 }
 
@@ -419,8 +423,9 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   CHK(check_lat(L));
   if (!U) return fail(DDQ_ERR_ARG, "U is null");
   if (storage_flags == 0) storage_flags = DDQ_STORE_F64 | DDQ_STORE_F32;
-  if (storage_flags & ~(unsigned)(DDQ_STORE_F64 | DDQ_STORE_F32))
+  if (storage_flags & ~(unsigned)(DDQ_STORE_F64 | DDQ_STORE_F32 | DDQ_STORE_F32_LINK12))
     return fail(DDQ_ERR_ARG, "unknown storage flag");
+  if (storage_flags & DDQ_STORE_F32_LINK12) storage_flags |= DDQ_STORE_F32;
   L->have_gauge = false;
   L->have_clover = false;
   const size_t ubytes = (size_t)L->V * 4 * 9 * 16;
@@ -435,11 +440,16 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
     }
   HIPCHK(launch_pack_gauge_f64(L->geo, (const d2_t*)L->U, (d2_t*)L->links[DDQ_F64][0],
                                (d2_t*)L->links[DDQ_F64][1], L->stream));
+  L->link12 = (storage_flags & DDQ_STORE_F32_LINK12) != 0;
   if (storage_flags & DDQ_STORE_F32) {
     for (int q = 0; q < 2; ++q) {
       if (!L->links[DDQ_F32][q]) CHK(dalloc(&L->links[DDQ_F32][q], n * 8));
-      HIPCHK(launch_field_to_f32((const d2_t*)L->links[DDQ_F64][q], L->links[DDQ_F32][q], 4, LINK_ROWS,
-                                 (int)L->Vh, L->stream));
+      if (L->link12)
+        HIPCHK(launch_links_to_f32_12((const d2_t*)L->links[DDQ_F64][q], L->links[DDQ_F32][q], (int)L->Vh,
+                                      L->stream));
+      else
+        HIPCHK(launch_field_to_f32((const d2_t*)L->links[DDQ_F64][q], L->links[DDQ_F32][q], 4, LINK_ROWS,
+                                   (int)L->Vh, L->stream));
     }
   } else {
     for (int q = 0; q < 2; ++q) dfree(L->links[DDQ_F32][q]);

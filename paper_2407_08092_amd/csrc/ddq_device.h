@@ -334,6 +334,29 @@ __device__ __forceinline__ Link<R> load_link_half(const Field& U, int half, uint
   load_rows<R, DDQ_STREAM_AUX>(U, 9 * half, 9, off, l.u);  // FP64 only: 9 rows = 9 elements
   return l;
 }
+// SU(3) from its first two rows: row 2 = conj(row 0 x row 1)
+template <typename R>
+__device__ __forceinline__ void su3_third_row(Link<R>& l) {
+  l.u[6] = conj(l.u[1] * l.u[5] - l.u[2] * l.u[4]);
+  l.u[7] = conj(l.u[2] * l.u[3] - l.u[0] * l.u[5]);
+  l.u[8] = conj(l.u[0] * l.u[4] - l.u[1] * l.u[3]);
+}
+
+// 12-real storage (LINK12_ROWS complex rows per direction: the first two rows of
+// U_mu(x), then of U_mu(x - mu)^H); the third rows are rebuilt
+constexpr int LINK12_ROWS = 12;
+template <typename R>
+__device__ __forceinline__ void load_link_pair12(const Field& U, uint32_t off, Link<R>& fwd, Link<R>& bwd) {
+  cpx<R> c[LINK12_ROWS];
+  load_rows<R, DDQ_STREAM_AUX>(U, 0, LINK12_ROWS, off, c);
+#pragma unroll
+  for (int e = 0; e < 6; ++e) {
+    fwd.u[e] = c[e];
+    bwd.u[e] = c[6 + e];
+  }
+  su3_third_row(fwd);  // the backward link's third row is rebuilt where it is used
+}
+
 template <typename R>
 __device__ __forceinline__ void load_link_pair(const Field& U, uint32_t off, Link<R>& fwd, Link<R>& bwd) {
   cpx<R> c[LINK_ROWS];

@@ -33,8 +33,10 @@ struct HopArgs {
   const pair<R>* b;          // own-parity right-hand side (RECON, RICH, RESID, PREP)
   pair<R>* out;
   R omega;
-  int nblk;                  // workgroups along x, padded to a multiple of 8
-  long long rhs_stride;      // elements between right-hand sides (blockIdx.y)
+  int link12;                // FP32: links stored as their first two rows
+  int nblk;                  // workgroups along x, padded to a multiple of 8 (one right-hand side)
+  int nrhs;                  // right-hand sides of the launch
+  long long rhs_stride;      // complex elements between right-hand sides
 };
 
 #ifndef DDQ_HOP_BLOCK
@@ -76,6 +78,7 @@ hipError_t launch_force(const Geo& g, const d2_t* U, const d2_t* chi_e, const d2
 hipError_t launch_pack_gauge_f64(const Geo& g, const d2_t* U, d2_t* out_even, d2_t* out_odd,
                                  hipStream_t s);
 hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows, int vh, hipStream_t s);
+hipError_t launch_links_to_f32_12(const d2_t* in, void* out, int vh, hipStream_t s);
 hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0,

@@ -74,6 +74,33 @@ __global__ void k_field_to_f32(const d2_t* __restrict__ in, f4_t* __restrict__ o
   out[(size_t)f * er * fv + fidx(e, i, er, vh)] = o;
 }
 
+// FP64 link fields (4 directions x LINK_ROWS) -> FP32 12-real link fields: complex
+// rows 0..5 (first two rows of U_mu(x)) and 9..14 (of U_mu(x - mu)^H), paired
+__global__ void k_links_to_f32_12(const d2_t* __restrict__ in, f4_t* __restrict__ out, int vh) {
+  const long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int er = LINK12_ROWS / 2;
+  if (tid >= 4LL * er * vh) return;
+  const int i = (int)(tid % vh);
+  const int e = (int)((tid / vh) % er);
+  const int mu = (int)(tid / ((long long)vh * er));
+  const size_t fv = (size_t)field_vh(vh);
+  const d2_t* src = in + (size_t)mu * LINK_ROWS * fv;
+  auto row = [](int k) { return k < 6 ? k : k + 3; };  // 12-real row -> 18-entry row
+  d2_t a = src[fidx(row(2 * e), i, LINK_ROWS, vh)], b = src[fidx(row(2 * e + 1), i, LINK_ROWS, vh)];
+  f4_t o;
+  o.x = (float)a.x;
+  o.y = (float)a.y;
+  o.z = (float)b.x;
+  o.w = (float)b.y;
+  out[(size_t)mu * er * fv + fidx(e, i, er, vh)] = o;
+}
+
+hipError_t launch_links_to_f32_12(const d2_t* in, void* out, int vh, hipStream_t s) {
+  const long long total = 4LL * (LINK12_ROWS / 2) * vh;
+  hipLaunchKernelGGL(k_links_to_f32_12, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, in, (f4_t*)out, vh);
+  return hipGetLastError();
+}
+
 hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows, int vh, hipStream_t s) {
   const long long total = (long long)nfields * (crows / 2) * vh;
   hipLaunchKernelGGL(k_field_to_f32, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, in, (f4_t*)out,

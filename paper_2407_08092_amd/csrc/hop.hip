@@ -69,6 +69,7 @@ template <typename R>
 struct HopCtx {
   Field in;
   const pair<R>* links;
+  int lrows;      // complex rows of one direction's link field (18, or 12 with LINK12)
   int vh;
   uint32_t loff;  // lane offset of the output site in a link field
   Nbr nb;
@@ -78,7 +79,7 @@ struct HopCtx {
 // link field of direction mu (LINK_ROWS complex rows, blocked)
 template <typename R>
 __device__ __forceinline__ Field link_field(const HopCtx<R>& c, int mu) {
-  return bfield(c.links + (size_t)mu * LINK_ROWS * field_vh(c.vh), LINK_ROWS / CPE<R>, c.vh);
+  return bfield(c.links + (size_t)mu * c.lrows * field_vh(c.vh), c.lrows / CPE<R>, c.vh);
 }
 
 // acc += (1 + sg g_mu) U in(neighbour), hop H
@@ -96,36 +97,40 @@ __device__ __forceinline__ void hop_compute(Spinor<R>& acc, const Spinor<R>& p, 
 // Loads of hop H: the neighbour spinor, and the link.  FP64 reads one 9-entry half
 // of a direction's link field per hop; FP32 reads both halves (nine 16-byte
 // elements) at the forward hop and keeps the backward link for the next hop.
-template <int H, typename R>
+template <int H, typename R, bool L12>
 __device__ __forceinline__ void hop_loads(const HopCtx<R>& c, Spinor<R>& p, Link<R>& u, Link<R>& u_bwd) {
   p = load_spinor<R>(c.in, voff(c.nb.j[H]));
-  if constexpr (CPE<R> == 1) {
+  if constexpr (CPE<R> == 1 && !L12) {
     u = load_link_half<R>(link_field(c, H >> 1), H & 1, c.loff);
   } else if constexpr ((H & 1) == 0) {
-    load_link_pair<R>(link_field(c, H >> 1), c.loff, u, u_bwd);
+    if constexpr (L12)
+      load_link_pair12<R>(link_field(c, H >> 1), c.loff, u, u_bwd);
+    else
+      load_link_pair<R>(link_field(c, H >> 1), c.loff, u, u_bwd);
   } else {
     u = u_bwd;
+    if constexpr (L12) su3_third_row(u);
   }
 }
 
-template <int H, typename R>
+template <int H, typename R, bool L12>
 __device__ __forceinline__ void hop_steps(Spinor<R>& acc, Spinor<R>& p, Link<R>& u, Link<R>& u_bwd,
                                           const HopCtx<R>& c) {
   if constexpr (DDQ_PREFETCH && H < 7) {
     Spinor<R> pn;
     Link<R> un, ub = u_bwd;
-    hop_loads<H + 1, R>(c, pn, un, ub);
+    hop_loads<H + 1, R, L12>(c, pn, un, ub);
     hop_compute<H, R>(acc, p, u, c);
     hop_fence<R>(acc);
-    hop_steps<H + 1, R>(acc, pn, un, ub, c);
+    hop_steps<H + 1, R, L12>(acc, pn, un, ub, c);
   } else {
     hop_compute<H, R>(acc, p, u, c);
     hop_fence<R>(acc);
     if constexpr (H < 7) {
       Spinor<R> pn;
       Link<R> un, ub = u_bwd;
-      hop_loads<H + 1, R>(c, pn, un, ub);
-      hop_steps<H + 1, R>(acc, pn, un, ub, c);
+      hop_loads<H + 1, R, L12>(c, pn, un, ub);
+      hop_steps<H + 1, R, L12>(acc, pn, un, ub, c);
     }
   }
 }
@@ -140,14 +145,28 @@ __device__ __forceinline__ void hop_steps(Spinor<R>& acc, Spinor<R>& p, Link<R>&
 template <typename R> struct HOP_WAVES { static constexpr int value = DDQ_WAVES_F32; };
 template <> struct HOP_WAVES<double> { static constexpr int value = DDQ_WAVES_F64; };
 
-template <typename R, int MODE, bool DAG>
+template <typename R, int MODE, bool DAG, bool L12, bool MR>
 __global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(HOP_WAVES<R>::value)))
 hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
-  const int i = xcd_block(a.nblk) * HOP_BLOCK + (int)threadIdx.x;
+  int i, rhs;
+  if constexpr (!MR) {
+    i = xcd_block(a.nblk) * HOP_BLOCK + (int)threadIdx.x;
+    rhs = 0;
+  } else {
+    // several right-hand sides: a workgroup is 64 sites x (HOP_BLOCK / 64) right-hand
+    // sides, so its wavefronts read the same link and clover entries; consecutive
+    // workgroups take the other right-hand-side groups of the same 64 sites
+    // the wavefront's right-hand side, made explicitly uniform (an SGPR)
+    const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    const int groups = (a.nrhs + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+    i = (int)(blockIdx.x / groups) * 64 + ((int)threadIdx.x & 63);
+    rhs = (int)(blockIdx.x % groups) * (HOP_BLOCK / 64) + w;
+    if (rhs >= a.nrhs) return;
+  }
   if (i >= vh) return;
   constexpr int SP_E = SPINOR_ROWS / CPE<R>;  // element rows of a spinor
-  const size_t roff = (size_t)blockIdx.y * (size_t)a.rhs_stride;
+  const size_t roff = (size_t)rhs * (size_t)a.rhs_stride;
   const Field cl = bfield(a.clov, CLOVER_ROWS / CPE<R>, vh);
   const uint32_t coff = boff(i, CLOVER_ROWS / CPE<R>);
   const uint32_t off = voff(i);
@@ -155,8 +174,9 @@ hop_kernel(HopArgs<R> a) {
   HopCtx<R> c;
   c.in = vfield(a.in + roff, SP_E, vh);
   c.links = a.links;
+  c.lrows = L12 ? LINK12_ROWS : LINK_ROWS;
   c.vh = vh;
-  c.loff = boff(i, LINK_ROWS / CPE<R>);
+  c.loff = boff(i, c.lrows / CPE<R>);
   c.nb = neighbours(a.g, s);
   // D: forward (1 - g), backward (1 + g).  D^H = g5 D g5 flips both projectors.
   c.sf = DAG ? R(1) : R(-1);
@@ -167,8 +187,8 @@ hop_kernel(HopArgs<R> a) {
   {
     Spinor<R> p;
     Link<R> u, ub;
-    hop_loads<0, R>(c, p, u, ub);
-    hop_steps<0, R>(acc, p, u, ub, c);
+    hop_loads<0, R, L12>(c, p, u, ub);
+    hop_steps<0, R, L12>(acc, p, u, ub, c);
   }
   // h = 1/2 acc
 #pragma unroll
@@ -225,17 +245,38 @@ hop_kernel(HopArgs<R> a) {
 
 template <typename R, int MODE>
 static hipError_t launch_mode(const HopArgs<R>& a, bool dagger, int nrhs, hipStream_t s) {
-  dim3 grid(a.nblk, nrhs), block(HOP_BLOCK);
-  if (dagger)
-    hipLaunchKernelGGL((hop_kernel<R, MODE, true>), grid, block, 0, s, a);
-  else
-    hipLaunchKernelGGL((hop_kernel<R, MODE, false>), grid, block, 0, s, a);
+  dim3 block(HOP_BLOCK), grid(a.nblk);
+  if (nrhs > 1) {
+    const long long groups = (nrhs + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+    const long long nb = ((long long)a.g.Vh + 63) / 64 * groups;
+    if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+    grid = dim3((unsigned)nb);
+  }
+  // 12-real links exist for FP32 storage only
+  const bool l12 = sizeof(R) == 4 && a.link12;
+  constexpr bool F32 = sizeof(R) == 4;
+#define DDQ_HOP_LAUNCH(D, L, M) hipLaunchKernelGGL((hop_kernel<R, MODE, D, L, M>), grid, block, 0, s, a)
+  if (nrhs > 1) {
+    if (l12) {
+      if (dagger) DDQ_HOP_LAUNCH(true, F32, true); else DDQ_HOP_LAUNCH(false, F32, true);
+    } else {
+      if (dagger) DDQ_HOP_LAUNCH(true, false, true); else DDQ_HOP_LAUNCH(false, false, true);
+    }
+  } else {
+    if (l12) {
+      if (dagger) DDQ_HOP_LAUNCH(true, F32, false); else DDQ_HOP_LAUNCH(false, F32, false);
+    } else {
+      if (dagger) DDQ_HOP_LAUNCH(true, false, false); else DDQ_HOP_LAUNCH(false, false, false);
+    }
+  }
+#undef DDQ_HOP_LAUNCH
   return hipGetLastError();
 }
 
 template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a0, int mode, bool dagger, int nrhs, hipStream_t s) {
   HopArgs<R> a = a0;
+  a.nrhs = nrhs;
   int nb = (a.g.Vh + HOP_BLOCK - 1) / HOP_BLOCK;
   const int pad = 8 * (DDQ_XCD_CHUNK > 0 ? DDQ_XCD_CHUNK : 1);
   a.nblk = ((nb + pad - 1) / pad) * pad;

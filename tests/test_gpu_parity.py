@@ -71,14 +71,35 @@ def test_apply_schur_dagger(dims):
     assert rel(to_host(y32), ref) < 1e-5
 
 
-@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (8, 8, 8, 16)])
-def test_apply_schur_multi_rhs(dims):
+@pytest.mark.parametrize("dims,n", [((4, 6, 8, 10), 3), ((8, 8, 8, 16), 5), ((6, 6, 6, 10), 12), ((2, 2, 2, 2), 2)])
+def test_apply_schur_multi_rhs(dims, n):
+    # several right-hand sides per launch (workgroups of 64 sites x 4 right-hand sides,
+    # ragged counts leave idle wavefronts)
     c = case(dims)
-    x = c.vec(14, n=3)
+    x = c.vec(14, n=n)
     y = api.apply_schur(c.lat, to_dev(x))
+    y32 = api.apply_schur(c.lat, to_dev(x, torch.complex64))
+    yd = api.apply_schur(c.lat, to_dev(x), dagger=True)
     torch.cuda.synchronize()
-    for r in range(3):
+    for r in range(n):
         assert rel(to_host(y)[r], c.op.schur(x[r])) < 1e-12
+        assert rel(to_host(y32)[r], c.op.schur(x[r])) < 1e-5
+        assert rel(to_host(yd)[r], c.op.schur_adjoint(x[r])) < 1e-12
+
+
+def test_richardson_multi_rhs():
+    c = case((4, 6, 8, 10))
+    b = c.vec(16, n=4)
+    x0 = c.vec(17, n=4)
+    xd = to_dev(x0)
+    api.richardson_smooth(c.lat, xd, to_dev(b), 6, 0.15)
+    x32 = to_dev(x0, torch.complex64)
+    api.richardson_smooth(c.lat, x32, to_dev(b, torch.complex64), 6, 0.15)
+    torch.cuda.synchronize()
+    for r in range(4):
+        ref = solvers.richardson(c.op.schur, b[r], x0[r], 6, 0.15)
+        assert rel(to_host(xd)[r], ref) < 1e-12
+        assert rel(to_host(x32)[r], ref) < 1e-5
 
 
 def test_periodic_t_lattice():
@@ -112,6 +133,28 @@ def test_richardson_f32(dims):
     ref = solvers.richardson(c.op.schur, b, np.zeros_like(b), 20, omega)
     xd = api.parity_vector(c.lat, dtype=torch.complex64).zero_()
     api.richardson_smooth(c.lat, xd, to_dev(b, torch.complex64), 20, omega)
+    torch.cuda.synchronize()
+    assert rel(to_host(xd), ref) < 1e-5
+
+
+@pytest.mark.parametrize("dims", [(2, 2, 2, 2), (4, 6, 8, 10), (8, 8, 8, 16)])
+def test_link12_f32(dims):
+    # FP32 links stored as two rows, the third rebuilt from unitarity in the kernel
+    c = Case(dims, 0.5, 1.0, -0.2, 301)
+    api.set_gauge(c.lat, torch.from_numpy(c.U).cuda(), link12=True)
+    api.set_clover(c.lat, 1.0, -0.2)
+    x = c.vec(71)
+    y = api.apply_schur(c.lat, to_dev(x, torch.complex64))
+    yd = api.apply_schur(c.lat, to_dev(x, torch.complex64), dagger=True)
+    y64 = api.apply_schur(c.lat, to_dev(x))  # FP64 keeps all 18 reals
+    torch.cuda.synchronize()
+    assert rel(to_host(y), c.op.schur(x)) < 1e-5
+    assert rel(to_host(yd), c.op.schur_adjoint(x)) < 1e-5
+    assert rel(to_host(y64), c.op.schur(x)) < 1e-12
+    b = c.vec(72)
+    ref = solvers.richardson(c.op.schur, b, np.zeros_like(b), 20, 0.17)
+    xd = api.parity_vector(c.lat, dtype=torch.complex64).zero_()
+    api.richardson_smooth(c.lat, xd, to_dev(b, torch.complex64), 20, 0.17)
     torch.cuda.synchronize()
     assert rel(to_host(xd), ref) < 1e-5
 

@@ -178,6 +178,44 @@ typedef struct {
 int ddq_oe_gmres_solve(ddq_lattice* lat, void* x, const void* b,
                        const ddq_gmres_params* params, ddq_solve_info* info);
 
+/* Batched solves: several lattices of different extents, several right-hand
+ * sides each, all solved to their own tolerance in one call.  Each (lattice,
+ * right-hand side) pair is one system x = D^-1 b treated exactly as by
+ * ddq_oe_gmres_solve with inner_prec = DDQ_F32 (eq. 2 around the flexible,
+ * mixed-precision GMRES(m) of Alg. 2 with the Richardson preconditioner of
+ * Alg. 4); the paper solves one system at a time, the batching is this
+ * library's.  All systems advance in lock-step: every Arnoldi step is one
+ * replay of a HIP graph holding, for every lattice, the normalisation of v_k,
+ * the nu FP32 Richardson sweeps and the FP32 D_S apply on all its right-hand
+ * sides at once (the multi-right-hand-side kernels) and the FP64 classical
+ * Gram-Schmidt (two passes) with the norms; the host then applies the Givens
+ * rotations of every system after one synchronisation.  A system that has met
+ * its cycle target idles on zero vectors until the slowest one finishes the
+ * cycle; every cycle starts with FP64 residuals of all systems.
+ *
+ * ddq_batch_create: lats[nlat] distinct lattice handles, each with FP64 and FP32
+ *   links (ddq_set_gauge) and clover (ddq_set_clover); nrhs[l] >= 1 right-hand
+ *   sides for lattice l.  The batch keeps the handles (destroy it before them) and
+ *   owns its own stream (default priority) and work buffers, allocated on the first
+ *   solve: per lattice (2m + 5) FP64 and 3 FP32 batched parity vectors.
+ *   hip_stream: the caller's stream; a solve starts after the work enqueued on it.
+ * ddq_batch_solve: x[l], b[l] complex128 full vectors [nrhs[l]][t][z][y][x][4][3]
+ *   on the device (x in: initial guess, out: solution; b not modified).  params as
+ *   for ddq_oe_gmres_solve (m <= 127, inner_prec must be DDQ_F32); omegas[l] (or
+ *   NULL: params->omega for all) the Richardson weight of lattice l.  info (may be
+ *   NULL) receives one record per system in (lattice, right-hand side) order; the
+ *   counts are those of the lock-step run.  Synchronises; returns DDQ_OK when
+ *   every system met |b~_e - D_S x_e| <= tol |b|, DDQ_NOT_CONVERGED otherwise.
+ *   Graphs are captured on the first solve and again when m, nu, an omega or a
+ *   lattice's buffers change.  One thread at a time per batch; a lattice in a
+ *   batch must not be used by other calls while a batch solve runs. */
+typedef struct ddq_batch ddq_batch;
+
+int ddq_batch_create(ddq_lattice* const* lats, const int* nrhs, int nlat, void* hip_stream, ddq_batch** out);
+int ddq_batch_solve(ddq_batch* batch, void* const* x, const void* const* b, const ddq_gmres_params* params,
+                    const double* omegas, ddq_solve_info* info);
+int ddq_batch_destroy(ddq_batch* batch);
+
 /* Backward pass of y_e = D_S(U) x_e (pattern: differentiation).
  * ddq_backward_apply: grad_x_e = D_S^H grad_y_e = g5 D_S g5 grad_y_e (the adjoint
  *   apply; the same as ddq_apply_schur with dagger = 1).

@@ -62,6 +62,10 @@ _SIGNATURES = {
     "ddq_oe_prepare": [_P, C.c_int, _P, _P],
     "ddq_oe_reconstruct": [_P, C.c_int, _P, _P, _P],
     "ddq_oe_gmres_solve": [_P, _P, _P, C.POINTER(GmresParams), C.POINTER(SolveInfo)],
+    "ddq_batch_create": [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, _P, C.POINTER(_P)],
+    "ddq_batch_solve": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(GmresParams), C.POINTER(C.c_double),
+                        C.POINTER(SolveInfo)],
+    "ddq_batch_destroy": [_P],
     "ddq_backward_apply": [_P, C.c_int, C.c_int, _P, _P],
     "ddq_backward_link_force": [_P, _P, _P, _P, _P, C.c_int],
     "ddq_stream_copy": [_P, _P, C.c_int64, _P],

@@ -24,6 +24,7 @@ __all__ = [
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
     "stream_copy", "backward_apply", "backward_link_force", "convert_parity",
+    "Batch", "batch_create", "batch_solve", "batch_destroy",
     "DDQ_F64", "DDQ_F32",
 ]
 
@@ -71,9 +72,10 @@ class Lattice:
 
     def __del__(self):
         h = getattr(self, "handle", None)
-        if h is not None and _lib._lib is not None:
+        L = getattr(_lib, "_lib", None) if _lib is not None else None  # None at interpreter exit
+        if h is not None and L is not None:
             try:
-                _lib._lib.ddq_destroy_lattice(h)
+                L.ddq_destroy_lattice(h)
             except Exception:  # pragma: no cover
                 pass
             self.handle = None
@@ -255,6 +257,72 @@ def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: in
     st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
                "ddq_oe_gmres_solve", allow=(0, 1))
     return x, info.as_dict(), st == 0
+
+
+class Batch:
+    """Handle of a ddq_batch; keeps its lattices alive while it exists."""
+
+    def __init__(self, handle: C.c_void_p, lats, nrhs):
+        self.handle = handle
+        self.lats = list(lats)
+        self.nrhs = list(nrhs)
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        L = getattr(_lib, "_lib", None) if _lib is not None else None  # None at interpreter exit
+        if h is not None and L is not None:
+            try:
+                L.ddq_batch_destroy(h)
+            except Exception:  # pragma: no cover
+                pass
+            self.handle = None
+
+
+def batch_create(lats, nrhs) -> Batch:
+    """A batch of lattices (distinct handles) with nrhs[l] right-hand sides each."""
+    lats = list(lats)
+    nrhs = [int(n) for n in nrhs]
+    if len(lats) != len(nrhs):
+        raise ValueError("one nrhs per lattice")
+    dev = lats[0].device
+    arr = (C.c_void_p * len(lats))(*[l.handle for l in lats])
+    nr = (C.c_int * len(lats))(*nrhs)
+    h = C.c_void_p()
+    s = torch.cuda.current_stream(dev).cuda_stream
+    check(lib().ddq_batch_create(arr, nr, len(lats), C.c_void_p(s), C.byref(h)), "ddq_batch_create")
+    return Batch(h, lats, nrhs)
+
+
+def batch_destroy(batch: Batch) -> None:
+    if batch.handle is not None:
+        check(lib().ddq_batch_destroy(batch.handle), "ddq_batch_destroy")
+        batch.handle = None
+
+
+def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, tol: float = 1e-10,
+                smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0):
+    """Solve every (lattice, right-hand side) system of the batch.  bs[l]: complex128
+    [nrhs[l], Lt, Lz, Ly, Lx, 4, 3]; omega: one weight or one per lattice.
+    Returns (xs, infos, converged) with infos in (lattice, right-hand side) order."""
+    if len(bs) != len(batch.lats):
+        raise ValueError("one right-hand-side tensor per lattice")
+    xs = []
+    for l, (lat, n, b) in enumerate(zip(batch.lats, batch.nrhs, bs)):
+        want = (n,) + lat.full_shape
+        if b.dtype != torch.complex128 or tuple(b.shape) != want:
+            raise ValueError(f"b[{l}] must be complex128 of shape {want}")
+        xs.append(torch.zeros_like(b) if x0s is None else x0s[l].clone())
+    om = [float(omega)] * len(bs) if isinstance(omega, (int, float)) else [float(w) for w in omega]
+    if len(om) != len(bs):
+        raise ValueError("one omega per lattice")
+    xp = (C.c_void_p * len(bs))(*[_dev(x, "x").value for x in xs])
+    bp = (C.c_void_p * len(bs))(*[_dev(b, "b").value for b in bs])
+    op = (C.c_double * len(bs))(*om)
+    p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F32, int(smoother_sweeps), om[0],
+                    float(inner_reduction))
+    infos = (SolveInfo * sum(batch.nrhs))()
+    st = check(lib().ddq_batch_solve(batch.handle, xp, bp, C.byref(p), op, infos), "ddq_batch_solve", allow=(0, 1))
+    return xs, [i.as_dict() for i in infos], st == 0
 
 
 def profile_begin(lat: Lattice) -> None:

@@ -237,6 +237,169 @@ hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStr
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// batched forms: nrhs independent systems, vector r at offset r * n, basis vector
+// j of system r at V + j * vstride + r * n
+// ---------------------------------------------------------------------------
+
+// partial[(r * k + j) * nbx + bx] = sum over a workgroup's elements of conj(V_j[r]) w[r]
+__global__ void __launch_bounds__(RB) k_dot_partial_b(const d2_t* __restrict__ V, long long vstride, int k,
+                                                      const d2_t* __restrict__ w, long long n,
+                                                      d2_t* __restrict__ partial) {
+  __shared__ double lds[4 * 2 * DOT_J];
+  const int r = blockIdx.z;
+  const int j0 = blockIdx.y * DOT_J;
+  const int nj = min(DOT_J, k - j0);
+  const d2_t* Vr = V + (size_t)r * n;
+  const d2_t* wr = w + (size_t)r * n;
+  double acc[2 * DOT_J];
+#pragma unroll
+  for (int q = 0; q < 2 * DOT_J; ++q) acc[q] = 0.0;
+  const long long stride = (long long)gridDim.x * RB;
+  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    d2_t we = wr[e];
+#pragma unroll
+    for (int jj = 0; jj < DOT_J; ++jj) {
+      if (jj < nj) {
+        d2_t v = Vr[(size_t)(j0 + jj) * vstride + e];
+        acc[2 * jj] = fma(v.x, we.x, fma(v.y, we.y, acc[2 * jj]));
+        acc[2 * jj + 1] = fma(v.x, we.y, fma(-v.y, we.x, acc[2 * jj + 1]));
+      }
+    }
+  }
+  block_sum<2 * DOT_J>(acc, lds);
+  if (threadIdx.x == 0) {
+    for (int jj = 0; jj < nj; ++jj) {
+      d2_t o;
+      o.x = acc[2 * jj];
+      o.y = acc[2 * jj + 1];
+      partial[((size_t)r * k + j0 + jj) * gridDim.x + blockIdx.x] = o;
+    }
+  }
+}
+
+// out[r * ldo + j] = sum_b partial[(r * k + j) * nbx + b]
+__global__ void __launch_bounds__(RB) k_reduce_partial_b(const d2_t* __restrict__ partial, int nbx, int k, int ldo,
+                                                         d2_t* __restrict__ out) {
+  __shared__ double lds[4 * 2];
+  const int j = blockIdx.x, r = blockIdx.y;
+  double v[2] = {0.0, 0.0};
+  const d2_t* p = partial + ((size_t)r * k + j) * nbx;
+  for (int b = threadIdx.x; b < nbx; b += RB) {
+    d2_t q = p[b];
+    v[0] += q.x;
+    v[1] += q.y;
+  }
+  block_sum<2>(v, lds);
+  if (threadIdx.x == 0) {
+    d2_t o;
+    o.x = v[0];
+    o.y = v[1];
+    out[(size_t)r * ldo + j] = o;
+  }
+}
+
+hipError_t launch_dot_b(const d2_t* V, long long vstride, int k, const d2_t* w, long long n, int nrhs, d2_t* partial,
+                        int nbx, d2_t* out, int ldo, hipStream_t s) {
+  if (k < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_dot_partial_b, dim3(nbx, (k + DOT_J - 1) / DOT_J, nrhs), dim3(RB), 0, s, V, vstride, k, w, n,
+                     partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_partial_b, dim3(k, nrhs), dim3(RB), 0, s, partial, nbx, k, ldo, out);
+  return hipGetLastError();
+}
+
+// w[r] += sign * sum_{j < k} V_j[r] h[r * ldh + j]
+__global__ void __launch_bounds__(RB) k_update_b(d2_t* __restrict__ w, const d2_t* __restrict__ V, long long vstride,
+                                                 int k, const d2_t* __restrict__ h, int ldh, double sign, long long n) {
+  __shared__ d2_t hs[256];
+  const int r = blockIdx.y;
+  for (int j = threadIdx.x; j < k; j += RB) hs[j] = h[(size_t)r * ldh + j];
+  __syncthreads();
+  const d2_t* Vr = V + (size_t)r * n;
+  d2_t* wr = w + (size_t)r * n;
+  const long long stride = (long long)gridDim.x * RB;
+  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    double ar = 0.0, ai = 0.0;
+    for (int j = 0; j < k; ++j) {
+      d2_t v = Vr[(size_t)j * vstride + e];
+      d2_t hj = hs[j];
+      ar = fma(v.x, hj.x, fma(-v.y, hj.y, ar));
+      ai = fma(v.x, hj.y, fma(v.y, hj.x, ai));
+    }
+    d2_t we = wr[e];
+    we.x = fma(sign, ar, we.x);
+    we.y = fma(sign, ai, we.y);
+    wr[e] = we;
+  }
+}
+
+hipError_t launch_update_b(d2_t* w, const d2_t* V, long long vstride, int k, const d2_t* h, int ldh, double sign,
+                           long long n, int nrhs, hipStream_t s) {
+  if (k < 1) return hipSuccess;
+  if (k > 256) return hipErrorInvalidValue;
+  long long b = (n + RB - 1) / RB;
+  const int nb = (int)(b > 2048 ? 2048 : b);
+  hipLaunchKernelGGL(k_update_b, dim3(nb, nrhs), dim3(RB), 0, s, w, V, vstride, k, h, ldh, sign, n);
+  return hipGetLastError();
+}
+
+// out[r] = |w[r]|^2
+__global__ void __launch_bounds__(RB) k_norm2_partial_b(const d2_t* __restrict__ w, long long n,
+                                                        double* __restrict__ partial) {
+  __shared__ double lds[4];
+  const int r = blockIdx.y;
+  const d2_t* wr = w + (size_t)r * n;
+  double v[1] = {0.0};
+  const long long stride = (long long)gridDim.x * RB;
+  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    d2_t a = wr[e];
+    v[0] = fma(a.x, a.x, fma(a.y, a.y, v[0]));
+  }
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) partial[(size_t)r * gridDim.x + blockIdx.x] = v[0];
+}
+
+__global__ void __launch_bounds__(RB) k_reduce_real_b(const double* __restrict__ partial, int nbx,
+                                                      double* __restrict__ out) {
+  __shared__ double lds[4];
+  const int r = blockIdx.x;
+  double v[1] = {0.0};
+  for (int b = threadIdx.x; b < nbx; b += RB) v[0] += partial[(size_t)r * nbx + b];
+  block_sum<1>(v, lds);
+  if (threadIdx.x == 0) out[r] = v[0];
+}
+
+hipError_t launch_norm2_b(const d2_t* w, long long n, int nrhs, double* partial, int nbx, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_norm2_partial_b, dim3(nbx, nrhs), dim3(RB), 0, s, w, n, partial);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_reduce_real_b, dim3(nrhs), dim3(RB), 0, s, partial, nbx, out);
+  return hipGetLastError();
+}
+
+// out[r] = f[r] * in[r]  (f on the device)
+__global__ void k_scale_b(d2_t* __restrict__ out, const d2_t* __restrict__ in, const double* __restrict__ f,
+                          long long n) {
+  const int r = blockIdx.y;
+  const double a = f[r];
+  const long long stride = (long long)gridDim.x * RB;
+  for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
+    d2_t v = in[(size_t)r * n + e];
+    v.x *= a;
+    v.y *= a;
+    out[(size_t)r * n + e] = v;
+  }
+}
+
+hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long n, int nrhs, hipStream_t s) {
+  long long b = (n + RB - 1) / RB;
+  const int nb = (int)(b > 2048 ? 2048 : b);
+  hipLaunchKernelGGL(k_scale_b, dim3(nb, nrhs), dim3(RB), 0, s, out, in, f, n);
+  return hipGetLastError();
+}
+
 // STREAM-style copy with 16-byte accesses, one element per thread: the
 // attainable-bandwidth probe and the calibration kernel for the traffic counters
 __global__ void __launch_bounds__(RB) k_stream_copy(u4_t* __restrict__ dst, const u4_t* __restrict__ src,

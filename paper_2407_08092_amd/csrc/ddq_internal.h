@@ -69,6 +69,14 @@ hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStr
 
 hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s);
 
+// batched (nrhs systems, vector r at offset r * n; basis j at j * vstride)
+hipError_t launch_dot_b(const d2_t* V, long long vstride, int k, const d2_t* w, long long n, int nrhs, d2_t* partial,
+                        int nbx, d2_t* out, int ldo, hipStream_t s);
+hipError_t launch_update_b(d2_t* w, const d2_t* V, long long vstride, int k, const d2_t* h, int ldh, double sign,
+                           long long n, int nrhs, hipStream_t s);
+hipError_t launch_norm2_b(const d2_t* w, long long n, int nrhs, double* partial, int nbx, double* out, hipStream_t s);
+hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long n, int nrhs, hipStream_t s);
+
 // link force: insertions W (V x 54 complex) then per-link G (V x 4 x 9 complex) / F (V x 4 x 8)
 hipError_t launch_force(const Geo& g, const d2_t* U, const d2_t* chi_e, const d2_t* lam_o, const d2_t* phi_e,
                         const d2_t* psi_o, double c_sw, d2_t* W, d2_t* G, double* F, int accumulate,

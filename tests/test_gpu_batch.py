@@ -1,0 +1,139 @@
+"""Batched solves through the C ABI: several lattices of different extents with
+several right-hand sides each, all solved in lock-step by ddq_batch_solve.  Every
+(lattice, right-hand side) system is checked on its own against the FP64 oracle:
+its true residual |b - D x| / |b| computed by the oracle's D, and on the small
+lattices its solution against the oracle's own odd-even GMRES solve.
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Case, rel
+from oracle import solvers
+from paper_2407_08092_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+# uneven extents: 4^4, 4x6x8x10 (V/2 = 960: four workgroups with a ragged tail),
+# 6x6x6x10; eps 0.5, c_sw 1, m0 -0.2
+BATCH = [((4, 4, 4, 4), 3, 402), ((4, 6, 8, 10), 2, 403), ((6, 6, 6, 10), 1, 404)]
+_cache = {}
+
+
+def setup_batch():
+    if "cases" not in _cache:
+        cases, bs, omegas = [], [], []
+        for dims, n, seed in BATCH:
+            c = Case(dims, 0.5, 1.0, -0.2, seed)
+            lam = solvers.power_iteration(c.op.schur, c.vec(seed + 2000), 50)
+            cases.append(c)
+            omegas.append(0.8 / lam)
+            bs.append(np.stack([synth.gaussian_spinor(dims, seed + 1000 + r) for r in range(n)]))
+        _cache["cases"], _cache["bs"], _cache["omegas"] = cases, bs, omegas
+    return _cache["cases"], _cache["bs"], _cache["omegas"]
+
+
+def true_relres(c, x, b):
+    return solvers.vnorm(b - c.op.D(x)) / solvers.vnorm(b)
+
+
+def test_batch_uneven_lattices_converge():
+    cases, bs, omegas = setup_batch()
+    batch = api.batch_create([c.lat for c in cases], [b.shape[0] for b in bs])
+    xs, infos, ok = api.batch_solve(batch, [torch.from_numpy(b).cuda() for b in bs], m=30, max_cycles=40,
+                                    tol=1e-10, smoother_sweeps=4, omega=omegas)
+    assert ok, infos
+    k = 0
+    for c, b, x in zip(cases, bs, xs):
+        xh = x.cpu().numpy()
+        for r in range(b.shape[0]):
+            res = true_relres(c, xh[r], b[r])
+            assert res <= 1.5e-10, (c.dims, r, res)
+            assert infos[k]["true_relres"] <= 1e-10
+            k += 1
+    # the 4^4 systems against the oracle's own solve
+    c, b = cases[0], bs[0]
+    for r in range(b.shape[0]):
+        x_ref, info = solvers.oe_solve(c.op, b[r], 30, 100, 1e-10)
+        assert info.converged
+        assert rel(xs[0][r].cpu().numpy(), x_ref) < 1e-8
+
+
+def test_batch_replay_is_deterministic_and_recaptures():
+    cases, bs, omegas = setup_batch()
+    batch = api.batch_create([c.lat for c in cases[:2]], [bs[0].shape[0], bs[1].shape[0]])
+    bd = [torch.from_numpy(b).cuda() for b in bs[:2]]
+    x1, _, ok1 = api.batch_solve(batch, bd, m=20, tol=1e-10, smoother_sweeps=3, omega=omegas[:2])
+    x2, _, ok2 = api.batch_solve(batch, bd, m=20, tol=1e-10, smoother_sweeps=3, omega=omegas[:2])
+    assert ok1 and ok2
+    for a, b in zip(x1, x2):  # the same graphs replayed on the same inputs
+        assert torch.equal(a, b)
+    # a lattice's work buffer grows under another call: the graphs are captured again
+    c = cases[0]
+    api.apply_schur(c.lat, torch.zeros((7, 12, c.lat.Vh), dtype=torch.complex128, device="cuda"))
+    x3, _, ok3 = api.batch_solve(batch, bd, m=16, tol=1e-10, smoother_sweeps=2, omega=omegas[:2])
+    assert ok3
+    for cc, b, x in zip(cases[:2], bs[:2], x3):
+        xh = x.cpu().numpy()
+        for r in range(b.shape[0]):
+            assert true_relres(cc, xh[r], b[r]) <= 1.5e-10
+
+
+def test_batch_single_system_matches_single_solver():
+    cases, bs, omegas = setup_batch()
+    c, b = cases[1], bs[1][:1]
+    batch = api.batch_create([c.lat], [1])
+    xs, infos, ok = api.batch_solve(batch, [torch.from_numpy(b).cuda()], m=30, tol=1e-10, smoother_sweeps=4,
+                                    omega=omegas[1])
+    x1, info1, ok1 = api.oe_gmres_solve(c.lat, torch.from_numpy(b[0]).cuda(), m=30, tol=1e-10,
+                                        inner_prec=api.DDQ_F32, smoother_sweeps=4, omega=omegas[1])
+    assert ok and ok1
+    assert infos[0]["cycles"] == info1["cycles"]
+    assert abs(infos[0]["iters"] - info1["iters"]) <= 1
+    assert rel(xs[0][0].cpu().numpy(), x1.cpu().numpy()) < 1e-8
+
+
+def test_batch_initial_guess_and_zero_rhs():
+    cases, bs, omegas = setup_batch()
+    c, b = cases[0], bs[0].copy()
+    b[1] = 0.0  # a zero right-hand side is converged from the start (x = 0)
+    batch = api.batch_create([c.lat], [3])
+    x_ref = np.stack([solvers.oe_solve(c.op, b[r], 30, 100, 1e-12)[0] if r != 1 else np.zeros_like(b[r])
+                      for r in range(3)])
+    x0 = torch.from_numpy(x_ref + 1e-3 * synth.gaussian_complex(x_ref.shape, 77)).cuda()
+    x0[1] = 0
+    xs, infos, ok = api.batch_solve(batch, [torch.from_numpy(b).cuda()], x0s=[x0], m=30, tol=1e-10,
+                                    smoother_sweeps=4, omega=omegas[0])
+    assert ok
+    xh = xs[0].cpu().numpy()
+    assert np.all(xh[1] == 0)
+    for r in (0, 2):
+        assert true_relres(c, xh[r], b[r]) <= 1.5e-10
+
+
+def test_batch_not_converged_status():
+    cases, bs, omegas = setup_batch()
+    batch = api.batch_create([cases[0].lat], [2])
+    xs, infos, ok = api.batch_solve(batch, [torch.from_numpy(bs[0][:2]).cuda()], m=2, max_cycles=1, tol=1e-12,
+                                    smoother_sweeps=2, omega=omegas[0])
+    assert not ok
+    assert all(i["cycles"] == 1 and i["iters"] == 2 for i in infos)
+
+
+def test_batch_argument_errors():
+    cases, bs, omegas = setup_batch()
+    with pytest.raises(api.DDQError):
+        api.batch_create([cases[0].lat, cases[0].lat], [1, 1])  # a lattice twice
+    with pytest.raises(api.DDQError):
+        api.batch_create([cases[0].lat], [0])
+    batch = api.batch_create([cases[0].lat], [1])
+    b = torch.from_numpy(bs[0][:1]).cuda()
+    with pytest.raises(api.DDQError):
+        api.batch_solve(batch, [b], m=128, omega=omegas[0])
+    with pytest.raises(api.DDQError):
+        api.batch_solve(batch, [b], m=8, smoother_sweeps=2, omega=-1.0)
+    bad = b.clone()
+    bad[0, 0, 0, 0, 0, 0, 0] = float("nan")
+    with pytest.raises(api.DDQError) as e:
+        api.batch_solve(batch, [bad], m=8, omega=omegas[0])
+    assert e.value.status == -6

@@ -14,9 +14,15 @@ the timed region.  Reported:
   mixed_vs_fp64  time to |b - D x| / |b| <= 1e-10 on 16^3 x 32 (eps 0.5, c_sw 1.0,
                  m0 -0.2, Gaussian b) for FP64 GMRES(50) and for the same solver
                  with the operator and Richardson preconditioner in FP32
+  multi_rhs      24^3 x 48 with 12 right-hand sides: FP32 Schur apply GB/s with the
+                 autotuned register-blocked tile vs a loop of single applies
+  batched        12 right-hand sides on 24^3 x 48 plus 8^4, 12^4, 16^3 x 32 with 4
+                 each (eps 0.5, c_sw 1.0, m0 -0.2): all 24 systems to 1e-10 in one
+                 lock-step batched solve (FP32 inner, FP64 outer) vs the same
+                 systems solved one by one, mixed and plain FP64
   cpu_baseline   the FP64 NumPy oracle on the host, on a bounded sample
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-cpu]
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-batch] [--no-cpu]
 """
 from __future__ import annotations
 
@@ -34,14 +40,18 @@ METRIC = "Schur apply GB/s (% HBM peak) + smoother sweeps/s, mixed vs FP64 at 1e
 HBM_PEAK_GBS = 8000.0
 LARGE = dict(dims=(48, 48, 48, 96), eps=0.5, c_sw=1.2, m0=-0.25, seed_gauge=301, seed_vec=302)
 MIXED = dict(dims=(16, 16, 16, 32), eps=0.5, c_sw=1.0, m0=-0.2, seed_gauge=201, seed_vec=202)
+# (dims, right-hand sides, gauge seed); right-hand side r of a lattice uses seed + 1000 + r
+BATCH = [((24, 24, 24, 48), 12, 401), ((8, 8, 8, 8), 4, 402), ((12, 12, 12, 12), 4, 403), ((16, 16, 16, 32), 4, 404)]
 SWEEPS = 20
 BYTES_APPLY_F32 = 2208    # per even site, FP32 links/spinors/clover, every field once per kernel
 BYTES_APPLY_F64 = 4416
 BYTES_APPLY_F32_L12 = 1824  # 12-real FP32 links
+BYTES_APPLY_H16 = 944       # 16-bit spinors, 12-real links, clover padded to 40 slots
 
 
 MODE_CODE = {"clinv": 0, "recon": 1, "apply": 2, "richardson": 3, "resid": 4, "prep": 5}
-KERNEL_SOURCES = ("paper_2407_08092_amd/csrc/hop.hip", "paper_2407_08092_amd/csrc/ddq_device.h",
+KERNEL_SOURCES = ("paper_2407_08092_amd/csrc/hop.hip", "paper_2407_08092_amd/csrc/hop_common.h",
+                  "paper_2407_08092_amd/csrc/ddq_device.h",
                   "paper_2407_08092_amd/csrc/ddq_internal.h")
 PROFILE = "profiles/hop_kernels_48x96.md"
 
@@ -111,6 +121,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-solve", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -214,6 +225,46 @@ def main():
               "bytes_per_even_site": BYTES_APPLY_F32_L12, "sweeps_per_s": round(SWEEPS / (s12 * 1e-3), 1)}
     log(f"FP32 12-real links: apply {t12:.3f} ms, {link12['sweeps_per_s']} sweeps/s")
 
+    # 16-bit storage (FP16, BF16) with FP32 arithmetic
+    U = synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev)
+    api.set_gauge(lat, U, store=(api.DDQ_F64, api.DDQ_F32, api.DDQ_F16, api.DDQ_BF16), link12=True)
+    del U
+    torch.cuda.empty_cache()
+    api.set_clover(lat, cfg["c_sw"], cfg["m0"])
+    h16 = {}
+    for label, dt in (("fp16", torch.float16), ("bf16", torch.bfloat16)):
+        x16 = api.convert_parity(lat, x64, dt)
+        b16 = api.convert_parity(lat, b64, dt)
+        y16, xs16 = torch.empty_like(x16), torch.empty_like(x16)
+
+        def step16(ev=None):
+            if ev is not None:
+                ev[0].record(stream)
+            api.apply_schur(lat, x16, y16)
+            if ev is not None:
+                ev[1].record(stream)
+            xs16.zero_()
+            api.richardson_smooth(lat, xs16, b16, SWEEPS, omega)
+            if ev is not None:
+                ev[2].record(stream)
+
+        for _ in range(max(1, args.warmup)):
+            step16()
+        torch.cuda.synchronize()
+        ev16 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+        for k in range(args.steps):
+            step16(ev16[k])
+        torch.cuda.synchronize()
+        ta = sum(e[0].elapsed_time(e[1]) for e in ev16) / args.steps
+        tsw = sum(e[1].elapsed_time(e[2]) for e in ev16) / args.steps
+        ref = api.convert_parity(lat, y32, torch.complex128)
+        got = api.convert_parity(lat, y16, torch.complex128)
+        h16[label] = {"apply_ms": round(ta, 4), "apply_GBs": round(BYTES_APPLY_H16 * vh / (ta * 1e-3) / 1e9, 1),
+                      "bytes_per_even_site": BYTES_APPLY_H16, "sweeps_per_s": round(SWEEPS / (tsw * 1e-3), 1),
+                      "rel_diff_vs_fp32_apply": float((got - ref).norm() / ref.norm())}
+        log(f"{label} storage: apply {ta:.3f} ms, {h16[label]['sweeps_per_s']} sweeps/s")
+        del x16, b16, y16, xs16, ref, got
+
     # FP64 apply and sweeps on the same lattice (context)
     y64 = torch.empty_like(x64)
     for _ in range(2):
@@ -243,6 +294,9 @@ def main():
     mixed = None
     if not args.no_solve:
         mixed = mixed_vs_fp64(api, synth, torch, dev)
+    multi, batch = None, None
+    if not args.no_batch:
+        multi, batch = batched(api, synth, torch, dev)
 
     out = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -257,8 +311,11 @@ def main():
         "schur_apply_ms": round(t_apply, 4),
         "sweeps_per_s": round(sweeps_per_s, 1),
         "fp32_link12": link12,
+        "storage_16bit": h16,
         "fp64": fp64,
         "mixed_vs_fp64": mixed,
+        "multi_rhs": multi,
+        "batched": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -289,7 +346,8 @@ def mixed_vs_fp64(api, synth, torch, dev):
     cfg = MIXED
     dims = cfg["dims"]
     lat = api.create_lattice(dims, device=dev)
-    api.set_gauge(lat, synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev))
+    api.set_gauge(lat, synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev),
+                  store=(api.DDQ_F64, api.DDQ_F32, api.DDQ_F16, api.DDQ_BF16))
     api.set_clover(lat, cfg["c_sw"], cfg["m0"])
     b = torch.from_numpy(synth.gaussian_spinor(dims, cfg["seed_vec"])).to(dev)
     v0 = torch.from_numpy(synth.gaussian_complex((12, lat.Vh), cfg["seed_vec"] + 1)).to(dev)
@@ -300,6 +358,9 @@ def mixed_vs_fp64(api, synth, torch, dev):
         "fp64_gmres50_rich4": dict(inner_prec=api.DDQ_F64, smoother_sweeps=4),
         "mixed_gmres50": dict(inner_prec=api.DDQ_F32, smoother_sweeps=0),
         "mixed_gmres50_rich4": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4),
+        "mixed_gmres50_rich4_fp16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4, smoother_prec=api.DDQ_F16),
+        "mixed_gmres50_rich4_bf16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4, smoother_prec=api.DDQ_BF16),
+        "mixed_gmres50_rich8_fp16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=8, smoother_prec=api.DDQ_F16),
     }
     for name, kw in variants.items():
         best = None
@@ -320,6 +381,90 @@ def mixed_vs_fp64(api, synth, torch, dev):
     return {"workload": "16^3x32, eps 0.5, c_sw 1.0, m0 -0.2, Gaussian b, tol 1e-10 (|b~_e - D_S x_e| / |b|)",
             "runs": runs, "fp64_best_s": fp64_best, "mixed_best_s": mixed_best,
             "speedup": round(fp64_best / mixed_best, 3)}
+
+
+def batched(api, synth, torch, dev):
+    """Multi-right-hand-side apply and the batched solve of uneven lattices."""
+    lats, bs, oms = [], [], []
+    for dims, n, seed in BATCH:
+        lat = api.create_lattice(dims, device=dev)
+        api.set_gauge(lat, synth.gauge_field(dims, 0.5, seed, device=dev))
+        api.set_clover(lat, 1.0, -0.2)
+        v0 = torch.from_numpy(synth.gaussian_complex((12, lat.Vh), seed + 2000)).to(dev)
+        oms.append(0.8 / api.estimate_lambda_max(lat, 50, v0))
+        bs.append(torch.stack([torch.from_numpy(synth.gaussian_spinor(dims, seed + 1000 + r)) for r in range(n)]).to(dev))
+        lats.append(lat)
+
+    # 12-right-hand-side FP32 apply on 24^3 x 48
+    lat, n = lats[0], BATCH[0][1]
+    vh = lat.Vh
+    best, cands = api.tune_multi_rhs(lat, n, reps=10)
+    x = api.convert_parity(lat, torch.from_numpy(synth.gaussian_complex((n, 12, vh), 405)).to(dev), torch.complex64)
+    y = torch.empty_like(x)
+
+    def timed(fn, reps=20):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_multi = timed(lambda: api.apply_schur(lat, x, y))
+    x1, y1 = x[0].contiguous(), torch.empty_like(x[0])
+    t_one = timed(lambda: api.apply_schur(lat, x1, y1))
+    bytes_multi = (12 * 5 * n + 144 + 72) * 8 * vh  # 5 spinor passes per rhs; links and clover twice
+    multi = {"workload": "24^3x48, 12 right-hand sides, FP32 Schur apply", "tile": best,
+             "candidates": [(c["nb"], c["waves"], c["xcd_map"], round(c["ms"], 4)) for c in cands],
+             "apply_ms": round(t_multi, 4), "apply_GBs": round(bytes_multi / (t_multi * 1e-3) / 1e9, 1),
+             "bytes_per_apply": bytes_multi, "single_apply_ms": round(t_one, 4),
+             "speedup_vs_single_loop": round(n * t_one / t_multi, 3)}
+    log(f"multi-rhs: {multi['apply_ms']} ms = {multi['apply_GBs']} GB/s, x{multi['speedup_vs_single_loop']} "
+        f"vs {n} single applies, tile {best}")
+    del x, y, x1, y1
+
+    # all 24 systems: one batched solve vs one by one
+    kw = dict(m=50, tol=1e-10, smoother_sweeps=4)
+    batch = api.batch_create(lats, [b.shape[0] for b in bs])
+    t_batch = None
+    for _ in range(2):  # the first call tunes, sizes and captures
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xs, infos, ok = api.batch_solve(batch, bs, omega=oms, **kw)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_batch = dt if t_batch is None else min(t_batch, dt)
+    seq = {}
+    for name, inner, nu in (("mixed", api.DDQ_F32, 4), ("fp64", api.DDQ_F64, 4), ("fp64_plain", api.DDQ_F64, 0)):
+        for lat, b, om in zip(lats, bs, oms):  # warm-up: size every basis
+            api.oe_gmres_solve(lat, b[0].contiguous(), m=50, tol=1e-10, inner_prec=inner, smoother_sweeps=nu, omega=om)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        worst, conv = 0.0, True
+        for lat, b, om in zip(lats, bs, oms):
+            for r in range(b.shape[0]):
+                _, info, okr = api.oe_gmres_solve(lat, b[r].contiguous(), m=50, tol=1e-10, inner_prec=inner,
+                                                  smoother_sweeps=nu, omega=om)
+                worst, conv = max(worst, info["true_relres"]), conv and okr
+        torch.cuda.synchronize()
+        seq[name] = {"time_s": round(time.perf_counter() - t0, 4), "converged": conv, "max_relres": worst}
+    out = {"workload": "24^3x48 x 12 rhs + 8^4, 12^4, 16^3x32 x 4 rhs; eps 0.5, c_sw 1.0, m0 -0.2; GMRES(50), "
+                       "4 Richardson sweeps as preconditioner; tol 1e-10",
+           "systems": len(infos), "batched_s": round(t_batch, 4), "converged": bool(ok),
+           "max_relres": max(i["true_relres"] for i in infos), "cycles": infos[0]["cycles"],
+           "iters": infos[0]["iters"], "sequential": seq,
+           "speedup_vs_sequential_mixed": round(seq["mixed"]["time_s"] / t_batch, 3),
+           "speedup_vs_sequential_fp64": round(min(seq["fp64"]["time_s"], seq["fp64_plain"]["time_s"]) / t_batch, 3)}
+    log(f"batched: {out}")
+    api.batch_destroy(batch)
+    for lat in lats:
+        api.destroy_lattice(lat)
+    torch.cuda.empty_cache()
+    return multi, out
 
 
 if __name__ == "__main__":

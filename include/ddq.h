@@ -60,8 +60,14 @@ typedef struct ddq_lattice ddq_lattice;
 
 /* Arithmetic of a call.  DDQ_F64: complex128 vectors, FP64 links and clover.
  * DDQ_F32: complex64 vectors, FP32 links and clover (blocks inverted in FP64,
- * then rounded). */
-enum ddq_prec { DDQ_F64 = 0, DDQ_F32 = 1 };
+ * then rounded).  DDQ_F16 / DDQ_BF16: 16-bit storage of vectors, links (12-real)
+ * and clover blocks (rounded from FP64) with FP32 arithmetic: the lower-precision
+ * storage the paper leaves to future work (Sect. 6).  16-bit parity vectors are
+ * [rhs][sc/4][i][sc%4] complex pairs of 16-bit values (four complex numbers per
+ * 16-byte element); FP16's range (normal numbers 6.1e-5 .. 65504) is the
+ * caller's to respect.  The 16-bit path applies D_S and runs the Richardson
+ * smoother (not daggered) and serves as the GMRES preconditioner's storage. */
+enum ddq_prec { DDQ_F64 = 0, DDQ_F32 = 1, DDQ_F16 = 2, DDQ_BF16 = 3 };
 
 enum ddq_status {
   DDQ_OK = 0,
@@ -78,8 +84,9 @@ enum ddq_status {
  * links are always kept (the outer residual of the solver uses them).
  * DDQ_STORE_F32_LINK12 stores the FP32 links as their first two rows only and
  * rebuilds the third from SU(3) unitarity (row 2 = conj(row 0 x row 1)) inside
- * the kernels: one third fewer link bytes. */
-enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2, DDQ_STORE_F32_LINK12 = 4 };
+ * the kernels: one third fewer link bytes.  DDQ_STORE_F16 / DDQ_STORE_BF16 add
+ * 16-bit 12-real links (and, at ddq_set_clover, 16-bit clover blocks). */
+enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2, DDQ_STORE_F32_LINK12 = 4, DDQ_STORE_F16 = 8, DDQ_STORE_BF16 = 16 };
 
 /* Lattice of extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2, with
  * V = Lx*Ly*Lz*Lt < 2^31.  t_antiperiodic != 0 selects antiperiodic t.
@@ -129,6 +136,38 @@ int ddq_apply_schur(ddq_lattice* lat, int prec, int nrhs, const void* x_e, void*
 int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const void* b_e,
                           int nsweeps, double omega);
 
+/* Tiles of the FP32 multi-right-hand-side stencil (nrhs >= 2 in ddq_apply_schur
+ * and ddq_richardson_smooth, not daggered).  The operator is that of Sect. 2.4.5
+ * applied to nrhs vectors that share the links and clover blocks; the paper applies
+ * one vector at a time and names several right-hand sides as a way to make the
+ * block applications cache-friendly (Sect. 5); the tiling is this library's.
+ *   nb       right-hand sides per thread (links and clover slots loaded once for
+ *            nb spinors); 1..4 and dividing nrhs.  0: one right-hand side per
+ *            thread, 64 sites x 4 right-hand sides per workgroup (the default).
+ *   waves    1: a workgroup covers 256 sites; 4: its four wavefronts take four
+ *            consecutive right-hand-side groups of the same 64 sites
+ *   xcd_map  nonzero: every right-hand-side group of a site block is placed on
+ *            the same XCD (shares its L2)
+ *   ms       (tuner output) mean time of one Richardson sweep with this tile
+ * ddq_set_multi_rhs_tile: use `tile` for launches with nrhs right-hand sides.
+ * ddq_tune_multi_rhs: the autotuner.  Times one FP32 Richardson sweep (kernel A +
+ *   kernel B) for every valid tile, `reps` times each (HIP events on the lattice's
+ *   stream, zeroed work vectors), keeps the fastest for nrhs, and reports up to
+ *   max_results timed candidates (n_results receives their count) and the choice.
+ *   Allocates two FP32 work vectors of nrhs right-hand sides on first use;
+ *   synchronises the stream.  A batch solve tunes every (lattice, nrhs) it meets
+ *   untuned. */
+typedef struct {
+  int nb;
+  int waves;
+  int xcd_map;
+  double ms;
+} ddq_mr_tile;
+
+int ddq_set_multi_rhs_tile(ddq_lattice* lat, int nrhs, const ddq_mr_tile* tile);
+int ddq_tune_multi_rhs(ddq_lattice* lat, int nrhs, int reps, ddq_mr_tile* results, int max_results,
+                       int* n_results, ddq_mr_tile* chosen);
+
 /* |lambda_max(D_S)| by power iteration in FP64 (Sect. 2.4.4):
  * out = (|D_S^iters v0| / |v0|)^(1/iters).  v0: FP64 parity vector (device,
  * not modified).  Synchronises the stream. */
@@ -153,6 +192,12 @@ int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* 
  *   omega        Richardson weight of the preconditioner
  *   inner_reduction  a cycle ends once its residual estimate has fallen by
  *                this factor (0 = automatic: 0 for FP64, 1e-5 for FP32)
+ *   smoother_prec  DDQ_F16 / DDQ_BF16: the preconditioner's Richardson sweeps
+ *                run on 16-bit storage (inner_prec must be DDQ_F32, the lattice
+ *                must hold 16-bit links: DDQ_STORE_F16 / DDQ_STORE_BF16); the
+ *                basis vector is scaled by sqrt(12 V/2) on the way in and back on
+ *                the way out (the sweeps are linear); any other value: the
+ *                sweeps run in inner_prec
  * x: full vector, in the initial guess, out the solution; b: full vector;
  * both complex128.  info (may be NULL) receives counts and the final residual
  * (FP64, recomputed).  Synchronises the stream. */
@@ -164,6 +209,7 @@ typedef struct {
   int smoother_sweeps;
   double omega;
   double inner_reduction;
+  int smoother_prec;
 } ddq_gmres_params;
 
 typedef struct {

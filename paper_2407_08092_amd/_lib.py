@@ -12,8 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 # DDQ_LIBRARY selects an alternative build of the same library (tuning runs)
 LIB_PATH = os.environ.get("DDQ_LIBRARY") or os.path.join(PKG, "libddq.so")
 
-DDQ_F64, DDQ_F32 = 0, 1
-DDQ_STORE_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12 = 1, 2, 4
+DDQ_F64, DDQ_F32, DDQ_F16, DDQ_BF16 = 0, 1, 2, 3
+DDQ_STORE_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12, DDQ_STORE_F16, DDQ_STORE_BF16 = 1, 2, 4, 8, 16
 STATUS = {
     0: "DDQ_OK", 1: "DDQ_NOT_CONVERGED", -1: "DDQ_ERR_ARG", -2: "DDQ_ERR_STATE", -3: "DDQ_ERR_HIP",
     -4: "DDQ_ERR_OOM", -5: "DDQ_ERR_NOT_PD", -6: "DDQ_ERR_NONFINITE",
@@ -28,12 +28,20 @@ class DDQError(RuntimeError):
 
 class GmresParams(C.Structure):
     _fields_ = [("m", C.c_int), ("max_cycles", C.c_int), ("tol", C.c_double), ("inner_prec", C.c_int),
-                ("smoother_sweeps", C.c_int), ("omega", C.c_double), ("inner_reduction", C.c_double)]
+                ("smoother_sweeps", C.c_int), ("omega", C.c_double), ("inner_reduction", C.c_double),
+                ("smoother_prec", C.c_int)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("cycles", C.c_int), ("iters", C.c_int), ("applies_f64", C.c_int), ("applies_lo", C.c_int),
                 ("true_relres", C.c_double), ("t_total_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class MrTile(C.Structure):
+    _fields_ = [("nb", C.c_int), ("waves", C.c_int), ("xcd_map", C.c_int), ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -59,6 +67,8 @@ _SIGNATURES = {
     "ddq_apply_schur": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_richardson_smooth": [_P, C.c_int, C.c_int, _P, _P, C.c_int, C.c_double],
     "ddq_estimate_lambda_max": [_P, C.c_int, _P, C.POINTER(C.c_double)],
+    "ddq_set_multi_rhs_tile": [_P, C.c_int, C.POINTER(MrTile)],
+    "ddq_tune_multi_rhs": [_P, C.c_int, C.c_int, C.POINTER(MrTile), C.c_int, C.POINTER(C.c_int), C.POINTER(MrTile)],
     "ddq_oe_prepare": [_P, C.c_int, _P, _P],
     "ddq_oe_reconstruct": [_P, C.c_int, _P, _P, _P],
     "ddq_oe_gmres_solve": [_P, _P, _P, C.POINTER(GmresParams), C.POINTER(SolveInfo)],

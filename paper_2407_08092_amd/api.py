@@ -6,8 +6,11 @@ Tensor layouts (see include/ddq.h):
   gauge links   complex128 [Lt, Lz, Ly, Lx, 4, 3, 3]
   full vector   complex128 / complex64 [Lt, Lz, Ly, Lx, 4, 3]   (or [nrhs, ...])
   parity vector complex128 [12, V/2] (or [nrhs, 12, V/2]);
-                complex64 [6, V/2, 2] (or [nrhs, 6, V/2, 2]): rows 2k, 2k+1 paired per site
-The arithmetic of a call follows the dtype: complex128 -> FP64, complex64 -> FP32.
+                complex64 [6, V/2, 2] (or [nrhs, 6, V/2, 2]): rows 2k, 2k+1 paired per site;
+                float16 / bfloat16 [3, V/2, 4, 2] (or [nrhs, ...]): rows 4k..4k+3 per
+                site, (re, im) in the last axis (16-bit storage, FP32 arithmetic)
+The arithmetic of a call follows the dtype: complex128 -> FP64, complex64 -> FP32,
+float16 / bfloat16 -> 16-bit storage with FP32 arithmetic.
 """
 from __future__ import annotations
 
@@ -16,25 +19,27 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import (DDQ_F32, DDQ_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12, DDQ_STORE_F64, DDQError, GmresParams,
-                   SolveInfo, check, lib)
+from ._lib import (DDQ_BF16, DDQ_F16, DDQ_F32, DDQ_F64, DDQ_STORE_BF16, DDQ_STORE_F16, DDQ_STORE_F32,
+                   DDQ_STORE_F32_LINK12, DDQ_STORE_F64, DDQError, GmresParams, SolveInfo, check, lib)
 
 __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
     "stream_copy", "backward_apply", "backward_link_force", "convert_parity",
-    "Batch", "batch_create", "batch_solve", "batch_destroy",
-    "DDQ_F64", "DDQ_F32",
+    "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
+    "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
 
 
+_PREC_OF = {torch.complex128: DDQ_F64, torch.complex64: DDQ_F32, torch.float16: DDQ_F16, torch.bfloat16: DDQ_BF16}
+_DTYPE_OF = {v: k for k, v in _PREC_OF.items()}
+
+
 def _prec(t: torch.Tensor) -> int:
-    if t.dtype == torch.complex128:
-        return DDQ_F64
-    if t.dtype == torch.complex64:
-        return DDQ_F32
-    raise TypeError(f"expected complex128 or complex64, got {t.dtype}")
+    if t.dtype not in _PREC_OF:
+        raise TypeError(f"expected complex128, complex64, float16 or bfloat16, got {t.dtype}")
+    return _PREC_OF[t.dtype]
 
 
 def _dev(t: torch.Tensor, name: str) -> C.c_void_p:
@@ -102,12 +107,14 @@ def destroy_lattice(lat: Lattice) -> None:
 
 
 def set_gauge(lat: Lattice, U: torch.Tensor, store=(DDQ_F64, DDQ_F32), link12: bool = False) -> None:
-    """Links U (complex128, canonical).  link12: keep the FP32 links as two rows
-    (third rebuilt from unitarity in the kernels)."""
+    """Links U (complex128, canonical).  store: the precisions to keep (DDQ_F64 always,
+    DDQ_F32, DDQ_F16, DDQ_BF16).  link12: keep the FP32 links as two rows (third
+    rebuilt from unitarity in the kernels); 16-bit links are always 12-real."""
     if U.dtype != torch.complex128 or tuple(U.shape) != lat.full_shape[:4] + (4, 3, 3):
         raise ValueError(f"U must be complex128 of shape {lat.full_shape[:4] + (4, 3, 3)}")
     U = U.contiguous()
     flags = (DDQ_STORE_F64 if DDQ_F64 in store else 0) | (DDQ_STORE_F32 if DDQ_F32 in store else 0)
+    flags |= (DDQ_STORE_F16 if DDQ_F16 in store else 0) | (DDQ_STORE_BF16 if DDQ_BF16 in store else 0)
     if link12:
         flags |= DDQ_STORE_F32_LINK12
     lat.sync_stream()
@@ -131,7 +138,11 @@ def get_clover(lat: Lattice):
 
 
 def _parity_shape(lat, dtype):
-    return (12, lat.Vh) if dtype == torch.complex128 else (6, lat.Vh, 2)
+    if dtype == torch.complex128:
+        return (12, lat.Vh)
+    if dtype == torch.complex64:
+        return (6, lat.Vh, 2)
+    return (3, lat.Vh, 4, 2)
 
 
 def parity_vector(lat: Lattice, nrhs=None, dtype=torch.complex128) -> torch.Tensor:
@@ -211,6 +222,25 @@ def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweep
     return x_e
 
 
+def set_multi_rhs_tile(lat: Lattice, nrhs: int, nb: int, waves: int = 4, xcd_map: bool = False) -> None:
+    """Tile of the FP32 multi-right-hand-side stencil for launches of nrhs right-hand
+    sides (nb = 0: one right-hand side per thread)."""
+    t = _lib.MrTile(int(nb), int(waves), int(bool(xcd_map)), 0.0)
+    check(lib().ddq_set_multi_rhs_tile(lat.handle, int(nrhs), C.byref(t)), "ddq_set_multi_rhs_tile")
+
+
+def tune_multi_rhs(lat: Lattice, nrhs: int, reps: int = 5):
+    """Time every tile for nrhs right-hand sides and keep the fastest.  Returns
+    (chosen, candidates) as dicts."""
+    arr = (_lib.MrTile * 64)()
+    n = C.c_int()
+    best = _lib.MrTile()
+    lat.sync_stream()
+    check(lib().ddq_tune_multi_rhs(lat.handle, int(nrhs), int(reps), arr, 64, C.byref(n), C.byref(best)),
+          "ddq_tune_multi_rhs")
+    return best.as_dict(), [arr[k].as_dict() for k in range(min(n.value, 64))]
+
+
 def estimate_lambda_max(lat: Lattice, iters: int, v0: torch.Tensor) -> float:
     if v0.dtype != torch.complex128:
         raise TypeError("v0 must be complex128")
@@ -245,13 +275,13 @@ def oe_reconstruct(lat: Lattice, x_e: torch.Tensor, b: torch.Tensor) -> torch.Te
 
 def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
                    tol: float = 1e-10, inner_prec: int = DDQ_F64, smoother_sweeps: int = 0, omega: float = 0.0,
-                   inner_reduction: float = 0.0):
+                   inner_reduction: float = 0.0, smoother_prec: int = None):
     """Odd-even GMRES(m) of Alg. 2 with eq. 2 around it.  Returns (x, info, converged)."""
     if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
         raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
-                    float(inner_reduction))
+                    float(inner_reduction), int(inner_prec if smoother_prec is None else smoother_prec))
     info = SolveInfo()
     lat.sync_stream()
     st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
@@ -300,7 +330,7 @@ def batch_destroy(batch: Batch) -> None:
 
 
 def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, tol: float = 1e-10,
-                smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0):
+                smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0, smoother_prec: int = DDQ_F32):
     """Solve every (lattice, right-hand side) system of the batch.  bs[l]: complex128
     [nrhs[l], Lt, Lz, Ly, Lx, 4, 3]; omega: one weight or one per lattice.
     Returns (xs, infos, converged) with infos in (lattice, right-hand side) order."""
@@ -319,7 +349,7 @@ def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, 
     bp = (C.c_void_p * len(bs))(*[_dev(b, "b").value for b in bs])
     op = (C.c_double * len(bs))(*om)
     p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F32, int(smoother_sweeps), om[0],
-                    float(inner_reduction))
+                    float(inner_reduction), int(smoother_prec))
     infos = (SolveInfo * sum(batch.nrhs))()
     st = check(lib().ddq_batch_solve(batch.handle, xp, bp, C.byref(p), op, infos), "ddq_batch_solve", allow=(0, 1))
     return xs, [i.as_dict() for i in infos], st == 0

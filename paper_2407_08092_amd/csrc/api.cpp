@@ -86,14 +86,14 @@ struct ddq_lattice {
   void* U = nullptr;
   bool have_gauge = false;
   unsigned store = 0;
-  void* links[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [prec][parity]
-  void* clov[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};   // [prec][0: A_ee, 1: A_oo^-1]
+  void* links[4][2] = {};  // [prec][parity]; FP16 / BF16 fields are 12-real
+  void* clov[4][2] = {};   // [prec][0: A_ee, 1: A_oo^-1]
   bool have_clover = false;
   bool link12 = false;  // FP32 links stored as their first two rows
   double c_sw = 0.0, m0 = 0.0;
   // work buffers
   Grow force_ws;      // force: psi_o, lambda_o, insertions
-  Grow tmp[2];        // u_o per precision
+  Grow tmp[4];        // u_o per precision
   Grow scratch64;     // FP64 parity vectors
   Grow scratch32;     // FP32 parity vectors
   Grow partial;       // reduction partials
@@ -111,6 +111,14 @@ struct ddq_lattice {
   std::vector<double> kind_ms, kind_bytes;
   std::vector<int> kind_n;
 
+  // FP32 multi-right-hand-side tiles by right-hand-side count (ddq_tune_multi_rhs)
+  std::vector<std::pair<int, MrTile>> tiles;
+  const MrTile* tile_for(int nrhs) const {
+    for (const auto& t : tiles)
+      if (t.first == nrhs) return &t.second;
+    return nullptr;
+  }
+
   long long nvec() const { return 12LL * Vh; }  // complex elements of one parity vector
 };
 
@@ -122,9 +130,12 @@ int check_lat(const ddq_lattice* L) {
 }
 
 int check_prec(int prec) {
-  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "precision must be DDQ_F64 or DDQ_F32");
+  if (prec != DDQ_F64 && prec != DDQ_F32 && prec != DDQ_F16 && prec != DDQ_BF16)
+    return fail(DDQ_ERR_ARG, "precision must be DDQ_F64, DDQ_F32, DDQ_F16 or DDQ_BF16");
   return DDQ_OK;
 }
+bool is16(int prec) { return prec == DDQ_F16 || prec == DDQ_BF16; }
+int h16_kind(int prec) { return prec == DDQ_BF16 ? H16_BF16 : H16_F16; }
 
 int check_ready(const ddq_lattice* L, int prec) {
   CHK(check_lat(L));
@@ -135,7 +146,8 @@ int check_ready(const ddq_lattice* L, int prec) {
   return DDQ_OK;
 }
 
-size_t elem_bytes(int prec) { return prec == DDQ_F64 ? 16 : 8; }
+// bytes per stored complex number of a parity vector
+size_t elem_bytes(int prec) { return prec == DDQ_F64 ? 16 : (prec == DDQ_F32 ? 8 : 4); }
 
 int ensure_host(ddq_lattice* L, size_t bytes) {
   if (bytes <= L->host_bytes) return DDQ_OK;
@@ -164,6 +176,8 @@ double hop_bytes(const ddq_lattice* L, int prec, int mode, int nrhs) {
     case M_RESID: spin = 4; break;                // in, x, b, out
     case M_PREP: spin = 3; clover = false; break; // in, b, out
   }
+  if (is16(prec))  // 12-real links, clover padded to 40 slots, 4 bytes per complex
+    return (double)(12 * spin * nrhs + 48 + (clover ? 40 : 0)) * 4 * (double)L->Vh;
   const int link = (prec == DDQ_F32 && L->link12) ? 48 : 72;
   const double per_site = (double)(12 * spin * nrhs + link + (clover ? 36 : 0)) * (prec == DDQ_F64 ? 16 : 8);
   return per_site * (double)L->Vh;
@@ -188,13 +202,27 @@ int prof_flush(ddq_lattice* L) {
 }
 
 // launch a stencil kernel, bracketed by events while profiling
+// the multi-right-hand-side FP32 kernels take the lattice's tuned tile when one fits
 template <typename R>
-hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
-  if (!L->prof_on) return launch_hop<R>(a, mode, dag, nrhs, L->stream);
-  const int prec = sizeof(R) == 8 ? DDQ_F64 : DDQ_F32;
-  std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
-                     (dag ? "_dag" : "") +
-                     (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
+hipError_t launch_any(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
+  if constexpr (sizeof(R) == 4) {
+    if (nrhs > 1) {
+      const MrTile* t = L->tile_for(nrhs);
+      if (t && hop_rb_supported(mode, dag, nrhs, *t)) {
+        HopArgs<float> b = a;
+        b.tile = *t;
+        return launch_hop_rb(b, mode, nrhs, L->stream);
+      }
+    }
+  }
+  return launch_hop<R>(a, mode, dag, nrhs, L->stream);
+}
+
+// run `launch` bracketed by profiling events on the lattice's stream (when on),
+// its time booked under `name` with `bytes` algorithmic bytes per launch
+template <typename F>
+hipError_t prof_launch(ddq_lattice* L, const std::string& name, double bytes, F launch) {
+  if (!L->prof_on) return launch();
   int kind = -1;
   for (size_t k = 0; k < L->kind_name.size(); ++k)
     if (L->kind_name[k] == name) kind = (int)k;
@@ -203,7 +231,7 @@ hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int 
     L->kind_name.push_back(name);
     L->kind_ms.push_back(0.0);
     L->kind_n.push_back(0);
-    L->kind_bytes.push_back(hop_bytes(L, prec, mode, nrhs));
+    L->kind_bytes.push_back(bytes);
   }
   if (L->ev_used * 2 == (int)L->ev.size()) {
     if (L->ev.size() < 2048) {
@@ -223,9 +251,63 @@ hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int 
   L->ev_kind[k] = kind;
   hipError_t e = hipEventRecord(L->ev[2 * k], L->stream);
   if (e != hipSuccess) return e;
-  e = launch_hop<R>(a, mode, dag, nrhs, L->stream);
+  e = launch();
   if (e != hipSuccess) return e;
   return hipEventRecord(L->ev[2 * k + 1], L->stream);
+}
+
+// launch a stencil kernel, bracketed by events while profiling
+template <typename R>
+hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
+  if (!L->prof_on) return launch_any<R>(L, a, mode, dag, nrhs);
+  const int prec = sizeof(R) == 8 ? DDQ_F64 : DDQ_F32;
+  std::string tile;
+  if (prec == DDQ_F32 && nrhs > 1) {
+    const MrTile* t = L->tile_for(nrhs);
+    if (t && hop_rb_supported(mode, dag, nrhs, *t))
+      tile = "_nb" + std::to_string(t->nb) + "g" + std::to_string(t->g) + (t->xmap ? "x" : "");
+  }
+  std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
+                     (dag ? "_dag" : "") + (nrhs > 1 ? "_x" + std::to_string(nrhs) : "") + tile;
+  return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
+                     [&]() { return launch_any<R>(L, a, mode, dag, nrhs); });
+}
+
+// the 16-bit-storage stencil: kernel A (M_HOP_CLINV) or kernel B (M_APPLY / M_RICH)
+hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* in, const void* x, const void* b,
+                     void* out, float omega) {
+  Hop16Args a{};
+  const int p_out = mode == M_HOP_CLINV ? 1 : 0;
+  a.g = L->geo;
+  a.p_out = p_out;
+  a.in = (const u4_t*)in;
+  a.links = (const u4_t*)L->links[prec][p_out];
+  a.clov = (const u4_t*)L->clov[prec][p_out];
+  a.x = (const u4_t*)x;
+  a.b = (const u4_t*)b;
+  a.out = (u4_t*)out;
+  a.omega = omega;
+  a.nrhs = nrhs;
+  std::string name = std::string(mode_name(mode)) + (prec == DDQ_BF16 ? "_bf16" : "_f16") +
+                     (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
+  return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
+                     [&]() { return launch_hop16(h16_kind(prec), a, mode, L->stream); });
+}
+
+int schur16(ddq_lattice* L, int prec, int nrhs, const void* x, void* y) {
+  void* u = L->tmp[prec].p;
+  HIPCHK(run_hop16(L, prec, nrhs, M_HOP_CLINV, x, nullptr, nullptr, u, 0.f));
+  HIPCHK(run_hop16(L, prec, nrhs, M_APPLY, u, x, nullptr, y, 0.f));
+  return DDQ_OK;
+}
+
+int sweeps16(ddq_lattice* L, int prec, int nrhs, void* x, const void* b, int n, float omega) {
+  void* u = L->tmp[prec].p;
+  for (int k = 0; k < n; ++k) {
+    HIPCHK(run_hop16(L, prec, nrhs, M_HOP_CLINV, x, nullptr, nullptr, u, 0.f));
+    HIPCHK(run_hop16(L, prec, nrhs, M_RICH, u, x, b, x, omega));
+  }
+  return DDQ_OK;
 }
 
 template <typename R>
@@ -388,13 +470,13 @@ int ddq_create_lattice(const int dims[4], int t_antiperiodic, void* hip_stream, 
 int ddq_destroy_lattice(ddq_lattice* L) {
   if (!L) return DDQ_OK;
   dfree(L->U);
-  for (int p = 0; p < 2; ++p)
+  for (int p = 0; p < 4; ++p) {
     for (int q = 0; q < 2; ++q) {
       dfree(L->links[p][q]);
       dfree(L->clov[p][q]);
     }
-  L->tmp[0].release();
-  L->tmp[1].release();
+    L->tmp[p].release();
+  }
   L->scratch64.release();
   L->scratch32.release();
   L->force_ws.release();
@@ -423,7 +505,8 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   CHK(check_lat(L));
   if (!U) return fail(DDQ_ERR_ARG, "U is null");
   if (storage_flags == 0) storage_flags = DDQ_STORE_F64 | DDQ_STORE_F32;
-  if (storage_flags & ~(unsigned)(DDQ_STORE_F64 | DDQ_STORE_F32 | DDQ_STORE_F32_LINK12))
+  if (storage_flags &
+      ~(unsigned)(DDQ_STORE_F64 | DDQ_STORE_F32 | DDQ_STORE_F32_LINK12 | DDQ_STORE_F16 | DDQ_STORE_BF16))
     return fail(DDQ_ERR_ARG, "unknown storage flag");
   if (storage_flags & DDQ_STORE_F32_LINK12) storage_flags |= DDQ_STORE_F32;
   L->have_gauge = false;
@@ -454,6 +537,24 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   } else {
     for (int q = 0; q < 2; ++q) dfree(L->links[DDQ_F32][q]);
   }
+  // 16-bit storage: 12-real links, 3 element rows per direction
+  const size_t n16 = (size_t)4 * 3 * field_vh((int)L->Vh) * 16;
+  for (int prec : {DDQ_F16, DDQ_BF16}) {
+    const unsigned flag = prec == DDQ_F16 ? DDQ_STORE_F16 : DDQ_STORE_BF16;
+    for (int q = 0; q < 2; ++q) {
+      if (!(storage_flags & flag)) {
+        dfree(L->links[prec][q]);
+        dfree(L->clov[prec][q]);
+        continue;
+      }
+      if (!L->links[prec][q]) {
+        CHK(dalloc(&L->links[prec][q], n16));
+        HIPCHK(hipMemsetAsync(L->links[prec][q], 0, n16, L->stream));  // block padding
+      }
+      HIPCHK(launch_links_to_h16(h16_kind(prec), (const d2_t*)L->links[DDQ_F64][q], L->links[prec][q], (int)L->Vh,
+                                 L->stream));
+    }
+  }
   L->store = storage_flags | DDQ_STORE_F64;
   L->have_gauge = true;
   return DDQ_OK;
@@ -482,6 +583,18 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
       if (!L->clov[DDQ_F32][q]) CHK(dalloc(&L->clov[DDQ_F32][q], n * 8));
       HIPCHK(launch_field_to_f32((const d2_t*)L->clov[DDQ_F64][q], L->clov[DDQ_F32][q], 1, CLOVER_ROWS,
                                  (int)L->Vh, L->stream));
+    }
+  }
+  const size_t n16 = (size_t)10 * field_vh((int)L->Vh) * 16;  // 16-bit: 10 element rows
+  for (int prec : {DDQ_F16, DDQ_BF16}) {
+    if (!L->links[prec][0]) continue;
+    for (int q = 0; q < 2; ++q) {
+      if (!L->clov[prec][q]) {
+        CHK(dalloc(&L->clov[prec][q], n16));
+        HIPCHK(hipMemsetAsync(L->clov[prec][q], 0, n16, L->stream));
+      }
+      HIPCHK(launch_clover_to_h16(h16_kind(prec), (const d2_t*)L->clov[DDQ_F64][q], L->clov[prec][q], (int)L->Vh,
+                                  L->stream));
     }
   }
   HIPCHK(hipStreamSynchronize(L->stream));
@@ -527,6 +640,10 @@ int ddq_apply_schur(ddq_lattice* L, int prec, int nrhs, const void* x_e, void* y
   if (nrhs < 1 || !x_e || !y_e) return fail(DDQ_ERR_ARG, "bad apply arguments");
   if (x_e == y_e) return fail(DDQ_ERR_ARG, "x_e and y_e must not overlap");
   CHK(ensure_tmp(L, prec, nrhs));
+  if (is16(prec)) {
+    if (dagger) return fail(DDQ_ERR_ARG, "the 16-bit path has no daggered apply");
+    return schur16(L, prec, nrhs, x_e, y_e);
+  }
   if (prec == DDQ_F64) return schur<double>(L, prec, nrhs, (const d2_t*)x_e, (d2_t*)y_e, dagger != 0);
   return schur<float>(L, prec, nrhs, (const f2_t*)x_e, (f2_t*)y_e, dagger != 0);
 }
@@ -537,8 +654,86 @@ int ddq_richardson_smooth(ddq_lattice* L, int prec, int nrhs, void* x_e, const v
   if (nrhs < 1 || !x_e || !b_e || nsweeps < 0) return fail(DDQ_ERR_ARG, "bad smoother arguments");
   if (x_e == b_e) return fail(DDQ_ERR_ARG, "x_e and b_e must not overlap");
   CHK(ensure_tmp(L, prec, nrhs));
+  if (is16(prec)) return sweeps16(L, prec, nrhs, x_e, b_e, nsweeps, (float)omega);
   if (prec == DDQ_F64) return sweeps<double>(L, prec, nrhs, (d2_t*)x_e, (const d2_t*)b_e, nsweeps, omega);
   return sweeps<float>(L, prec, nrhs, (f2_t*)x_e, (const f2_t*)b_e, nsweeps, (float)omega);
+}
+
+int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
+  CHK(check_lat(L));
+  if (!tile || nrhs < 2) return fail(DDQ_ERR_ARG, "need a tile and nrhs >= 2");
+  MrTile t;
+  t.nb = tile->nb;
+  t.g = tile->waves;
+  t.xmap = tile->xcd_map ? 1 : 0;
+  if (t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t))
+    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4");
+  for (auto& e : L->tiles)
+    if (e.first == nrhs) {
+      e.second = t;
+      return DDQ_OK;
+    }
+  L->tiles.push_back({nrhs, t});
+  return DDQ_OK;
+}
+
+int ddq_tune_multi_rhs(ddq_lattice* L, int nrhs, int reps, ddq_mr_tile* results, int max_results, int* n_results,
+                       ddq_mr_tile* chosen) {
+  CHK(check_ready(L, DDQ_F32));
+  if (nrhs < 2 || nrhs > 4096) return fail(DDQ_ERR_ARG, "nrhs must be in [2, 4096]");
+  if (reps < 1) reps = 5;
+  const size_t N = (size_t)nrhs * L->nvec();
+  CHK(L->scratch32.ensure(2 * N * 8));
+  CHK(ensure_tmp(L, DDQ_F32, nrhs));
+  f2_t* x = (f2_t*)L->scratch32.p;
+  f2_t* b = x + N;
+  HIPCHK(hipMemsetAsync(x, 0, 2 * N * 8, L->stream));
+  std::vector<ddq_mr_tile> cand;
+  cand.push_back({0, 4, 0, 0.0});  // one right-hand side per thread, the 64-site x 4 mapping
+  for (int nb = 1; nb <= MR_MAX_NB; ++nb)
+    if (nrhs % nb == 0)
+      for (int g : {1, 4})
+        for (int xm : {0, 1}) cand.push_back({nb, g, xm, 0.0});
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    HIPCHK(he);
+  }
+  const bool prof = L->prof_on;
+  L->prof_on = false;
+  int rc = DDQ_OK;
+  size_t best = 0;
+  for (size_t k = 0; k < cand.size() && rc == DDQ_OK; ++k) {
+    rc = ddq_set_multi_rhs_tile(L, nrhs, &cand[k]);
+    if (rc == DDQ_OK) rc = sweeps<float>(L, DDQ_F32, nrhs, x, b, 1, 0.1f);  // warm-up
+    if (rc == DDQ_OK && hipEventRecord(e0, L->stream) != hipSuccess) rc = fail(DDQ_ERR_HIP, "event record");
+    if (rc == DDQ_OK) rc = sweeps<float>(L, DDQ_F32, nrhs, x, b, reps, 0.1f);
+    if (rc == DDQ_OK && hipEventRecord(e1, L->stream) != hipSuccess) rc = fail(DDQ_ERR_HIP, "event record");
+    float ms = 0.f;
+    if (rc == DDQ_OK && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = fail(DDQ_ERR_HIP, "event timing");
+    cand[k].ms = ms / reps;
+    if (rc == DDQ_OK && cand[k].ms < cand[best].ms) best = k;
+  }
+  L->prof_on = prof;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != DDQ_OK) {
+    for (auto it = L->tiles.begin(); it != L->tiles.end(); ++it)
+      if (it->first == nrhs) {
+        L->tiles.erase(it);
+        break;
+      }
+    return rc;
+  }
+  CHK(ddq_set_multi_rhs_tile(L, nrhs, &cand[best]));
+  if (results)
+    for (int k = 0; k < max_results && k < (int)cand.size(); ++k) results[k] = cand[k];
+  if (n_results) *n_results = (int)cand.size();
+  if (chosen) *chosen = cand[best];
+  return DDQ_OK;
 }
 
 int ddq_estimate_lambda_max(ddq_lattice* L, int iters, const void* v0, double* out) {
@@ -593,10 +788,18 @@ int ddq_convert_parity(ddq_lattice* L, int nrhs, int src_prec, const void* src, 
   if (src_prec == dst_prec) {
     HIPCHK(hipMemcpyAsync(dst, src, (size_t)nrhs * L->nvec() * elem_bytes(src_prec), hipMemcpyDeviceToDevice,
                           L->stream));
-  } else if (src_prec == DDQ_F64) {
+  } else if (src_prec == DDQ_F64 && dst_prec == DDQ_F32) {
     HIPCHK(launch_parity_to_f32(dst, (const d2_t*)src, nrhs, (int)L->Vh, L->stream));
-  } else {
+  } else if (src_prec == DDQ_F32 && dst_prec == DDQ_F64) {
     HIPCHK(launch_parity_to_f64((d2_t*)dst, src, nrhs, (int)L->Vh, L->stream));
+  } else if (src_prec == DDQ_F64 && is16(dst_prec)) {
+    HIPCHK(launch_parity_to_h16(h16_kind(dst_prec), dst, (const d2_t*)src, 1.0, nrhs, (int)L->Vh, L->stream));
+  } else if (is16(src_prec) && dst_prec == DDQ_F64) {
+    HIPCHK(launch_parity_from_h16(h16_kind(src_prec), (d2_t*)dst, src, 1.0, nrhs, (int)L->Vh, L->stream));
+  } else if (is16(src_prec) && dst_prec == DDQ_F32) {
+    HIPCHK(launch_h16_to_f32(h16_kind(src_prec), dst, src, 1.0f, nrhs, (int)L->Vh, L->stream));
+  } else {
+    return fail(DDQ_ERR_ARG, "unsupported conversion (narrow to 16 bits from FP64)");
   }
   return DDQ_OK;
 }
@@ -694,9 +897,16 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
   if (m < 1 || m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
   if (P->max_cycles < 0 || !(P->tol >= 0.0) || P->smoother_sweeps < 0)
     return fail(DDQ_ERR_ARG, "bad max_cycles, tol or smoother_sweeps");
-  CHK(check_prec(P->inner_prec));
+  if (P->inner_prec != DDQ_F64 && P->inner_prec != DDQ_F32)
+    return fail(DDQ_ERR_ARG, "inner_prec must be DDQ_F64 or DDQ_F32");
   const bool lo = P->inner_prec == DDQ_F32;
   if (lo) CHK(check_ready(L, DDQ_F32));
+  const int sp = P->smoother_prec;  // 16-bit storage for the Richardson preconditioner
+  const bool s16 = is16(sp) && P->smoother_sweeps > 0;
+  if (s16) {
+    if (!lo) return fail(DDQ_ERR_ARG, "a 16-bit smoother needs inner_prec = DDQ_F32");
+    CHK(check_ready(L, sp));
+  }
   const int nu = P->smoother_sweeps;
   const bool flexible = nu > 0 || lo;
   const double red = P->inner_reduction > 0.0 ? P->inner_reduction : (lo ? 1e-5 : 0.0);
@@ -718,6 +928,7 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
   if (lo) {
     CHK(L->scratch32.ensure(3 * (size_t)n * 8));
     CHK(ensure_tmp(L, DDQ_F32, 1));
+    if (s16) CHK(ensure_tmp(L, sp, 1));
     b32 = (f2_t*)L->scratch32.p;
     x32 = b32 + n;
     w32 = b32 + 2 * n;
@@ -764,7 +975,19 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
       d2_t* zk = flexible ? Z + (size_t)k * n : vk;
       // z_k = M v_k, w = D_S z_k
       if (lo) {
-        if (nu > 0) {
+        if (s16) {
+          // the same sweeps on 16-bit storage: v_k (unit norm) scaled by sqrt(n) so its
+          // entries are of order one, b16 = s v, x16 = omega s v, then back with 1/s
+          // (the sweeps are linear in b, so the scale cancels exactly)
+          const double sc = std::sqrt((double)n);
+          void* b16 = b32;
+          void* x16 = (char*)b32 + (size_t)n * 4;
+          HIPCHK(launch_parity_to_h16(h16_kind(sp), b16, vk, sc, 1, (int)L->Vh, L->stream));
+          HIPCHK(launch_parity_to_h16(h16_kind(sp), x16, vk, sc * P->omega, 1, (int)L->Vh, L->stream));
+          CHK(sweeps16(L, sp, 1, x16, b16, nu - 1, (float)P->omega));
+          HIPCHK(launch_h16_to_f32(h16_kind(sp), x32, x16, (float)(1.0 / sc), 1, (int)L->Vh, L->stream));
+          applies_lo += nu - 1;
+        } else if (nu > 0) {
           HIPCHK(launch_parity_to_f32(b32, vk, 1, (int)L->Vh, L->stream));
           HIPCHK(launch_scale_f32(x32, b32, (float)P->omega, n, L->stream));  // first sweep from 0
           CHK(sweeps<float>(L, DDQ_F32, 1, x32, b32, nu - 1, (float)P->omega));
@@ -878,6 +1101,7 @@ struct ddq_batch {
   hipEvent_t ev = nullptr;
   std::vector<hipGraphExec_t> step_graph;  // one per Arnoldi step index
   std::vector<uintptr_t> graph_key;        // what the captured graphs bake in
+  int sprec = DDQ_F32;                     // storage of the Richardson preconditioner
   double* host = nullptr;                  // pinned
   size_t host_bytes = 0;
 };
@@ -947,7 +1171,16 @@ int batch_step(ddq_batch* B, int k, int nu) {
     d2_t* zk = S.Z + (size_t)k * N;
     const int vh = (int)L->Vh;
     if (k > 0) HIPCHK(launch_scale_b(vk, S.w, S.f, S.n, S.nrhs, B->stream));
-    if (nu > 0) {
+    if (nu > 0 && is16(B->sprec)) {
+      // 16-bit storage: scaled so that the unit-norm v_k has entries of order one
+      const double sc = std::sqrt((double)S.n);
+      void* b16 = S.b32;
+      void* x16 = (char*)S.b32 + N * 4;
+      HIPCHK(launch_parity_to_h16(h16_kind(B->sprec), b16, vk, sc, S.nrhs, vh, B->stream));
+      HIPCHK(launch_parity_to_h16(h16_kind(B->sprec), x16, vk, sc * S.omega, S.nrhs, vh, B->stream));
+      CHK(sweeps16(L, B->sprec, S.nrhs, x16, b16, nu - 1, (float)S.omega));
+      HIPCHK(launch_h16_to_f32(h16_kind(B->sprec), S.x32, x16, (float)(1.0 / sc), S.nrhs, vh, B->stream));
+    } else if (nu > 0) {
       HIPCHK(launch_parity_to_f32(S.b32, vk, S.nrhs, vh, B->stream));
       HIPCHK(launch_scale_f32((f2_t*)S.x32, (const f2_t*)S.b32, (float)S.omega, (long long)N, B->stream));
       CHK(sweeps<float>(L, DDQ_F32, S.nrhs, (f2_t*)S.x32, (const f2_t*)S.b32, nu - 1, (float)S.omega));
@@ -969,17 +1202,21 @@ int batch_step(ddq_batch* B, int k, int nu) {
 
 // every pointer and value a captured step graph holds
 std::vector<uintptr_t> batch_key(const ddq_batch* B, int m, int nu) {
-  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu};
+  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu, (uintptr_t)B->sprec};
   for (const auto& S : B->sys) {
     const ddq_lattice* L = S.L;
     uint64_t om;
     std::memcpy(&om, &S.omega, 8);
     for (uintptr_t v : {(uintptr_t)S.w64.p, (uintptr_t)S.w32.p, (uintptr_t)S.small.p, (uintptr_t)S.partial.p,
-                        (uintptr_t)L->tmp[DDQ_F32].p,
+                        (uintptr_t)L->tmp[DDQ_F32].p, (uintptr_t)L->tmp[B->sprec].p,
+                        (uintptr_t)L->links[B->sprec][0], (uintptr_t)L->links[B->sprec][1],
+                        (uintptr_t)L->clov[B->sprec][0], (uintptr_t)L->clov[B->sprec][1],
                         (uintptr_t)L->links[DDQ_F32][0], (uintptr_t)L->links[DDQ_F32][1],
                         (uintptr_t)L->clov[DDQ_F32][0], (uintptr_t)L->clov[DDQ_F32][1], (uintptr_t)L->link12,
                         (uintptr_t)om})
       key.push_back(v);
+    const MrTile* t = L->tile_for(S.nrhs);
+    key.push_back(t ? (uintptr_t)(1 + t->nb + 8 * t->g + 64 * t->xmap) : 0);
   }
   return key;
 }
@@ -1102,12 +1339,14 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   const int nu = P->smoother_sweeps;
   const double red = P->inner_reduction > 0.0 ? P->inner_reduction : 1e-5;
   const int ns = (int)B->sys.size();
+  const int sprec = is16(P->smoother_prec) ? P->smoother_prec : DDQ_F32;
   // pinned host layout: per system, the D2H block then the H2D block
   std::vector<size_t> d2h(ns), h2d(ns);
   size_t host_doubles = 0;
   for (int s = 0; s < ns; ++s) {
     auto& S = B->sys[s];
     CHK(check_ready(S.L, DDQ_F32));
+    if (sprec != DDQ_F32) CHK(check_ready(S.L, sprec));
     if (!x[s] || !b[s] || x[s] == b[s]) return fail(DDQ_ERR_ARG, "bad x / b pointers in the batch");
     S.omega = omegas ? omegas[s] : P->omega;
     if (nu > 0 && !(std::isfinite(S.omega) && S.omega > 0.0)) return fail(DDQ_ERR_ARG, "omega must be positive");
@@ -1121,7 +1360,14 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   HIPCHK(hipEventRecord(B->ev, B->user));
   HIPCHK(hipStreamWaitEvent(B->stream, B->ev, 0));
   LatticeStreamGuard guard(B);
-  for (auto& S : B->sys) CHK(batch_workspace(S, m));
+  B->sprec = sprec;
+  for (auto& S : B->sys) {
+    CHK(batch_workspace(S, m));
+    if (sprec != DDQ_F32) CHK(ensure_tmp(S.L, sprec, S.nrhs));
+  }
+  // multi-right-hand-side tiles: tuned on first use
+  for (auto& S : B->sys)
+    if (S.nrhs > 1 && !S.L->tile_for(S.nrhs)) CHK(ddq_tune_multi_rhs(S.L, S.nrhs, 3, nullptr, 0, nullptr, nullptr));
 
   std::vector<std::vector<RhsState>> st(ns);
   int iters = 0, cycles = 0;

@@ -22,6 +22,18 @@ enum HopMode {
   M_NMODES = 6
 };
 
+// Tile of the register-blocked multi-right-hand-side stencil (FP32): every thread
+// handles nb right-hand sides of one site, so a link or clover entry is loaded
+// once for nb spinors; g wavefronts of a workgroup take consecutive groups of
+// right-hand sides of the same 64 sites (g = 1: 256 sites per workgroup); xmap
+// places all right-hand-side groups of a site block on one XCD.
+struct MrTile {
+  int nb = 0;
+  int g = 1;
+  int xmap = 0;
+};
+constexpr int MR_MAX_NB = 4;
+
 template <typename R>
 struct HopArgs {
   Geo g;
@@ -37,6 +49,7 @@ struct HopArgs {
   int nblk;                  // workgroups along x, padded to a multiple of 8 (one right-hand side)
   int nrhs;                  // right-hand sides of the launch
   long long rhs_stride;      // complex elements between right-hand sides
+  MrTile tile;               // FP32 multi-right-hand-side tile (nb = 0: one right-hand side per thread)
 };
 
 #ifndef DDQ_HOP_BLOCK
@@ -46,6 +59,36 @@ constexpr int HOP_BLOCK = DDQ_HOP_BLOCK;
 
 template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a, int mode, bool dagger, int nrhs, hipStream_t s);
+
+// register-blocked FP32 multi-right-hand-side stencil for modes M_HOP_CLINV, M_APPLY
+// and M_RICH (not daggered); a.tile.nb in [2, MR_MAX_NB] must divide nrhs.  Returns
+// hipErrorInvalidValue for anything else (the caller falls back to launch_hop).
+bool hop_rb_supported(int mode, bool dagger, int nrhs, const MrTile& t);
+hipError_t launch_hop_rb(const HopArgs<float>& a, int mode, int nrhs, hipStream_t s);
+
+// 16-bit storage (FP16 or BF16 values, FP32 arithmetic): modes M_HOP_CLINV, M_APPLY,
+// M_RICH, not daggered.  Parity vectors are [nrhs][3][V/2] 16-byte elements of four
+// complex numbers; links 12-real; clover padded to 20 slots per block.
+enum H16Kind { H16_F16 = 0, H16_BF16 = 1 };
+struct Hop16Args {
+  Geo g;
+  int p_out;
+  const u4_t* in;
+  const u4_t* links;
+  const u4_t* clov;
+  const u4_t* x;
+  const u4_t* b;
+  u4_t* out;
+  float omega;
+  int nrhs;
+  int nb;  // right-hand sides per thread, 1..3 (0: the largest of 3, 2, 1 dividing nrhs)
+};
+hipError_t launch_hop16(int kind, const Hop16Args& a, int mode, hipStream_t s);
+hipError_t launch_parity_to_h16(int kind, void* y, const d2_t* x, double scale, int nrhs, int vh, hipStream_t s);
+hipError_t launch_parity_from_h16(int kind, d2_t* y, const void* x, double scale, int nrhs, int vh, hipStream_t s);
+hipError_t launch_h16_to_f32(int kind, void* y, const void* x, float scale, int nrhs, int vh, hipStream_t s);
+hipError_t launch_links_to_h16(int kind, const d2_t* in, void* out, int vh, hipStream_t s);
+hipError_t launch_clover_to_h16(int kind, const d2_t* in, void* out, int vh, hipStream_t s);
 
 // out = C v for every site of one parity (C = that parity's stored clover blocks)
 template <typename R>

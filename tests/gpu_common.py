@@ -19,8 +19,23 @@ def to_dev(v_np, dtype=torch.complex128):
     return t.to(device="cuda", dtype=dtype).contiguous()
 
 
+def to_dev16(v_np, dtype):
+    """oracle parity vector [.., V/2, 12] -> 16-bit ABI layout [.., 3, V/2, 4, 2]
+    (float16 / bfloat16), rounded on the host FP64 -> FP32 -> 16 bit."""
+    a = np.swapaxes(v_np, -1, -2)  # [.., 12, Vh]
+    vh = a.shape[-1]
+    a = np.swapaxes(a.reshape(a.shape[:-2] + (3, 4, vh)), -1, -2)  # [.., 3, Vh, 4]
+    t = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(a)))  # [.., 3, Vh, 4, 2] float64
+    return t.to(torch.float32).to(dtype).contiguous().cuda()
+
+
 def to_host(t):
     """ABI parity vector -> oracle layout [.., V/2, 12] (complex128 numpy)."""
+    if t.dtype in (torch.float16, torch.bfloat16):
+        a = torch.view_as_complex(t.detach().cpu().to(torch.float64).contiguous()).numpy()  # [.., 3, Vh, 4]
+        a = np.swapaxes(a, -1, -2)  # [.., 3, 4, Vh]
+        a = a.reshape(a.shape[:-3] + (12, a.shape[-1]))
+        return np.ascontiguousarray(np.swapaxes(a, -1, -2))
     a = t.detach().cpu().numpy().astype(np.complex128)
     if t.dtype == torch.complex64:
         a = np.swapaxes(a, -1, -2)  # [.., 6, 2, Vh]

@@ -65,7 +65,8 @@ typedef struct ddq_lattice ddq_lattice;
  * storage the paper leaves to future work (Sect. 6).  16-bit parity vectors are
  * [rhs][sc/4][i][sc%4] complex pairs of 16-bit values (four complex numbers per
  * 16-byte element); FP16's range (normal numbers 6.1e-5 .. 65504) is the
- * caller's to respect.  The 16-bit path applies D_S and runs the Richardson
+ * caller's to respect.  Narrowing from FP64 rounds to nearest even: FP16 in one
+ * rounding, BF16 through FP32 (two roundings); widening is exact.  The 16-bit path applies D_S and runs the Richardson
  * smoother (not daggered) and serves as the GMRES preconditioner's storage. */
 enum ddq_prec { DDQ_F64 = 0, DDQ_F32 = 1, DDQ_F16 = 2, DDQ_BF16 = 3 };
 

@@ -1190,12 +1190,13 @@ int batch_step(ddq_batch* B, int k, int nu) {
     HIPCHK(launch_parity_to_f64(zk, S.x32, S.nrhs, vh, B->stream));
     CHK(schur<float>(L, DDQ_F32, S.nrhs, (const f2_t*)S.x32, (f2_t*)S.w32v, false));
     HIPCHK(launch_parity_to_f64(S.w, S.w32v, S.nrhs, vh, B->stream));
-    for (int pass = 0; pass < 2; ++pass) {
-      d2_t* h = pass ? S.h2 : S.h1;
-      HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, (d2_t*)S.partial.p, S.nbx, h, BLD, B->stream));
-      HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, h, BLD, -1.0, S.n, S.nrhs, B->stream));
-    }
-    HIPCHK(launch_norm2_b(S.w, S.n, S.nrhs, (double*)S.partial.p, S.nbx, S.hn, B->stream));
+    // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, then |w|^2
+    d2_t* part = (d2_t*)S.partial.p;
+    HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h1, BLD, B->stream));
+    HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h1, BLD, -1.0, S.n, S.nrhs, B->stream));
+    HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h2, BLD, B->stream));
+    HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h2, BLD, -1.0, S.n, S.nrhs, B->stream));
+    HIPCHK(launch_norm2_b(S.w, S.n, S.nrhs, (double*)part, S.nbx, S.hn, B->stream));
   }
   return DDQ_OK;
 }

@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(RB) k_update(d2_t* __restrict__ w, const d2_t*
     we.x = fma(sign, ar, we.x);
     we.y = fma(sign, ai, we.y);
     w[e] = we;
+    store_fence();
   }
 }
 
@@ -332,6 +333,7 @@ __global__ void __launch_bounds__(RB) k_update_b(d2_t* __restrict__ w, const d2_
     we.x = fma(sign, ar, we.x);
     we.y = fma(sign, ai, we.y);
     wr[e] = we;
+    store_fence();
   }
 }
 

@@ -135,8 +135,21 @@ template <int AUX = 0>
 __device__ __forceinline__ u4_t ld16(const Field& f, int row, uint32_t off) {
   return __builtin_amdgcn_raw_buffer_load_b128(f.rsrc, (int)off, (int)(row * f.row_bytes), AUX);
 }
+// A vector store reads its data registers after it issues (the read is tracked by
+// the EXP counter); the compiler may schedule a write to those registers before that
+// read has happened, and the store then writes the new values.  Measured on gfx950:
+// kernels that store one right-hand side and reuse the registers for the next
+// returned nondeterministic wrong values, which an expcnt(0) wait after each store
+// removes.  Every kernel whose stores are followed by more register writes calls
+// store_fence() after them.
+__device__ __forceinline__ void store_fence() {
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(0xCF0F);  // expcnt(0); vmcnt and lgkmcnt left at their maxima
+  __builtin_amdgcn_sched_barrier(0);
+}
 __device__ __forceinline__ void st16(const Field& f, int row, uint32_t off, u4_t v) {
   __builtin_amdgcn_raw_buffer_store_b128(v, f.rsrc, (int)off, (int)(row * f.row_bytes), 0);
+  store_fence();
 }
 
 // 16-byte element <-> CPE complex numbers

@@ -32,7 +32,10 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
   const size_t fsz = (size_t)LINK_ROWS * field_vh(vh);  // one direction's link field
   for (int mu = 0; mu < 4; ++mu) {
     const d2_t* u = U + (n * 4 + mu) * 9;
-    for (int e = 0; e < 9; ++e) out[mu * fsz + fidx(e, i, LINK_ROWS, vh)] = u[e];
+    for (int e = 0; e < 9; ++e) {
+      out[mu * fsz + fidx(e, i, LINK_ROWS, vh)] = u[e];
+      store_fence();
+    }
     int c[4] = {s.x, s.y, s.z, s.t};
     coords_shift(g, c, mu, -1);
     const long long nb = lex(g, c[0], c[1], c[2], c[3]);
@@ -42,6 +45,7 @@ __global__ void k_pack_gauge(Geo g, const d2_t* __restrict__ U, d2_t* __restrict
         d2_t v = ub[3 * b + a];
         v.y = -v.y;
         out[mu * fsz + fidx(9 + 3 * a + b, i, LINK_ROWS, vh)] = v;
+        store_fence();
       }
   }
 }
@@ -227,6 +231,7 @@ __device__ __forceinline__ void store_packed(d2_t* C, int blk, int i, int vh, co
     v.x = M[2 * k][2 * k].r;
     v.y = M[2 * k + 1][2 * k + 1].r;
     C[fidx(18 * blk + k, i, 36, vh)] = v;
+    store_fence();
   }
   for (int j = 0; j < 6; ++j)
     for (int k = j + 1; k < 6; ++k) {
@@ -234,6 +239,7 @@ __device__ __forceinline__ void store_packed(d2_t* C, int blk, int i, int vh, co
       v.x = M[j][k].r;
       v.y = M[j][k].i;
       C[fidx(18 * blk + tri_slot(j, k), i, 36, vh)] = v;
+      store_fence();
     }
 }
 
@@ -284,7 +290,7 @@ __device__ bool hpd_inverse6(cpx<double> A[6][6]) {
 // E_l^+- = +-F_{l t} - F_{jk}, (l, j, k) cyclic over (x, y, z).  This is the
 // chiral-basis form of (4 + m0) + (i c_sw / 4) sum sigma_munu F_munu:
 // sigma_{l t} = diag(s_l, -s_l) and sigma_{jk} = -diag(s_l, s_l).
-__global__ void k_clover_build(Geo g, const d2_t* __restrict__ U, double c_sw, double m0,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) k_clover_build(Geo g, const d2_t* __restrict__ U, double c_sw, double m0,
                                d2_t* __restrict__ cl_e, d2_t* __restrict__ cl_o_inv, int* notpd) {
   const int vh = g.Vh;
   long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -366,13 +372,16 @@ __global__ void k_clover_export(Geo g, const d2_t* __restrict__ P, d2_t* __restr
     b.x = d.y; b.y = 0.0;
     out[(2 * k) * 6 + 2 * k] = a;
     out[(2 * k + 1) * 6 + 2 * k + 1] = b;
+    store_fence();
   }
   for (int j = 0; j < 6; ++j)
     for (int k = j + 1; k < 6; ++k) {
       d2_t v = P[fidx(18 * blk + tri_slot(j, k), i, 36, vh)];
       out[j * 6 + k] = v;
+      store_fence();
       v.y = -v.y;
       out[k * 6 + j] = v;
+      store_fence();
     }
 }
 
@@ -397,7 +406,10 @@ __global__ void k_pack_parity(Geo g, int parity, const pair<R>* __restrict__ ful
   const pair<R>* src = full + r * (size_t)2 * vh * 12 + n * 12;
   pair<R>* dst = v + r * (size_t)vh * 12;
   constexpr int C = CPE<R>;
-  for (int k = 0; k < 12; ++k) dst[((size_t)(k / C) * vh + i) * C + (k % C)] = src[k];
+  for (int k = 0; k < 12; ++k) {
+    dst[((size_t)(k / C) * vh + i) * C + (k % C)] = src[k];
+    store_fence();
+  }
 }
 
 template <typename R>
@@ -411,7 +423,10 @@ __global__ void k_unpack_parity(Geo g, int parity, const pair<R>* __restrict__ v
   pair<R>* dst = full + r * (size_t)2 * vh * 12 + n * 12;
   const pair<R>* src = v + r * (size_t)vh * 12;
   constexpr int C = CPE<R>;
-  for (int k = 0; k < 12; ++k) dst[k] = src[((size_t)(k / C) * vh + i) * C + (k % C)];
+  for (int k = 0; k < 12; ++k) {
+    dst[k] = src[((size_t)(k / C) * vh + i) * C + (k % C)];
+    store_fence();
+  }
 }
 
 template <typename R>
@@ -468,6 +483,7 @@ __global__ void k_parity_to_f64(d2_t* __restrict__ y, const f4_t* __restrict__ x
   b.x = q.z;
   b.y = q.w;
   yr[(size_t)(2 * k) * vh + i] = a;
+  store_fence();
   yr[(size_t)(2 * k + 1) * vh + i] = b;
 }
 

@@ -131,7 +131,7 @@ __device__ __forceinline__ Spinor<double> sigma_mul(int plane, const Spinor<doub
 
 // per site: W~_pq = (W - W^H) / 8 with W = (i c_sw / 2) sum_s (sigma_pq b)_s a_s^H,
 // stored [site (lexicographic)][plane 6][3][3]
-__global__ void k_force_insertions(Geo g, const d2_t* __restrict__ chi_e, const d2_t* __restrict__ lam_o,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) k_force_insertions(Geo g, const d2_t* __restrict__ chi_e, const d2_t* __restrict__ lam_o,
                                    const d2_t* __restrict__ phi_e, const d2_t* __restrict__ psi_o, double c_sw,
                                    d2_t* __restrict__ W) {
   const long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -165,6 +165,7 @@ __global__ void k_force_insertions(Geo g, const d2_t* __restrict__ chi_e, const 
         v.x = 0.125 * (wij.r - wji.r);
         v.y = 0.125 * (wij.i + wji.i);
         out[3 * i + j] = v;
+        store_fence();
       }
   }
 }
@@ -199,7 +200,7 @@ __device__ void add_leaves(C3& M, double s, const C3& U2, const C3& U3, const C3
 
 // One thread per link U_mu(y).  Outputs G = M^H (torch convention) and/or the
 // su(3) projection F_a = -Im tr(T_a U M).
-__global__ void __launch_bounds__(128) k_force_links(Geo g, const d2_t* __restrict__ U, const d2_t* __restrict__ W,
+__global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) k_force_links(Geo g, const d2_t* __restrict__ U, const d2_t* __restrict__ W,
                                                      const d2_t* __restrict__ chi_e, const d2_t* __restrict__ lam_o,
                                                      const d2_t* __restrict__ phi_e, const d2_t* __restrict__ psi_o,
                                                      d2_t* __restrict__ G, double* __restrict__ F, int accum) {
@@ -301,6 +302,7 @@ __global__ void __launch_bounds__(128) k_force_links(Geo g, const d2_t* __restri
           o.y = v.i;
         }
         out[3 * i + j] = o;
+        store_fence();
       }
   }
   if (F) {
@@ -319,7 +321,10 @@ __global__ void __launch_bounds__(128) k_force_links(Geo g, const d2_t* __restri
     f[6] = 0.5 * (UM.a[2][1].r - UM.a[1][2].r);
     f[7] = -0.5 * r3 * (UM.a[0][0].i + UM.a[1][1].i - 2.0 * UM.a[2][2].i);
     double* outf = F + li * 8;
-    for (int k = 0; k < 8; ++k) outf[k] = accum ? outf[k] + f[k] : f[k];
+    for (int k = 0; k < 8; ++k) {
+      outf[k] = accum ? outf[k] + f[k] : f[k];
+      store_fence();
+    }
   }
 }
 

@@ -304,6 +304,7 @@ __global__ void k_parity_from_h16(d2_t* __restrict__ y, const u4_t* __restrict__
     v.x = (double)c[j].r * scale;
     v.y = (double)c[j].i * scale;
     yr[(size_t)(4 * e + j) * vh + i] = v;
+    store_fence();
   }
 }
 
@@ -327,6 +328,7 @@ __global__ void k_h16_to_f32(f4_t* __restrict__ y, const u4_t* __restrict__ x, f
     o.z = c[2 * h + 1].r * scale;
     o.w = c[2 * h + 1].i * scale;
     yr[(size_t)(2 * e + h) * vh + i] = o;
+    store_fence();
   }
 }
 

@@ -21,12 +21,16 @@ def to_dev(v_np, dtype=torch.complex128):
 
 def to_dev16(v_np, dtype):
     """oracle parity vector [.., V/2, 12] -> 16-bit ABI layout [.., 3, V/2, 4, 2]
-    (float16 / bfloat16), rounded on the host FP64 -> FP32 -> 16 bit."""
+    (float16 / bfloat16), rounded on the host as the library narrows: FP16 in one
+    rounding from FP64 (numpy's conversion is correctly rounded), BF16 through FP32
+    (two roundings to nearest even)."""
     a = np.swapaxes(v_np, -1, -2)  # [.., 12, Vh]
     vh = a.shape[-1]
     a = np.swapaxes(a.reshape(a.shape[:-2] + (3, 4, vh)), -1, -2)  # [.., 3, Vh, 4]
-    t = torch.view_as_real(torch.from_numpy(np.ascontiguousarray(a)))  # [.., 3, Vh, 4, 2] float64
-    return t.to(torch.float32).to(dtype).contiguous().cuda()
+    r = np.ascontiguousarray(np.stack([a.real, a.imag], axis=-1))  # [.., 3, Vh, 4, 2] float64
+    if dtype == torch.float16:
+        return torch.from_numpy(r.astype(np.float16)).contiguous().cuda()
+    return torch.from_numpy(r).to(torch.float32).to(dtype).contiguous().cuda()
 
 
 def to_host(t):

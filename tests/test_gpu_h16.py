@@ -47,7 +47,7 @@ def test_conversion_matches_host_rounding(dtype):
     x = c.vec(83, 2)
     lib16 = api.convert_parity(c.lat, to_dev(x), dtype)
     host16 = to_dev16(x, dtype)
-    assert torch.equal(lib16, host16)  # FP64 -> FP32 -> 16 bit, round to nearest even both ways
+    assert torch.equal(lib16, host16)  # FP16: one rounding from FP64; BF16: through FP32
     back = api.convert_parity(c.lat, lib16, torch.complex128)
     assert torch.equal(back, to_dev(to_host(host16)))  # widening is exact
     f32 = api.convert_parity(c.lat, lib16, torch.complex64)

@@ -361,6 +361,9 @@ def mixed_vs_fp64(api, synth, torch, dev):
         "mixed_gmres50_rich4_fp16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4, smoother_prec=api.DDQ_F16),
         "mixed_gmres50_rich4_bf16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=4, smoother_prec=api.DDQ_BF16),
         "mixed_gmres50_rich8_fp16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=8, smoother_prec=api.DDQ_F16),
+        "mixed_gmres50_rich12_fp16": dict(inner_prec=api.DDQ_F32, smoother_sweeps=12, smoother_prec=api.DDQ_F16),
+        "mixed_gmres50_rich12_fp16_cgs1": dict(inner_prec=api.DDQ_F32, smoother_sweeps=12,
+                                               smoother_prec=api.DDQ_F16, orth_passes=1),
     }
     for name, kw in variants.items():
         best = None
@@ -430,13 +433,16 @@ def batched(api, synth, torch, dev):
     # all 24 systems: one batched solve (several preconditioner settings) vs one by one
     batch = api.batch_create(lats, [b.shape[0] for b in bs])
     variants = {}
-    for label, nu, sp in (("rich4_fp32", 4, api.DDQ_F32), ("rich4_fp16", 4, api.DDQ_F16),
-                          ("rich8_fp16", 8, api.DDQ_F16), ("rich12_fp16", 12, api.DDQ_F16)):
+    for label, nu, sp, op in (("rich4_fp32", 4, api.DDQ_F32, 2), ("rich4_fp16", 4, api.DDQ_F16, 2),
+                              ("rich8_fp16", 8, api.DDQ_F16, 2), ("rich12_fp16", 12, api.DDQ_F16, 2),
+                              ("rich16_fp16", 16, api.DDQ_F16, 2), ("rich12_fp16_cgs1", 12, api.DDQ_F16, 1),
+                              ("rich16_fp16_cgs1", 16, api.DDQ_F16, 1)):
         best = None
         for _ in range(2):  # the first call tunes, sizes and captures
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            xs, infos, ok = api.batch_solve(batch, bs, omega=oms, m=50, tol=1e-10, smoother_sweeps=nu, smoother_prec=sp)
+            xs, infos, ok = api.batch_solve(batch, bs, omega=oms, m=50, tol=1e-10, smoother_sweeps=nu, smoother_prec=sp,
+                                            orth_passes=op)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             best = dt if best is None else min(best, dt)
@@ -463,8 +469,8 @@ def batched(api, synth, torch, dev):
         torch.cuda.synchronize()
         seq[name] = {"time_s": round(time.perf_counter() - t0, 4), "converged": conv, "max_relres": worst}
     out = {"workload": "24^3x48 x 12 rhs + 8^4, 12^4, 16^3x32 x 4 rhs; eps 0.5, c_sw 1.0, m0 -0.2; GMRES(50) with "
-                       "a Richardson preconditioner (batched: 4-12 sweeps, FP32 or FP16 storage; one by one: 4 "
-                       "sweeps); tol 1e-10",
+                       "a Richardson preconditioner (batched: 4-16 sweeps, FP32 or FP16 storage, CGS2 or one-pass "
+                       "Gram-Schmidt; one by one: 4 FP32 sweeps, CGS2); tol 1e-10",
            "systems": len(infos), "batched_s": round(t_batch, 4), "batched_best": best_label,
            "batched_variants": variants, "sequential": seq,
            "speedup_same_settings_vs_sequential_mixed": round(seq["mixed"]["time_s"] / t_batch4, 3),

@@ -147,8 +147,11 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
  *            thread, 64 sites x 4 right-hand sides per workgroup (the default).
  *   waves    1: a workgroup covers 256 sites; 4: its four wavefronts take four
  *            consecutive right-hand-side groups of the same 64 sites
- *   xcd_map  nonzero: every right-hand-side group of a site block is placed on
- *            the same XCD (shares its L2)
+ *   xcd_map  c in 1..1024: workgroups are ordered XCD by XCD, each XCD walking
+ *            chunks of c consecutive site blocks with every right-hand-side group
+ *            of a block together, so neighbour rows are read through one L2;
+ *            0: the dispatcher's round-robin order.  The 16-bit kernels use the
+ *            xcd_map of the tile set for the same nrhs.
  *   ms       (tuner output) mean time of one Richardson sweep with this tile
  * ddq_set_multi_rhs_tile: use `tile` for launches with nrhs right-hand sides.
  * ddq_tune_multi_rhs: the autotuner.  Times one FP32 Richardson sweep (kernel A +
@@ -199,6 +202,10 @@ int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* 
  *                basis vector is scaled by sqrt(12 V/2) on the way in and back on
  *                the way out (the sweeps are linear); any other value: the
  *                sweeps run in inner_prec
+ *   orth_passes  classical Gram-Schmidt passes per Arnoldi step: 2 (CGS2, the
+ *                default; 0 means 2) or 1 (one pass: half the reads of the basis;
+ *                enough where the cycle's own target, 1e-5 with an FP32 operator,
+ *                lies far above the FP64 loss of orthogonality)
  * x: full vector, in the initial guess, out the solution; b: full vector;
  * both complex128.  info (may be NULL) receives counts and the final residual
  * (FP64, recomputed).  Synchronises the stream. */
@@ -211,6 +218,7 @@ typedef struct {
   double omega;
   double inner_reduction;
   int smoother_prec;
+  int orth_passes;
 } ddq_gmres_params;
 
 typedef struct {

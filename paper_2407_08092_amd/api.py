@@ -275,13 +275,14 @@ def oe_reconstruct(lat: Lattice, x_e: torch.Tensor, b: torch.Tensor) -> torch.Te
 
 def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
                    tol: float = 1e-10, inner_prec: int = DDQ_F64, smoother_sweeps: int = 0, omega: float = 0.0,
-                   inner_reduction: float = 0.0, smoother_prec: int = None):
+                   inner_reduction: float = 0.0, smoother_prec: int = None, orth_passes: int = 2):
     """Odd-even GMRES(m) of Alg. 2 with eq. 2 around it.  Returns (x, info, converged)."""
     if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
         raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
-                    float(inner_reduction), int(inner_prec if smoother_prec is None else smoother_prec))
+                    float(inner_reduction), int(inner_prec if smoother_prec is None else smoother_prec),
+                    int(orth_passes))
     info = SolveInfo()
     lat.sync_stream()
     st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
@@ -330,7 +331,8 @@ def batch_destroy(batch: Batch) -> None:
 
 
 def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, tol: float = 1e-10,
-                smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0, smoother_prec: int = DDQ_F32):
+                smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0, smoother_prec: int = DDQ_F32,
+                orth_passes: int = 2):
     """Solve every (lattice, right-hand side) system of the batch.  bs[l]: complex128
     [nrhs[l], Lt, Lz, Ly, Lx, 4, 3]; omega: one weight or one per lattice.
     Returns (xs, infos, converged) with infos in (lattice, right-hand side) order."""
@@ -349,7 +351,7 @@ def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, 
     bp = (C.c_void_p * len(bs))(*[_dev(b, "b").value for b in bs])
     op = (C.c_double * len(bs))(*om)
     p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F32, int(smoother_sweeps), om[0],
-                    float(inner_reduction), int(smoother_prec))
+                    float(inner_reduction), int(smoother_prec), int(orth_passes))
     infos = (SolveInfo * sum(batch.nrhs))()
     st = check(lib().ddq_batch_solve(batch.handle, xp, bp, C.byref(p), op, infos), "ddq_batch_solve", allow=(0, 1))
     return xs, [i.as_dict() for i in infos], st == 0

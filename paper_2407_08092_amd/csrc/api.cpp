@@ -265,7 +265,7 @@ hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int 
   if (prec == DDQ_F32 && nrhs > 1) {
     const MrTile* t = L->tile_for(nrhs);
     if (t && hop_rb_supported(mode, dag, nrhs, *t))
-      tile = "_nb" + std::to_string(t->nb) + "g" + std::to_string(t->g) + (t->xmap ? "x" : "");
+      tile = "_nb" + std::to_string(t->nb) + "g" + std::to_string(t->g) + (t->xmap ? "x" + std::to_string(t->xmap) : "");
   }
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
                      (dag ? "_dag" : "") + (nrhs > 1 ? "_x" + std::to_string(nrhs) : "") + tile;
@@ -288,6 +288,10 @@ hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* i
   a.out = (u4_t*)out;
   a.omega = omega;
   a.nrhs = nrhs;
+  if (nrhs > 1) {  // the XCD order of the lattice's tuned FP32 tile for this count
+    const MrTile* t = L->tile_for(nrhs);
+    a.chunk = t ? t->xmap : 0;
+  }
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_BF16 ? "_bf16" : "_f16") +
                      (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
   return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
@@ -665,9 +669,9 @@ int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
   MrTile t;
   t.nb = tile->nb;
   t.g = tile->waves;
-  t.xmap = tile->xcd_map ? 1 : 0;
+  t.xmap = tile->xcd_map;
   if (t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t))
-    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4");
+    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4, xcd_map 0..1024");
   for (auto& e : L->tiles)
     if (e.first == nrhs) {
       e.second = t;
@@ -693,7 +697,7 @@ int ddq_tune_multi_rhs(ddq_lattice* L, int nrhs, int reps, ddq_mr_tile* results,
   for (int nb = 1; nb <= MR_MAX_NB; ++nb)
     if (nrhs % nb == 0)
       for (int g : {1, 4})
-        for (int xm : {0, 1}) cand.push_back({nb, g, xm, 0.0});
+        for (int xm : {0, 1, 8, 32}) cand.push_back({nb, g, xm, 0.0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   hipError_t he = hipEventCreate(&e1);
@@ -909,6 +913,8 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
   }
   const int nu = P->smoother_sweeps;
   const bool flexible = nu > 0 || lo;
+  if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
+  const int passes = P->orth_passes == 1 ? 1 : 2;
   const double red = P->inner_reduction > 0.0 ? P->inner_reduction : (lo ? 1e-5 : 0.0);
   const long long n = L->nvec();
   const size_t vb = (size_t)n * 16;
@@ -1010,7 +1016,7 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
       }
       // classical Gram-Schmidt, twice: h = V^H w, w -= V h
       const int kk = k + 1;
-      for (int pass = 0; pass < 2; ++pass) {
+      for (int pass = 0; pass < passes; ++pass) {
         d2_t* h = hdev + pass * 128;
         HIPCHK(launch_dot_partial(V, n, kk, w, n, (d2_t*)L->partial.p, L->nbx, L->stream));
         HIPCHK(launch_reduce_partial((const d2_t*)L->partial.p, L->nbx, kk, h, L->stream));
@@ -1019,7 +1025,9 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
       CHK(norm2_dev(L, w, n, ndev));
       CHK(fetch(L, hdev, 256 * sizeof(d2_t) + sizeof(double)));
       const double* hh = L->host;
-      for (int j = 0; j < kk; ++j) Hcol[j] = cd(hh[2 * j] + hh[256 + 2 * j], hh[2 * j + 1] + hh[256 + 2 * j + 1]);
+      for (int j = 0; j < kk; ++j)
+        Hcol[j] = passes == 2 ? cd(hh[2 * j] + hh[256 + 2 * j], hh[2 * j + 1] + hh[256 + 2 * j + 1])
+                              : cd(hh[2 * j], hh[2 * j + 1]);
       const double hn = std::sqrt(hh[512]);
       if (!std::isfinite(hn)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
       Hcol[kk] = hn;
@@ -1102,6 +1110,7 @@ struct ddq_batch {
   std::vector<hipGraphExec_t> step_graph;  // one per Arnoldi step index
   std::vector<uintptr_t> graph_key;        // what the captured graphs bake in
   int sprec = DDQ_F32;                     // storage of the Richardson preconditioner
+  int passes = 2;                          // Gram-Schmidt passes per Arnoldi step
   double* host = nullptr;                  // pinned
   size_t host_bytes = 0;
 };
@@ -1190,12 +1199,15 @@ int batch_step(ddq_batch* B, int k, int nu) {
     HIPCHK(launch_parity_to_f64(zk, S.x32, S.nrhs, vh, B->stream));
     CHK(schur<float>(L, DDQ_F32, S.nrhs, (const f2_t*)S.x32, (f2_t*)S.w32v, false));
     HIPCHK(launch_parity_to_f64(S.w, S.w32v, S.nrhs, vh, B->stream));
-    // CGS2: h1 = V^H w, w -= V h1, h2 = V^H w, w -= V h2, then |w|^2
+    // classical Gram-Schmidt, one or two passes (h1 = V^H w, w -= V h1, and again
+    // with h2), then |w|^2
     d2_t* part = (d2_t*)S.partial.p;
     HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h1, BLD, B->stream));
     HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h1, BLD, -1.0, S.n, S.nrhs, B->stream));
-    HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h2, BLD, B->stream));
-    HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h2, BLD, -1.0, S.n, S.nrhs, B->stream));
+    if (B->passes == 2) {
+      HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h2, BLD, B->stream));
+      HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h2, BLD, -1.0, S.n, S.nrhs, B->stream));
+    }
     HIPCHK(launch_norm2_b(S.w, S.n, S.nrhs, (double*)part, S.nbx, S.hn, B->stream));
   }
   return DDQ_OK;
@@ -1203,7 +1215,7 @@ int batch_step(ddq_batch* B, int k, int nu) {
 
 // every pointer and value a captured step graph holds
 std::vector<uintptr_t> batch_key(const ddq_batch* B, int m, int nu) {
-  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu, (uintptr_t)B->sprec};
+  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu, (uintptr_t)B->sprec, (uintptr_t)B->passes};
   for (const auto& S : B->sys) {
     const ddq_lattice* L = S.L;
     uint64_t om;
@@ -1341,6 +1353,7 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   const double red = P->inner_reduction > 0.0 ? P->inner_reduction : 1e-5;
   const int ns = (int)B->sys.size();
   const int sprec = is16(P->smoother_prec) ? P->smoother_prec : DDQ_F32;
+  if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
   // pinned host layout: per system, the D2H block then the H2D block
   std::vector<size_t> d2h(ns), h2d(ns);
   size_t host_doubles = 0;
@@ -1362,6 +1375,7 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   HIPCHK(hipStreamWaitEvent(B->stream, B->ev, 0));
   LatticeStreamGuard guard(B);
   B->sprec = sprec;
+  B->passes = P->orth_passes == 1 ? 1 : 2;
   for (auto& S : B->sys) {
     CHK(batch_workspace(S, m));
     if (sprec != DDQ_F32) CHK(ensure_tmp(S.L, sprec, S.nrhs));
@@ -1463,7 +1477,8 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
           const double* h1 = hh + (size_t)r * BLD * 2;
           const double* h2 = hh + ((size_t)S.nrhs + r) * BLD * 2;
           std::vector<cd> col(k + 2);
-          for (int j = 0; j <= k; ++j) col[j] = cd(h1[2 * j] + h2[2 * j], h1[2 * j + 1] + h2[2 * j + 1]);
+          for (int j = 0; j <= k; ++j)
+            col[j] = B->passes == 2 ? cd(h1[2 * j] + h2[2 * j], h1[2 * j + 1] + h2[2 * j + 1]) : cd(h1[2 * j], h1[2 * j + 1]);
           const double nrm = std::sqrt(hn[r]);
           if (!std::isfinite(nrm)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
           col[k + 1] = nrm;

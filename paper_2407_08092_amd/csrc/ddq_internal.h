@@ -25,13 +25,35 @@ enum HopMode {
 // Tile of the register-blocked multi-right-hand-side stencil (FP32): every thread
 // handles nb right-hand sides of one site, so a link or clover entry is loaded
 // once for nb spinors; g wavefronts of a workgroup take consecutive groups of
-// right-hand sides of the same 64 sites (g = 1: 256 sites per workgroup); xmap
-// places all right-hand-side groups of a site block on one XCD.
+// right-hand sides of the same 64 sites (g = 1: 256 sites per workgroup); xmap = c > 0
+// orders workgroups XCD by XCD: each XCD walks chunks of c consecutive site blocks,
+// all right-hand-side groups of a block together, so a block's neighbour rows
+// (+-z, +-t) are mostly read through the same L2 (xmap = 0: the dispatcher's
+// round-robin order).
 struct MrTile {
   int nb = 0;
   int g = 1;
   int xmap = 0;
 };
+
+// workgroup blk -> (site block sb, right-hand-side group rg) of a launch with gr
+// groups per site block; with chunk c > 0 the grid holds nsb padded to 8 c site blocks
+__device__ __forceinline__ void tile_map(int blk, int gr, int c, int& sb, int& rg) {
+  if (c <= 0) {
+    sb = blk / gr;
+    rg = blk % gr;
+    return;
+  }
+  const int xcd = blk & 7, local = blk >> 3;
+  const int per = c * gr;  // workgroups of one chunk
+  const int chunk = local / per, within = local % per;
+  sb = (chunk * 8 + xcd) * c + within / gr;
+  rg = within % gr;
+}
+inline long long tile_grid(long long nsb, int gr, int c) {
+  if (c > 0) nsb = (nsb + 8LL * c - 1) / (8LL * c) * (8LL * c);
+  return nsb * gr;
+}
 constexpr int MR_MAX_NB = 4;
 
 template <typename R>
@@ -81,7 +103,8 @@ struct Hop16Args {
   u4_t* out;
   float omega;
   int nrhs;
-  int nb;  // right-hand sides per thread, 1..3 (0: the largest of 3, 2, 1 dividing nrhs)
+  int nb;     // right-hand sides per thread, 1..3 (0: the largest of 3, 2, 1 dividing nrhs)
+  int chunk;  // XCD order of the workgroups (tile_map), 0: dispatcher order
 };
 hipError_t launch_hop16(int kind, const Hop16Args& a, int mode, hipStream_t s);
 hipError_t launch_parity_to_h16(int kind, void* y, const d2_t* x, double scale, int nrhs, int vh, hipStream_t s);

@@ -63,16 +63,7 @@ hop_kernel_rb(HopArgs<float> a) {
   const int GR = (a.nrhs + NB * G - 1) / (NB * G);  // workgroups per site block
   const int blk = (int)blockIdx.x;
   int sb, rg;
-  if (a.tile.xmap) {
-    // the dispatcher deals workgroups round-robin over the eight XCDs: keep every
-    // right-hand-side group of a site block on the XCD of blk % 8
-    const int local = blk >> 3;
-    sb = (local / GR) * 8 + (blk & 7);
-    rg = local % GR;
-  } else {
-    sb = blk / GR;
-    rg = blk % GR;
-  }
+  tile_map(blk, GR, a.tile.xmap, sb, rg);  // the dispatcher deals workgroups round-robin over 8 XCDs
   const int lane = G == 1 ? (int)threadIdx.x : ((int)threadIdx.x & 63);
   const int w = G == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int r0 = (rg * G + w) * NB;
@@ -141,6 +132,7 @@ bool hop_rb_supported(int mode, bool dagger, int nrhs, const MrTile& t) {
   if (dagger || nrhs < 2) return false;
   if (mode != M_HOP_CLINV && mode != M_APPLY && mode != M_RICH) return false;
   if (t.nb < 1 || t.nb > MR_MAX_NB || nrhs % t.nb != 0) return false;
+  if (t.xmap < 0 || t.xmap > 1024) return false;
   return t.g == 1 || t.g == 4;
 }
 
@@ -148,10 +140,9 @@ template <int MODE, bool L12, int NB>
 static hipError_t rb_launch_g(const HopArgs<float>& a, hipStream_t s) {
   const int G = a.tile.g;
   const long long spw = HOP_BLOCK / G;
-  long long nsb = ((long long)a.g.Vh + spw - 1) / spw;
-  if (a.tile.xmap) nsb = (nsb + 7) / 8 * 8;
-  const long long gr = (a.nrhs + NB * G - 1) / (NB * G);
-  const long long nb = nsb * gr;
+  const long long nsb = ((long long)a.g.Vh + spw - 1) / spw;
+  const int gr = (a.nrhs + NB * G - 1) / (NB * G);
+  const long long nb = tile_grid(nsb, gr, a.tile.xmap);
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   if (G == 1)
     hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 1>), dim3((unsigned)nb), dim3(HOP_BLOCK), 0, s, a);

@@ -137,3 +137,21 @@ def test_batch_argument_errors():
     with pytest.raises(api.DDQError) as e:
         api.batch_solve(batch, [bad], m=8, omega=omegas[0])
     assert e.value.status == -6
+
+
+def test_one_pass_gram_schmidt_converges():
+    cases, bs, omegas = setup_batch()
+    batch = api.batch_create([c.lat for c in cases], [b.shape[0] for b in bs])
+    xs, infos, ok = api.batch_solve(batch, [torch.from_numpy(b).cuda() for b in bs], m=30, tol=1e-10,
+                                    smoother_sweeps=4, omega=omegas, orth_passes=1)
+    assert ok, infos
+    for c, b, x in zip(cases, bs, xs):
+        xh = x.cpu().numpy()
+        for r in range(b.shape[0]):
+            assert true_relres(c, xh[r], b[r]) <= 1.5e-10
+    c, b = cases[2], bs[2][0]
+    x, info, ok = api.oe_gmres_solve(c.lat, torch.from_numpy(b).cuda(), m=30, tol=1e-10, inner_prec=api.DDQ_F32,
+                                     smoother_sweeps=4, omega=omegas[2], orth_passes=1)
+    assert ok and true_relres(c, x.cpu().numpy(), b) <= 1.5e-10
+    with pytest.raises(api.DDQError):
+        api.oe_gmres_solve(c.lat, torch.from_numpy(b).cuda(), m=8, orth_passes=3)

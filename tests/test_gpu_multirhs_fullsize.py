@@ -20,7 +20,7 @@ from paper_2407_08092_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 DIMS = (24, 24, 24, 48)
-TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (0, 1)))
+TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (0, 1, 8, 32)))
 OMEGA = 0.15
 
 
@@ -69,9 +69,12 @@ def test_fp32_tiles_match_single_and_repeat(lat, n):
     api.set_multi_rhs_tile(lat, n, 0, 4, 0)
 
 
+@pytest.mark.parametrize("chunk", [0, 8])
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
 @pytest.mark.parametrize("n", [4, 12])
-def test_16bit_multi_matches_single_and_repeat(lat, dtype, n):
+def test_16bit_multi_matches_single_and_repeat(lat, dtype, n, chunk):
+    # the 16-bit kernels take the XCD order of the FP32 tile set for n
+    api.set_multi_rhs_tile(lat, n, 1, 1, chunk)
     g = synth.gaussian_complex((2, n, 12, lat.Vh), 420 + n)
     x = api.convert_parity(lat, torch.from_numpy(g[0]).cuda(), dtype)
     b = api.convert_parity(lat, torch.from_numpy(g[1]).cuda(), dtype)

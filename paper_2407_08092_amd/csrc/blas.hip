@@ -402,12 +402,19 @@ hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long 
   return hipGetLastError();
 }
 
+#ifndef DDQ_COPY_NT
+#define DDQ_COPY_NT 0
+#endif
 // STREAM-style copy with 16-byte accesses, one element per thread: the
 // attainable-bandwidth probe and the calibration kernel for the traffic counters
 __global__ void __launch_bounds__(RB) k_stream_copy(u4_t* __restrict__ dst, const u4_t* __restrict__ src,
                                                     long long n16) {
   const long long e = (long long)blockIdx.x * RB + threadIdx.x;
+#if DDQ_COPY_NT
+  if (e < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + e), dst + e);
+#else
   if (e < n16) dst[e] = src[e];
+#endif
 }
 
 hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s) {

@@ -147,8 +147,17 @@ __device__ __forceinline__ void store_fence() {
   __builtin_amdgcn_s_waitcnt(0xCF0F);  // expcnt(0); vmcnt and lgkmcnt left at their maxima
   __builtin_amdgcn_sched_barrier(0);
 }
+// cache-policy bits of the stencil's output stores: nt, so that written rows do not
+// displace the neighbour rows still to be read (measured +3.7% on the 48^3 x 96 apply)
+#ifndef DDQ_STORE_AUX
+#define DDQ_STORE_AUX 2
+#endif
+// cache-policy bits of the epilogue's own-site loads (x, b: read once per launch): nt
+#ifndef DDQ_OWN_AUX
+#define DDQ_OWN_AUX 2
+#endif
 __device__ __forceinline__ void st16(const Field& f, int row, uint32_t off, u4_t v) {
-  __builtin_amdgcn_raw_buffer_store_b128(v, f.rsrc, (int)off, (int)(row * f.row_bytes), 0);
+  __builtin_amdgcn_raw_buffer_store_b128(v, f.rsrc, (int)off, (int)(row * f.row_bytes), DDQ_STORE_AUX);
   store_fence();
 }
 
@@ -259,10 +268,10 @@ template <typename R> __device__ __forceinline__ void zero(Spinor<R>& s) {
 }
 
 // spinor of a parity vector (12 complex rows) at lane offset off = voff(i)
-template <typename R>
+template <typename R, int AUX = DDQ_SPINOR_AUX>
 __device__ __forceinline__ Spinor<R> load_spinor(const Field& v, uint32_t off) {
   cpx<R> c[SPINOR_ROWS];
-  load_rows<R, DDQ_SPINOR_AUX>(v, 0, SPINOR_ROWS, off, c);
+  load_rows<R, AUX>(v, 0, SPINOR_ROWS, off, c);
   Spinor<R> s;
 #pragma unroll
   for (int a = 0; a < 4; ++a)

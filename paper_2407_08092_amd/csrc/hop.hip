@@ -76,22 +76,22 @@ hop_kernel(HopArgs<R> a) {
   if constexpr (MODE == M_HOP_CLINV) {
     store_spinor<R>(out, off, clover_mul<R>(cl, coff, acc));
   } else if constexpr (MODE == M_RECON) {
-    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
+    Spinor<R> bb = load_spinor<R, DDQ_OWN_AUX>(vfield(a.b + roff, SP_E, vh), off);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) bb.c[sp][cc] = bb.c[sp][cc] + acc.c[sp][cc];
     store_spinor<R>(out, off, clover_mul<R>(cl, coff, bb));
   } else if constexpr (MODE == M_APPLY) {
-    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(vfield(a.x + roff, SP_E, vh), off));
+    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R, DDQ_OWN_AUX>(vfield(a.x + roff, SP_E, vh), off));
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) cx.c[sp][cc] = cx.c[sp][cc] - acc.c[sp][cc];
     store_spinor<R>(out, off, cx);
   } else if constexpr (MODE == M_RICH) {
-    Spinor<R> xx = load_spinor<R>(vfield(a.x + roff, SP_E, vh), off);
-    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
+    Spinor<R> xx = load_spinor<R, DDQ_OWN_AUX>(vfield(a.x + roff, SP_E, vh), off);
+    Spinor<R> bb = load_spinor<R, DDQ_OWN_AUX>(vfield(a.b + roff, SP_E, vh), off);
     Spinor<R> cx = clover_mul<R>(cl, coff, xx);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
@@ -102,15 +102,15 @@ hop_kernel(HopArgs<R> a) {
       }
     store_spinor<R>(out, off, xx);
   } else if constexpr (MODE == M_RESID) {
-    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
-    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R>(vfield(a.x + roff, SP_E, vh), off));
+    Spinor<R> bb = load_spinor<R, DDQ_OWN_AUX>(vfield(a.b + roff, SP_E, vh), off);
+    Spinor<R> cx = clover_mul<R>(cl, coff, load_spinor<R, DDQ_OWN_AUX>(vfield(a.x + roff, SP_E, vh), off));
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
       for (int cc = 0; cc < 3; ++cc) bb.c[sp][cc] = bb.c[sp][cc] - cx.c[sp][cc] + acc.c[sp][cc];
     store_spinor<R>(out, off, bb);
   } else {  // M_PREP
-    Spinor<R> bb = load_spinor<R>(vfield(a.b + roff, SP_E, vh), off);
+    Spinor<R> bb = load_spinor<R, DDQ_OWN_AUX>(vfield(a.b + roff, SP_E, vh), off);
 #pragma unroll
     for (int sp = 0; sp < 4; ++sp)
 #pragma unroll

@@ -53,11 +53,11 @@ __device__ __forceinline__ Spinor<float> unpack_spinor(const u4_t (&q)[SP16_E]) 
   for (int k = 0; k < 12; ++k) s.c[k / 3][k % 3] = c[k];
   return s;
 }
-template <typename S>
+template <typename S, int AUX = DDQ_SPINOR_AUX>
 __device__ __forceinline__ Spinor<float> load_spinor16(const Field& v, uint32_t off) {
   u4_t q[SP16_E];
 #pragma unroll
-  for (int e = 0; e < SP16_E; ++e) q[e] = ld16<DDQ_SPINOR_AUX>(v, e, off);
+  for (int e = 0; e < SP16_E; ++e) q[e] = ld16<AUX>(v, e, off);
   return unpack_spinor<S>(q);
 }
 template <typename S>
@@ -198,8 +198,8 @@ hop16_kernel(Hop16Args a) {
   for (int q = 0; q < NB; ++q) {
     const size_t roff = (size_t)(r0 + q) * SP16_E * (size_t)vh;
     Spinor<float> xx, bb;
-    if constexpr (MODE != M_HOP_CLINV) xx = load_spinor16<S>(vfield(a.x + roff, SP16_E, vh), off);
-    if constexpr (MODE == M_RICH) bb = load_spinor16<S>(vfield(a.b + roff, SP16_E, vh), off);
+    if constexpr (MODE != M_HOP_CLINV) xx = load_spinor16<S, DDQ_OWN_AUX>(vfield(a.x + roff, SP16_E, vh), off);
+    if constexpr (MODE == M_RICH) bb = load_spinor16<S, DDQ_OWN_AUX>(vfield(a.b + roff, SP16_E, vh), off);
     Spinor<float> res;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {

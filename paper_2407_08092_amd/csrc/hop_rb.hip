@@ -111,14 +111,14 @@ hop_kernel_rb(HopArgs<float> a) {
         clover_block_apply<R>(sl, h, o);
       } else {
         cpx<R> xx[6];
-        load_rows<R, DDQ_SPINOR_AUX>(vfield(a.x + roff, SP_E, vh), 6 * b, 6, off, xx);
+        load_rows<R, DDQ_OWN_AUX>(vfield(a.x + roff, SP_E, vh), 6 * b, 6, off, xx);
         clover_block_apply<R>(sl, xx, o);
         if constexpr (MODE == M_APPLY) {
 #pragma unroll
           for (int k = 0; k < 6; ++k) o[k] = o[k] - h[k];
         } else {  // M_RICH
           cpx<R> bb[6];
-          load_rows<R, DDQ_SPINOR_AUX>(vfield(a.b + roff, SP_E, vh), 6 * b, 6, off, bb);
+          load_rows<R, DDQ_OWN_AUX>(vfield(a.b + roff, SP_E, vh), 6 * b, 6, off, bb);
 #pragma unroll
           for (int k = 0; k < 6; ++k) o[k] = xx[k] + a.omega * (bb[k] - o[k] + h[k]);
         }

@@ -288,7 +288,8 @@ def main():
     del lat
     torch.cuda.empty_cache()
 
-    stream_gbs = stream_probe(api, torch, dev)
+    copy = stream_probe(api, torch, dev)
+    stream_gbs = max(copy.values())
     log(f"stream copy {stream_gbs:.0f} GB/s")
 
     mixed = None
@@ -307,6 +308,7 @@ def main():
                    "dims": list(dims), "even_sites": vh, "sweeps_per_step": SWEEPS, "omega": round(omega, 6)},
         "pct_hbm_peak": round(100 * gbs / HBM_PEAK_GBS, 2),
         "stream_copy_GBs": round(stream_gbs, 1),
+        "stream_copy_detail_GBs": {k: round(v, 1) for k, v in copy.items()},
         "pct_of_stream_copy": round(100 * gbs / stream_gbs, 2),
         "schur_apply_ms": round(t_apply, 4),
         "sweeps_per_s": round(sweeps_per_s, 1),
@@ -324,22 +326,24 @@ def main():
 
 def stream_probe(api, torch, dev, nbytes=4 << 30, reps=5):
     """Attainable HBM bandwidth: the library's STREAM-style copy of 4 GiB,
-    (read + write bytes) / time."""
+    (read + write bytes) / time, plain and with non-temporal accesses."""
     src = torch.empty(nbytes, dtype=torch.uint8, device=dev)
     dst = torch.empty_like(src)
     src.fill_(1)
-    api.stream_copy(dst, src)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    for _ in range(reps):
-        api.stream_copy(dst, src)
-    e1.record()
-    torch.cuda.synchronize()
-    ms = e0.elapsed_time(e1) / reps
+    out = {}
+    for nt in (False, True):
+        api.stream_copy(dst, src, nt)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            api.stream_copy(dst, src, nt)
+        e1.record()
+        torch.cuda.synchronize()
+        out["nontemporal" if nt else "plain"] = 2 * nbytes / (e0.elapsed_time(e1) / reps * 1e-3) / 1e9
     del src, dst
     torch.cuda.empty_cache()
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return out
 
 
 def mixed_vs_fp64(api, synth, torch, dev):

@@ -307,9 +307,12 @@ int ddq_profile_begin(ddq_lattice* lat);
 int ddq_profile_end(ddq_lattice* lat, ddq_kernel_stats* out, int max_entries, int* n_out);
 
 /* STREAM-style device copy of `bytes` (a multiple of 16) from src to dst on
- * hip_stream: the attainable-bandwidth probe reported next to the HBM peak.
- * dst and src are device pointers, 16-byte aligned, not overlapping. */
-int ddq_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream);
+ * hip_stream, one 16-byte element per thread: the attainable-bandwidth probe
+ * reported next to the HBM peak, and (plain form) the calibration kernel of the
+ * traffic counters.  nontemporal != 0 reads and writes with the non-temporal
+ * cache policy.  dst and src are device pointers, 16-byte aligned, not
+ * overlapping. */
+int ddq_stream_copy(void* dst, const void* src, int64_t bytes, int nontemporal, void* hip_stream);
 
 /* Thread-local message of the last error (empty string if none). */
 const char* ddq_last_error(void);

@@ -377,13 +377,15 @@ def profile_end(lat: Lattice):
     return out
 
 
-def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
-    """Device copy through the library's STREAM-style kernel on torch's current stream."""
+def stream_copy(dst: torch.Tensor, src: torch.Tensor, nontemporal: bool = False) -> None:
+    """Device copy through the library's STREAM-style kernel on torch's current stream
+    (nontemporal: non-temporal loads and stores)."""
     nb = src.numel() * src.element_size()
     if dst.numel() * dst.element_size() < nb:
         raise ValueError("dst too small")
     s = torch.cuda.current_stream(src.device).cuda_stream
-    check(lib().ddq_stream_copy(_dev(dst, "dst"), _dev(src, "src"), nb, C.c_void_p(s)), "ddq_stream_copy")
+    check(lib().ddq_stream_copy(_dev(dst, "dst"), _dev(src, "src"), nb, int(bool(nontemporal)), C.c_void_p(s)),
+          "ddq_stream_copy")
 
 
 def backward_apply(lat: Lattice, grad_y_e: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:

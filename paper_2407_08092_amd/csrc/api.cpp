@@ -832,11 +832,11 @@ int ddq_backward_link_force(ddq_lattice* L, const void* chi_e, const void* phi_e
   return DDQ_OK;
 }
 
-int ddq_stream_copy(void* dst, const void* src, int64_t bytes, void* hip_stream) {
+int ddq_stream_copy(void* dst, const void* src, int64_t bytes, int nontemporal, void* hip_stream) {
   if (!dst || !src || bytes < 0 || (bytes & 15) || (((uintptr_t)dst | (uintptr_t)src) & 15))
     return fail(DDQ_ERR_ARG, "stream copy needs 16-byte aligned pointers and a multiple of 16 bytes");
   if (bytes == 0) return DDQ_OK;
-  HIPCHK(launch_stream_copy(dst, src, bytes, (hipStream_t)hip_stream));
+  HIPCHK(launch_stream_copy(dst, src, bytes, nontemporal != 0, (hipStream_t)hip_stream));
   return DDQ_OK;
 }
 

@@ -11,6 +11,19 @@ namespace ddq {
 constexpr int RB = 256;    // threads per reduction workgroup
 constexpr int DOT_J = 8;   // basis vectors per dot workgroup
 
+// Basis vectors are streamed once per kernel: non-temporal loads keep them from
+// displacing the vector w that the dot kernels re-read per basis chunk.
+#ifndef DDQ_BASIS_NT
+#define DDQ_BASIS_NT 1
+#endif
+__device__ __forceinline__ d2_t ld_basis(const d2_t* p) {
+#if DDQ_BASIS_NT
+  return __builtin_nontemporal_load(p);
+#else
+  return *p;
+#endif
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -49,7 +62,7 @@ __global__ void __launch_bounds__(RB) k_dot_partial(const d2_t* __restrict__ V, 
 #pragma unroll
     for (int jj = 0; jj < DOT_J; ++jj) {
       if (jj < nj) {
-        d2_t v = V[(size_t)(j0 + jj) * vstride + e];
+        d2_t v = ld_basis(V + (size_t)(j0 + jj) * vstride + e);
         acc[2 * jj] = fma(v.x, we.x, fma(v.y, we.y, acc[2 * jj]));
         acc[2 * jj + 1] = fma(v.x, we.y, fma(-v.y, we.x, acc[2 * jj + 1]));
       }
@@ -109,7 +122,7 @@ __global__ void __launch_bounds__(RB) k_update(d2_t* __restrict__ w, const d2_t*
   for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
     double ar = 0.0, ai = 0.0;
     for (int j = 0; j < k; ++j) {
-      d2_t v = V[(size_t)j * vstride + e];
+      d2_t v = ld_basis(V + (size_t)j * vstride + e);
       d2_t hj = hs[j];
       ar = fma(v.x, hj.x, fma(-v.y, hj.y, ar));
       ai = fma(v.x, hj.y, fma(v.y, hj.x, ai));
@@ -262,7 +275,7 @@ __global__ void __launch_bounds__(RB) k_dot_partial_b(const d2_t* __restrict__ V
 #pragma unroll
     for (int jj = 0; jj < DOT_J; ++jj) {
       if (jj < nj) {
-        d2_t v = Vr[(size_t)(j0 + jj) * vstride + e];
+        d2_t v = ld_basis(Vr + (size_t)(j0 + jj) * vstride + e);
         acc[2 * jj] = fma(v.x, we.x, fma(v.y, we.y, acc[2 * jj]));
         acc[2 * jj + 1] = fma(v.x, we.y, fma(-v.y, we.x, acc[2 * jj + 1]));
       }
@@ -324,7 +337,7 @@ __global__ void __launch_bounds__(RB) k_update_b(d2_t* __restrict__ w, const d2_
   for (long long e = (long long)blockIdx.x * RB + threadIdx.x; e < n; e += stride) {
     double ar = 0.0, ai = 0.0;
     for (int j = 0; j < k; ++j) {
-      d2_t v = Vr[(size_t)j * vstride + e];
+      d2_t v = ld_basis(Vr + (size_t)j * vstride + e);
       d2_t hj = hs[j];
       ar = fma(v.x, hj.x, fma(-v.y, hj.y, ar));
       ai = fma(v.x, hj.y, fma(v.y, hj.x, ai));
@@ -402,26 +415,28 @@ hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long 
   return hipGetLastError();
 }
 
-#ifndef DDQ_COPY_NT
-#define DDQ_COPY_NT 0
-#endif
 // STREAM-style copy with 16-byte accesses, one element per thread: the
 // attainable-bandwidth probe and the calibration kernel for the traffic counters
+template <bool NT>
 __global__ void __launch_bounds__(RB) k_stream_copy(u4_t* __restrict__ dst, const u4_t* __restrict__ src,
                                                     long long n16) {
   const long long e = (long long)blockIdx.x * RB + threadIdx.x;
-#if DDQ_COPY_NT
-  if (e < n16) __builtin_nontemporal_store(__builtin_nontemporal_load(src + e), dst + e);
-#else
-  if (e < n16) dst[e] = src[e];
-#endif
+  if (e >= n16) return;
+  if constexpr (NT)
+    __builtin_nontemporal_store(__builtin_nontemporal_load(src + e), dst + e);
+  else
+    dst[e] = src[e];
 }
 
-hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s) {
+hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, bool nontemporal, hipStream_t s) {
   const long long n16 = bytes / 16;
   const long long blocks = (n16 + RB - 1) / RB;
   if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_stream_copy, dim3((unsigned)blocks), dim3(RB), 0, s, (u4_t*)dst, (const u4_t*)src, n16);
+  if (nontemporal)
+    hipLaunchKernelGGL(k_stream_copy<true>, dim3((unsigned)blocks), dim3(RB), 0, s, (u4_t*)dst, (const u4_t*)src, n16);
+  else
+    hipLaunchKernelGGL(k_stream_copy<false>, dim3((unsigned)blocks), dim3(RB), 0, s, (u4_t*)dst, (const u4_t*)src,
+                       n16);
   return hipGetLastError();
 }
 

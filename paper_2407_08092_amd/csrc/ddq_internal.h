@@ -133,7 +133,7 @@ hipError_t launch_axpy(d2_t* y, double ar, double ai, const d2_t* x, long long n
 hipError_t launch_copy(d2_t* y, const d2_t* x, long long n, hipStream_t s);
 hipError_t launch_scale_f32(f2_t* y, const f2_t* x, float a, long long n, hipStream_t s);
 
-hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, hipStream_t s);
+hipError_t launch_stream_copy(void* dst, const void* src, long long bytes, bool nontemporal, hipStream_t s);
 
 // batched (nrhs systems, vector r at offset r * n; basis j at j * vstride)
 hipError_t launch_dot_b(const d2_t* V, long long vstride, int k, const d2_t* w, long long n, int nrhs, d2_t* partial,

@@ -440,13 +440,15 @@ def batched(api, synth, torch, dev):
     for label, nu, sp, op in (("rich4_fp32", 4, api.DDQ_F32, 2), ("rich4_fp16", 4, api.DDQ_F16, 2),
                               ("rich8_fp16", 8, api.DDQ_F16, 2), ("rich12_fp16", 12, api.DDQ_F16, 2),
                               ("rich16_fp16", 16, api.DDQ_F16, 2), ("rich12_fp16_cgs1", 12, api.DDQ_F16, 1),
-                              ("rich16_fp16_cgs1", 16, api.DDQ_F16, 1)):
+                              ("rich16_fp16_cgs1", 16, api.DDQ_F16, 1), ("rich16_fp16_cgs1_cycle12", 16, api.DDQ_F16, 1)):
         best = None
         for _ in range(2):  # the first call tunes, sizes and captures
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            xs, infos, ok = api.batch_solve(batch, bs, omega=oms, m=50, tol=1e-10, smoother_sweeps=nu, smoother_prec=sp,
-                                            orth_passes=op)
+            cyc = "_cycle" in label  # one graph launch per restart cycle of m steps
+            m = int(label.split("_cycle")[1]) if cyc else 50
+            xs, infos, ok = api.batch_solve(batch, bs, omega=oms, m=m, tol=1e-10, smoother_sweeps=nu, smoother_prec=sp,
+                                            orth_passes=op, cycle_graph=cyc)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             best = dt if best is None else min(best, dt)

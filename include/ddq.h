@@ -202,6 +202,13 @@ int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* 
  *                basis vector is scaled by sqrt(12 V/2) on the way in and back on
  *                the way out (the sweeps are linear); any other value: the
  *                sweeps run in inner_prec
+ *   cycle_graph  (ddq_batch_solve only) nonzero: every restart cycle runs exactly
+ *                m Arnoldi steps as one HIP graph launch, the basis normalisation
+ *                computed on the device, and the host reads every step's
+ *                coefficients once per cycle, keeping per system the columns up to
+ *                the first whose estimate meets the cycle target (the steps after it
+ *                are spent); 0: one graph and one host synchronisation per step,
+ *                each system leaving the cycle when its estimate meets the target
  *   orth_passes  classical Gram-Schmidt passes per Arnoldi step: 2 (CGS2, the
  *                default; 0 means 2) or 1 (one pass: half the reads of the basis;
  *                enough where the cycle's own target, 1e-5 with an FP32 operator,
@@ -219,6 +226,7 @@ typedef struct {
   double inner_reduction;
   int smoother_prec;
   int orth_passes;
+  int cycle_graph;
 } ddq_gmres_params;
 
 typedef struct {

@@ -29,7 +29,7 @@ class DDQError(RuntimeError):
 class GmresParams(C.Structure):
     _fields_ = [("m", C.c_int), ("max_cycles", C.c_int), ("tol", C.c_double), ("inner_prec", C.c_int),
                 ("smoother_sweeps", C.c_int), ("omega", C.c_double), ("inner_reduction", C.c_double),
-                ("smoother_prec", C.c_int), ("orth_passes", C.c_int)]
+                ("smoother_prec", C.c_int), ("orth_passes", C.c_int), ("cycle_graph", C.c_int)]
 
 
 class SolveInfo(C.Structure):

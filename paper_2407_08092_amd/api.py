@@ -332,7 +332,7 @@ def batch_destroy(batch: Batch) -> None:
 
 def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, tol: float = 1e-10,
                 smoother_sweeps: int = 4, omega=0.0, inner_reduction: float = 0.0, smoother_prec: int = DDQ_F32,
-                orth_passes: int = 2):
+                orth_passes: int = 2, cycle_graph: bool = False):
     """Solve every (lattice, right-hand side) system of the batch.  bs[l]: complex128
     [nrhs[l], Lt, Lz, Ly, Lx, 4, 3]; omega: one weight or one per lattice.
     Returns (xs, infos, converged) with infos in (lattice, right-hand side) order."""
@@ -351,7 +351,7 @@ def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, 
     bp = (C.c_void_p * len(bs))(*[_dev(b, "b").value for b in bs])
     op = (C.c_double * len(bs))(*om)
     p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F32, int(smoother_sweeps), om[0],
-                    float(inner_reduction), int(smoother_prec), int(orth_passes))
+                    float(inner_reduction), int(smoother_prec), int(orth_passes), int(bool(cycle_graph)))
     infos = (SolveInfo * sum(batch.nrhs))()
     st = check(lib().ddq_batch_solve(batch.handle, xp, bp, C.byref(p), op, infos), "ddq_batch_solve", allow=(0, 1))
     return xs, [i.as_dict() for i in infos], st == 0

@@ -1101,6 +1101,10 @@ struct ddq_batch {
     void *b32 = nullptr, *x32 = nullptr, *w32v = nullptr;
     d2_t *h1 = nullptr, *h2 = nullptr, *y = nullptr;
     double *hn = nullptr, *f = nullptr;
+    // cycle mode: the coefficients of every step of a cycle, [step][rhs][...]
+    Grow cyc;
+    d2_t *ch1 = nullptr, *ch2 = nullptr;
+    double *chn = nullptr, *cf = nullptr;
     double omega = 0.0;
   };
   std::vector<Sys> sys;
@@ -1111,6 +1115,7 @@ struct ddq_batch {
   std::vector<uintptr_t> graph_key;        // what the captured graphs bake in
   int sprec = DDQ_F32;                     // storage of the Richardson preconditioner
   int passes = 2;                          // Gram-Schmidt passes per Arnoldi step
+  int cycle = 0;                           // 1: one graph per restart cycle of m steps
   double* host = nullptr;                  // pinned
   size_t host_bytes = 0;
 };
@@ -1138,10 +1143,10 @@ int batch_host(ddq_batch* B, size_t bytes) {
 
 // device scalars of one system: h1, h2 (BLD complex per right-hand side), |w|^2
 // (contiguous, fetched in one copy), then y (BLD complex) and the scale factors
-size_t batch_d2h_bytes(int nrhs) { return (size_t)nrhs * (2 * BLD * 16 + 8); }
+size_t batch_d2h_bytes(int nrhs, int steps = 1) { return (size_t)steps * nrhs * (2 * BLD * 16 + 8); }
 size_t batch_h2d_doubles(int nrhs) { return (size_t)nrhs * (2 * BLD + 1); }
 
-int batch_workspace(ddq_batch::Sys& S, int m) {
+int batch_workspace(ddq_batch::Sys& S, int m, bool cycle) {
   const size_t N = (size_t)S.nrhs * S.n;  // complex numbers of a batched vector
   CHK(S.w64.ensure((size_t)(2 * m + 5) * N * 16));
   d2_t* p = (d2_t*)S.w64.p;
@@ -1162,6 +1167,14 @@ int batch_workspace(ddq_batch::Sys& S, int m) {
   S.y = (d2_t*)(S.hn + S.nrhs);
   S.f = (double*)(S.y + (size_t)S.nrhs * BLD);
   CHK(S.partial.ensure((size_t)S.nbx * S.nrhs * BLD * 16));
+  if (cycle) {
+    const size_t mr = (size_t)m * S.nrhs;
+    CHK(S.cyc.ensure(batch_d2h_bytes(S.nrhs, m) + mr * 8));
+    S.ch1 = (d2_t*)S.cyc.p;
+    S.ch2 = S.ch1 + mr * BLD;
+    S.chn = (double*)(S.ch2 + mr * BLD);
+    S.cf = S.chn + mr;
+  }
   CHK(ensure_tmp(S.L, DDQ_F32, S.nrhs));
   CHK(ensure_tmp(S.L, DDQ_F64, S.nrhs));
   return DDQ_OK;
@@ -1179,7 +1192,13 @@ int batch_step(ddq_batch* B, int k, int nu) {
     d2_t* vk = S.V + (size_t)k * N;
     d2_t* zk = S.Z + (size_t)k * N;
     const int vh = (int)L->Vh;
-    if (k > 0) HIPCHK(launch_scale_b(vk, S.w, S.f, S.n, S.nrhs, B->stream));
+    // per-step coefficient slots in cycle mode, else one set reused every step
+    const size_t cs = (size_t)k * S.nrhs;
+    d2_t* h1 = B->cycle ? S.ch1 + cs * BLD : S.h1;
+    d2_t* h2 = B->cycle ? S.ch2 + cs * BLD : S.h2;
+    double* hn = B->cycle ? S.chn + cs : S.hn;
+    const double* fk = B->cycle ? S.cf + cs - S.nrhs : S.f;  // factor of v_k from step k - 1
+    if (k > 0) HIPCHK(launch_scale_b(vk, S.w, fk, S.n, S.nrhs, B->stream));
     if (nu > 0 && is16(B->sprec)) {
       // 16-bit storage: scaled so that the unit-norm v_k has entries of order one
       const double sc = std::sqrt((double)S.n);
@@ -1202,25 +1221,29 @@ int batch_step(ddq_batch* B, int k, int nu) {
     // classical Gram-Schmidt, one or two passes (h1 = V^H w, w -= V h1, and again
     // with h2), then |w|^2
     d2_t* part = (d2_t*)S.partial.p;
-    HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h1, BLD, B->stream));
-    HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h1, BLD, -1.0, S.n, S.nrhs, B->stream));
+    HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, h1, BLD, B->stream));
+    HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, h1, BLD, -1.0, S.n, S.nrhs, B->stream));
     if (B->passes == 2) {
-      HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, S.h2, BLD, B->stream));
-      HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, S.h2, BLD, -1.0, S.n, S.nrhs, B->stream));
+      HIPCHK(launch_dot_b(S.V, (long long)N, k + 1, S.w, S.n, S.nrhs, part, S.nbx, h2, BLD, B->stream));
+      HIPCHK(launch_update_b(S.w, S.V, (long long)N, k + 1, h2, BLD, -1.0, S.n, S.nrhs, B->stream));
     }
-    HIPCHK(launch_norm2_b(S.w, S.n, S.nrhs, (double*)part, S.nbx, S.hn, B->stream));
+    HIPCHK(launch_norm2_b(S.w, S.n, S.nrhs, (double*)part, S.nbx, hn, B->stream));
+    // cycle mode: the next basis vector's factor 1/|w| on the device (0 after a
+    // breakdown |w| <= 1e-14 and for right-hand sides that entered the cycle converged)
+    if (B->cycle) HIPCHK(launch_inv_norm_b(hn, S.cf + cs, S.nrhs, 1e-28, B->stream));
   }
   return DDQ_OK;
 }
 
 // every pointer and value a captured step graph holds
 std::vector<uintptr_t> batch_key(const ddq_batch* B, int m, int nu) {
-  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu, (uintptr_t)B->sprec, (uintptr_t)B->passes};
+  std::vector<uintptr_t> key{(uintptr_t)m, (uintptr_t)nu, (uintptr_t)B->sprec, (uintptr_t)B->passes,
+                             (uintptr_t)B->cycle};
   for (const auto& S : B->sys) {
     const ddq_lattice* L = S.L;
     uint64_t om;
     std::memcpy(&om, &S.omega, 8);
-    for (uintptr_t v : {(uintptr_t)S.w64.p, (uintptr_t)S.w32.p, (uintptr_t)S.small.p, (uintptr_t)S.partial.p,
+    for (uintptr_t v : {(uintptr_t)S.w64.p, (uintptr_t)S.w32.p, (uintptr_t)S.small.p, (uintptr_t)S.partial.p, (uintptr_t)S.cyc.p,
                         (uintptr_t)L->tmp[DDQ_F32].p, (uintptr_t)L->tmp[B->sprec].p,
                         (uintptr_t)L->links[B->sprec][0], (uintptr_t)L->links[B->sprec][1],
                         (uintptr_t)L->clov[B->sprec][0], (uintptr_t)L->clov[B->sprec][1],
@@ -1238,11 +1261,14 @@ int batch_capture(ddq_batch* B, int m, int nu) {
   std::vector<uintptr_t> key = batch_key(B, m, nu);
   if (key == B->graph_key) return DDQ_OK;
   batch_release_graphs(B);
-  B->step_graph.assign(m, nullptr);
-  for (int k = 0; k < m; ++k) {
+  // per-step mode: one graph per step index; cycle mode: one graph of all m steps
+  const int ngraph = B->cycle ? 1 : m;
+  B->step_graph.assign(ngraph, nullptr);
+  for (int k = 0; k < ngraph; ++k) {
     hipGraph_t g = nullptr;
     HIPCHK(hipStreamBeginCapture(B->stream, hipStreamCaptureModeThreadLocal));
-    int r = batch_step(B, k, nu);
+    int r = DDQ_OK;
+    for (int q = B->cycle ? 0 : k; q <= (B->cycle ? m - 1 : k) && r == DDQ_OK; ++q) r = batch_step(B, q, nu);
     hipError_t e = hipStreamEndCapture(B->stream, &g);
     if (r < 0 || e != hipSuccess) {
       if (g) (void)hipGraphDestroy(g);
@@ -1332,6 +1358,7 @@ int ddq_batch_destroy(ddq_batch* B) {
     S.w32.release();
     S.small.release();
     S.partial.release();
+    S.cyc.release();
   }
   if (B->host) (void)hipHostFree(B->host);
   if (B->ev) (void)hipEventDestroy(B->ev);
@@ -1354,6 +1381,7 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   const int ns = (int)B->sys.size();
   const int sprec = is16(P->smoother_prec) ? P->smoother_prec : DDQ_F32;
   if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
+  const int cycle = P->cycle_graph ? 1 : 0;
   // pinned host layout: per system, the D2H block then the H2D block
   std::vector<size_t> d2h(ns), h2d(ns);
   size_t host_doubles = 0;
@@ -1365,7 +1393,7 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
     S.omega = omegas ? omegas[s] : P->omega;
     if (nu > 0 && !(std::isfinite(S.omega) && S.omega > 0.0)) return fail(DDQ_ERR_ARG, "omega must be positive");
     d2h[s] = host_doubles;
-    host_doubles += batch_d2h_bytes(S.nrhs) / 8;
+    host_doubles += batch_d2h_bytes(S.nrhs, cycle ? m : 1) / 8;
     h2d[s] = host_doubles;
     host_doubles += batch_h2d_doubles(S.nrhs);
   }
@@ -1376,8 +1404,9 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
   LatticeStreamGuard guard(B);
   B->sprec = sprec;
   B->passes = P->orth_passes == 1 ? 1 : 2;
+  B->cycle = cycle;
   for (auto& S : B->sys) {
-    CHK(batch_workspace(S, m));
+    CHK(batch_workspace(S, m, cycle));
     if (sprec != DDQ_F32) CHK(ensure_tmp(S.L, sprec, S.nrhs));
   }
   // multi-right-hand-side tiles: tuned on first use
@@ -1457,7 +1486,59 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
       CHK(push(s, S.f, 2 * BLD * S.nrhs, S.nrhs * 8));
       HIPCHK(launch_scale_b(S.V, S.V, S.f, S.n, S.nrhs, B->stream));
     }
-    for (int k = 0; k < m; ++k) {
+    // Givens update of right-hand side R with Hessenberg column k (h1 + h2, |w| = nrm);
+    // returns false on a non-finite norm
+    auto column = [&](RhsState& R, int k, const double* h1, const double* h2, double nrm) -> bool {
+      if (!std::isfinite(nrm)) return false;
+      std::vector<cd> col(k + 2);
+      for (int j = 0; j <= k; ++j)
+        col[j] = h2 ? cd(h1[2 * j] + h2[2 * j], h1[2 * j + 1] + h2[2 * j + 1]) : cd(h1[2 * j], h1[2 * j + 1]);
+      col[k + 1] = nrm;
+      for (int j = 0; j < k; ++j) {
+        cd t = R.rot[j].c * col[j] + R.rot[j].s * col[j + 1];
+        col[j + 1] = -std::conj(R.rot[j].s) * col[j] + R.rot[j].c * col[j + 1];
+        col[j] = t;
+      }
+      R.rot[k] = make_givens(col[k], col[k + 1]);
+      col[k] = R.rot[k].c * col[k] + R.rot[k].s * col[k + 1];
+      R.g[k + 1] = -std::conj(R.rot[k].s) * R.g[k];
+      R.g[k] = R.rot[k].c * R.g[k];
+      for (int j = 0; j <= k; ++j) R.R[k][j] = col[j];
+      R.k_used = k + 1;
+      return true;
+    };
+    if (cycle) {
+      // the whole cycle is one graph of m steps (basis factors on the device); the
+      // host reads every step's coefficients once and, per right-hand side, takes the
+      // columns up to the first whose estimate meets the cycle target (or a
+      // breakdown): the update the step-by-step mode makes, the later steps unused
+      HIPCHK(hipGraphLaunch(B->step_graph[0], B->stream));
+      for (int s = 0; s < ns; ++s)
+        HIPCHK(hipMemcpyAsync(B->host + d2h[s], B->sys[s].ch1, batch_d2h_bytes(B->sys[s].nrhs, m),
+                              hipMemcpyDeviceToHost, B->stream));
+      HIPCHK(hipStreamSynchronize(B->stream));
+      iters += m;
+      for (int s = 0; s < ns; ++s) {
+        auto& S = B->sys[s];
+        const size_t mr = (size_t)m * S.nrhs;
+        const double* c1 = B->host + d2h[s];
+        const double* c2 = c1 + mr * BLD * 2;
+        const double* cn = c2 + mr * BLD * 2;
+        for (int r = 0; r < S.nrhs; ++r) {
+          auto& R = st[s][r];
+          if (!R.active) continue;
+          for (int k = 0; k < m; ++k) {
+            const size_t slot = (size_t)k * S.nrhs + r;
+            const double nrm = std::sqrt(cn[slot]);
+            if (!column(R, k, c1 + slot * BLD * 2, B->passes == 2 ? c2 + slot * BLD * 2 : nullptr, nrm))
+              return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
+            // breakdown: the device zeroed the later basis vectors
+            if (std::abs(R.g[k + 1]) <= std::max(R.target, red * R.beta) || nrm <= 1e-14) break;
+          }
+        }
+      }
+    }
+    for (int k = 0; k < m && !cycle; ++k) {
       HIPCHK(hipGraphLaunch(B->step_graph[k], B->stream));
       for (int s = 0; s < ns; ++s)
         HIPCHK(hipMemcpyAsync(B->host + d2h[s], B->sys[s].h1, batch_d2h_bytes(B->sys[s].nrhs),
@@ -1476,23 +1557,9 @@ int ddq_batch_solve(ddq_batch* B, void* const* x, const void* const* b, const dd
           if (R.stopped) continue;
           const double* h1 = hh + (size_t)r * BLD * 2;
           const double* h2 = hh + ((size_t)S.nrhs + r) * BLD * 2;
-          std::vector<cd> col(k + 2);
-          for (int j = 0; j <= k; ++j)
-            col[j] = B->passes == 2 ? cd(h1[2 * j] + h2[2 * j], h1[2 * j + 1] + h2[2 * j + 1]) : cd(h1[2 * j], h1[2 * j + 1]);
           const double nrm = std::sqrt(hn[r]);
-          if (!std::isfinite(nrm)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
-          col[k + 1] = nrm;
-          for (int j = 0; j < k; ++j) {
-            cd t = R.rot[j].c * col[j] + R.rot[j].s * col[j + 1];
-            col[j + 1] = -std::conj(R.rot[j].s) * col[j] + R.rot[j].c * col[j + 1];
-            col[j] = t;
-          }
-          R.rot[k] = make_givens(col[k], col[k + 1]);
-          col[k] = R.rot[k].c * col[k] + R.rot[k].s * col[k + 1];
-          R.g[k + 1] = -std::conj(R.rot[k].s) * R.g[k];
-          R.g[k] = R.rot[k].c * R.g[k];
-          for (int j = 0; j <= k; ++j) R.R[k][j] = col[j];
-          R.k_used = k + 1;
+          if (!column(R, k, h1, B->passes == 2 ? h2 : nullptr, nrm))
+            return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
           if (std::abs(R.g[k + 1]) <= std::max(R.target, red * R.beta) || nrm <= 1e-14 * R.beta) {
             R.stopped = true;
           } else {

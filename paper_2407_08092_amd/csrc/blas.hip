@@ -415,6 +415,19 @@ hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long 
   return hipGetLastError();
 }
 
+// f[r] = 1 / sqrt(hn[r]) where hn[r] > tiny2, else 0 (the next basis vector's factor)
+__global__ void k_inv_norm_b(const double* __restrict__ hn, double* __restrict__ f, int nrhs, double tiny2) {
+  const int r = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (r >= nrhs) return;
+  const double h = hn[r];
+  f[r] = h > tiny2 ? 1.0 / sqrt(h) : 0.0;
+}
+
+hipError_t launch_inv_norm_b(const double* hn, double* f, int nrhs, double tiny2, hipStream_t s) {
+  hipLaunchKernelGGL(k_inv_norm_b, dim3((nrhs + 63) / 64), dim3(64), 0, s, hn, f, nrhs, tiny2);
+  return hipGetLastError();
+}
+
 // STREAM-style copy with 16-byte accesses, one element per thread: the
 // attainable-bandwidth probe and the calibration kernel for the traffic counters
 template <bool NT>

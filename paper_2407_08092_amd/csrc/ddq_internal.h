@@ -142,6 +142,7 @@ hipError_t launch_update_b(d2_t* w, const d2_t* V, long long vstride, int k, con
                            long long n, int nrhs, hipStream_t s);
 hipError_t launch_norm2_b(const d2_t* w, long long n, int nrhs, double* partial, int nbx, double* out, hipStream_t s);
 hipError_t launch_scale_b(d2_t* out, const d2_t* in, const double* f, long long n, int nrhs, hipStream_t s);
+hipError_t launch_inv_norm_b(const double* hn, double* f, int nrhs, double tiny2, hipStream_t s);
 
 // link force: insertions W (V x 54 complex) then per-link G (V x 4 x 9 complex) / F (V x 4 x 8)
 hipError_t launch_force(const Geo& g, const d2_t* U, const d2_t* chi_e, const d2_t* lam_o, const d2_t* phi_e,

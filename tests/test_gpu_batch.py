@@ -155,3 +155,28 @@ def test_one_pass_gram_schmidt_converges():
     assert ok and true_relres(c, x.cpu().numpy(), b) <= 1.5e-10
     with pytest.raises(api.DDQError):
         api.oe_gmres_solve(c.lat, torch.from_numpy(b).cuda(), m=8, orth_passes=3)
+
+
+def test_cycle_graph_mode_matches_step_mode():
+    # one graph launch per restart cycle: the same systems to the same tolerance;
+    # with the cycle target met inside the cycle the update equals the step mode's
+    cases, bs, omegas = setup_batch()
+    bd = [torch.from_numpy(b).cuda() for b in bs]
+    batch = api.batch_create([c.lat for c in cases], [b.shape[0] for b in bs])
+    xs, infos, ok = api.batch_solve(batch, bd, m=24, tol=1e-10, smoother_sweeps=4, omega=omegas, cycle_graph=True)
+    x1, infos1, ok1 = api.batch_solve(batch, bd, m=24, tol=1e-10, smoother_sweeps=4, omega=omegas)
+    assert ok and ok1, infos
+    assert infos[0]["cycles"] == infos1[0]["cycles"]
+    for c, b, x, y in zip(cases, bs, xs, x1):
+        xh = x.cpu().numpy()
+        for r in range(b.shape[0]):
+            assert true_relres(c, xh[r], b[r]) <= 1.5e-10
+        assert rel(xh, y.cpu().numpy()) < 1e-8
+    # a short cycle that cannot reach the target within m steps still converges
+    xs, infos, ok = api.batch_solve(batch, bd, m=4, max_cycles=200, tol=1e-10, smoother_sweeps=4, omega=omegas,
+                                    cycle_graph=True)
+    assert ok
+    for c, b, x in zip(cases, bs, xs):
+        xh = x.cpu().numpy()
+        for r in range(b.shape[0]):
+            assert true_relres(c, xh[r], b[r]) <= 1.5e-10

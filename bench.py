@@ -23,6 +23,8 @@ the timed region.  Reported:
   cpu_baseline   the FP64 NumPy oracle on the host, on a bounded sample
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-batch] [--no-cpu]
+       python bench.py --multi-rhs-only   (profiling run: only the 12-right-hand-side apply on 24^3 x 48,
+                                           prints its own JSON, not the benchmark line)
 """
 from __future__ import annotations
 
@@ -123,11 +125,22 @@ def main():
     ap.add_argument("--no-solve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--multi-rhs-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is single-GPU; "
               f"multi-GPU sharding is design only)", file=sys.stderr)
         sys.exit(2)
+
+    if args.multi_rhs_only:
+        import torch
+
+        from paper_2407_08092_amd import api, synth
+
+        torch.cuda.set_device(0)
+        multi, _ = batched(api, synth, torch, torch.device("cuda:0"), solve=False)
+        print(json.dumps({"multi_rhs": multi}), flush=True)
+        return
 
     cpu = None if args.no_cpu else cpu_baseline()
     if cpu:
@@ -390,8 +403,8 @@ def mixed_vs_fp64(api, synth, torch, dev):
             "speedup": round(fp64_best / mixed_best, 3)}
 
 
-def batched(api, synth, torch, dev):
-    """Multi-right-hand-side apply and the batched solve of uneven lattices."""
+def batched(api, synth, torch, dev, solve=True):
+    """Multi-right-hand-side apply and (solve) the batched solve of uneven lattices."""
     lats, bs, oms = [], [], []
     for dims, n, seed in BATCH:
         lat = api.create_lattice(dims, device=dev)
@@ -433,6 +446,11 @@ def batched(api, synth, torch, dev):
     log(f"multi-rhs: {multi['apply_ms']} ms = {multi['apply_GBs']} GB/s, x{multi['speedup_vs_single_loop']} "
         f"vs {n} single applies, tile {best}")
     del x, y, x1, y1
+    if not solve:
+        for lat in lats:
+            api.destroy_lattice(lat)
+        torch.cuda.empty_cache()
+        return multi, None
 
     # all 24 systems: one batched solve (several preconditioner settings) vs one by one
     batch = api.batch_create(lats, [b.shape[0] for b in bs])

@@ -150,8 +150,12 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
  *   xcd_map  c in 1..1024: workgroups are ordered XCD by XCD, each XCD walking
  *            chunks of c consecutive site blocks with every right-hand-side group
  *            of a block together, so neighbour rows are read through one L2;
- *            0: the dispatcher's round-robin order.  The 16-bit kernels use the
- *            xcd_map of the tile set for the same nrhs.
+ *            0: the dispatcher's round-robin order; -1: slab order (every
+ *            t-slice cut into eight pieces of whole 64-site groups, XCD k walking
+ *            piece k of each slice in t order, so z- and t-neighbours share its
+ *            L2; the order of the one-right-hand-side kernels).  The 16-bit
+ *            kernels use the xcd_map of the tile set for the same nrhs, slab
+ *            order if none.
  *   ms       (tuner output) mean time of one Richardson sweep with this tile
  * ddq_set_multi_rhs_tile: use `tile` for launches with nrhs right-hand sides.
  * ddq_tune_multi_rhs: the autotuner.  Times one FP32 Richardson sweep (kernel A +

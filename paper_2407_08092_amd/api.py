@@ -222,10 +222,11 @@ def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweep
     return x_e
 
 
-def set_multi_rhs_tile(lat: Lattice, nrhs: int, nb: int, waves: int = 4, xcd_map: bool = False) -> None:
+def set_multi_rhs_tile(lat: Lattice, nrhs: int, nb: int, waves: int = 4, xcd_map: int = 0) -> None:
     """Tile of the FP32 multi-right-hand-side stencil for launches of nrhs right-hand
-    sides (nb = 0: one right-hand side per thread)."""
-    t = _lib.MrTile(int(nb), int(waves), int(bool(xcd_map)), 0.0)
+    sides (nb = 0: one right-hand side per thread; xcd_map: 0 dispatcher order, c > 0
+    chunks of c site blocks per XCD, -1 slab order)."""
+    t = _lib.MrTile(int(nb), int(waves), int(xcd_map), 0.0)
     check(lib().ddq_set_multi_rhs_tile(lat.handle, int(nrhs), C.byref(t)), "ddq_set_multi_rhs_tile")
 
 

@@ -288,10 +288,9 @@ hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* i
   a.out = (u4_t*)out;
   a.omega = omega;
   a.nrhs = nrhs;
-  if (nrhs > 1) {  // the XCD order of the lattice's tuned FP32 tile for this count
-    const MrTile* t = L->tile_for(nrhs);
-    a.chunk = t ? t->xmap : 0;
-  }
+  // workgroup order: that of the lattice's FP32 tile for this count, else slab order
+  const MrTile* t = nrhs > 1 ? L->tile_for(nrhs) : nullptr;
+  a.chunk = t ? t->xmap : XMAP_SLAB;
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_BF16 ? "_bf16" : "_f16") +
                      (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
   return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
@@ -671,7 +670,7 @@ int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
   t.g = tile->waves;
   t.xmap = tile->xcd_map;
   if (t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t))
-    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4, xcd_map 0..1024");
+    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4, xcd_map -1..1024");
   for (auto& e : L->tiles)
     if (e.first == nrhs) {
       e.second = t;
@@ -697,7 +696,7 @@ int ddq_tune_multi_rhs(ddq_lattice* L, int nrhs, int reps, ddq_mr_tile* results,
   for (int nb = 1; nb <= MR_MAX_NB; ++nb)
     if (nrhs % nb == 0)
       for (int g : {1, 4})
-        for (int xm : {0, 1, 8, 32}) cand.push_back({nb, g, xm, 0.0});
+        for (int xm : {XMAP_SLAB, 0, 1, 8, 32}) cand.push_back({nb, g, xm, 0.0});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   hipError_t he = hipEventCreate(&e1);

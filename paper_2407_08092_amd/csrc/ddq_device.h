@@ -254,6 +254,30 @@ __device__ __forceinline__ int xcd_block(int nblocks_padded) {
   return (b & 7) * per + (b >> 3);
 }
 
+// Slab order.  Each t-slice (g.sT sites) is cut into eight contiguous pieces of whole
+// 64-site groups; XCD k (workgroup w runs on XCD w mod 8) walks piece k of slice 0,
+// then piece k of slice 1, and so on.  All XCDs advance through the same t-slices
+// together, and the z- and t-neighbours of an XCD's sites lie in its own pieces a few
+// workgroups apart, so they are fetched once into that XCD's L2.
+// q: the caller's 64-site group within XCD xcd's walk.  Returns false past the end;
+// else sets [base, end): the group's sites (end clips a partial group at the slice end).
+__device__ __forceinline__ bool slab_group(const Geo& g, int xcd, int q, int& base, int& end) {
+  const int P = g.sT;
+  const int ng = (P + 63) >> 6;
+  const int g0 = (xcd * ng) >> 3, n = (((xcd + 1) * ng) >> 3) - g0;
+  if (n <= 0) return false;
+  const int t = q / n;
+  if (t >= g.L[3]) return false;
+  base = t * P + (g0 + q - t * n) * 64;
+  end = min(base + 64, (t + 1) * P);
+  return true;
+}
+// 64-site groups in the longest XCD walk
+inline long long slab_groups_per_xcd(const Geo& g) {
+  const long long ng = (g.sT + 63) / 64;
+  return (long long)g.L[3] * ((ng + 7) / 8);
+}
+
 // ---------------------------------------------------------------------------
 // spinors: 4 spins x 3 colours
 // ---------------------------------------------------------------------------

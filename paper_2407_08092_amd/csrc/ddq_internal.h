@@ -29,7 +29,7 @@ enum HopMode {
 // orders workgroups XCD by XCD: each XCD walks chunks of c consecutive site blocks,
 // all right-hand-side groups of a block together, so a block's neighbour rows
 // (+-z, +-t) are mostly read through the same L2 (xmap = 0: the dispatcher's
-// round-robin order).
+// round-robin order; xmap = XMAP_SLAB: slab order, slab_group).
 struct MrTile {
   int nb = 0;
   int g = 1;
@@ -53,6 +53,35 @@ __device__ __forceinline__ void tile_map(int blk, int gr, int c, int& sb, int& r
 inline long long tile_grid(long long nsb, int gr, int c) {
   if (c > 0) nsb = (nsb + 8LL * c - 1) / (8LL * c) * (8LL * c);
   return nsb * gr;
+}
+constexpr int XMAP_SLAB = -1;
+// site i of thread `lane` of workgroup blk and its right-hand-side group rg, for site
+// blocks of spw sites (a multiple of 64; lane >> 6 is the thread's wavefront) and gr
+// workgroups per site block; false if the thread has no site.  Slab order walks
+// 64-site groups (slab_group) with all gr workgroups of a site block together.
+__device__ __forceinline__ bool tile_site(const Geo& g, int blk, int gr, int c, int spw, int lane, int& i,
+                                          int& rg) {
+  if (c != XMAP_SLAB) {
+    int sb;
+    tile_map(blk, gr, c, sb, rg);
+    i = sb * spw + lane;
+    return i < g.Vh;
+  }
+  const int local = blk >> 3;
+  rg = local % gr;
+  const int q = (local / gr) * (spw >> 6) + __builtin_amdgcn_readfirstlane(lane >> 6);
+  int base, end;
+  if (!slab_group(g, blk & 7, q, base, end)) return false;
+  i = base + (lane & 63);
+  return i < end;
+}
+// workgroups of a tile_site launch
+inline long long tile_grid_sites(const Geo& g, int spw, int gr, int c) {
+  if (c == XMAP_SLAB) {
+    const long long per = spw / 64;
+    return 8LL * ((slab_groups_per_xcd(g) + per - 1) / per) * gr;
+  }
+  return tile_grid(((long long)g.Vh + spw - 1) / spw, gr, c);
 }
 constexpr int MR_MAX_NB = 4;
 
@@ -104,7 +133,7 @@ struct Hop16Args {
   float omega;
   int nrhs;
   int nb;     // right-hand sides per thread, 1..3 (0: the largest of 3, 2, 1 dividing nrhs)
-  int chunk;  // XCD order of the workgroups (tile_map), 0: dispatcher order
+  int chunk;  // XCD order of the workgroups (tile_site): 0 dispatcher order, c > 0 chunks, XMAP_SLAB
 };
 hipError_t launch_hop16(int kind, const Hop16Args& a, int mode, hipStream_t s);
 hipError_t launch_parity_to_h16(int kind, void* y, const d2_t* x, double scale, int nrhs, int vh, hipStream_t s);

@@ -18,6 +18,11 @@ namespace ddq {
 #ifndef DDQ_WAVES_F32
 #define DDQ_WAVES_F32 4
 #endif
+// workgroup order of the one-right-hand-side kernels: 0 = the dispatcher's, 1 = slab
+// order (slab_group)
+#ifndef DDQ_SITE_ORDER
+#define DDQ_SITE_ORDER 1
+#endif
 template <typename R> struct HOP_WAVES { static constexpr int value = DDQ_WAVES_F32; };
 template <> struct HOP_WAVES<double> { static constexpr int value = DDQ_WAVES_F64; };
 
@@ -27,7 +32,15 @@ hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
   int i, rhs;
   if constexpr (!MR) {
+#if DDQ_SITE_ORDER
+    const int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+    int base, end;
+    if (!slab_group(a.g, (int)(blockIdx.x & 7), q, base, end)) return;
+    i = base + ((int)threadIdx.x & 63);
+    if (i >= end) return;
+#else
     i = xcd_block(a.nblk) * HOP_BLOCK + (int)threadIdx.x;
+#endif
     rhs = 0;
   } else {
     // several right-hand sides: a workgroup is 64 sites x (HOP_BLOCK / 64) right-hand
@@ -153,9 +166,15 @@ template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a0, int mode, bool dagger, int nrhs, hipStream_t s) {
   HopArgs<R> a = a0;
   a.nrhs = nrhs;
+#if DDQ_SITE_ORDER
+  const long long per = (slab_groups_per_xcd(a.g) + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+  if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
+  a.nblk = (int)(8 * per);
+#else
   int nb = (a.g.Vh + HOP_BLOCK - 1) / HOP_BLOCK;
   const int pad = 8 * (DDQ_XCD_CHUNK > 0 ? DDQ_XCD_CHUNK : 1);
   a.nblk = ((nb + pad - 1) / pad) * pad;
+#endif
   switch (mode) {
     case M_HOP_CLINV: return launch_mode<R, M_HOP_CLINV>(a, dagger, nrhs, s);
     case M_RECON: return launch_mode<R, M_RECON>(a, dagger, nrhs, s);

@@ -152,16 +152,14 @@ __device__ __forceinline__ void set_block_rows(Spinor<float>& s, int b, const cp
 }
 
 // One thread per output site and NB right-hand sides; workgroup blk covers 256 sites
-// of one group of NB right-hand sides (tile_map); the links and clover slots of the
+// of one group of NB right-hand sides (tile_site); the links and clover slots of the
 // site are loaded once for the NB spinors.
 template <typename S, int MODE, int NB>
 __global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(NB > 1 ? 2 : 4)))
 hop16_kernel(Hop16Args a) {
   const int vh = a.g.Vh;
-  int sb, rg;
-  tile_map((int)blockIdx.x, a.nrhs / NB, a.chunk, sb, rg);
-  const int i = sb * HOP_BLOCK + (int)threadIdx.x;
-  if (i >= vh) return;
+  int i, rg;
+  if (!tile_site(a.g, (int)blockIdx.x, a.nrhs / NB, a.chunk, HOP_BLOCK, (int)threadIdx.x, i, rg)) return;
   const int r0 = rg * NB;
   Field in[NB];
 #pragma unroll
@@ -232,7 +230,7 @@ hop16_kernel(Hop16Args a) {
 
 template <typename S, int NB>
 static hipError_t launch16_nb(const Hop16Args& a, int mode, hipStream_t s) {
-  const long long nb = tile_grid((a.g.Vh + HOP_BLOCK - 1) / HOP_BLOCK, a.nrhs / NB, a.chunk);
+  const long long nb = tile_grid_sites(a.g, HOP_BLOCK, a.nrhs / NB, a.chunk);
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(HOP_BLOCK);
   switch (mode) {
@@ -262,7 +260,7 @@ hipError_t launch_hop16(int kind, const Hop16Args& a0, int mode, hipStream_t s) 
         a.nb = nb;
         break;
       }
-  if (a.nrhs < 1 || a.nb < 1 || a.nb > 3 || a.nrhs % a.nb != 0 || a.chunk < 0 || a.chunk > 1024)
+  if (a.nrhs < 1 || a.nb < 1 || a.nb > 3 || a.nrhs % a.nb != 0 || a.chunk < XMAP_SLAB || a.chunk > 1024)
     return hipErrorInvalidValue;
   return kind == H16_BF16 ? launch16_s<__bf16>(a, mode, s) : launch16_s<_Float16>(a, mode, s);
 }

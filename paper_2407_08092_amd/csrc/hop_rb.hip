@@ -61,14 +61,12 @@ hop_kernel_rb(HopArgs<float> a) {
   constexpr int SP_E = SPINOR_ROWS / CPE<R>;
   const int vh = a.g.Vh;
   const int GR = (a.nrhs + NB * G - 1) / (NB * G);  // workgroups per site block
-  const int blk = (int)blockIdx.x;
-  int sb, rg;
-  tile_map(blk, GR, a.tile.xmap, sb, rg);  // the dispatcher deals workgroups round-robin over 8 XCDs
   const int lane = G == 1 ? (int)threadIdx.x : ((int)threadIdx.x & 63);
   const int w = G == 1 ? 0 : __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int i, rg;  // the dispatcher deals workgroups round-robin over 8 XCDs
+  if (!tile_site(a.g, (int)blockIdx.x, GR, a.tile.xmap, SPW, lane, i, rg)) return;
   const int r0 = (rg * G + w) * NB;
-  const int i = sb * SPW + lane;
-  if (r0 >= a.nrhs || i >= vh) return;
+  if (r0 >= a.nrhs) return;
 
   Field in[NB];
 #pragma unroll
@@ -132,17 +130,15 @@ bool hop_rb_supported(int mode, bool dagger, int nrhs, const MrTile& t) {
   if (dagger || nrhs < 2) return false;
   if (mode != M_HOP_CLINV && mode != M_APPLY && mode != M_RICH) return false;
   if (t.nb < 1 || t.nb > MR_MAX_NB || nrhs % t.nb != 0) return false;
-  if (t.xmap < 0 || t.xmap > 1024) return false;
+  if (t.xmap < XMAP_SLAB || t.xmap > 1024) return false;
   return t.g == 1 || t.g == 4;
 }
 
 template <int MODE, bool L12, int NB>
 static hipError_t rb_launch_g(const HopArgs<float>& a, hipStream_t s) {
   const int G = a.tile.g;
-  const long long spw = HOP_BLOCK / G;
-  const long long nsb = ((long long)a.g.Vh + spw - 1) / spw;
   const int gr = (a.nrhs + NB * G - 1) / (NB * G);
-  const long long nb = tile_grid(nsb, gr, a.tile.xmap);
+  const long long nb = tile_grid_sites(a.g, HOP_BLOCK / G, gr, a.tile.xmap);
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   if (G == 1)
     hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 1>), dim3((unsigned)nb), dim3(HOP_BLOCK), 0, s, a);

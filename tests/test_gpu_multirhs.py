@@ -3,9 +3,10 @@ oracle applied to each right-hand side on its own (FP32 bar: 1e-5 relative per
 right-hand side), and against the one-right-hand-side-per-thread kernel.
 
 Every tile is covered: nb (right-hand sides per thread) 0..4, one or four
-wavefronts per site block, XCD order off or in chunks of 1, 8, 32 site blocks
-(more chunks than the small lattices have blocks: the padded grid), 18- and
-12-real links.
+wavefronts per site block, XCD order off, in chunks of 1, 8, 32 site blocks
+(more chunks than the small lattices have blocks: the padded grid) or slab order
+(t-slices cut into eight pieces of 64-site groups: on these lattices some XCDs get
+none), 18- and 12-real links.
 Lattices 4x6x8x10 (V/2 = 960: 15 blocks of 64 sites, 3.75 of 256) and 6x6x6x10
 (V/2 = 1080: ragged for both) with 12 right-hand sides (divisible by 1, 2, 3, 4).
 """
@@ -23,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 NRHS = 12
 DIMS = [(4, 6, 8, 10), (6, 6, 6, 10)]
-TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (0, 1, 8, 32)))
+TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
 _cache = {}
 
 

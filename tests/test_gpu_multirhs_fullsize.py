@@ -20,7 +20,7 @@ from paper_2407_08092_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 DIMS = (24, 24, 24, 48)
-TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (0, 1, 8, 32)))
+TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
 OMEGA = 0.15
 
 
@@ -69,7 +69,7 @@ def test_fp32_tiles_match_single_and_repeat(lat, n):
     api.set_multi_rhs_tile(lat, n, 0, 4, 0)
 
 
-@pytest.mark.parametrize("chunk", [0, 8])
+@pytest.mark.parametrize("chunk", [-1, 0, 8])
 @pytest.mark.parametrize("dtype", [torch.float16, torch.bfloat16], ids=["f16", "bf16"])
 @pytest.mark.parametrize("n", [4, 12])
 def test_16bit_multi_matches_single_and_repeat(lat, dtype, n, chunk):

@@ -144,7 +144,9 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
  * block applications cache-friendly (Sect. 5); the tiling is this library's.
  *   nb       right-hand sides per thread (links and clover slots loaded once for
  *            nb spinors); 1..4 and dividing nrhs.  0: one right-hand side per
- *            thread, 64 sites x 4 right-hand sides per workgroup (the default).
+ *            thread, 64 sites x 4 right-hand sides per workgroup, the workgroups
+ *            in the order xcd_map (the default, with slab order; also the FP64
+ *            kernels' and the modes the tiles do not cover).
  *   waves    1: a workgroup covers 256 sites; 4: its four wavefronts take four
  *            consecutive right-hand-side groups of the same 64 sites
  *   xcd_map  c in 1..1024: workgroups are ordered XCD by XCD, each XCD walking

@@ -205,17 +205,19 @@ int prof_flush(ddq_lattice* L) {
 // the multi-right-hand-side FP32 kernels take the lattice's tuned tile when one fits
 template <typename R>
 hipError_t launch_any(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
+  const MrTile* t = nrhs > 1 ? L->tile_for(nrhs) : nullptr;
+  HopArgs<R> b = a;
   if constexpr (sizeof(R) == 4) {
-    if (nrhs > 1) {
-      const MrTile* t = L->tile_for(nrhs);
-      if (t && hop_rb_supported(mode, dag, nrhs, *t)) {
-        HopArgs<float> b = a;
-        b.tile = *t;
-        return launch_hop_rb(b, mode, nrhs, L->stream);
-      }
+    if (t && hop_rb_supported(mode, dag, nrhs, *t)) {
+      b.tile = *t;
+      return launch_hop_rb(b, mode, nrhs, L->stream);
     }
   }
-  return launch_hop<R>(a, mode, dag, nrhs, L->stream);
+  // one right-hand side per thread: the workgroup order of an nb = 0 tile set for
+  // nrhs, else slab order
+  b.tile = MrTile{};
+  b.tile.xmap = (t && t->nb == 0) ? t->xmap : XMAP_SLAB;
+  return launch_hop<R>(b, mode, dag, nrhs, L->stream);
 }
 
 // run `launch` bracketed by profiling events on the lattice's stream (when on),
@@ -669,7 +671,7 @@ int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
   t.nb = tile->nb;
   t.g = tile->waves;
   t.xmap = tile->xcd_map;
-  if (t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t))
+  if ((t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t)) || t.xmap < XMAP_SLAB || t.xmap > 1024)
     return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4, xcd_map -1..1024");
   for (auto& e : L->tiles)
     if (e.first == nrhs) {
@@ -692,7 +694,8 @@ int ddq_tune_multi_rhs(ddq_lattice* L, int nrhs, int reps, ddq_mr_tile* results,
   f2_t* b = x + N;
   HIPCHK(hipMemsetAsync(x, 0, 2 * N * 8, L->stream));
   std::vector<ddq_mr_tile> cand;
-  cand.push_back({0, 4, 0, 0.0});  // one right-hand side per thread, the 64-site x 4 mapping
+  for (int xm : {XMAP_SLAB, 0})  // one right-hand side per thread, the 64-site x 4 mapping
+    cand.push_back({0, 4, xm, 0.0});
   for (int nb = 1; nb <= MR_MAX_NB; ++nb)
     if (nrhs % nb == 0)
       for (int g : {1, 4})

@@ -44,13 +44,15 @@ hop_kernel(HopArgs<R> a) {
     rhs = 0;
   } else {
     // several right-hand sides: a workgroup is 64 sites x (HOP_BLOCK / 64) right-hand
-    // sides, so its wavefronts read the same link and clover entries; consecutive
-    // workgroups take the other right-hand-side groups of the same 64 sites
+    // sides, so its wavefronts read the same link and clover entries; the workgroups
+    // of the other right-hand-side groups of the same 64 sites follow it on the same
+    // XCD (workgroup order a.tile.xmap, tile_site)
     // the wavefront's right-hand side, made explicitly uniform (an SGPR)
     const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
     const int groups = (a.nrhs + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
-    i = (int)(blockIdx.x / groups) * 64 + ((int)threadIdx.x & 63);
-    rhs = (int)(blockIdx.x % groups) * (HOP_BLOCK / 64) + w;
+    int rg;
+    if (!tile_site(a.g, (int)blockIdx.x, groups, a.tile.xmap, 64, (int)threadIdx.x & 63, i, rg)) return;
+    rhs = rg * (HOP_BLOCK / 64) + w;
     if (rhs >= a.nrhs) return;
   }
   if (i >= vh) return;
@@ -136,8 +138,9 @@ template <typename R, int MODE>
 static hipError_t launch_mode(const HopArgs<R>& a, bool dagger, int nrhs, hipStream_t s) {
   dim3 block(HOP_BLOCK), grid(a.nblk);
   if (nrhs > 1) {
-    const long long groups = (nrhs + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
-    const long long nb = ((long long)a.g.Vh + 63) / 64 * groups;
+    const int groups = (nrhs + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+    if (a.tile.xmap < XMAP_SLAB || a.tile.xmap > 1024) return hipErrorInvalidValue;
+    const long long nb = tile_grid_sites(a.g, 64, groups, a.tile.xmap);
     if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
     grid = dim3((unsigned)nb);
   }

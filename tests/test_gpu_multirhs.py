@@ -24,7 +24,7 @@ pytestmark = pytest.mark.gpu
 
 NRHS = 12
 DIMS = [(4, 6, 8, 10), (6, 6, 6, 10)]
-TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
+TILES = [(0, 4, 0), (0, 4, -1)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
 _cache = {}
 
 

@@ -20,7 +20,7 @@ from paper_2407_08092_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 DIMS = (24, 24, 24, 48)
-TILES = [(0, 4, 0)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
+TILES = [(0, 4, 0), (0, 4, -1)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
 OMEGA = 0.15
 
 

@@ -219,6 +219,13 @@ def main():
                                 "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
                             for k, v in prof.items()}}
 
+    # the streaming ceiling of each stencil kernel's byte mix on the same fields
+    mix = stencil_stream_ceiling(api, torch, lat, x32, xs, b32, y32, args.steps)
+    roof["stream_mix_GBs"] = mix
+    if "stream_" + name in mix:
+        roof["frac_of_stream_mix"] = round(ach / mix["stream_" + name], 4)
+    log(f"streaming ceilings of the stencil kernels' byte mix: {mix}")
+
     # the same FP32 step with 12-real links (third row rebuilt from unitarity)
     U = synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev)
     api.set_gauge(lat, U, link12=True)
@@ -335,6 +342,23 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def stencil_stream_ceiling(api, torch, lat, vin, x, b, out, reps):
+    """GB/s of the library's streaming-ceiling probe for kernels A, B apply and B
+    Richardson: each kernel's algorithmic bytes, layouts, workgroup order and cache
+    policies without the neighbour gathers and the arithmetic, timed by the same
+    library profiling as the stencil."""
+    for k in range(3):
+        api.stencil_stream(lat, k, vin, out, x, b)
+    torch.cuda.synchronize()
+    api.profile_begin(lat)
+    for _ in range(max(reps, 5)):
+        for k in range(3):
+            api.stencil_stream(lat, k, vin, out, x, b)
+    torch.cuda.synchronize()
+    prof = api.profile_end(lat)
+    return {k: round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1) for k, v in prof.items()}
 
 
 def stream_probe(api, torch, dev, nbytes=4 << 30, reps=5):

@@ -328,6 +328,24 @@ int ddq_profile_end(ddq_lattice* lat, ddq_kernel_stats* out, int max_entries, in
  * overlapping. */
 int ddq_stream_copy(void* dst, const void* src, int64_t bytes, int nontemporal, void* hip_stream);
 
+/* Streaming ceiling of a one-right-hand-side stencil kernel: a measurement aid
+ * reported next to the HBM peak, not part of the operator.  For every site it moves
+ * the bytes that kernel moves once per site -- the input spinor (the site's own rows
+ * in place of its eight neighbours'), the four link fields and the clover field of
+ * the lattice's `prec` storage (12-real FP32 links if stored so), x and b where the
+ * kernel reads them, the output rows -- with the same layouts, workgroup order and
+ * cache policies, combined without arithmetic: the rate the memory system delivers
+ * for the kernel's byte mix without its neighbour gathers.
+ *   kernel  0: A (in -> out, odd links and clover), 1: B apply (in, x -> out),
+ *           2: B Richardson (in, x, b -> out; even links and clover)
+ *   prec    DDQ_F32 or DDQ_F64; in, x, b, out: parity vectors of that precision on
+ *           the lattice's device (x, b may be NULL where unread; out receives
+ *           meaningless values and must not overlap the others)
+ * Launched on the lattice's stream; profiled as stream_<kernel name> when
+ * profiling is on (the same algorithmic bytes as the stencil kernel). */
+int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, const void* x, const void* b,
+                       void* out);
+
 /* Thread-local message of the last error (empty string if none). */
 const char* ddq_last_error(void);
 

@@ -26,7 +26,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
-    "stream_copy", "backward_apply", "backward_link_force", "convert_parity",
+    "stream_copy", "stencil_stream", "backward_apply", "backward_link_force", "convert_parity",
     "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
@@ -387,6 +387,23 @@ def stream_copy(dst: torch.Tensor, src: torch.Tensor, nontemporal: bool = False)
     s = torch.cuda.current_stream(src.device).cuda_stream
     check(lib().ddq_stream_copy(_dev(dst, "dst"), _dev(src, "src"), nb, int(bool(nontemporal)), C.c_void_p(s)),
           "ddq_stream_copy")
+
+
+def stencil_stream(lat: Lattice, kernel: int, in_e: torch.Tensor, out: torch.Tensor, x_e: torch.Tensor = None,
+                   b_e: torch.Tensor = None) -> None:
+    """Streaming ceiling of stencil kernel 0 (A), 1 (B apply) or 2 (B Richardson) on
+    FP32 or FP64 parity vectors: the kernel's bytes without gathers or arithmetic
+    (out receives meaningless values)."""
+    if tuple(in_e.shape) != _parity_shape(lat, in_e.dtype):
+        raise ValueError("one right-hand side parity vector expected")
+    vecs = [v for v in (in_e, out, x_e, b_e) if v is not None]
+    if any(v.dtype != in_e.dtype or v.shape != in_e.shape for v in vecs):
+        raise ValueError("all vectors must match in dtype and shape")
+    lat.sync_stream()
+    check(lib().ddq_stencil_stream(lat.handle, _prec(in_e), int(kernel), _dev(in_e, "in_e"),
+                                   None if x_e is None else _dev(x_e, "x_e"),
+                                   None if b_e is None else _dev(b_e, "b_e"), _dev(out, "out")),
+          "ddq_stencil_stream")
 
 
 def backward_apply(lat: Lattice, grad_y_e: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:

@@ -842,6 +842,32 @@ int ddq_stream_copy(void* dst, const void* src, int64_t bytes, int nontemporal, 
   return DDQ_OK;
 }
 
+int ddq_stencil_stream(ddq_lattice* L, int prec, int kernel, const void* in, const void* x, const void* b, void* out) {
+  CHK(check_ready(L, prec));
+  if (prec != DDQ_F32 && prec != DDQ_F64) return fail(DDQ_ERR_ARG, "the stencil stream probe takes DDQ_F32 or DDQ_F64");
+  if (kernel < 0 || kernel > 2) return fail(DDQ_ERR_ARG, "kernel must be 0 (A), 1 (B apply) or 2 (B Richardson)");
+  if (!in || !out || (kernel >= 1 && !x) || (kernel == 2 && !b)) return fail(DDQ_ERR_ARG, "missing vector");
+  const int mode = kernel == 0 ? M_HOP_CLINV : (kernel == 1 ? M_APPLY : M_RICH);
+  const int p_out = kernel == 0 ? 1 : 0;
+  auto run = [&](auto tag) -> hipError_t {
+    using T = decltype(tag);
+    HopArgs<T> a = hop_args<T>(L, prec, p_out);
+    a.in = (const pair<T>*)in;
+    a.x = (const pair<T>*)x;
+    a.b = (const pair<T>*)b;
+    a.out = (pair<T>*)out;
+    a.nrhs = 1;
+    std::string name = std::string("stream_") + mode_name(mode) +
+                       (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32"));
+    return prof_launch(L, name, hop_bytes(L, prec, mode, 1), [&]() { return launch_hop_stream<T>(a, mode, L->stream); });
+  };
+  if (prec == DDQ_F64)
+    HIPCHK(run(double{}));
+  else
+    HIPCHK(run(float{}));
+  return DDQ_OK;
+}
+
 int ddq_profile_begin(ddq_lattice* L) {
   CHK(check_lat(L));
   L->prof_on = true;

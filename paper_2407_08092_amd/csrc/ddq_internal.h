@@ -110,6 +110,10 @@ constexpr int HOP_BLOCK = DDQ_HOP_BLOCK;
 
 template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a, int mode, bool dagger, int nrhs, hipStream_t s);
+// the streaming ceiling of launch_hop's one-right-hand-side kernel for mode
+// (M_HOP_CLINV, M_APPLY, M_RICH): the same bytes without gathers or arithmetic
+template <typename R>
+hipError_t launch_hop_stream(const HopArgs<R>& a, int mode, hipStream_t s);
 
 // register-blocked FP32 multi-right-hand-side stencil for modes M_HOP_CLINV, M_APPLY
 // and M_RICH (not daggered); a.tile.nb in [2, MR_MAX_NB] must divide nrhs.  Returns

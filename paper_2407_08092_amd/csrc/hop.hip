@@ -26,21 +26,37 @@ namespace ddq {
 template <typename R> struct HOP_WAVES { static constexpr int value = DDQ_WAVES_F32; };
 template <> struct HOP_WAVES<double> { static constexpr int value = DDQ_WAVES_F64; };
 
+// site of this thread in a one-right-hand-side launch (grid: one_rhs_grid); false if none
+__device__ __forceinline__ bool one_rhs_site(const Geo& g, int nblk, int& i) {
+#if DDQ_SITE_ORDER
+  const int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int base, end;
+  if (!slab_group(g, (int)(blockIdx.x & 7), q, base, end)) return false;
+  i = base + ((int)threadIdx.x & 63);
+  return i < end;
+#else
+  i = xcd_block(nblk) * HOP_BLOCK + (int)threadIdx.x;
+  return i < g.Vh;
+#endif
+}
+static int one_rhs_grid(const Geo& g) {
+#if DDQ_SITE_ORDER
+  const long long per = (slab_groups_per_xcd(g) + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+  return 8 * per > 0x7fffffffLL ? -1 : (int)(8 * per);
+#else
+  int nb = (g.Vh + HOP_BLOCK - 1) / HOP_BLOCK;
+  const int pad = 8 * (DDQ_XCD_CHUNK > 0 ? DDQ_XCD_CHUNK : 1);
+  return ((nb + pad - 1) / pad) * pad;
+#endif
+}
+
 template <typename R, int MODE, bool DAG, bool L12, bool MR>
 __global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(HOP_WAVES<R>::value)))
 hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
   int i, rhs;
   if constexpr (!MR) {
-#if DDQ_SITE_ORDER
-    const int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
-    int base, end;
-    if (!slab_group(a.g, (int)(blockIdx.x & 7), q, base, end)) return;
-    i = base + ((int)threadIdx.x & 63);
-    if (i >= end) return;
-#else
-    i = xcd_block(a.nblk) * HOP_BLOCK + (int)threadIdx.x;
-#endif
+    if (!one_rhs_site(a.g, a.nblk, i)) return;
     rhs = 0;
   } else {
     // several right-hand sides: a workgroup is 64 sites x (HOP_BLOCK / 64) right-hand
@@ -134,6 +150,80 @@ hop_kernel(HopArgs<R> a) {
   }
 }
 
+// Streaming ceiling of hop_kernel<R, MODE> with one right-hand side (a measurement
+// aid, not part of D_S): every site moves the element rows the stencil kernel moves
+// once per site -- the input spinor (the site's own rows in place of its eight
+// neighbours'), the four link fields, the clover field, x and b where the mode reads
+// them, the output rows -- with the same layouts, workgroup order and cache
+// policies, combined by XOR without arithmetic.
+template <typename R, int MODE, bool L12>
+__global__ void __launch_bounds__(HOP_BLOCK) hop_stream_kernel(HopArgs<R> a) {
+  int i;
+  if (!one_rhs_site(a.g, a.nblk, i)) return;
+  const int vh = a.g.Vh;
+  constexpr int SP_E = SPINOR_ROWS / CPE<R>;
+  constexpr int LR = L12 ? LINK12_ROWS : LINK_ROWS;
+  constexpr int CL_E = CLOVER_ROWS / CPE<R>;
+  const uint32_t off = voff(i);
+  u4_t acc = {0u, 0u, 0u, 0u};
+  const Field in = vfield(a.in, SP_E, vh);
+#pragma unroll
+  for (int k = 0; k < SP_E; ++k) acc ^= ld16<DDQ_SPINOR_AUX>(in, k, off);
+  const uint32_t loff = boff(i, LR / CPE<R>);
+#pragma unroll
+  for (int mu = 0; mu < 4; ++mu) {
+    const Field U = bfield(a.links + (size_t)mu * LR * field_vh(vh), LR / CPE<R>, vh);
+#pragma unroll
+    for (int k = 0; k < LR / CPE<R>; ++k) acc ^= ld16<DDQ_STREAM_AUX>(U, k, loff);
+  }
+  const Field cl = bfield(a.clov, CL_E, vh);
+  const uint32_t coff = boff(i, CL_E);
+#pragma unroll
+  for (int k = 0; k < CL_E; ++k) acc ^= ld16<DDQ_STREAM_AUX>(cl, k, coff);
+  if constexpr (MODE != M_HOP_CLINV) {
+    const Field x = vfield(a.x, SP_E, vh);
+#pragma unroll
+    for (int k = 0; k < SP_E; ++k) acc ^= ld16<DDQ_OWN_AUX>(x, k, off);
+  }
+  if constexpr (MODE == M_RICH) {
+    const Field b = vfield(a.b, SP_E, vh);
+#pragma unroll
+    for (int k = 0; k < SP_E; ++k) acc ^= ld16<DDQ_OWN_AUX>(b, k, off);
+  }
+  const Field out = vfield(a.out, SP_E, vh);
+#pragma unroll
+  for (int k = 0; k < SP_E; ++k) {
+    u4_t v = acc;
+    v.x += (unsigned)k;
+    st16(out, k, off, v);
+  }
+}
+
+template <typename R>
+hipError_t launch_hop_stream(const HopArgs<R>& a0, int mode, hipStream_t s) {
+  HopArgs<R> a = a0;
+  a.nblk = one_rhs_grid(a.g);
+  if (a.nblk < 0) return hipErrorInvalidValue;
+  const bool l12 = sizeof(R) == 4 && a.link12;
+  constexpr bool F32 = sizeof(R) == 4;
+  dim3 grid(a.nblk), block(HOP_BLOCK);
+#define DDQ_STREAM_LAUNCH(M)                                                    \
+  if (l12)                                                                      \
+    hipLaunchKernelGGL((hop_stream_kernel<R, M, F32>), grid, block, 0, s, a);   \
+  else                                                                          \
+    hipLaunchKernelGGL((hop_stream_kernel<R, M, false>), grid, block, 0, s, a)
+  switch (mode) {
+    case M_HOP_CLINV: DDQ_STREAM_LAUNCH(M_HOP_CLINV); break;
+    case M_APPLY: DDQ_STREAM_LAUNCH(M_APPLY); break;
+    case M_RICH: DDQ_STREAM_LAUNCH(M_RICH); break;
+    default: return hipErrorInvalidValue;
+  }
+#undef DDQ_STREAM_LAUNCH
+  return hipGetLastError();
+}
+template hipError_t launch_hop_stream<float>(const HopArgs<float>&, int, hipStream_t);
+template hipError_t launch_hop_stream<double>(const HopArgs<double>&, int, hipStream_t);
+
 template <typename R, int MODE>
 static hipError_t launch_mode(const HopArgs<R>& a, bool dagger, int nrhs, hipStream_t s) {
   dim3 block(HOP_BLOCK), grid(a.nblk);
@@ -169,15 +259,8 @@ template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a0, int mode, bool dagger, int nrhs, hipStream_t s) {
   HopArgs<R> a = a0;
   a.nrhs = nrhs;
-#if DDQ_SITE_ORDER
-  const long long per = (slab_groups_per_xcd(a.g) + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
-  if (8 * per > 0x7fffffffLL) return hipErrorInvalidValue;
-  a.nblk = (int)(8 * per);
-#else
-  int nb = (a.g.Vh + HOP_BLOCK - 1) / HOP_BLOCK;
-  const int pad = 8 * (DDQ_XCD_CHUNK > 0 ? DDQ_XCD_CHUNK : 1);
-  a.nblk = ((nb + pad - 1) / pad) * pad;
-#endif
+  a.nblk = one_rhs_grid(a.g);
+  if (a.nblk < 0) return hipErrorInvalidValue;
   switch (mode) {
     case M_HOP_CLINV: return launch_mode<R, M_HOP_CLINV>(a, dagger, nrhs, s);
     case M_RECON: return launch_mode<R, M_RECON>(a, dagger, nrhs, s);

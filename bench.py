@@ -25,6 +25,7 @@ the timed region.  Reported:
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-batch] [--no-cpu]
        python bench.py --multi-rhs-only   (profiling run: only the 12-right-hand-side apply on 24^3 x 48,
                                            prints its own JSON, not the benchmark line)
+       python bench.py --batch-only       (profiling run: that apply and the batched solves, own JSON)
 """
 from __future__ import annotations
 
@@ -126,20 +127,21 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multi-rhs-only", action="store_true")
+    ap.add_argument("--batch-only", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is single-GPU; "
               f"multi-GPU sharding is design only)", file=sys.stderr)
         sys.exit(2)
 
-    if args.multi_rhs_only:
+    if args.multi_rhs_only or args.batch_only:
         import torch
 
         from paper_2407_08092_amd import api, synth
 
         torch.cuda.set_device(0)
-        multi, _ = batched(api, synth, torch, torch.device("cuda:0"), solve=False)
-        print(json.dumps({"multi_rhs": multi}), flush=True)
+        multi, batch = batched(api, synth, torch, torch.device("cuda:0"), solve=args.batch_only)
+        print(json.dumps({"multi_rhs": multi, "batched": batch}), flush=True)
         return
 
     cpu = None if args.no_cpu else cpu_baseline()
@@ -302,7 +304,8 @@ def main():
     torch.cuda.synchronize()
     t64 = e0.elapsed_time(e1) / n64
     fp64 = {"apply_ms": round(t64, 4), "apply_GBs": round(BYTES_APPLY_F64 * vh / (t64 * 1e-3) / 1e9, 1),
-            "sweeps_per_s": round(SWEEPS / (e1.elapsed_time(e2) * 1e-3), 1)}
+            "sweeps_per_s": round(SWEEPS / (e1.elapsed_time(e2) * 1e-3), 1),
+            "stream_mix_GBs": stencil_stream_ceiling(api, torch, lat, x64, xs64, b64, y64, 5)}
     del y64, xs64, x64, b64
     api.destroy_lattice(lat)
     del lat

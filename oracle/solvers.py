@@ -23,6 +23,14 @@ algorithm in its order and notation.  Readings of points the paper leaves open:
   listing's line "check convergence via beta").
 * Flexible GMRES: the same with a right preconditioner z_k = M v_k and the
   update x += Z_k y_k.
+* Odd-even smoother M_nu (Sect. 2.4.5, the right panel of Fig. 1): eq. 2's
+  factorised D^-1 with D_S^-1 replaced by the Richardson polynomial
+  p_{R,nu}(D_S) = (I - (I - omega D_S)^nu) D_S^-1 of Sect. 2.4.4, i.e. prepare,
+  nu Richardson sweeps on D_S from zero, reconstruct.  nu = 0 is p = 0: the
+  even half of M_0 r is zero and its odd half is D_oo^-1 r_o.
+* FGMRES on the full D (Sect. 2.3: the fine level runs FGMRES; here M_nu alone
+  is its right preconditioner, the smoother of a two-level method without the
+  coarse-grid correction); the tolerance is relative to |b|.
 """
 from __future__ import annotations
 
@@ -128,3 +136,21 @@ def richardson_preconditioner(apply, nsweeps: int, omega: float):
     def M(v):
         return richardson(apply, v, np.zeros_like(v), nsweeps, omega)
     return M
+
+
+def oe_smoother(op, nsweeps: int, omega: float):
+    """M_nu r: prepare (eq. 2), nu Richardson sweeps on D_S from zero (Alg. 4),
+    reconstruct (eq. 2) -- eq. 2 with D_S^-1 replaced by p_{R,nu}(D_S)."""
+    def M(r):
+        bt = op.prepare(r)
+        xe = richardson(op.schur, bt, np.zeros_like(bt), nsweeps, omega)
+        return op.reconstruct(xe, r)
+    return M
+
+
+def fgmres_full(op, b, m: int, max_cycles: int, tol: float, nsweeps: int, omega: float, x0=None):
+    """FGMRES(m) of Alg. 2 on the full D x = b with M_nu as right preconditioner,
+    to |b - D x| <= tol |b|.  Returns (x, GmresResult)."""
+    x0 = np.zeros_like(b) if x0 is None else x0
+    res = gmres(op.D, b, x0, m, max_cycles, tol * vnorm(b), oe_smoother(op, nsweeps, omega))
+    return res.x, res

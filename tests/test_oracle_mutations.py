@@ -85,3 +85,51 @@ def test_single_leaf_clover_caught(monkeypatch):
     pins.test_constant_abelian_clover(1)
     with pytest.raises(AssertionError):
         pins.test_abelian_field_clover_leaf_average()
+
+
+# odd-even smoother M_nu: a skipped prepare step, one sweep too few, a reconstruct
+# that drops the D_oe x_e term
+from oracle import solvers  # noqa: E402
+
+_orig_richardson = solvers.richardson
+
+
+def _smoother_no_prepare(op, nsweeps, omega):
+    def M(r):
+        be = op.lat.to_parity(r, 0)  # mistake: b_e instead of b~_e
+        xe = solvers.richardson(op.schur, be, np.zeros_like(be), nsweeps, omega)
+        return op.reconstruct(xe, r)
+    return M
+
+
+def _smoother_short(op, nsweeps, omega):
+    return _orig_smoother(op, max(nsweeps - 1, 0), omega)
+
+
+def _smoother_bad_reconstruct(op, nsweeps, omega):
+    def M(r):
+        bt = op.prepare(r)
+        xe = solvers.richardson(op.schur, bt, np.zeros_like(bt), nsweeps, omega)
+        x_o = op.D_oo_inv(op.lat.to_parity(r, 1))  # mistake: D_oe x_e dropped
+        return op.lat.from_parity(xe, 0) + op.lat.from_parity(x_o, 1)
+    return M
+
+
+_orig_smoother = solvers.oe_smoother
+
+
+@pytest.mark.parametrize("mutant,pin", [
+    # a wrong outer factor (prepare or reconstruct) leaves D M similar to a block-
+    # triangular matrix with the same diagonal blocks: the spectrum is unchanged, but
+    # M_nu is no longer eq. 2's product and no longer tends to D^-1
+    (_smoother_no_prepare, pins.test_oe_smoother_tends_to_inverse),
+    (_smoother_no_prepare, pins.test_oe_smoother_matches_dense_factorisation),
+    (_smoother_short, lambda: pins.test_oe_smoother_spectrum_closed_form(3)),
+    (_smoother_short, pins.test_oe_smoother_matches_dense_factorisation),
+    (_smoother_bad_reconstruct, pins.test_oe_smoother_tends_to_inverse),
+    (_smoother_bad_reconstruct, pins.test_oe_smoother_matches_dense_factorisation),
+])
+def test_oe_smoother_mutants_caught(monkeypatch, mutant, pin):
+    monkeypatch.setattr(solvers, "oe_smoother", mutant)
+    with pytest.raises(AssertionError):
+        pin()

@@ -496,3 +496,104 @@ def test_fig1_qualitative_4444():
     lDM = np.linalg.eigvals(D[np.ix_(perm, perm)] @ M3)
     assert np.mean(np.abs(1 - lDM)) < np.mean(np.abs(1 - lDp))
     assert np.abs(lDM).min() > np.abs(lDp).min()        # spectrum kept away from zero
+
+
+# --------------------------------------------------------------------------
+# P12 the odd-even smoother M_nu and FGMRES on the full D (Sect. 2.4.5, Fig. 1 right)
+# --------------------------------------------------------------------------
+def _full_vec(lat, seed):
+    return synth.gaussian_complex(lat.shape + (4, 3), seed)
+
+
+def _match_multisets(a, b):
+    """largest distance after the best one-to-one pairing of two eigenvalue lists"""
+    from scipy.optimize import linear_sum_assignment
+    cost = np.abs(a[:, None] - b[None, :])
+    r, c = linear_sum_assignment(cost)
+    return float(cost[r, c].max())
+
+
+def test_oe_smoother_nu0_closed_form():
+    # p_{R,0} = 0: M_0 r = (0, D_oo^-1 r_o)
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 121), 1.0, -0.1)
+    r = _full_vec(lat, 122)
+    z = solvers.oe_smoother(op, 0, 0.2)(r)
+    assert np.all(lat.to_parity(z, 0) == 0)
+    z_o = np.linalg.solve(op.A_oo, lat.to_parity(r, 1)[..., None])[..., 0]
+    assert rel_err(lat.to_parity(z, 1), z_o) < 1e-13
+
+
+@pytest.mark.parametrize("nu", [1, 3, 6])
+def test_oe_smoother_spectrum_closed_form(nu):
+    # D M_nu is similar to diag(D_S p_{R,nu}(D_S), 1): its spectrum is
+    # {1 - (1 - omega lambda)^nu : lambda in spec(D_S)} and 1 with multiplicity 12 V / 2
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 123), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    lS = np.linalg.eigvals(dense_schur(op))
+    omega = 0.8 / np.abs(lS).max()
+    M = solvers.oe_smoother(op, nu, omega)
+    n = D.shape[0]
+    cols = np.empty((n, n), complex)
+    for j in range(n):  # the matrix of M_nu, column by column, through the oracle function
+        e = np.zeros(n, complex)
+        e[j] = 1.0
+        cols[:, j] = M(e.reshape(lat.shape + (4, 3))).ravel()
+    got = np.linalg.eigvals(D @ cols)
+    expect = np.concatenate([1 - (1 - omega * lS) ** nu, np.ones(n // 2)])
+    assert _match_multisets(got, expect) < 1e-10
+
+
+def test_oe_smoother_matches_dense_factorisation():
+    # eq. 2 with D_S^-1 -> p_{R,nu}(D_S), from the dense blocks of the assembled D
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 131), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    e, o = dirac.parity_dofs(lat, 0), dirac.parity_dofs(lat, 1)
+    Dee, Deo, Doe, Doo = D[np.ix_(e, e)], D[np.ix_(e, o)], D[np.ix_(o, e)], D[np.ix_(o, o)]
+    Doo_inv = np.linalg.inv(Doo)
+    DS = Dee - Deo @ Doo_inv @ Doe
+    nu, omega = 4, 0.8 / np.abs(np.linalg.eigvals(DS)).max()
+    Ie = np.eye(len(e))
+    p = (Ie - np.linalg.matrix_power(Ie - omega * DS, nu)) @ np.linalg.inv(DS)
+    r = _full_vec(lat, 132).ravel()
+    t_e = r[e] - Deo @ (Doo_inv @ r[o])          # right factor
+    x_e = p @ t_e                                # middle factor
+    x_o = Doo_inv @ r[o] - Doo_inv @ (Doe @ x_e)  # left factor
+    z = solvers.oe_smoother(op, nu, omega)(r.reshape(lat.shape + (4, 3))).ravel()
+    assert rel_err(z[e], x_e) < 1e-12 and rel_err(z[o], x_o) < 1e-12
+
+
+def test_oe_smoother_tends_to_inverse():
+    # omega |lambda_max| < 1 makes (I - omega D_S)^nu -> 0: M_nu r -> D^-1 r
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 124), 1.0, -0.1)
+    lS = np.linalg.eigvals(dense_schur(op))
+    omega = 0.8 / np.abs(lS).max()
+    rate = np.abs(1 - omega * lS).max()
+    r = _full_vec(lat, 125)
+    x = np.linalg.solve(sparse_D(op).toarray(), r.ravel())
+    errs = [rel_err(solvers.oe_smoother(op, nu, omega)(r).ravel(), x) for nu in (10, 20, 40)]
+    assert errs[2] < errs[1] < errs[0]
+    assert errs[2] < 3 * rate ** 40 * np.linalg.cond(dense_schur(op))
+
+
+def test_fgmres_full_with_oe_smoother():
+    lat = Lattice(DISTINCT)
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.4, 126), 1.0, -0.2)
+    b = _full_vec(lat, 127)
+    omega = 0.8 / solvers.power_iteration(op.schur, rand_vec(lat.Vh, 128), 50)
+    x, res = solvers.fgmres_full(op, b, 16, 30, 1e-10, 3, omega)
+    assert res.converged
+    assert solvers.vnorm(b - op.D(x)) <= 1e-10 * solvers.vnorm(b)
+    # fewer outer steps than with the identity preconditioner on the full D
+    res0 = solvers.gmres(op.D, b, np.zeros_like(b), 16, 60, 1e-10 * solvers.vnorm(b))
+    assert res0.converged and res.iters < res0.iters
+    # against the dense solve on a smaller lattice
+    lat2 = Lattice((4, 4, 2, 2))
+    op2 = WilsonClover(lat2, synth.gauge_field(lat2.dims, 0.3, 129), 1.0, -0.1)
+    b2 = _full_vec(lat2, 130)
+    x2, res2 = solvers.fgmres_full(op2, b2, 12, 40, 1e-12, 2, 0.2)
+    assert res2.converged
+    assert rel_err(x2.ravel(), np.linalg.solve(sparse_D(op2).toarray(), b2.ravel())) < 1e-10

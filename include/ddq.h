@@ -247,6 +247,38 @@ typedef struct {
 int ddq_oe_gmres_solve(ddq_lattice* lat, void* x, const void* b,
                        const ddq_gmres_params* params, ddq_solve_info* info);
 
+/* The full Wilson-clover operator D of eq. 1 (nine 12x12 blocks per block row, Sect.
+ * 2.3): y = D x for nrhs full FP64 vectors (the layout of ddq_pack_parity's full
+ * vectors).  Kernel B's apply mode on each parity: y_e = A_ee x_e - H_eo x_o and
+ * y_o = A_oo x_o - H_oe x_e, with the undivided odd clover blocks A_oo that
+ * ddq_set_clover keeps for this.  x, y: device, not overlapping.  Allocates 8 FP64
+ * parity vectors per right-hand side of work space on first use (kept until the
+ * lattice is destroyed). */
+int ddq_apply_dirac(ddq_lattice* lat, int nrhs, const void* x, void* y);
+
+/* The odd-even smoother M_nu of Sect. 2.4.5 (the right panel of Fig. 1): z = M_nu r for
+ * nrhs full FP64 vectors, eq. 2's factorised D^-1 with D_S^-1 replaced by the
+ * Richardson polynomial p_{R,nu}(D_S) = (I - (I - omega D_S)^nu) D_S^-1 of Sect. 2.4.4:
+ * b~_e = b_e - D_eo D_oo^-1 r_o, x_e = nsweeps Richardson sweeps (Alg. 4) on D_S x_e = b~_e
+ * from zero, z = (x_e, D_oo^-1 (r_o - D_oe x_e)).  prec: DDQ_F64, or DDQ_F32 for the
+ * sweeps (FP32 storage and arithmetic; prepare and reconstruct stay FP64).  nsweeps = 0
+ * gives z = (0, D_oo^-1 r_o).  r, z: device, not overlapping.  Work space as
+ * ddq_apply_dirac, plus 2 FP32 parity vectors per right-hand side for DDQ_F32. */
+int ddq_oe_smoother(ddq_lattice* lat, int nrhs, const void* r, void* z, int nsweeps, double omega, int prec);
+
+/* Flexible GMRES(m) of Alg. 2 on the full D x = b (FP64 full vectors; the fine-level
+ * solver of Sect. 2.3) with M_nu (ddq_oe_smoother) as right preconditioner: nu =
+ * params->smoother_sweeps, omega = params->omega, the sweeps in params->inner_prec
+ * (DDQ_F64 or DDQ_F32; params->smoother_prec must be 0 or equal to it).  The
+ * Gram-Schmidt passes and the stopping rule are those of ddq_oe_gmres_solve: |b - D x|
+ * <= tol |b| on the FP64 residual recomputed at a restart; inner_reduction > 0 ends a
+ * cycle once its residual estimate has fallen by that factor (0: at the target).
+ * cycle_graph is ignored.  x: initial guess in, solution out (device).  Work space:
+ * 2m + 2 full FP64 vectors plus the smoother's.  Returns DDQ_NOT_CONVERGED when
+ * max_cycles restarts did not reach the target (x holds the last iterate). */
+int ddq_fgmres_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_params* params,
+                     ddq_solve_info* info);
+
 /* Batched solves: several lattices of different extents, several right-hand
  * sides each, all solved to their own tolerance in one call.  Each (lattice,
  * right-hand side) pair is one system x = D^-1 b treated exactly as by

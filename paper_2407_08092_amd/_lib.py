@@ -80,6 +80,9 @@ _SIGNATURES = {
     "ddq_backward_link_force": [_P, _P, _P, _P, _P, C.c_int],
     "ddq_stream_copy": [_P, _P, C.c_int64, C.c_int, _P],
     "ddq_stencil_stream": [_P, C.c_int, C.c_int, _P, _P, _P, _P],
+    "ddq_apply_dirac": [_P, C.c_int, _P, _P],
+    "ddq_oe_smoother": [_P, C.c_int, _P, _P, C.c_int, C.c_double, C.c_int],
+    "ddq_fgmres_solve": [_P, _P, _P, _P, _P],
     "ddq_profile_begin": [_P],
     "ddq_profile_end": [_P, C.POINTER(KernelStats), C.c_int, C.POINTER(C.c_int)],
     "ddq_last_error": [],

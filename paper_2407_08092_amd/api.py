@@ -26,7 +26,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
-    "stream_copy", "stencil_stream", "backward_apply", "backward_link_force", "convert_parity",
+    "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "fgmres_solve", "backward_apply", "backward_link_force", "convert_parity",
     "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
@@ -288,6 +288,56 @@ def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: in
     lat.sync_stream()
     st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
                "ddq_oe_gmres_solve", allow=(0, 1))
+    return x, info.as_dict(), st == 0
+
+
+def _full_nrhs(lat, v, name):
+    if v.dtype != torch.complex128:
+        raise TypeError(f"{name} must be complex128")
+    if tuple(v.shape) == lat.full_shape:
+        return 1
+    if v.dim() == len(lat.full_shape) + 1 and tuple(v.shape[1:]) == lat.full_shape:
+        return v.shape[0]
+    raise ValueError(f"{name} must be {lat.full_shape} or [nrhs, *{lat.full_shape}]")
+
+
+def apply_dirac(lat: Lattice, x: torch.Tensor, y: torch.Tensor = None) -> torch.Tensor:
+    """y = D x on full FP64 vectors (eq. 1)."""
+    n = _full_nrhs(lat, x, "x")
+    if y is None:
+        y = torch.empty_like(x)
+    lat.sync_stream()
+    check(lib().ddq_apply_dirac(lat.handle, n, _dev(x, "x"), _dev(y, "y")), "ddq_apply_dirac")
+    return y
+
+
+def oe_smoother(lat: Lattice, r: torch.Tensor, nsweeps: int, omega: float, prec: int = DDQ_F64,
+                z: torch.Tensor = None) -> torch.Tensor:
+    """z = M_nu r (Sect. 2.4.5): eq. 2 with D_S^-1 replaced by nsweeps Richardson sweeps
+    from zero, the sweeps in prec (DDQ_F64 or DDQ_F32)."""
+    n = _full_nrhs(lat, r, "r")
+    if z is None:
+        z = torch.empty_like(r)
+    lat.sync_stream()
+    check(lib().ddq_oe_smoother(lat.handle, n, _dev(r, "r"), _dev(z, "z"), int(nsweeps), float(omega), int(prec)),
+          "ddq_oe_smoother")
+    return z
+
+
+def fgmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
+                 tol: float = 1e-10, smoother_sweeps: int = 3, omega: float = 0.0, inner_prec: int = DDQ_F64,
+                 inner_reduction: float = 0.0, orth_passes: int = 2):
+    """FGMRES(m) of Alg. 2 on the full D x = b with M_nu as right preconditioner.
+    Returns (x, info, converged)."""
+    if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
+        raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
+                    float(inner_reduction), int(inner_prec), int(orth_passes))
+    info = SolveInfo()
+    lat.sync_stream()
+    st = check(lib().ddq_fgmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
+               "ddq_fgmres_solve", allow=(0, 1))
     return x, info.as_dict(), st == 0
 
 

@@ -8,6 +8,7 @@
 #include <complex>
 #include <cstring>
 #include <string>
+#include <functional>
 #include <vector>
 
 #include "../../include/ddq.h"
@@ -88,6 +89,7 @@ struct ddq_lattice {
   unsigned store = 0;
   void* links[4][2] = {};  // [prec][parity]; FP16 / BF16 fields are 12-real
   void* clov[4][2] = {};   // [prec][0: A_ee, 1: A_oo^-1]
+  void* clov_oo = nullptr;  // FP64 A_oo (undivided), for the full operator D
   bool have_clover = false;
   bool link12 = false;  // FP32 links stored as their first two rows
   double c_sw = 0.0, m0 = 0.0;
@@ -96,6 +98,8 @@ struct ddq_lattice {
   Grow tmp[4];        // u_o per precision
   Grow scratch64;     // FP64 parity vectors
   Grow scratch32;     // FP32 parity vectors
+  Grow oe_ws64;       // full operator and odd-even smoother: FP64 parity vectors
+  Grow oe_ws32;       // the smoother's FP32 parity vectors
   Grow partial;       // reduction partials
   Grow small;         // device scalars: h (2 x 256 complex), norms
   double* host = nullptr;  // pinned host mirror of `small`
@@ -482,8 +486,11 @@ int ddq_destroy_lattice(ddq_lattice* L) {
     }
     L->tmp[p].release();
   }
+  dfree(L->clov_oo);
   L->scratch64.release();
   L->scratch32.release();
+  L->oe_ws64.release();
+  L->oe_ws32.release();
   L->force_ws.release();
   L->partial.release();
   L->small.release();
@@ -576,10 +583,14 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
       CHK(dalloc(&L->clov[DDQ_F64][q], n * 16));
       HIPCHK(hipMemsetAsync(L->clov[DDQ_F64][q], 0, n * 16, L->stream));  // block padding
     }
+  if (!L->clov_oo) {
+    CHK(dalloc(&L->clov_oo, n * 16));
+    HIPCHK(hipMemsetAsync(L->clov_oo, 0, n * 16, L->stream));
+  }
   int* flag = (int*)L->small.p;
   HIPCHK(hipMemsetAsync(flag, 0, sizeof(int), L->stream));
   HIPCHK(launch_clover_build(L->geo, (const d2_t*)L->U, c_sw, m0, (d2_t*)L->clov[DDQ_F64][0],
-                             (d2_t*)L->clov[DDQ_F64][1], flag, L->stream));
+                             (d2_t*)L->clov[DDQ_F64][1], (d2_t*)L->clov_oo, flag, L->stream));
   CHK(fetch(L, flag, sizeof(int)));
   int notpd = ((int*)L->host)[0];
   if (notpd) return fail(DDQ_ERR_NOT_PD, "a 6x6 clover block is not positive definite");
@@ -917,6 +928,178 @@ Givens make_givens(cd a, cd b) {
   return {na / rho, (a / na) * std::conj(b) / rho};
 }
 
+// Restarted GMRES(m) of Alg. 2 on device vectors of n complex128 numbers, flexible
+// when Z is given (z_k = M v_k kept, x += Z y): resid(x, r) forms r = b - A x in FP64,
+// precop(v, z, w) forms z = M v (z = v when Z is null) and w = A z.  Classical
+// Gram-Schmidt in `passes` passes, Givens rotations on the host, a cycle ends at
+// max(target, red * beta) or on breakdown; convergence only on the recomputed
+// residual at a restart.  x is updated in place; V holds m + 1 vectors, Z m, w one.
+struct KrylovOps {
+  std::function<int(const d2_t*, d2_t*)> resid;
+  std::function<int(const d2_t*, d2_t*, d2_t*)> precop;
+};
+struct KrylovRun {
+  int cycles = 0, iters = 0;
+  double beta = 0.0;
+};
+
+int gmres_core(ddq_lattice* L, long long n, d2_t* x, d2_t* V, d2_t* Z, d2_t* w, int m, int max_cycles,
+               double target, double red, int passes, const KrylovOps& ops, KrylovRun& run, int& status) {
+  const bool flexible = Z != nullptr;
+  d2_t* hdev = (d2_t*)L->small.p;        // [0, 128): first pass, [128, 256): second pass
+  double* ndev = (double*)(hdev + 256);  // |w|^2
+  CHK(ensure_host(L, 4096 * sizeof(double)));
+  std::vector<cd> Hcol(m + 2), g(m + 2), y(m + 1);
+  std::vector<std::vector<cd>> R(m, std::vector<cd>(m + 1));
+  std::vector<Givens> rot(m);
+  status = DDQ_NOT_CONVERGED;
+  double beta = 0.0;
+  int cycles, iters = 0;
+  for (cycles = 0;; ++cycles) {
+    // r = b - A x (FP64), the iterative-refinement residual
+    CHK(ops.resid(x, V));
+    CHK(norm_host(L, V, n, &beta));
+    if (!std::isfinite(beta)) return fail(DDQ_ERR_NONFINITE, "residual norm is not finite");
+    if (beta <= target) {
+      status = DDQ_OK;
+      break;
+    }
+    if (cycles == max_cycles) break;
+    HIPCHK(launch_scale(V, V, 1.0 / beta, n, L->stream));
+    std::fill(g.begin(), g.end(), cd(0.0));
+    g[0] = beta;
+    const double cycle_target = std::max(target, red * beta);
+    int k_used = 0;
+    for (int k = 0; k < m; ++k) {
+      d2_t* vk = V + (size_t)k * n;
+      d2_t* zk = flexible ? Z + (size_t)k * n : vk;
+      CHK(ops.precop(vk, zk, w));
+      // classical Gram-Schmidt: h = V^H w, w -= V h (twice for CGS2)
+      const int kk = k + 1;
+      for (int pass = 0; pass < passes; ++pass) {
+        d2_t* h = hdev + pass * 128;
+        HIPCHK(launch_dot_partial(V, n, kk, w, n, (d2_t*)L->partial.p, L->nbx, L->stream));
+        HIPCHK(launch_reduce_partial((const d2_t*)L->partial.p, L->nbx, kk, h, L->stream));
+        HIPCHK(launch_update(w, V, n, kk, h, -1.0, n, L->stream));
+      }
+      CHK(norm2_dev(L, w, n, ndev));
+      CHK(fetch(L, hdev, 256 * sizeof(d2_t) + sizeof(double)));
+      const double* hh = L->host;
+      for (int j = 0; j < kk; ++j)
+        Hcol[j] = passes == 2 ? cd(hh[2 * j] + hh[256 + 2 * j], hh[2 * j + 1] + hh[256 + 2 * j + 1])
+                              : cd(hh[2 * j], hh[2 * j + 1]);
+      const double hn = std::sqrt(hh[512]);
+      if (!std::isfinite(hn)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
+      Hcol[kk] = hn;
+      // apply the previous rotations, then a new one
+      for (int j = 0; j < k; ++j) {
+        cd t = rot[j].c * Hcol[j] + rot[j].s * Hcol[j + 1];
+        Hcol[j + 1] = -std::conj(rot[j].s) * Hcol[j] + rot[j].c * Hcol[j + 1];
+        Hcol[j] = t;
+      }
+      rot[k] = make_givens(Hcol[k], Hcol[kk]);
+      Hcol[k] = rot[k].c * Hcol[k] + rot[k].s * Hcol[kk];
+      Hcol[kk] = 0.0;
+      g[kk] = -std::conj(rot[k].s) * g[k];
+      g[k] = rot[k].c * g[k];
+      for (int j = 0; j <= k; ++j) R[k][j] = Hcol[j];
+      ++iters;
+      k_used = kk;
+      const double est = std::abs(g[kk]);
+      if (est <= cycle_target || hn <= 1e-14 * beta) break;
+      HIPCHK(launch_scale(V + (size_t)kk * n, w, 1.0 / hn, n, L->stream));
+    }
+    // y = R^-1 g, x += Z y (or V y)
+    for (int j = k_used - 1; j >= 0; --j) {
+      cd sum = g[j];
+      for (int q = j + 1; q < k_used; ++q) sum -= R[q][j] * y[q];
+      y[j] = sum / R[j][j];
+    }
+    double* yh = L->host;
+    for (int j = 0; j < k_used; ++j) {
+      yh[2 * j] = y[j].real();
+      yh[2 * j + 1] = y[j].imag();
+    }
+    d2_t* ydev = hdev;
+    HIPCHK(hipMemcpyAsync(ydev, yh, (size_t)k_used * sizeof(d2_t), hipMemcpyHostToDevice, L->stream));
+    HIPCHK(launch_update(x, flexible ? Z : V, n, k_used, ydev, 1.0, n, L->stream));
+    HIPCHK(hipStreamSynchronize(L->stream));  // yh is reused next cycle
+  }
+  run.cycles = cycles;
+  run.iters = iters;
+  run.beta = beta;
+  return DDQ_OK;
+}
+
+// Richardson preconditioner z = p_{R,nu}(D_S) v (Alg. 4, nu sweeps from zero) on nrhs
+// FP64 parity vectors, with the sweeps in FP64 or in FP32 storage (b32, x32: FP32 work
+// vectors; on return x32 holds z in FP32).  nu = 0 gives z = 0.
+int rich_prec_impl(ddq_lattice* L, int nrhs, const d2_t* v, d2_t* z, int nu, double omega, int prec, f2_t* b32,
+                   f2_t* x32) {
+  const long long n = (long long)nrhs * L->nvec();
+  if (nu == 0) {
+    HIPCHK(hipMemsetAsync(z, 0, (size_t)n * 16, L->stream));
+    if (prec == DDQ_F32) HIPCHK(hipMemsetAsync(x32, 0, (size_t)n * 8, L->stream));
+    return DDQ_OK;
+  }
+  if (prec == DDQ_F64) {
+    HIPCHK(launch_scale(z, v, omega, n, L->stream));  // the first sweep from zero
+    return sweeps<double>(L, DDQ_F64, nrhs, z, v, nu - 1, omega);
+  }
+  HIPCHK(launch_parity_to_f32(b32, v, nrhs, (int)L->Vh, L->stream));
+  HIPCHK(launch_scale_f32(x32, b32, (float)omega, n, L->stream));
+  CHK(sweeps<float>(L, DDQ_F32, nrhs, x32, b32, nu - 1, (float)omega));
+  HIPCHK(launch_parity_to_f64(z, x32, nrhs, (int)L->Vh, L->stream));
+  return DDQ_OK;
+}
+
+// y = D x for nrhs full FP64 vectors (eq. 1): y_e = A_ee x_e - H_eo x_o and
+// y_o = A_oo x_o - H_oe x_e, kernel B's APPLY mode on each parity (the odd one with
+// the undivided A_oo).  ws: 4 nrhs parity vectors.
+int dirac_impl(ddq_lattice* L, int nrhs, const d2_t* x, d2_t* y, d2_t* ws) {
+  const size_t nb = (size_t)nrhs * L->nvec();
+  d2_t *xe = ws, *xo = ws + nb, *ye = ws + 2 * nb, *yo = ws + 3 * nb;
+  HIPCHK(launch_pack_parity<double>(L->geo, 0, nrhs, x, xe, L->stream));
+  HIPCHK(launch_pack_parity<double>(L->geo, 1, nrhs, x, xo, L->stream));
+  HIPCHK(kernel_B<double>(L, DDQ_F64, nrhs, M_APPLY, xo, xe, nullptr, ye, 0.0, false));
+  HopArgs<double> a = hop_args<double>(L, DDQ_F64, 1);
+  a.clov = (const d2_t*)L->clov_oo;
+  a.in = xe;
+  a.x = xo;
+  a.out = yo;
+  HIPCHK(run_hop<double>(L, a, M_APPLY, false, nrhs));
+  HIPCHK(launch_unpack_parity<double>(L->geo, 0, nrhs, ye, y, L->stream));
+  HIPCHK(launch_unpack_parity<double>(L->geo, 1, nrhs, yo, y, L->stream));
+  return DDQ_OK;
+}
+
+// z = M_nu r for nrhs full FP64 vectors (Sect. 2.4.5): eq. 2 with D_S^-1 replaced by
+// p_{R,nu}(D_S) -- prepare, nu Richardson sweeps from zero in `prec`, reconstruct.
+// ws: 4 nrhs FP64 parity vectors; b32, x32: nrhs FP32 parity vectors (prec DDQ_F32).
+int smoother_impl(ddq_lattice* L, int nrhs, const d2_t* r, d2_t* z, int nu, double omega, int prec, d2_t* ws,
+                  f2_t* b32, f2_t* x32) {
+  const size_t nb = (size_t)nrhs * L->nvec();
+  d2_t *bt = ws, *xe = ws + nb, *bo = ws + 2 * nb, *xo = ws + 3 * nb;
+  CHK(prepare_impl(L, nrhs, r, bt, bo));
+  CHK(rich_prec_impl(L, nrhs, bt, xe, nu, omega, prec, b32, x32));
+  return reconstruct_impl(L, nrhs, xe, r, z, bo, xo);
+}
+
+// the smoother's and the full operator's work vectors (8 FP64 + 2 FP32 parity vectors
+// per right-hand side)
+int oe_workspace(ddq_lattice* L, int nrhs, int prec, d2_t** ws64, f2_t** ws32) {
+  const size_t nb = (size_t)nrhs * L->nvec();
+  CHK(L->oe_ws64.ensure(8 * nb * 16));
+  *ws64 = (d2_t*)L->oe_ws64.p;
+  *ws32 = nullptr;
+  if (prec == DDQ_F32) {
+    CHK(L->oe_ws32.ensure(2 * nb * 8));
+    CHK(ensure_tmp(L, DDQ_F32, nrhs));
+    *ws32 = (f2_t*)L->oe_ws32.p;
+  }
+  return ensure_tmp(L, DDQ_F64, nrhs);
+}
+
 }  // namespace
 
 extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
@@ -967,11 +1150,8 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
     x32 = b32 + n;
     w32 = b32 + 2 * n;
   }
-  d2_t* hdev = (d2_t*)L->small.p;          // [0, 128): first pass, [128, 256): second pass
-  double* ndev = (double*)(hdev + 256);    // |w|^2
-  CHK(ensure_host(L, 4096 * sizeof(double)));
 
-  int applies64 = 0, applies_lo = 0, iters = 0, cycles = 0;
+  int applies64 = 0, applies_lo = 0;
   // |b| of the full right-hand side (2 parities: 2n complex numbers)
   double bnorm;
   CHK(norm_host(L, (const d2_t*)b, 2 * n, &bnorm));
@@ -982,129 +1162,153 @@ extern "C" int ddq_oe_gmres_solve(ddq_lattice* L, void* x, const void* b, const 
   CHK(prepare_impl(L, 1, (const d2_t*)b, bt, w));
   HIPCHK(launch_pack_parity<double>(L->geo, 0, 1, (const d2_t*)x, xe, L->stream));
 
-  std::vector<cd> Hcol(m + 2), g(m + 2), y(m + 1);
-  std::vector<std::vector<cd>> R(m, std::vector<cd>(m + 1));
-  std::vector<Givens> rot(m);
-  int status = DDQ_NOT_CONVERGED;
-  double beta = 0.0;
-
-  for (cycles = 0;; ++cycles) {
-    // r = b~ - D_S x (FP64), the iterative-refinement residual
-    CHK(resid<double>(L, DDQ_F64, 1, xe, bt, V));
+  KrylovOps ops;
+  ops.resid = [&](const d2_t* xx, d2_t* r) -> int {
     ++applies64;
-    CHK(norm_host(L, V, n, &beta));
-    if (!std::isfinite(beta)) return fail(DDQ_ERR_NONFINITE, "residual norm is not finite");
-    if (beta <= target) {
-      status = DDQ_OK;
-      break;
-    }
-    if (cycles == P->max_cycles) break;
-    HIPCHK(launch_scale(V, V, 1.0 / beta, n, L->stream));
-    std::fill(g.begin(), g.end(), cd(0.0));
-    g[0] = beta;
-    const double cycle_target = std::max(target, red * beta);
-    int k_used = 0;
-    for (int k = 0; k < m; ++k) {
-      d2_t* vk = V + (size_t)k * n;
-      d2_t* zk = flexible ? Z + (size_t)k * n : vk;
-      // z_k = M v_k, w = D_S z_k
-      if (lo) {
-        if (s16) {
-          // the same sweeps on 16-bit storage: v_k (unit norm) scaled by sqrt(n) so its
-          // entries are of order one, b16 = s v, x16 = omega s v, then back with 1/s
-          // (the sweeps are linear in b, so the scale cancels exactly)
-          const double sc = std::sqrt((double)n);
-          void* b16 = b32;
-          void* x16 = (char*)b32 + (size_t)n * 4;
-          HIPCHK(launch_parity_to_h16(h16_kind(sp), b16, vk, sc, 1, (int)L->Vh, L->stream));
-          HIPCHK(launch_parity_to_h16(h16_kind(sp), x16, vk, sc * P->omega, 1, (int)L->Vh, L->stream));
-          CHK(sweeps16(L, sp, 1, x16, b16, nu - 1, (float)P->omega));
-          HIPCHK(launch_h16_to_f32(h16_kind(sp), x32, x16, (float)(1.0 / sc), 1, (int)L->Vh, L->stream));
-          applies_lo += nu - 1;
-        } else if (nu > 0) {
-          HIPCHK(launch_parity_to_f32(b32, vk, 1, (int)L->Vh, L->stream));
-          HIPCHK(launch_scale_f32(x32, b32, (float)P->omega, n, L->stream));  // first sweep from 0
-          CHK(sweeps<float>(L, DDQ_F32, 1, x32, b32, nu - 1, (float)P->omega));
-          applies_lo += nu - 1;
-        } else {
-          HIPCHK(launch_parity_to_f32(x32, vk, 1, (int)L->Vh, L->stream));
-        }
-        HIPCHK(launch_parity_to_f64(zk, x32, 1, (int)L->Vh, L->stream));
-        CHK(schur<float>(L, DDQ_F32, 1, x32, w32, false));
-        ++applies_lo;
-        HIPCHK(launch_parity_to_f64(w, w32, 1, (int)L->Vh, L->stream));
+    return resid<double>(L, DDQ_F64, 1, xx, bt, r);
+  };
+  // z_k = M v_k, w = D_S z_k
+  ops.precop = [&](const d2_t* vk, d2_t* zk, d2_t* ww) -> int {
+    if (lo) {
+      if (s16) {
+        // the same sweeps on 16-bit storage: v_k (unit norm) scaled by sqrt(n) so its
+        // entries are of order one, b16 = s v, x16 = omega s v, then back with 1/s
+        // (the sweeps are linear in b, so the scale cancels exactly)
+        const double sc = std::sqrt((double)n);
+        void* b16 = b32;
+        void* x16 = (char*)b32 + (size_t)n * 4;
+        HIPCHK(launch_parity_to_h16(h16_kind(sp), b16, vk, sc, 1, (int)L->Vh, L->stream));
+        HIPCHK(launch_parity_to_h16(h16_kind(sp), x16, vk, sc * P->omega, 1, (int)L->Vh, L->stream));
+        CHK(sweeps16(L, sp, 1, x16, b16, nu - 1, (float)P->omega));
+        HIPCHK(launch_h16_to_f32(h16_kind(sp), x32, x16, (float)(1.0 / sc), 1, (int)L->Vh, L->stream));
+        applies_lo += nu - 1;
+      } else if (nu > 0) {
+        CHK(rich_prec_impl(L, 1, vk, zk, nu, P->omega, DDQ_F32, b32, x32));
+        applies_lo += nu - 1;
       } else {
-        if (nu > 0) {
-          HIPCHK(launch_scale(zk, vk, P->omega, n, L->stream));
-          CHK(sweeps<double>(L, DDQ_F64, 1, zk, vk, nu - 1, P->omega));
-          applies64 += nu - 1;
-        }
-        CHK(schur<double>(L, DDQ_F64, 1, zk, w, false));
-        ++applies64;
+        HIPCHK(launch_parity_to_f32(x32, vk, 1, (int)L->Vh, L->stream));
       }
-      // classical Gram-Schmidt, twice: h = V^H w, w -= V h
-      const int kk = k + 1;
-      for (int pass = 0; pass < passes; ++pass) {
-        d2_t* h = hdev + pass * 128;
-        HIPCHK(launch_dot_partial(V, n, kk, w, n, (d2_t*)L->partial.p, L->nbx, L->stream));
-        HIPCHK(launch_reduce_partial((const d2_t*)L->partial.p, L->nbx, kk, h, L->stream));
-        HIPCHK(launch_update(w, V, n, kk, h, -1.0, n, L->stream));
+      if (s16 || nu == 0) HIPCHK(launch_parity_to_f64(zk, x32, 1, (int)L->Vh, L->stream));
+      CHK(schur<float>(L, DDQ_F32, 1, x32, w32, false));
+      ++applies_lo;
+      HIPCHK(launch_parity_to_f64(ww, w32, 1, (int)L->Vh, L->stream));
+    } else {
+      if (nu > 0) {
+        CHK(rich_prec_impl(L, 1, vk, zk, nu, P->omega, DDQ_F64, nullptr, nullptr));
+        applies64 += nu - 1;
       }
-      CHK(norm2_dev(L, w, n, ndev));
-      CHK(fetch(L, hdev, 256 * sizeof(d2_t) + sizeof(double)));
-      const double* hh = L->host;
-      for (int j = 0; j < kk; ++j)
-        Hcol[j] = passes == 2 ? cd(hh[2 * j] + hh[256 + 2 * j], hh[2 * j + 1] + hh[256 + 2 * j + 1])
-                              : cd(hh[2 * j], hh[2 * j + 1]);
-      const double hn = std::sqrt(hh[512]);
-      if (!std::isfinite(hn)) return fail(DDQ_ERR_NONFINITE, "Arnoldi norm is not finite");
-      Hcol[kk] = hn;
-      // apply the previous rotations, then a new one
-      for (int j = 0; j < k; ++j) {
-        cd t = rot[j].c * Hcol[j] + rot[j].s * Hcol[j + 1];
-        Hcol[j + 1] = -std::conj(rot[j].s) * Hcol[j] + rot[j].c * Hcol[j + 1];
-        Hcol[j] = t;
-      }
-      rot[k] = make_givens(Hcol[k], Hcol[kk]);
-      Hcol[k] = rot[k].c * Hcol[k] + rot[k].s * Hcol[kk];
-      Hcol[kk] = 0.0;
-      g[kk] = -std::conj(rot[k].s) * g[k];
-      g[k] = rot[k].c * g[k];
-      for (int j = 0; j <= k; ++j) R[k][j] = Hcol[j];
-      ++iters;
-      k_used = kk;
-      const double est = std::abs(g[kk]);
-      if (est <= cycle_target || hn <= 1e-14 * beta) break;
-      HIPCHK(launch_scale(V + (size_t)kk * n, w, 1.0 / hn, n, L->stream));
+      CHK(schur<double>(L, DDQ_F64, 1, zk, ww, false));
+      ++applies64;
     }
-    // y = R^-1 g, x_e += Z y (or V y)
-    for (int j = k_used - 1; j >= 0; --j) {
-      cd s = g[j];
-      for (int q = j + 1; q < k_used; ++q) s -= R[q][j] * y[q];
-      y[j] = s / R[j][j];
-    }
-    double* yh = L->host;
-    for (int j = 0; j < k_used; ++j) {
-      yh[2 * j] = y[j].real();
-      yh[2 * j + 1] = y[j].imag();
-    }
-    d2_t* ydev = hdev;
-    HIPCHK(hipMemcpyAsync(ydev, yh, (size_t)k_used * sizeof(d2_t), hipMemcpyHostToDevice, L->stream));
-    HIPCHK(launch_update(xe, flexible ? Z : V, n, k_used, ydev, 1.0, n, L->stream));
-    HIPCHK(hipStreamSynchronize(L->stream));  // yh is reused next cycle
-  }
+    return DDQ_OK;
+  };
+  KrylovRun run;
+  int status = DDQ_NOT_CONVERGED;
+  CHK(gmres_core(L, n, xe, V, Z, w, m, P->max_cycles, target, red, passes, ops, run, status));
   CHK(reconstruct_impl(L, 1, xe, (const d2_t*)b, (d2_t*)x, w, V));
   HIPCHK(hipStreamSynchronize(L->stream));
   if (info) {
-    info->cycles = cycles;
-    info->iters = iters;
+    info->cycles = run.cycles;
+    info->iters = run.iters;
     info->applies_f64 = applies64;
     info->applies_lo = applies_lo;
-    info->true_relres = bnorm > 0 ? beta / bnorm : 0.0;
+    info->true_relres = bnorm > 0 ? run.beta / bnorm : 0.0;
     info->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (status == DDQ_NOT_CONVERGED) g_err = "GMRES stopped at max_cycles";
+  return status;
+}
+
+extern "C" int ddq_apply_dirac(ddq_lattice* L, int nrhs, const void* x, void* y) {
+  CHK(check_ready(L, DDQ_F64));
+  if (nrhs < 1 || !x || !y) return fail(DDQ_ERR_ARG, "bad apply arguments");
+  if (x == y) return fail(DDQ_ERR_ARG, "x and y must not overlap");
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, nrhs, DDQ_F64, &ws64, &ws32));
+  return dirac_impl(L, nrhs, (const d2_t*)x, (d2_t*)y, ws64);
+}
+
+extern "C" int ddq_oe_smoother(ddq_lattice* L, int nrhs, const void* r, void* z, int nsweeps, double omega,
+                               int prec) {
+  CHK(check_ready(L, DDQ_F64));
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "prec must be DDQ_F64 or DDQ_F32");
+  if (prec == DDQ_F32) CHK(check_ready(L, DDQ_F32));
+  if (nrhs < 1 || !r || !z || nsweeps < 0 || !std::isfinite(omega))
+    return fail(DDQ_ERR_ARG, "bad smoother arguments");
+  if (r == z) return fail(DDQ_ERR_ARG, "r and z must not overlap");
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, nrhs, prec, &ws64, &ws32));
+  const size_t nb = (size_t)nrhs * L->nvec();
+  return smoother_impl(L, nrhs, (const d2_t*)r, (d2_t*)z, nsweeps, omega, prec, ws64 + 4 * nb, ws32,
+                       ws32 ? ws32 + nb : nullptr);
+}
+
+extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
+                                ddq_solve_info* info) {
+  auto t0 = std::chrono::steady_clock::now();
+  CHK(check_ready(L, DDQ_F64));
+  if (!x || !b || !P) return fail(DDQ_ERR_ARG, "x, b and params must be non-null");
+  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
+  const int m = P->m;
+  if (m < 1 || m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
+  if (P->max_cycles < 0 || !(P->tol >= 0.0) || P->smoother_sweeps < 0 || !std::isfinite(P->omega))
+    return fail(DDQ_ERR_ARG, "bad max_cycles, tol, smoother_sweeps or omega");
+  const int prec = P->inner_prec;
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "inner_prec must be DDQ_F64 or DDQ_F32");
+  if (prec == DDQ_F32) CHK(check_ready(L, DDQ_F32));
+  if (P->smoother_prec != 0 && P->smoother_prec != prec)
+    return fail(DDQ_ERR_ARG, "the odd-even smoother runs its sweeps in inner_prec (smoother_prec must be 0)");
+  if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
+  const int passes = P->orth_passes == 1 ? 1 : 2;
+  const long long n = 2 * L->nvec();  // complex numbers of a full vector
+  const size_t vb = (size_t)n * 16;
+  // FP64 work: w, V[0..m], Z[0..m-1] (full vectors)
+  CHK(L->scratch64.ensure((1 + (size_t)(m + 1) + (size_t)m) * vb));
+  d2_t* w = (d2_t*)L->scratch64.p;
+  d2_t* V = w + n;
+  d2_t* Z = V + (size_t)(m + 1) * n;
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, 1, prec, &ws64, &ws32));
+  const size_t nb = L->nvec();
+  double bnorm;
+  CHK(norm_host(L, (const d2_t*)b, n, &bnorm));
+  if (!std::isfinite(bnorm)) return fail(DDQ_ERR_NONFINITE, "right-hand side is not finite");
+  int applies64 = 0, applies_lo = 0;
+  const double red = P->inner_reduction > 0.0 ? P->inner_reduction : 0.0;
+  KrylovOps ops;
+  ops.resid = [&](const d2_t* xx, d2_t* r) -> int {  // r = b - D x
+    CHK(dirac_impl(L, 1, xx, r, ws64));
+    ++applies64;
+    HIPCHK(launch_scale(r, r, -1.0, n, L->stream));
+    HIPCHK(launch_axpy(r, 1.0, 0.0, (const d2_t*)b, n, L->stream));
+    return DDQ_OK;
+  };
+  ops.precop = [&](const d2_t* vk, d2_t* zk, d2_t* ww) -> int {  // z = M_nu v, w = D z
+    CHK(smoother_impl(L, 1, vk, zk, P->smoother_sweeps, P->omega, prec, ws64 + 4 * nb, ws32,
+                      ws32 ? ws32 + nb : nullptr));
+    (prec == DDQ_F64 ? applies64 : applies_lo) += P->smoother_sweeps > 0 ? P->smoother_sweeps - 1 : 0;
+    CHK(dirac_impl(L, 1, zk, ww, ws64));
+    ++applies64;
+    return DDQ_OK;
+  };
+  KrylovRun run;
+  int status = DDQ_NOT_CONVERGED;
+  CHK(gmres_core(L, n, (d2_t*)x, V, Z, w, m, P->max_cycles, P->tol * bnorm, red, passes, ops, run, status));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  if (info) {
+    info->cycles = run.cycles;
+    info->iters = run.iters;
+    info->applies_f64 = applies64;
+    info->applies_lo = applies_lo;
+    info->true_relres = bnorm > 0 ? run.beta / bnorm : 0.0;
+    info->t_total_ms =
+        std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  if (status == DDQ_NOT_CONVERGED) g_err = "FGMRES stopped at max_cycles";
   return status;
 }
 

@@ -189,8 +189,9 @@ hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows
 hipError_t launch_links_to_f32_12(const d2_t* in, void* out, int vh, hipStream_t s);
 hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s);
+// A_ee into clov_even, A_oo^-1 into clov_odd_inv and (when not null) A_oo into clov_odd
 hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0,
-                               d2_t* clov_even, d2_t* clov_odd_inv, int* notpd, hipStream_t s);
+                               d2_t* clov_even, d2_t* clov_odd_inv, d2_t* clov_odd, int* notpd, hipStream_t s);
 hipError_t launch_clover_export(const Geo& g, const d2_t* packed, d2_t* dense, hipStream_t s);
 template <typename R>
 hipError_t launch_pack_parity(const Geo& g, int parity, int nrhs, const pair<R>* full, pair<R>* v,

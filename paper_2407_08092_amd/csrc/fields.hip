@@ -291,7 +291,8 @@ __device__ bool hpd_inverse6(cpx<double> A[6][6]) {
 // chiral-basis form of (4 + m0) + (i c_sw / 4) sum sigma_munu F_munu:
 // sigma_{l t} = diag(s_l, -s_l) and sigma_{jk} = -diag(s_l, s_l).
 __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))) k_clover_build(Geo g, const d2_t* __restrict__ U, double c_sw, double m0,
-                               d2_t* __restrict__ cl_e, d2_t* __restrict__ cl_o_inv, int* notpd) {
+                               d2_t* __restrict__ cl_e, d2_t* __restrict__ cl_o_inv,
+                               d2_t* __restrict__ cl_o, int* notpd) {
   const int vh = g.Vh;
   long long tid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (tid >= 2LL * vh) return;
@@ -338,6 +339,7 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))
     if (p == 0) {
       store_packed(cl_e, blk, i, vh, M);
     } else {
+      if (cl_o) store_packed(cl_o, blk, i, vh, M);  // A_oo itself, for the full operator
       if (!hpd_inverse6(M)) {
         *notpd = 1;
         for (int j = 0; j < 6; ++j)
@@ -349,10 +351,10 @@ __global__ void __launch_bounds__(128) __attribute__((amdgpu_waves_per_eu(1, 1))
 }
 
 hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0, d2_t* cl_e,
-                               d2_t* cl_o_inv, int* notpd, hipStream_t s) {
+                               d2_t* cl_o_inv, d2_t* cl_o, int* notpd, hipStream_t s) {
   long long n = 2LL * g.Vh;
   int blocks = (int)((n + 127) / 128);
-  hipLaunchKernelGGL(k_clover_build, dim3(blocks), dim3(128), 0, s, g, U, c_sw, m0, cl_e, cl_o_inv,
+  hipLaunchKernelGGL(k_clover_build, dim3(blocks), dim3(128), 0, s, g, U, c_sw, m0, cl_e, cl_o_inv, cl_o,
                      notpd);
   return hipGetLastError();
 }

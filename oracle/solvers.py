@@ -31,6 +31,18 @@ algorithm in its order and notation.  Readings of points the paper leaves open:
 * FGMRES on the full D (Sect. 2.3: the fine level runs FGMRES; here M_nu alone
   is its right preconditioner, the smoother of a two-level method without the
   coarse-grid correction); the tolerance is relative to |b|.
+* SAP(n, m) (Sect. 2.4.1, Alg. 1): the lattice is cut into blocks of fixed extent
+  aligned at the origin; a block's colour is the parity of the sum of its block
+  coordinates.  The block system D_kk e = r_k is D restricted to the block's rows
+  and columns (couplings that leave the block dropped, those that wrap around the
+  lattice inside one block kept), solved approximately by odd-even preconditioning
+  on the block (eq. 2 with the block's hopping terms) and m Minimal Residual steps
+  on the block's Schur complement from zero.  Red (colour 0) blocks first, all from
+  one residual, then black from a recomputed one; the listing's convergence exit is
+  left out (a fixed n, as a smoother).
+* Minimal Residual (the block solver of Alg. 1, the textbook method Sect. 2.4.1
+  cites): from x = 0, r = b; each step q = A r, alpha = (q^H r) / (q^H q),
+  x += alpha r, r -= alpha q.
 """
 from __future__ import annotations
 
@@ -154,3 +166,72 @@ def fgmres_full(op, b, m: int, max_cycles: int, tol: float, nsweeps: int, omega:
     x0 = np.zeros_like(b) if x0 is None else x0
     res = gmres(op.D, b, x0, m, max_cycles, tol * vnorm(b), oe_smoother(op, nsweeps, omega))
     return res.x, res
+
+
+def minimal_residual(apply, b, m: int):
+    """m Minimal Residual steps on A x = b from x = 0."""
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.complex128, copy=True)
+    for _ in range(m):
+        q = apply(r)
+        qq = vdot(q, q)
+        if qq == 0:
+            break
+        alpha = vdot(q, r) / qq
+        x = x + alpha * r
+        r = r - alpha * q
+    return x
+
+
+def sap_blocks(lat, block):
+    """(block index of every site, colour of every block, number of blocks) for
+    blocks of extent `block` (per direction, dividing the lattice)."""
+    assert all(L % b == 0 for L, b in zip(lat.dims, block))
+    nb = [L // b for L, b in zip(lat.dims, block)]
+    coords = np.indices(lat.shape)  # lattice axes in the order of lat.shape
+    # lat.shape lists the directions from t down to x; block extents are given x first
+    bc = [coords[3 - mu] // block[mu] for mu in range(4)]
+    idx = bc[0] + nb[0] * (bc[1] + nb[1] * (bc[2] + nb[2] * bc[3]))
+    colour_of_site = (bc[0] + bc[1] + bc[2] + bc[3]) % 2
+    nblk = nb[0] * nb[1] * nb[2] * nb[3]
+    colour = np.zeros(nblk, dtype=int)
+    colour[idx.ravel()] = colour_of_site.ravel()
+    return idx, colour, nblk
+
+
+def block_solve(op, in_block, r, m: int):
+    """Approximate solution of D_kk e = r_k on one block (in_block: boolean per site):
+    eq. 2 with the block's hopping terms, m Minimal Residual steps on the block Schur
+    complement from zero; returns e as a full field, zero outside the block."""
+    lat = op.lat
+    me = lat.to_parity(in_block.astype(float)[..., None, None] * np.ones(lat.shape + (4, 3)), 0)
+    mo = lat.to_parity(in_block.astype(float)[..., None, None] * np.ones(lat.shape + (4, 3)), 1)
+
+    def D_eo_k(v_o):
+        return me * op.D_eo(mo * v_o)
+
+    def D_oe_k(v_e):
+        return mo * op.D_oe(me * v_e)
+
+    def S_k(v_e):
+        return me * op.D_ee(v_e) - D_eo_k(op.D_oo_inv(D_oe_k(v_e)))
+
+    r_e = me * lat.to_parity(r, 0)
+    r_o = mo * lat.to_parity(r, 1)
+    bt = r_e - D_eo_k(op.D_oo_inv(r_o))
+    x_e = minimal_residual(S_k, bt, m)
+    x_o = mo * op.D_oo_inv(r_o - D_oe_k(x_e))
+    return lat.from_parity(x_e, 0) + lat.from_parity(x_o, 1)
+
+
+def sap(op, b, x0, n: int, m: int, block=(4, 4, 4, 4)):
+    """SAP(n, m) of Alg. 1 on D x = b from x0."""
+    idx, colour, nblk = sap_blocks(op.lat, block)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for _ in range(n):
+        for c in (0, 1):
+            r = b - op.D(x)
+            for k in range(nblk):
+                if colour[k] == c:
+                    x = x + block_solve(op, idx == k, r, m)
+    return x

@@ -133,3 +133,59 @@ def test_oe_smoother_mutants_caught(monkeypatch, mutant, pin):
     monkeypatch.setattr(solvers, "oe_smoother", mutant)
     with pytest.raises(AssertionError):
         pin()
+
+
+# SAP: a block solve that keeps the hops leaving the block, a Minimal Residual step with
+# the conjugated step length, a black pass that reuses the red pass's residual
+_orig_block_solve = solvers.block_solve
+_orig_mr = solvers.minimal_residual
+_orig_sap = solvers.sap
+
+
+def _block_solve_leaky(op, in_block, r, m):
+    lat = op.lat
+    me = lat.to_parity(in_block.astype(float)[..., None, None] * np.ones(lat.shape + (4, 3)), 0)
+    mo = lat.to_parity(in_block.astype(float)[..., None, None] * np.ones(lat.shape + (4, 3)), 1)
+
+    def S(v_e):  # mistake: the full lattice's hopping terms inside the block solve
+        return me * op.schur(me * v_e)
+
+    r_e, r_o = me * lat.to_parity(r, 0), mo * lat.to_parity(r, 1)
+    bt = r_e - me * op.D_eo(op.D_oo_inv(r_o))
+    x_e = solvers.minimal_residual(S, bt, m)
+    x_o = mo * op.D_oo_inv(r_o - op.D_oe(x_e))
+    return lat.from_parity(x_e, 0) + lat.from_parity(x_o, 1)
+
+
+def _mr_conj(apply, b, m):
+    x = np.zeros_like(b)
+    r = np.array(b, dtype=np.complex128, copy=True)
+    for _ in range(m):
+        q = apply(r)
+        alpha = solvers.vdot(r, q) / solvers.vdot(q, q)  # mistake: r^H q
+        x = x + alpha * r
+        r = r - alpha * q
+    return x
+
+
+def _sap_stale_residual(op, b, x0, n, m, block=(4, 4, 4, 4)):
+    idx, colour, nblk = solvers.sap_blocks(op.lat, block)
+    x = np.array(x0, dtype=np.complex128, copy=True)
+    for _ in range(n):
+        r = b - op.D(x)  # mistake: one residual for both colours
+        for c in (0, 1):
+            for k in range(nblk):
+                if colour[k] == c:
+                    x = x + solvers.block_solve(op, idx == k, r, m)
+    return x
+
+
+@pytest.mark.parametrize("name,mutant,pin", [
+    ("block_solve", _block_solve_leaky, lambda: pins.test_block_solve_converges_to_dense_block_inverse((2, 2, 2, 2))),
+    ("minimal_residual", _mr_conj, pins.test_minimal_residual_closed_form_and_orthogonality),
+    ("sap", _sap_stale_residual, pins.test_sap_is_multiplicative_schwarz),
+])
+def test_sap_mutants_caught(monkeypatch, name, mutant, pin):
+    monkeypatch.setattr(solvers, name, mutant)
+    with pytest.raises(AssertionError):
+        pin()

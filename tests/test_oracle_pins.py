@@ -597,3 +597,82 @@ def test_fgmres_full_with_oe_smoother():
     x2, res2 = solvers.fgmres_full(op2, b2, 12, 40, 1e-12, 2, 0.2)
     assert res2.converged
     assert rel_err(x2.ravel(), np.linalg.solve(sparse_D(op2).toarray(), b2.ravel())) < 1e-10
+
+
+# --------------------------------------------------------------------------
+# P13 SAP(n, m) with block-local odd-even Minimal Residual (Sect. 2.4.1, Alg. 1)
+# --------------------------------------------------------------------------
+def _block_dofs(lat, in_block):
+    sites = np.flatnonzero(in_block.ravel())
+    return (12 * sites[:, None] + np.arange(12)[None, :]).ravel()
+
+
+def test_minimal_residual_closed_form_and_orthogonality():
+    # diagonal A, b along one axis: one step solves it exactly
+    a = np.array([2.0 + 1.0j, 3.0, 0.5 - 0.25j])
+    b = np.array([0.0, 0.0, 1.0 + 2.0j])
+    x = solvers.minimal_residual(lambda v: a * v, b, 1)
+    assert np.allclose(x, b / a, atol=1e-15)
+    # a general step: the new residual is orthogonal to A r
+    rng = np.random.default_rng(141)
+    A = rng.normal(size=(20, 20)) + 1j * rng.normal(size=(20, 20)) + 8 * np.eye(20)
+    b = rng.normal(size=20) + 1j * rng.normal(size=20)
+    x1 = solvers.minimal_residual(lambda v: A @ v, b, 1)
+    r1 = b - A @ x1
+    assert abs(np.vdot(A @ b, r1)) < 1e-12 * np.linalg.norm(A @ b) * np.linalg.norm(b)
+    norms = [np.linalg.norm(b - A @ solvers.minimal_residual(lambda v: A @ v, b, k)) for k in range(6)]
+    assert all(norms[k + 1] <= norms[k] * (1 + 1e-14) for k in range(5))
+
+
+def test_sap_blocks_and_colours():
+    lat = Lattice((8, 4, 4, 8))
+    idx, colour, nblk = solvers.sap_blocks(lat, (4, 4, 4, 4))
+    assert nblk == 4 and sorted(np.bincount(idx.ravel())) == [256] * 4
+    # the block of site (x, y, z, t) = (5, 1, 2, 6): block coordinates (1, 0, 0, 1), colour 0
+    assert colour[idx[6, 2, 1, 5]] == 0 and idx[6, 2, 1, 5] == 1 + 2 * (0 + 1 * (0 + 1 * 1))
+    # neighbouring blocks along x have different colours
+    assert colour[idx[0, 0, 0, 0]] != colour[idx[0, 0, 0, 4]]
+
+
+@pytest.mark.parametrize("block", [(2, 2, 2, 2), (4, 4, 2, 2)])
+def test_block_solve_converges_to_dense_block_inverse(block):
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 142), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    idx, colour, nblk = solvers.sap_blocks(lat, block)
+    r = _full_vec(lat, 143)
+    for k in range(nblk):
+        in_block = idx == k
+        e = solvers.block_solve(op, in_block, r, 400)
+        d = _block_dofs(lat, in_block)
+        ek = np.linalg.solve(D[np.ix_(d, d)], r.ravel()[d])
+        assert rel_err(e.ravel()[d], ek) < 1e-10
+        assert np.all(e[~in_block] == 0)
+
+
+def test_single_block_is_the_whole_operator():
+    # one block covering the lattice keeps the couplings that wrap around it: D_kk = D
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 144), 1.0, -0.1)
+    r = _full_vec(lat, 145)
+    e = solvers.block_solve(op, np.ones(lat.shape, bool), r, 400)
+    assert rel_err(e.ravel(), np.linalg.solve(sparse_D(op).toarray(), r.ravel())) < 1e-10
+
+
+def test_sap_is_multiplicative_schwarz():
+    # with converged block solves one SAP sweep is x1 = x0 + B_black (b - D x_h),
+    # x_h = x0 + B_red (b - D x0), B_c = sum over blocks of colour c of P D_kk^-1 P^T
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 146), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    idx, colour, nblk = solvers.sap_blocks(lat, (2, 2, 2, 2))
+    n = D.shape[0]
+    B = [np.zeros((n, n), complex), np.zeros((n, n), complex)]
+    for k in range(nblk):
+        d = _block_dofs(lat, idx == k)
+        B[colour[k]][np.ix_(d, d)] = np.linalg.inv(D[np.ix_(d, d)])
+    b, x0 = _full_vec(lat, 147).ravel(), _full_vec(lat, 148).ravel()
+    xh = x0 + B[0] @ (b - D @ x0)
+    x1 = xh + B[1] @ (b - D @ xh)
+    got = solvers.sap(op, b.reshape(lat.shape + (4, 3)), x0.reshape(lat.shape + (4, 3)), 1, 400, (2, 2, 2, 2))
+    assert rel_err(got.ravel(), x1) < 1e-10

@@ -266,6 +266,21 @@ int ddq_apply_dirac(ddq_lattice* lat, int nrhs, const void* x, void* y);
  * ddq_apply_dirac, plus 2 FP32 parity vectors per right-hand side for DDQ_F32. */
 int ddq_oe_smoother(ddq_lattice* lat, int nrhs, const void* r, void* z, int nsweeps, double omega, int prec);
 
+/* SAP(n, m) of Alg. 1 (Sect. 2.4.1) on D x = b, FP64 full vectors, as a smoother: n
+ * sweeps, each over the red then the black blocks, every block solve from the residual
+ * b - D x recomputed before its colour (the listing's convergence exit is left out:
+ * exactly n sweeps).  Blocks are 4^4, aligned at the origin (every lattice extent a
+ * multiple of 4, else DDQ_ERR_ARG); a block's colour is the parity of the sum of its
+ * block coordinates (with an odd number of blocks along a direction, the blocks on
+ * either side of that boundary share a colour).  Block system: D restricted to the
+ * block's sites (hops that leave it dropped; a block that spans a whole direction keeps
+ * its wrap-around hops, with the antiperiodic sign in t), solved approximately by
+ * odd-even preconditioning on the block and m Minimal Residual steps on the block's
+ * Schur complement from zero, then added to x on the block.  x: initial guess in,
+ * iterate out; b: right-hand side (device, not overlapping).  One workgroup per block,
+ * the block's half vectors in LDS.  Synchronises the stream. */
+int ddq_sap_smooth(ddq_lattice* lat, void* x, const void* b, int n, int m);
+
 /* Flexible GMRES(m) of Alg. 2 on the full D x = b (FP64 full vectors; the fine-level
  * solver of Sect. 2.3) with M_nu (ddq_oe_smoother) as right preconditioner: nu =
  * params->smoother_sweeps, omega = params->omega, the sweeps in params->inner_prec

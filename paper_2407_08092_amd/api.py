@@ -26,7 +26,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
-    "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "fgmres_solve", "backward_apply", "backward_link_force", "convert_parity",
+    "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "sap_smooth", "fgmres_solve", "backward_apply", "backward_link_force", "convert_parity",
     "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
@@ -322,6 +322,15 @@ def oe_smoother(lat: Lattice, r: torch.Tensor, nsweeps: int, omega: float, prec:
     check(lib().ddq_oe_smoother(lat.handle, n, _dev(r, "r"), _dev(z, "z"), int(nsweeps), float(omega), int(prec)),
           "ddq_oe_smoother")
     return z
+
+
+def sap_smooth(lat: Lattice, b: torch.Tensor, x: torch.Tensor, n: int, m: int) -> torch.Tensor:
+    """SAP(n, m) of Alg. 1 on D x = b with 4^4 blocks, in place on x (full FP64)."""
+    if _full_nrhs(lat, b, "b") != 1 or _full_nrhs(lat, x, "x") != 1:
+        raise ValueError("one right-hand side")
+    lat.sync_stream()
+    check(lib().ddq_sap_smooth(lat.handle, _dev(x, "x"), _dev(b, "b"), int(n), int(m)), "ddq_sap_smooth")
+    return x
 
 
 def fgmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,

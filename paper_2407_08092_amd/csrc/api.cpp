@@ -1246,6 +1246,35 @@ extern "C" int ddq_oe_smoother(ddq_lattice* L, int nrhs, const void* r, void* z,
                        ws32 ? ws32 + nb : nullptr);
 }
 
+extern "C" int ddq_sap_smooth(ddq_lattice* L, void* x, const void* b, int n, int m) {
+  CHK(check_ready(L, DDQ_F64));
+  if (!x || !b || n < 0 || m < 0) return fail(DDQ_ERR_ARG, "bad SAP arguments");
+  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
+  for (int mu = 0; mu < 4; ++mu)
+    if (L->dims[mu] % 4 != 0) return fail(DDQ_ERR_ARG, "SAP blocks are 4^4: every extent must be a multiple of 4");
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
+  const long long nf = 2 * L->nvec();  // complex numbers of a full vector
+  CHK(L->scratch64.ensure((size_t)nf * 16));
+  d2_t* r = (d2_t*)L->scratch64.p;
+  // algorithmic bytes of one colour's launch: per site of that colour's blocks, the
+  // residual, the iterate (read and written), the links and the clover blocks once
+  const double bytes = (double)L->V / 2 * (192 + 384 + 1152 + 576);
+  for (int it = 0; it < n; ++it)
+    for (int colour = 0; colour < 2; ++colour) {
+      CHK(dirac_impl(L, 1, (const d2_t*)x, r, ws64));  // r = b - D x
+      HIPCHK(launch_scale(r, r, -1.0, nf, L->stream));
+      HIPCHK(launch_axpy(r, 1.0, 0.0, (const d2_t*)b, nf, L->stream));
+      HIPCHK(prof_launch(L, "sap_block_mr" + std::to_string(m) + "_f64", bytes, [&]() {
+        return launch_sap_blocks(L->geo, r, (d2_t*)x, L->links[DDQ_F64][0], L->links[DDQ_F64][1],
+                                 L->clov[DDQ_F64][0], L->clov[DDQ_F64][1], colour, m, L->stream);
+      }));
+    }
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return DDQ_OK;
+}
+
 extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
                                 ddq_solve_info* info) {
   auto t0 = std::chrono::steady_clock::now();

@@ -1,0 +1,69 @@
+"""SAP(n, m) of Alg. 1 (4^4 blocks, block-local odd-even Minimal Residual) through the C
+ABI, against the FP64 oracle's SAP with the same blocks (1e-12 relative).
+
+Lattices: 4^4 (one block spanning every direction: the wrap-around hops, with the
+antiperiodic sign in t, stay inside it), 8x4x4x4 (two blocks along x, one colour each),
+8x8x4x8 (a checkerboard of eight blocks), 12x4x8x4 (three blocks along x: two
+neighbouring blocks share a colour).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import Case, rel
+from oracle import solvers
+from paper_2407_08092_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+DIMS = [(4, 4, 4, 4), (8, 4, 4, 4), (8, 8, 4, 8), (12, 4, 8, 4)]
+_cases = {}
+
+
+def case(dims):
+    if dims not in _cases:
+        _cases[dims] = Case(dims, 0.4, 1.0, -0.2, 501)
+    return _cases[dims]
+
+
+@pytest.mark.parametrize("m", [1, 4])
+@pytest.mark.parametrize("dims", DIMS, ids=lambda d: "x".join(map(str, d)))
+def test_sap_matches_oracle(dims, m):
+    c = case(dims)
+    b = c.full(502)
+    x0 = c.full(503) * 0.1
+    n = 2
+    ref = solvers.sap(c.op, b, x0, n, m)
+    x = torch.from_numpy(x0.copy()).cuda()
+    api.sap_smooth(c.lat, torch.from_numpy(b).cuda(), x, n, m)
+    torch.cuda.synchronize()
+    assert rel(x.cpu().numpy(), ref) < 1e-12
+
+
+def test_sap_reduces_the_residual_and_zero_sweeps():
+    c = case((8, 8, 4, 8))
+    b = c.full(511)
+    bd = torch.from_numpy(b).cuda()
+    x = torch.zeros_like(bd)
+    api.sap_smooth(c.lat, bd, x, 0, 4)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(x) == 0  # n = 0: x unchanged
+    res = []
+    for n in (1, 2, 4):
+        x = torch.zeros_like(bd)
+        api.sap_smooth(c.lat, bd, x, n, 4)
+        res.append(solvers.vnorm(b - c.op.D(x.cpu().numpy())) / solvers.vnorm(b))
+    assert res[0] < 0.5 and res[2] < res[1] < res[0]
+
+
+def test_sap_argument_errors():
+    c = case((4, 4, 4, 4))
+    b = torch.from_numpy(c.full(521)).cuda()
+    with pytest.raises(api.DDQError):
+        api.sap_smooth(c.lat, b, b, 1, 2)  # x and b overlap
+    with pytest.raises(api.DDQError):
+        api.sap_smooth(c.lat, b, torch.zeros_like(b), 1, -1)
+    c6 = Case((6, 6, 6, 10), 0.4, 1.0, -0.2, 522)  # extents not multiples of 4
+    b6 = torch.from_numpy(c6.full(523)).cuda()
+    with pytest.raises(api.DDQError):
+        api.sap_smooth(c6.lat, b6, torch.zeros_like(b6), 1, 2)

@@ -294,6 +294,13 @@ int ddq_sap_smooth(ddq_lattice* lat, void* x, const void* b, int n, int m);
 int ddq_fgmres_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_params* params,
                      ddq_solve_info* info);
 
+/* The same FGMRES on the full D with SAP(sap_n, sap_m) (ddq_sap_smooth, from a zero
+ * initial guess) as the right preconditioner: z_k = SAP applied to D z = v_k.  The
+ * smoother fields of params are not used; the lattice extents must be multiples of 4.
+ * applies_f64 counts the D applies of the Arnoldi steps and residuals. */
+int ddq_fgmres_sap_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_params* params, int sap_n,
+                         int sap_m, ddq_solve_info* info);
+
 /* Batched solves: several lattices of different extents, several right-hand
  * sides each, all solved to their own tolerance in one call.  Each (lattice,
  * right-hand side) pair is one system x = D^-1 b treated exactly as by

@@ -235,3 +235,10 @@ def sap(op, b, x0, n: int, m: int, block=(4, 4, 4, 4)):
                 if colour[k] == c:
                     x = x + block_solve(op, idx == k, r, m)
     return x
+
+
+def sap_preconditioner(op, n: int, m: int, block=(4, 4, 4, 4)):
+    """M v = SAP(n, m) on D z = v from z = 0 (Alg. 1)."""
+    def M(v):
+        return sap(op, v, np.zeros_like(v), n, m, block)
+    return M

@@ -26,7 +26,7 @@ __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
-    "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "sap_smooth", "fgmres_solve", "backward_apply", "backward_link_force", "convert_parity",
+    "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "sap_smooth", "fgmres_solve", "fgmres_sap_solve", "backward_apply", "backward_link_force", "convert_parity",
     "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
@@ -347,6 +347,23 @@ def fgmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int 
     lat.sync_stream()
     st = check(lib().ddq_fgmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
                "ddq_fgmres_solve", allow=(0, 1))
+    return x, info.as_dict(), st == 0
+
+
+def fgmres_sap_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
+                     tol: float = 1e-10, sap_n: int = 1, sap_m: int = 4, inner_reduction: float = 0.0,
+                     orth_passes: int = 2):
+    """FGMRES(m) of Alg. 2 on the full D x = b with SAP(sap_n, sap_m) as right
+    preconditioner.  Returns (x, info, converged)."""
+    if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
+        raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
+    x = torch.zeros_like(b) if x0 is None else x0.clone()
+    p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F64, 0, 0.0, float(inner_reduction), DDQ_F64,
+                    int(orth_passes))
+    info = SolveInfo()
+    lat.sync_stream()
+    st = check(lib().ddq_fgmres_sap_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), int(sap_n),
+                                          int(sap_m), C.byref(info)), "ddq_fgmres_sap_solve", allow=(0, 1))
     return x, info.as_dict(), st == 0
 
 

@@ -1246,50 +1246,43 @@ extern "C" int ddq_oe_smoother(ddq_lattice* L, int nrhs, const void* r, void* z,
                        ws32 ? ws32 + nb : nullptr);
 }
 
-extern "C" int ddq_sap_smooth(ddq_lattice* L, void* x, const void* b, int n, int m) {
-  CHK(check_ready(L, DDQ_F64));
-  if (!x || !b || n < 0 || m < 0) return fail(DDQ_ERR_ARG, "bad SAP arguments");
-  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
-  for (int mu = 0; mu < 4; ++mu)
-    if (L->dims[mu] % 4 != 0) return fail(DDQ_ERR_ARG, "SAP blocks are 4^4: every extent must be a multiple of 4");
-  d2_t* ws64;
-  f2_t* ws32;
-  CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
+namespace {
+
+// SAP(n, m) of Alg. 1 on D x = b (full FP64 vectors), x updated in place: every sweep
+// recomputes r = b - D x before each colour's block solves.  ws64: the workspace of
+// oe_workspace (the residual uses its upper half).
+int sap_impl(ddq_lattice* L, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64) {
   const long long nf = 2 * L->nvec();  // complex numbers of a full vector
-  CHK(L->scratch64.ensure((size_t)nf * 16));
-  d2_t* r = (d2_t*)L->scratch64.p;
+  d2_t* r = ws64 + 4 * (size_t)L->nvec();
   // algorithmic bytes of one colour's launch: per site of that colour's blocks, the
   // residual, the iterate (read and written), the links and the clover blocks once
   const double bytes = (double)L->V / 2 * (192 + 384 + 1152 + 576);
   for (int it = 0; it < n; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      CHK(dirac_impl(L, 1, (const d2_t*)x, r, ws64));  // r = b - D x
+      CHK(dirac_impl(L, 1, x, r, ws64));  // r = b - D x
       HIPCHK(launch_scale(r, r, -1.0, nf, L->stream));
-      HIPCHK(launch_axpy(r, 1.0, 0.0, (const d2_t*)b, nf, L->stream));
+      HIPCHK(launch_axpy(r, 1.0, 0.0, b, nf, L->stream));
       HIPCHK(prof_launch(L, "sap_block_mr" + std::to_string(m) + "_f64", bytes, [&]() {
-        return launch_sap_blocks(L->geo, r, (d2_t*)x, L->links[DDQ_F64][0], L->links[DDQ_F64][1],
-                                 L->clov[DDQ_F64][0], L->clov[DDQ_F64][1], colour, m, L->stream);
+        return launch_sap_blocks(L->geo, r, x, L->links[DDQ_F64][0], L->links[DDQ_F64][1], L->clov[DDQ_F64][0],
+                                 L->clov[DDQ_F64][1], colour, m, L->stream);
       }));
     }
-  HIPCHK(hipStreamSynchronize(L->stream));
   return DDQ_OK;
 }
 
-extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
-                                ddq_solve_info* info) {
+int check_sap(ddq_lattice* L, int n, int m) {
+  if (n < 0 || m < 0) return fail(DDQ_ERR_ARG, "SAP sweeps and Minimal Residual steps must be >= 0");
+  for (int mu = 0; mu < 4; ++mu)
+    if (L->dims[mu] % 4 != 0) return fail(DDQ_ERR_ARG, "SAP blocks are 4^4: every extent must be a multiple of 4");
+  return DDQ_OK;
+}
+
+// FGMRES(m) of Alg. 2 on the full D with right preconditioner precop_z (z = M v)
+int fgmres_full(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P, ddq_solve_info* info,
+                d2_t* ws64, const std::function<int(const d2_t*, d2_t*)>& prec, const int* applies_lo,
+                const int* applies_prec64) {
   auto t0 = std::chrono::steady_clock::now();
-  CHK(check_ready(L, DDQ_F64));
-  if (!x || !b || !P) return fail(DDQ_ERR_ARG, "x, b and params must be non-null");
-  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
   const int m = P->m;
-  if (m < 1 || m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
-  if (P->max_cycles < 0 || !(P->tol >= 0.0) || P->smoother_sweeps < 0 || !std::isfinite(P->omega))
-    return fail(DDQ_ERR_ARG, "bad max_cycles, tol, smoother_sweeps or omega");
-  const int prec = P->inner_prec;
-  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "inner_prec must be DDQ_F64 or DDQ_F32");
-  if (prec == DDQ_F32) CHK(check_ready(L, DDQ_F32));
-  if (P->smoother_prec != 0 && P->smoother_prec != prec)
-    return fail(DDQ_ERR_ARG, "the odd-even smoother runs its sweeps in inner_prec (smoother_prec must be 0)");
   if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
   const int passes = P->orth_passes == 1 ? 1 : 2;
   const long long n = 2 * L->nvec();  // complex numbers of a full vector
@@ -1299,14 +1292,10 @@ extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const dd
   d2_t* w = (d2_t*)L->scratch64.p;
   d2_t* V = w + n;
   d2_t* Z = V + (size_t)(m + 1) * n;
-  d2_t* ws64;
-  f2_t* ws32;
-  CHK(oe_workspace(L, 1, prec, &ws64, &ws32));
-  const size_t nb = L->nvec();
   double bnorm;
   CHK(norm_host(L, (const d2_t*)b, n, &bnorm));
   if (!std::isfinite(bnorm)) return fail(DDQ_ERR_NONFINITE, "right-hand side is not finite");
-  int applies64 = 0, applies_lo = 0;
+  int applies64 = 0;
   const double red = P->inner_reduction > 0.0 ? P->inner_reduction : 0.0;
   KrylovOps ops;
   ops.resid = [&](const d2_t* xx, d2_t* r) -> int {  // r = b - D x
@@ -1316,10 +1305,8 @@ extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const dd
     HIPCHK(launch_axpy(r, 1.0, 0.0, (const d2_t*)b, n, L->stream));
     return DDQ_OK;
   };
-  ops.precop = [&](const d2_t* vk, d2_t* zk, d2_t* ww) -> int {  // z = M_nu v, w = D z
-    CHK(smoother_impl(L, 1, vk, zk, P->smoother_sweeps, P->omega, prec, ws64 + 4 * nb, ws32,
-                      ws32 ? ws32 + nb : nullptr));
-    (prec == DDQ_F64 ? applies64 : applies_lo) += P->smoother_sweeps > 0 ? P->smoother_sweeps - 1 : 0;
+  ops.precop = [&](const d2_t* vk, d2_t* zk, d2_t* ww) -> int {  // z = M v, w = D z
+    CHK(prec(vk, zk));
     CHK(dirac_impl(L, 1, zk, ww, ws64));
     ++applies64;
     return DDQ_OK;
@@ -1331,14 +1318,76 @@ extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const dd
   if (info) {
     info->cycles = run.cycles;
     info->iters = run.iters;
-    info->applies_f64 = applies64;
-    info->applies_lo = applies_lo;
+    info->applies_f64 = applies64 + (applies_prec64 ? *applies_prec64 : 0);
+    info->applies_lo = applies_lo ? *applies_lo : 0;
     info->true_relres = bnorm > 0 ? run.beta / bnorm : 0.0;
     info->t_total_ms =
         std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   }
   if (status == DDQ_NOT_CONVERGED) g_err = "FGMRES stopped at max_cycles";
   return status;
+}
+
+int check_fgmres(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P) {
+  CHK(check_ready(L, DDQ_F64));
+  if (!x || !b || !P) return fail(DDQ_ERR_ARG, "x, b and params must be non-null");
+  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
+  if (P->m < 1 || P->m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
+  if (P->max_cycles < 0 || !(P->tol >= 0.0)) return fail(DDQ_ERR_ARG, "bad max_cycles or tol");
+  return DDQ_OK;
+}
+
+}  // namespace
+
+extern "C" int ddq_sap_smooth(ddq_lattice* L, void* x, const void* b, int n, int m) {
+  CHK(check_ready(L, DDQ_F64));
+  if (!x || !b) return fail(DDQ_ERR_ARG, "bad SAP arguments");
+  if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
+  CHK(check_sap(L, n, m));
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
+  CHK(sap_impl(L, (d2_t*)x, (const d2_t*)b, n, m, ws64));
+  HIPCHK(hipStreamSynchronize(L->stream));
+  return DDQ_OK;
+}
+
+extern "C" int ddq_fgmres_sap_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
+                                    int sap_n, int sap_m, ddq_solve_info* info) {
+  CHK(check_fgmres(L, x, b, P));
+  CHK(check_sap(L, sap_n, sap_m));
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
+  const long long nf = 2 * L->nvec();
+  auto prec = [&](const d2_t* v, d2_t* z) -> int {  // z = SAP(n, m) on D z = v from zero
+    HIPCHK(hipMemsetAsync(z, 0, (size_t)nf * 16, L->stream));
+    return sap_impl(L, z, v, sap_n, sap_m, ws64);
+  };
+  return fgmres_full(L, x, b, P, info, ws64, prec, nullptr, nullptr);
+}
+
+extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,
+                                ddq_solve_info* info) {
+  CHK(check_fgmres(L, x, b, P));
+  if (P->smoother_sweeps < 0 || !std::isfinite(P->omega)) return fail(DDQ_ERR_ARG, "bad smoother_sweeps or omega");
+  const int prec = P->inner_prec;
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "inner_prec must be DDQ_F64 or DDQ_F32");
+  if (prec == DDQ_F32) CHK(check_ready(L, DDQ_F32));
+  if (P->smoother_prec != 0 && P->smoother_prec != prec)
+    return fail(DDQ_ERR_ARG, "the odd-even smoother runs its sweeps in inner_prec (smoother_prec must be 0)");
+  d2_t* ws64;
+  f2_t* ws32;
+  CHK(oe_workspace(L, 1, prec, &ws64, &ws32));
+  const size_t nb = L->nvec();
+  int applies_lo = 0, applies64 = 0;  // Schur applies of the sweeps (the first is a scaling)
+  auto smoother = [&](const d2_t* v, d2_t* z) -> int {  // z = M_nu v
+    CHK(smoother_impl(L, 1, v, z, P->smoother_sweeps, P->omega, prec, ws64 + 4 * nb, ws32,
+                      ws32 ? ws32 + nb : nullptr));
+    (prec == DDQ_F32 ? applies_lo : applies64) += P->smoother_sweeps > 0 ? P->smoother_sweeps - 1 : 0;
+    return DDQ_OK;
+  };
+  return fgmres_full(L, x, b, P, info, ws64, smoother, &applies_lo, &applies64);
 }
 
 // ===========================================================================

@@ -67,3 +67,21 @@ def test_sap_argument_errors():
     b6 = torch.from_numpy(c6.full(523)).cuda()
     with pytest.raises(api.DDQError):
         api.sap_smooth(c6.lat, b6, torch.zeros_like(b6), 1, 2)
+
+
+@pytest.mark.parametrize("sap_n,sap_m", [(1, 4), (2, 2)])
+def test_fgmres_with_sap_matches_oracle(sap_n, sap_m):
+    c = case((8, 8, 4, 8))
+    b = c.full(531)
+    x, info, ok = api.fgmres_sap_solve(c.lat, torch.from_numpy(b).cuda(), m=20, max_cycles=20, tol=1e-10,
+                                       sap_n=sap_n, sap_m=sap_m)
+    assert ok, info
+    xh = x.cpu().numpy()
+    assert solvers.vnorm(b - c.op.D(xh)) <= 1.5e-10 * solvers.vnorm(b)
+    res = solvers.gmres(c.op.D, b, np.zeros_like(b), 20, 20, 1e-10 * solvers.vnorm(b),
+                        solvers.sap_preconditioner(c.op, sap_n, sap_m))
+    assert res.converged
+    assert abs(info["iters"] - res.iters) <= 1
+    assert rel(xh, res.x) < 1e-8
+    with pytest.raises(api.DDQError):
+        api.fgmres_sap_solve(c.lat, torch.from_numpy(b).cuda(), m=8, sap_n=1, sap_m=-1)

@@ -307,6 +307,27 @@ def main():
     fp64 = {"apply_ms": round(t64, 4), "apply_GBs": round(BYTES_APPLY_F64 * vh / (t64 * 1e-3) / 1e9, 1),
             "sweeps_per_s": round(SWEEPS / (e1.elapsed_time(e2) * 1e-3), 1),
             "stream_mix_GBs": stencil_stream_ceiling(api, torch, lat, x64, xs64, b64, y64, 5)}
+    # SAP(1, 4) sweeps (Alg. 1, 4^4 blocks; block solves in FP64 and in FP32) on the same
+    # lattice: the block kernel's live profile and the sweep time
+    bf = torch.from_numpy(synth.gaussian_spinor(dims, cfg["seed_vec"] + 7)).to(dev)
+    xf = torch.zeros_like(bf)
+    for label, prec in (("sap_1x4_f64", api.DDQ_F64), ("sap_1x4_f32", api.DDQ_F32)):
+        api.sap_smooth(lat, bf, xf, 1, 4, prec=prec)
+        torch.cuda.synchronize()
+        api.profile_begin(lat)
+        e0.record(stream)
+        nsap = 3
+        api.sap_smooth(lat, bf, xf, nsap, 4, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sprof = api.profile_end(lat)
+        sap = {"sweep_ms": round(e0.elapsed_time(e1) / nsap, 3),
+               "kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
+                               "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
+                           for k, v in sprof.items()}}
+        fp64[label] = sap
+        log(f"SAP(1, 4) on 48^3x96, {label}: {sap}")
+    del bf, xf
     del y64, xs64, x64, b64
     api.destroy_lattice(lat)
     del lat
@@ -429,12 +450,18 @@ def mixed_vs_fp64(api, synth, torch, dev):
     for name, kw in {"fgmres50_full_oe3_f64": dict(smoother_sweeps=3, inner_prec=api.DDQ_F64),
                      "fgmres50_full_oe8_f64": dict(smoother_sweeps=8, inner_prec=api.DDQ_F64),
                      "fgmres50_full_oe8_f32": dict(smoother_sweeps=8, inner_prec=api.DDQ_F32),
-                     "fgmres50_full_oe16_f32": dict(smoother_sweeps=16, inner_prec=api.DDQ_F32)}.items():
+                     "fgmres50_full_oe16_f32": dict(smoother_sweeps=16, inner_prec=api.DDQ_F32),
+                     "fgmres50_full_sap1x4_f64": dict(sap_n=1, sap_m=4, inner_prec=api.DDQ_F64),
+                     "fgmres50_full_sap1x4_f32": dict(sap_n=1, sap_m=4, inner_prec=api.DDQ_F32),
+                     "fgmres50_full_sap2x4_f32": dict(sap_n=2, sap_m=4, inner_prec=api.DDQ_F32)}.items():
         best = None
         for _ in range(2):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            x, info, ok = api.fgmres_solve(lat, b, m=50, max_cycles=200, tol=1e-10, omega=omega, **kw)
+            if "sap" in name:
+                x, info, ok = api.fgmres_sap_solve(lat, b, m=50, max_cycles=200, tol=1e-10, **kw)
+            else:
+                x, info, ok = api.fgmres_solve(lat, b, m=50, max_cycles=200, tol=1e-10, omega=omega, **kw)
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             best = dt if best is None else min(best, dt)

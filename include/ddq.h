@@ -276,10 +276,13 @@ int ddq_oe_smoother(ddq_lattice* lat, int nrhs, const void* r, void* z, int nswe
  * block's sites (hops that leave it dropped; a block that spans a whole direction keeps
  * its wrap-around hops, with the antiperiodic sign in t), solved approximately by
  * odd-even preconditioning on the block and m Minimal Residual steps on the block's
- * Schur complement from zero, then added to x on the block.  x: initial guess in,
- * iterate out; b: right-hand side (device, not overlapping).  One workgroup per block,
- * the block's half vectors in LDS.  Synchronises the stream. */
-int ddq_sap_smooth(ddq_lattice* lat, void* x, const void* b, int n, int m);
+ * Schur complement from zero, then added to x on the block.  prec: the block solves in
+ * DDQ_F64, or in DDQ_F32 with the FP32 links (12-real if stored so) and clover blocks
+ * (their dot products accumulated in FP64); the residuals b - D x and the update of x
+ * are FP64 either way.  x: initial guess in, iterate out; b: right-hand side (device,
+ * not overlapping).  One workgroup per block, the block's half vectors in LDS.
+ * Synchronises the stream. */
+int ddq_sap_smooth(ddq_lattice* lat, int prec, void* x, const void* b, int n, int m);
 
 /* Flexible GMRES(m) of Alg. 2 on the full D x = b (FP64 full vectors; the fine-level
  * solver of Sect. 2.3) with M_nu (ddq_oe_smoother) as right preconditioner: nu =
@@ -295,8 +298,9 @@ int ddq_fgmres_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_p
                      ddq_solve_info* info);
 
 /* The same FGMRES on the full D with SAP(sap_n, sap_m) (ddq_sap_smooth, from a zero
- * initial guess) as the right preconditioner: z_k = SAP applied to D z = v_k.  The
- * smoother fields of params are not used; the lattice extents must be multiples of 4.
+ * initial guess, block solves in params->inner_prec) as the right preconditioner:
+ * z_k = SAP applied to D z = v_k.  The other smoother fields of params are not used;
+ * the lattice extents must be multiples of 4.
  * applies_f64 counts the D applies of the Arnoldi steps and residuals. */
 int ddq_fgmres_sap_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_params* params, int sap_n,
                          int sap_m, ddq_solve_info* info);

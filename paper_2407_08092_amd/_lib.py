@@ -83,7 +83,7 @@ _SIGNATURES = {
     "ddq_apply_dirac": [_P, C.c_int, _P, _P],
     "ddq_oe_smoother": [_P, C.c_int, _P, _P, C.c_int, C.c_double, C.c_int],
     "ddq_fgmres_solve": [_P, _P, _P, _P, _P],
-    "ddq_sap_smooth": [_P, _P, _P, C.c_int, C.c_int],
+    "ddq_sap_smooth": [_P, C.c_int, _P, _P, C.c_int, C.c_int],
     "ddq_fgmres_sap_solve": [_P, _P, _P, _P, C.c_int, C.c_int, _P],
     "ddq_profile_begin": [_P],
     "ddq_profile_end": [_P, C.POINTER(KernelStats), C.c_int, C.POINTER(C.c_int)],

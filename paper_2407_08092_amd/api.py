@@ -324,12 +324,13 @@ def oe_smoother(lat: Lattice, r: torch.Tensor, nsweeps: int, omega: float, prec:
     return z
 
 
-def sap_smooth(lat: Lattice, b: torch.Tensor, x: torch.Tensor, n: int, m: int) -> torch.Tensor:
-    """SAP(n, m) of Alg. 1 on D x = b with 4^4 blocks, in place on x (full FP64)."""
+def sap_smooth(lat: Lattice, b: torch.Tensor, x: torch.Tensor, n: int, m: int, prec: int = DDQ_F64) -> torch.Tensor:
+    """SAP(n, m) of Alg. 1 on D x = b with 4^4 blocks, in place on x (full FP64); the
+    block solves in prec (DDQ_F64 or DDQ_F32)."""
     if _full_nrhs(lat, b, "b") != 1 or _full_nrhs(lat, x, "x") != 1:
         raise ValueError("one right-hand side")
     lat.sync_stream()
-    check(lib().ddq_sap_smooth(lat.handle, _dev(x, "x"), _dev(b, "b"), int(n), int(m)), "ddq_sap_smooth")
+    check(lib().ddq_sap_smooth(lat.handle, int(prec), _dev(x, "x"), _dev(b, "b"), int(n), int(m)), "ddq_sap_smooth")
     return x
 
 
@@ -351,15 +352,15 @@ def fgmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int 
 
 
 def fgmres_sap_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
-                     tol: float = 1e-10, sap_n: int = 1, sap_m: int = 4, inner_reduction: float = 0.0,
-                     orth_passes: int = 2):
+                     tol: float = 1e-10, sap_n: int = 1, sap_m: int = 4, inner_prec: int = DDQ_F64,
+                     inner_reduction: float = 0.0, orth_passes: int = 2):
     """FGMRES(m) of Alg. 2 on the full D x = b with SAP(sap_n, sap_m) as right
-    preconditioner.  Returns (x, info, converged)."""
+    preconditioner (block solves in inner_prec).  Returns (x, info, converged)."""
     if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
         raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
-    p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F64, 0, 0.0, float(inner_reduction), DDQ_F64,
-                    int(orth_passes))
+    p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), 0, 0.0, float(inner_reduction),
+                    int(inner_prec), int(orth_passes))
     info = SolveInfo()
     lat.sync_stream()
     st = check(lib().ddq_fgmres_sap_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), int(sap_n),

@@ -100,6 +100,8 @@ struct ddq_lattice {
   Grow scratch32;     // FP32 parity vectors
   Grow oe_ws64;       // full operator and odd-even smoother: FP64 parity vectors
   Grow oe_ws32;       // the smoother's FP32 parity vectors
+  Grow sap_links[2], sap_clov[2];  // links and clover blocks per parity in SAP order
+  int sap_prec = -1;               // their precision; -1: not built for the current fields
   Grow partial;       // reduction partials
   Grow small;         // device scalars: h (2 x 256 complex), norms
   double* host = nullptr;  // pinned host mirror of `small`
@@ -491,6 +493,10 @@ int ddq_destroy_lattice(ddq_lattice* L) {
   L->scratch32.release();
   L->oe_ws64.release();
   L->oe_ws32.release();
+  for (int q = 0; q < 2; ++q) {
+    L->sap_links[q].release();
+    L->sap_clov[q].release();
+  }
   L->force_ws.release();
   L->partial.release();
   L->small.release();
@@ -523,6 +529,7 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   if (storage_flags & DDQ_STORE_F32_LINK12) storage_flags |= DDQ_STORE_F32;
   L->have_gauge = false;
   L->have_clover = false;
+  L->sap_prec = -1;
   const size_t ubytes = (size_t)L->V * 4 * 9 * 16;
   if (!L->U) CHK(dalloc(&L->U, ubytes));
   HIPCHK(hipMemcpyAsync(L->U, U, ubytes, U_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -577,6 +584,7 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
   if (!L->have_gauge) return fail(DDQ_ERR_STATE, "ddq_set_gauge has not been called");
   if (!std::isfinite(c_sw) || !std::isfinite(m0)) return fail(DDQ_ERR_ARG, "c_sw and m0 must be finite");
   L->have_clover = false;
+  L->sap_prec = -1;
   const size_t n = (size_t)36 * field_vh((int)L->Vh);  // (re, im) slots per parity
   for (int q = 0; q < 2; ++q)
     if (!L->clov[DDQ_F64][q]) {
@@ -1249,22 +1257,41 @@ extern "C" int ddq_oe_smoother(ddq_lattice* L, int nrhs, const void* r, void* z,
 namespace {
 
 // SAP(n, m) of Alg. 1 on D x = b (full FP64 vectors), x updated in place: every sweep
-// recomputes r = b - D x before each colour's block solves.  ws64: the workspace of
-// oe_workspace (the residual uses its upper half).
-int sap_impl(ddq_lattice* L, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64) {
+// recomputes r = b - D x (FP64) before each colour's block solves, which run in prec
+// (DDQ_F64 or DDQ_F32).  ws64: the workspace of oe_workspace (the residual uses its
+// upper half).
+int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64) {
   const long long nf = 2 * L->nvec();  // complex numbers of a full vector
   d2_t* r = ws64 + 4 * (size_t)L->nvec();
-  // algorithmic bytes of one colour's launch: per site of that colour's blocks, the
-  // residual, the iterate (read and written), the links and the clover blocks once
-  const double bytes = (double)L->V / 2 * (192 + 384 + 1152 + 576);
+  const bool f32 = prec == DDQ_F32;
+  const bool l12 = f32 && L->link12;
+  if (L->sap_prec != prec) {  // links and clover in SAP order, built once per gauge field and clover
+    const int cpe = f32 ? 2 : 1;
+    const int lrows = (l12 ? LINK12_ROWS : LINK_ROWS) / cpe, crows = CLOVER_ROWS / cpe;
+    const size_t fvh = (size_t)field_vh((int)L->Vh);
+    for (int q = 0; q < 2; ++q) {
+      CHK(L->sap_links[q].ensure(4 * (size_t)lrows * fvh * 16));
+      CHK(L->sap_clov[q].ensure((size_t)crows * fvh * 16));
+      for (int mu = 0; mu < 4; ++mu)
+        HIPCHK(launch_sap_reorder(L->geo, q, (const char*)L->links[prec][q] + (size_t)mu * lrows * fvh * 16,
+                                  (char*)L->sap_links[q].p + (size_t)mu * lrows * fvh * 16, lrows, L->stream));
+      HIPCHK(launch_sap_reorder(L->geo, q, L->clov[prec][q], L->sap_clov[q].p, crows, L->stream));
+    }
+    L->sap_prec = prec;
+  }
+  // algorithmic bytes of one colour's launch: per site of that colour's blocks, the FP64
+  // residual, the FP64 iterate (read and written), the links and the clover blocks once
+  const double per_site = 192 + 384 + (f32 ? (l12 ? 384 : 576) + 288 : 1152 + 576);
+  const double bytes = (double)L->V / 2 * per_site;
+  const std::string name = "sap_block_mr" + std::to_string(m) + (f32 ? (l12 ? "_f32l12" : "_f32") : "_f64");
   for (int it = 0; it < n; ++it)
     for (int colour = 0; colour < 2; ++colour) {
       CHK(dirac_impl(L, 1, x, r, ws64));  // r = b - D x
       HIPCHK(launch_scale(r, r, -1.0, nf, L->stream));
       HIPCHK(launch_axpy(r, 1.0, 0.0, b, nf, L->stream));
-      HIPCHK(prof_launch(L, "sap_block_mr" + std::to_string(m) + "_f64", bytes, [&]() {
-        return launch_sap_blocks(L->geo, r, x, L->links[DDQ_F64][0], L->links[DDQ_F64][1], L->clov[DDQ_F64][0],
-                                 L->clov[DDQ_F64][1], colour, m, L->stream);
+      HIPCHK(prof_launch(L, name, bytes, [&]() {
+        return launch_sap_blocks(L->geo, f32, l12, r, x, L->sap_links[0].p, L->sap_links[1].p, L->sap_clov[0].p,
+                                 L->sap_clov[1].p, colour, m, L->stream);
       }));
     }
   return DDQ_OK;
@@ -1339,15 +1366,17 @@ int check_fgmres(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params*
 
 }  // namespace
 
-extern "C" int ddq_sap_smooth(ddq_lattice* L, void* x, const void* b, int n, int m) {
+extern "C" int ddq_sap_smooth(ddq_lattice* L, int prec, void* x, const void* b, int n, int m) {
   CHK(check_ready(L, DDQ_F64));
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "prec must be DDQ_F64 or DDQ_F32");
+  CHK(check_ready(L, prec));
   if (!x || !b) return fail(DDQ_ERR_ARG, "bad SAP arguments");
   if (x == b) return fail(DDQ_ERR_ARG, "x and b must not overlap");
   CHK(check_sap(L, n, m));
   d2_t* ws64;
   f2_t* ws32;
   CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
-  CHK(sap_impl(L, (d2_t*)x, (const d2_t*)b, n, m, ws64));
+  CHK(sap_impl(L, prec, (d2_t*)x, (const d2_t*)b, n, m, ws64));
   HIPCHK(hipStreamSynchronize(L->stream));
   return DDQ_OK;
 }
@@ -1356,15 +1385,18 @@ extern "C" int ddq_fgmres_sap_solve(ddq_lattice* L, void* x, const void* b, cons
                                     int sap_n, int sap_m, ddq_solve_info* info) {
   CHK(check_fgmres(L, x, b, P));
   CHK(check_sap(L, sap_n, sap_m));
+  const int prec = P->inner_prec;
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "inner_prec must be DDQ_F64 or DDQ_F32");
+  CHK(check_ready(L, prec));
   d2_t* ws64;
   f2_t* ws32;
   CHK(oe_workspace(L, 1, DDQ_F64, &ws64, &ws32));
   const long long nf = 2 * L->nvec();
-  auto prec = [&](const d2_t* v, d2_t* z) -> int {  // z = SAP(n, m) on D z = v from zero
+  auto sap_prec = [&](const d2_t* v, d2_t* z) -> int {  // z = SAP(n, m) on D z = v from zero
     HIPCHK(hipMemsetAsync(z, 0, (size_t)nf * 16, L->stream));
-    return sap_impl(L, z, v, sap_n, sap_m, ws64);
+    return sap_impl(L, prec, z, v, sap_n, sap_m, ws64);
   };
-  return fgmres_full(L, x, b, P, info, ws64, prec, nullptr, nullptr);
+  return fgmres_full(L, x, b, P, info, ws64, sap_prec, nullptr, nullptr);
 }
 
 extern "C" int ddq_fgmres_solve(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* P,

@@ -189,10 +189,17 @@ hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows
 hipError_t launch_links_to_f32_12(const d2_t* in, void* out, int vh, hipStream_t s);
 hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s);
-// SAP block solves (FP64): for every 4^4 block of `colour`, m Minimal Residual steps on
-// the block Schur complement of D_kk e = r_k, then x += e on the block (full vectors)
-hipError_t launch_sap_blocks(const Geo& g, const d2_t* r, d2_t* x, const void* links_e, const void* links_o,
-                             const void* clov_e, const void* clov_oi, int colour, int m, hipStream_t s);
+// SAP block solves: for every 4^4 block of `colour`, m Minimal Residual steps on the
+// block Schur complement of D_kk e = r_k, then x += e on the block (FP64 full vectors r,
+// x); the block solve in FP64, or in FP32 (prec_f32) with FP32 links (12-real: link12)
+// and clover, all in SAP order (launch_sap_reorder)
+hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t* r, d2_t* x, const void* links_e,
+                             const void* links_o, const void* clov_e, const void* clov_oi, int colour, int m,
+                             hipStream_t s);
+// copy of a blocked field of parity `parity` (erows element rows) into SAP order (the
+// 128 sites of that parity of every 4^4 block consecutive), as launch_sap_blocks reads
+// its links and clover
+hipError_t launch_sap_reorder(const Geo& g, int parity, const void* src, void* dst, int erows, hipStream_t s);
 // A_ee into clov_even, A_oo^-1 into clov_odd_inv and (when not null) A_oo into clov_odd
 hipError_t launch_clover_build(const Geo& g, const d2_t* U, double c_sw, double m0,
                                d2_t* clov_even, d2_t* clov_odd_inv, d2_t* clov_odd, int* notpd, hipStream_t s);

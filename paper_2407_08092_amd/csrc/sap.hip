@@ -1,4 +1,4 @@
-// sap.hip -- the block solves of SAP(n, m) (Sect. 2.4.1, Alg. 1), FP64.
+// sap.hip -- the block solves of SAP(n, m) (Sect. 2.4.1, Alg. 1).
 //
 // The lattice is cut into 4^4 blocks aligned at the origin; a block's colour is the
 // parity of the sum of its block coordinates.  One workgroup solves one block of the
@@ -6,10 +6,15 @@
 // block dropped; a block that spans a whole direction keeps the wrap-around hops, with
 // the antiperiodic sign in t), by odd-even preconditioning on the block (eq. 2 with the
 // block's hopping terms) and m Minimal Residual steps on the block's Schur complement
-// from zero; then x += e on the block's sites.  Thread j of the 128 owns the j-th even
-// and the j-th odd site of the block (the checkerboard half index of the block's
+// from zero; then x += e on the block's sites.  The residual and the iterate are FP64
+// full vectors; the block solve runs in R (FP64, or FP32 with FP32 links and clover),
+// its dot products accumulated in FP64.  Thread j of the 128 owns the j-th even and
+// the j-th odd site of the block (the checkerboard half index of the block's
 // lexicographic site order); the hopping terms read the other parity's half-block
-// vector from LDS, the links and clover blocks from HBM.
+// vector from one LDS buffer, the links and clover blocks from HBM in SAP order: a copy
+// of the link and clover fields with the 128 sites of one parity of each block at
+// consecutive positions blockIdx * 128 + j (k_sap_reorder), so that every row a
+// wavefront loads is one contiguous run.
 #include "hop_common.h"
 
 namespace ddq {
@@ -31,9 +36,11 @@ __device__ __forceinline__ void sap_local(int j, int p, int lc[4]) {
 // the 8 hops of (1 -/+ g_mu) U p(neighbour), p read from the other parity's half-block
 // vector v[12][128] in LDS (zero for neighbours outside the block); `c` carries the
 // site's links and the t-boundary signs
-__device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cpx<double> (*v)[SAP_HALF],
-                                         const HopCtx<double>& c, Spinor<double>& acc) {
+template <typename R, bool L12>
+__device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cpx<R> (*v)[SAP_HALF],
+                                         const HopCtx<R>& c, Spinor<R>& acc) {
   zero(acc);
+  Link<R> ub;
 #pragma unroll
   for (int H = 0; H < 8; ++H) {
     const int mu = H >> 1;
@@ -44,7 +51,7 @@ __device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cp
       nc[mu] = (nc[mu] + SAP_B) % SAP_B;
       inside = true;
     }
-    Spinor<double> p;
+    Spinor<R> p;
     if (inside) {
       const int jn = (nc[0] + SAP_B * (nc[1] + SAP_B * (nc[2] + SAP_B * nc[3]))) >> 1;
 #pragma unroll
@@ -54,48 +61,62 @@ __device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cp
     } else {
       zero(p);
     }
-    const Link<double> u = load_link_half<double>(link_field(c, mu), H & 1, c.loff);
-    switch (H) {
-      case 0: hop_compute<0, double>(acc, p, u, c); break;
-      case 1: hop_compute<1, double>(acc, p, u, c); break;
-      case 2: hop_compute<2, double>(acc, p, u, c); break;
-      case 3: hop_compute<3, double>(acc, p, u, c); break;
-      case 4: hop_compute<4, double>(acc, p, u, c); break;
-      case 5: hop_compute<5, double>(acc, p, u, c); break;
-      case 6: hop_compute<6, double>(acc, p, u, c); break;
-      default: hop_compute<7, double>(acc, p, u, c); break;
+    Link<R> u;
+    if constexpr (CPE<R> == 1) {
+      u = load_link_half<R>(link_field(c, mu), H & 1, c.loff);
+    } else if ((H & 1) == 0) {
+      if constexpr (L12)
+        load_link_pair12<R>(link_field(c, mu), c.loff, u, ub);
+      else
+        load_link_pair<R>(link_field(c, mu), c.loff, u, ub);
+    } else {
+      u = ub;
+      if constexpr (L12) su3_third_row(u);
     }
-    hop_fence<double>(acc);  // one hop at a time: bounds the live registers
+    switch (H) {
+      case 0: hop_compute<0, R>(acc, p, u, c); break;
+      case 1: hop_compute<1, R>(acc, p, u, c); break;
+      case 2: hop_compute<2, R>(acc, p, u, c); break;
+      case 3: hop_compute<3, R>(acc, p, u, c); break;
+      case 4: hop_compute<4, R>(acc, p, u, c); break;
+      case 5: hop_compute<5, R>(acc, p, u, c); break;
+      case 6: hop_compute<6, R>(acc, p, u, c); break;
+      default: hop_compute<7, R>(acc, p, u, c); break;
+    }
+    hop_fence<R>(acc);  // one hop at a time: bounds the live registers
   }
 }
 
-__device__ __forceinline__ void sap_put(cpx<double> (*v)[SAP_HALF], int j, const Spinor<double>& s) {
+template <typename R>
+__device__ __forceinline__ void sap_put(cpx<R> (*v)[SAP_HALF], int j, const Spinor<R>& s) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int a = 0; a < 3; ++a) v[3 * sp + a][j] = s.c[sp][a];
 }
 
-__device__ __forceinline__ Spinor<double> sap_load_full(const d2_t* f, long long site) {
-  Spinor<double> s;
+template <typename R>
+__device__ __forceinline__ Spinor<R> sap_load_full(const d2_t* f, long long site) {
+  Spinor<R> s;
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       const d2_t q = f[site * 12 + 3 * sp + a];
-      s.c[sp][a] = {q.x, q.y};
+      s.c[sp][a] = {(R)q.x, (R)q.y};
     }
   return s;
 }
 
-__device__ __forceinline__ void sap_add_full(d2_t* f, long long site, const Spinor<double>& s) {
+template <typename R>
+__device__ __forceinline__ void sap_add_full(d2_t* f, long long site, const Spinor<R>& s) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
       d2_t q = f[site * 12 + 3 * sp + a];
-      q.x += s.c[sp][a].r;
-      q.y += s.c[sp][a].i;
+      q.x += (double)s.c[sp][a].r;
+      q.y += (double)s.c[sp][a].i;
       f[site * 12 + 3 * sp + a] = q;
     }
   store_fence();
@@ -120,18 +141,18 @@ struct SapArgs {
   Geo g;
   const d2_t* r;  // full residual b - D x (ABI full layout)
   d2_t* x;        // full iterate, updated on the blocks of `colour`
-  const pair<double>* links[2];  // FP64 links per parity
-  const pair<double>* clov_e;    // A_ee (even sites)
-  const pair<double>* clov_oi;   // A_oo^-1 (odd sites)
+  const void* links[2];  // links per parity, in the block solve's precision
+  const void* clov_e;    // A_ee (even sites)
+  const void* clov_oi;   // A_oo^-1 (odd sites)
   int nb[4];                     // blocks per direction
   int colour;
   int m;  // Minimal Residual steps
 };
 
+template <typename R, bool L12>
 __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
-  __shared__ cpx<double> ve[12][SAP_HALF];  // even half-block vector
-  __shared__ cpx<double> vo[12][SAP_HALF];  // odd half-block vector
-  __shared__ cpx<double> vx[12][SAP_HALF];  // the even half of the block correction (own slot only)
+  __shared__ cpx<R> vb[12][SAP_HALF];  // the other parity's half-block vector of the current hop
+  __shared__ cpx<R> vx[12][SAP_HALF];  // the even half of the block correction (own slot only)
   __shared__ double red[6];
   const Geo& g = a.g;
   int bc[4];
@@ -159,68 +180,72 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
     site_e = ge[0] + (long long)g.L[0] * (ge[1] + (long long)g.L[1] * (ge[2] + (long long)g.L[2] * ge[3]));
     site_o = go[0] + (long long)g.L[0] * (go[1] + (long long)g.L[1] * (go[2] + (long long)g.L[2] * go[3]));
   }
-  const int ie = (int)(site_e >> 1), io = (int)(site_o >> 1);  // checkerboard indices
+  const int ss = (int)blockIdx.x * SAP_HALF + j;  // SAP-order position of both sites
   const int vh = g.Vh;
+  constexpr int LR = L12 ? LINK12_ROWS : LINK_ROWS;
+  constexpr int CL_E = CLOVER_ROWS / CPE<R>;
   // hopping context of each of the thread's two sites: links, signs of the t hops
-  HopCtx<double> ce, co;
-  ce.links = a.links[0];
-  co.links = a.links[1];
-  ce.lrows = co.lrows = LINK_ROWS;
+  HopCtx<R> ce, co;
+  ce.links = (const pair<R>*)a.links[0];
+  co.links = (const pair<R>*)a.links[1];
+  ce.lrows = co.lrows = LR;
   ce.vh = co.vh = vh;
-  ce.loff = boff(ie, LINK_ROWS);
-  co.loff = boff(io, LINK_ROWS);
-  ce.sf = co.sf = -1.0;  // D: forward (1 - g), backward (1 + g)
-  ce.sb = co.sb = 1.0;
+  ce.loff = boff(ss, LR / CPE<R>);
+  co.loff = boff(ss, LR / CPE<R>);
+  ce.sf = co.sf = R(-1);  // D: forward (1 - g), backward (1 + g)
+  ce.sb = co.sb = R(1);
   const bool wrap_t = g.L[3] == SAP_B && g.antiperiodic;
   ce.nb.sgn_tf = (wrap_t && le[3] == SAP_B - 1) ? -1.f : 1.f;
   ce.nb.sgn_tb = (wrap_t && le[3] == 0) ? -1.f : 1.f;
   co.nb.sgn_tf = (wrap_t && lo[3] == SAP_B - 1) ? -1.f : 1.f;
   co.nb.sgn_tb = (wrap_t && lo[3] == 0) ? -1.f : 1.f;
-  const Field Ce = bfield(a.clov_e, CLOVER_ROWS, vh);
-  const Field Co = bfield(a.clov_oi, CLOVER_ROWS, vh);
-  const uint32_t cofe = boff(ie, CLOVER_ROWS), cofo = boff(io, CLOVER_ROWS);
+  const Field Ce = bfield(a.clov_e, CL_E, vh);
+  const Field Co = bfield(a.clov_oi, CL_E, vh);
+  const uint32_t cofe = boff(ss, CL_E), cofo = boff(ss, CL_E);
 
-  Spinor<double> acc, rr, q;
+  Spinor<R> acc, rr, q;
   // eq. 2 on the block: b~_e = r_e - D_eo A_oo^-1 r_o = r_e + H_eo (A_oo^-1 r_o)
-  sap_put(vo, j, clover_mul<double>(Co, cofo, sap_load_full(a.r, site_o)));
+  sap_put(vb, j, clover_mul<R>(Co, cofo, sap_load_full<R>(a.r, site_o)));
   __syncthreads();
-  sap_hops(g, le, vo, ce, acc);
-  rr = sap_load_full(a.r, site_e);
+  sap_hops<R, L12>(g, le, vb, ce, acc);
+  rr = sap_load_full<R>(a.r, site_e);
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      rr.c[s][c] = rr.c[s][c] + 0.5 * acc.c[s][c];
-      vx[3 * s + c][j] = {0.0, 0.0};
+      rr.c[s][c] = rr.c[s][c] + R(0.5) * acc.c[s][c];
+      vx[3 * s + c][j] = {R(0), R(0)};
     }
   // Minimal Residual on the block Schur complement S = A_ee - H_eo A_oo^-1 H_oe
   for (int it = 0; it < a.m; ++it) {
-    __syncthreads();  // every thread is done with ve and vo of the previous step
-    sap_put(ve, j, rr);
+    __syncthreads();  // every thread is done reading vb
+    sap_put(vb, j, rr);
     __syncthreads();
-    sap_hops(g, lo, ve, co, acc);  // H_oe r
+    sap_hops<R, L12>(g, lo, vb, co, acc);  // H_oe r
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int c = 0; c < 3; ++c) acc.c[s][c] = 0.5 * acc.c[s][c];
-    sap_put(vo, j, clover_mul<double>(Co, cofo, acc));  // A_oo^-1 H_oe r
+      for (int c = 0; c < 3; ++c) acc.c[s][c] = R(0.5) * acc.c[s][c];
+    const Spinor<R> t = clover_mul<R>(Co, cofo, acc);  // A_oo^-1 H_oe r
+    __syncthreads();  // every thread is done reading r from vb
+    sap_put(vb, j, t);
     __syncthreads();
-    sap_hops(g, le, vo, ce, acc);  // H_eo A_oo^-1 H_oe r
-    q = clover_mul<double>(Ce, cofe, rr);
+    sap_hops<R, L12>(g, le, vb, ce, acc);  // H_eo A_oo^-1 H_oe r
+    q = clover_mul<R>(Ce, cofe, rr);
     double d[3] = {0.0, 0.0, 0.0};  // q^H r, |q|^2
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        q.c[s][c] = q.c[s][c] - 0.5 * acc.c[s][c];
-        const cpx<double> qv = q.c[s][c], rv = rr.c[s][c];
-        d[0] += qv.r * rv.r + qv.i * rv.i;
-        d[1] += qv.r * rv.i - qv.i * rv.r;
-        d[2] += qv.r * qv.r + qv.i * qv.i;
+        q.c[s][c] = q.c[s][c] - R(0.5) * acc.c[s][c];
+        const double qr = q.c[s][c].r, qi = q.c[s][c].i, rr_ = rr.c[s][c].r, ri = rr.c[s][c].i;
+        d[0] += qr * rr_ + qi * ri;
+        d[1] += qr * ri - qi * rr_;
+        d[2] += qr * qr + qi * qi;
       }
     sap_sum3(d, red);
     if (d[2] == 0.0) break;  // uniform: every thread holds the same sums
-    const cpx<double> alpha = {d[0] / d[2], d[1] / d[2]};
+    const cpx<R> alpha = {(R)(d[0] / d[2]), (R)(d[1] / d[2])};
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -236,29 +261,66 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       q.c[s][c] = vx[3 * s + c][j];
-      ve[3 * s + c][j] = q.c[s][c];
+      vb[3 * s + c][j] = q.c[s][c];
     }
   sap_add_full(a.x, site_e, q);
   __syncthreads();
-  sap_hops(g, lo, ve, co, acc);
-  rr = sap_load_full(a.r, site_o);
+  sap_hops<R, L12>(g, lo, vb, co, acc);
+  rr = sap_load_full<R>(a.r, site_o);
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
-    for (int c = 0; c < 3; ++c) acc.c[s][c] = rr.c[s][c] + 0.5 * acc.c[s][c];
-  sap_add_full(a.x, site_o, clover_mul<double>(Co, cofo, acc));
+    for (int c = 0; c < 3; ++c) acc.c[s][c] = rr.c[s][c] + R(0.5) * acc.c[s][c];
+  sap_add_full(a.x, site_o, clover_mul<R>(Co, cofo, acc));
 }
 
-hipError_t launch_sap_blocks(const Geo& g, const d2_t* r, d2_t* x, const void* links_e, const void* links_o,
-                             const void* clov_e, const void* clov_oi, int colour, int m, hipStream_t s) {
+// dst = src with its sites of parity p in SAP order: element row e of SAP position
+// s = block * 128 + j comes from the site's checkerboard index (blocked fields of
+// erows element rows)
+__global__ void k_sap_reorder(Geo g, int p, int nb0, int nb1, int nb2, const u4_t* __restrict__ src,
+                              u4_t* __restrict__ dst, int erows) {
+  const long long t = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (long long)g.Vh * erows) return;
+  const int s = (int)(t % g.Vh), e = (int)(t / g.Vh);
+  int b = s / SAP_HALF;
+  const int j = s % SAP_HALF;
+  int bc[4];
+  bc[0] = b % nb0;
+  b /= nb0;
+  bc[1] = b % nb1;
+  b /= nb1;
+  bc[2] = b % nb2;
+  bc[3] = b / nb2;
+  int lc[4];
+  sap_local(j, p, lc);
+  long long lex = 0;
+  for (int mu = 3; mu >= 0; --mu) lex = lex * g.L[mu] + (SAP_B * bc[mu] + lc[mu]);
+  const int i = (int)(lex >> 1);
+  dst[fidx(e, s, erows, g.Vh)] = src[fidx(e, i, erows, g.Vh)];
+}
+
+hipError_t launch_sap_reorder(const Geo& g, int parity, const void* src, void* dst, int erows, hipStream_t s) {
+  for (int mu = 0; mu < 4; ++mu)
+    if (g.L[mu] % SAP_B != 0) return hipErrorInvalidValue;
+  const long long n = (long long)g.Vh * erows;
+  const long long blocks = (n + 255) / 256;
+  if (blocks > 0x7fffffffLL) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_sap_reorder, dim3((unsigned)blocks), dim3(256), 0, s, g, parity, g.L[0] / SAP_B,
+                     g.L[1] / SAP_B, g.L[2] / SAP_B, (const u4_t*)src, (u4_t*)dst, erows);
+  return hipGetLastError();
+}
+
+hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t* r, d2_t* x, const void* links_e,
+                             const void* links_o, const void* clov_e, const void* clov_oi, int colour, int m,
+                             hipStream_t s) {
   SapArgs a;
   a.g = g;
   a.r = r;
   a.x = x;
-  a.links[0] = (const pair<double>*)links_e;
-  a.links[1] = (const pair<double>*)links_o;
-  a.clov_e = (const pair<double>*)clov_e;
-  a.clov_oi = (const pair<double>*)clov_oi;
+  a.links[0] = links_e;
+  a.links[1] = links_o;
+  a.clov_e = clov_e;
+  a.clov_oi = clov_oi;
   long long nblk = 1;
   for (int mu = 0; mu < 4; ++mu) {
     if (g.L[mu] % SAP_B != 0) return hipErrorInvalidValue;
@@ -268,7 +330,13 @@ hipError_t launch_sap_blocks(const Geo& g, const d2_t* r, d2_t* x, const void* l
   if (nblk > 0x7fffffffLL || m < 0) return hipErrorInvalidValue;
   a.colour = colour & 1;
   a.m = m;
-  hipLaunchKernelGGL(k_sap_block, dim3((unsigned)nblk), dim3(SAP_HALF), 0, s, a);
+  const dim3 grid((unsigned)nblk), block(SAP_HALF);
+  if (!prec_f32)
+    hipLaunchKernelGGL((k_sap_block<double, false>), grid, block, 0, s, a);
+  else if (link12)
+    hipLaunchKernelGGL((k_sap_block<float, true>), grid, block, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sap_block<float, false>), grid, block, 0, s, a);
   return hipGetLastError();
 }
 

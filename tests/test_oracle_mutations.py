@@ -189,3 +189,22 @@ def test_sap_mutants_caught(monkeypatch, name, mutant, pin):
     monkeypatch.setattr(solvers, name, mutant)
     with pytest.raises(AssertionError):
         pin()
+
+
+# coarse operator: forward and backward neighbours swapped
+from oracle import coarse  # noqa: E402
+import test_oracle_coarse as cpins  # noqa: E402
+
+_orig_cnb = coarse.coarse_neighbour
+
+
+def _cnb_swapped(cd, i, d):
+    if d == 0:
+        return i
+    return _orig_cnb(cd, i, d + 1 if (d - 1) % 2 == 0 else d - 1)
+
+
+def test_coarse_direction_mutant_caught(monkeypatch):
+    monkeypatch.setattr(coarse, "coarse_neighbour", _cnb_swapped)
+    with pytest.raises(AssertionError):
+        cpins.test_free_field_blocks_closed_form()

@@ -404,6 +404,38 @@ int ddq_stream_copy(void* dst, const void* src, int64_t bytes, int nontemporal, 
 int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, const void* x, const void* b,
                        void* out);
 
+/* Coarse-grid operator of the two-level method (Sect. 2.3): the Galerkin operator
+ * D_c = P^H D P of an aggregation-based prolongation P is nearest-neighbour on the
+ * coarse lattice, with nine dense 2N_v x 2N_v complex blocks per coarse site, so
+ *     y(x) = sum_{d=0..8} A(x, d) v(x + d)
+ * with d = 0 the site's own block and d = 1 + 2 mu + s the block coupling to the
+ * neighbour in direction mu (0..3 = x, y, z, t), forward (s = 0) or backward (s = 1).
+ * The coarse lattice is periodic in all directions (a fine antiperiodic boundary sign
+ * is part of the blocks).  Coarse site index x + Cx*(y + Cy*(z + Cz*t)); a coarse
+ * vector row q in 0 .. 2N_v-1 is chirality q / N_v, test vector q % N_v.  Blocks are
+ * stored and applied in FP32 (Sect. 3.3 applies them in single precision), with FP32
+ * accumulation on the matrix cores; the library does not build P or the blocks.
+ *
+ * ddq_coarse_packed_bytes: bytes of the packed block array for coarse extents cdims
+ *   (each >= 1, at most 2^25 sites) and N_v test vectors (1 .. 32).
+ * ddq_coarse_pack_blocks: converts blocks[site][d][row i][column k] (row-major complex
+ *   numbers, complex128 for prec = DDQ_F64 or complex64 for DDQ_F32) into the apply's
+ *   packed FP32 operand order (zero-padded to 16 x 8 tiles) in `packed`, a caller-owned
+ *   device array of ddq_coarse_packed_bytes bytes, 16-byte aligned.  Enqueued on
+ *   hip_stream; allocates nothing.
+ * ddq_coarse_apply: y = D_c v for nrhs right-hand sides (1 .. 1048560); v and y are
+ *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost),
+ *   8-byte aligned, y not overlapping v.  One wavefront per coarse site and per group of
+ *   rhs_tiles_per_wave tiles of 16 right-hand sides (0 = the default, 4); every group
+ *   reads the packed blocks once.  Enqueued on hip_stream; allocates nothing.
+ * Errors: DDQ_ERR_ARG for null or misaligned pointers and sizes out of range,
+ * DDQ_ERR_HIP if a launch fails. */
+int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes);
+int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blocks, void* packed,
+                           void* hip_stream);
+int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
+                     int rhs_tiles_per_wave, void* hip_stream);
+
 /* Thread-local message of the last error (empty string if none). */
 const char* ddq_last_error(void);
 

@@ -27,6 +27,7 @@ __all__ = [
     "pack_parity", "unpack_parity", "apply_schur", "richardson_smooth", "estimate_lambda_max",
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
     "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "sap_smooth", "fgmres_solve", "fgmres_sap_solve", "backward_apply", "backward_link_force", "convert_parity",
+    "CoarseOperator",
     "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
@@ -516,3 +517,50 @@ def backward_link_force(lat: Lattice, chi_e: torch.Tensor, phi_e: torch.Tensor, 
                                         _dev(G, "G") if want_G else None, _dev(F, "F") if want_F else None,
                                         int(acc)), "ddq_backward_link_force")
     return G, F
+
+
+class CoarseOperator:
+    """The coarse-grid operator of Sect. 2.3 on the device: nine 2N_v x 2N_v complex
+    blocks per coarse site, packed once into the library's FP32 operand order.
+
+    blocks: complex128 or complex64 device tensor [sites, 9, 2 N_v, 2 N_v] (block d = 0
+    the site's own, d = 1 + 2 mu + s the neighbour in direction mu, forward s = 0 or
+    backward s = 1); cdims: coarse extents (x, y, z, t), site index x fastest."""
+
+    def __init__(self, cdims, blocks: torch.Tensor):
+        self.cdims = tuple(int(c) for c in cdims)
+        if len(self.cdims) != 4:
+            raise ValueError("cdims needs four extents")
+        vc = 1
+        for c in self.cdims:
+            vc *= c
+        if blocks.dim() != 4 or blocks.shape[0] != vc or blocks.shape[1] != 9 or blocks.shape[2] != blocks.shape[3] \
+                or blocks.shape[2] % 2:
+            raise ValueError(f"blocks must be [{vc}, 9, 2 N_v, 2 N_v], got {tuple(blocks.shape)}")
+        if blocks.dtype not in (torch.complex128, torch.complex64):
+            raise TypeError("blocks must be complex128 or complex64")
+        self.nv = blocks.shape[2] // 2
+        self.vc = vc
+        self.device = blocks.device
+        self._cd = (C.c_int * 4)(*self.cdims)
+        nb = C.c_int64()
+        check(lib().ddq_coarse_packed_bytes(self._cd, self.nv, C.byref(nb)), "ddq_coarse_packed_bytes")
+        self.packed = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib().ddq_coarse_pack_blocks(self._cd, self.nv, _prec(blocks), _dev(blocks, "blocks"),
+                                           _dev(self.packed, "packed"), C.c_void_p(s)), "ddq_coarse_pack_blocks")
+
+    def apply(self, v: torch.Tensor, out: torch.Tensor = None, rhs_tiles_per_wave: int = 0) -> torch.Tensor:
+        """y = D_c v; v complex64 [sites, 2 N_v] or [sites, 2 N_v, nrhs] (right-hand side innermost)"""
+        if v.dtype != torch.complex64:
+            raise TypeError("coarse vectors are complex64")
+        if v.dim() not in (2, 3) or v.shape[0] != self.vc or v.shape[1] != 2 * self.nv:
+            raise ValueError(f"v must be [{self.vc}, {2 * self.nv}(, nrhs)], got {tuple(v.shape)}")
+        nrhs = 1 if v.dim() == 2 else v.shape[2]
+        y = torch.empty_like(v) if out is None else out
+        if y.shape != v.shape or y.dtype != v.dtype:
+            raise ValueError("out must match v")
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        check(lib().ddq_coarse_apply(self._cd, self.nv, nrhs, _dev(self.packed, "packed"), _dev(v, "v"),
+                                     _dev(y, "out"), int(rhs_tiles_per_wave), C.c_void_p(s)), "ddq_coarse_apply")
+        return y

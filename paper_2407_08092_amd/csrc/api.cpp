@@ -13,6 +13,7 @@
 
 #include "../../include/ddq.h"
 #include "ddq_internal.h"
+#include "coarse_internal.h"
 
 using namespace ddq;
 using cd = std::complex<double>;
@@ -884,6 +885,38 @@ int ddq_stencil_stream(ddq_lattice* L, int prec, int kernel, const void* in, con
     HIPCHK(run(double{}));
   else
     HIPCHK(run(float{}));
+  return DDQ_OK;
+}
+
+int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes) {
+  if (!cdims || !bytes) return fail(DDQ_ERR_ARG, "null argument");
+  const long long n = coarse_packed_bytes(cdims, nv);
+  if (n < 0) return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  *bytes = n;
+  return DDQ_OK;
+}
+
+int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blocks, void* packed, void* hip_stream) {
+  if (!cdims || !blocks || !packed) return fail(DDQ_ERR_ARG, "null argument");
+  if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "blocks are complex128 (DDQ_F64) or complex64 (DDQ_F32)");
+  if (((uintptr_t)packed & 15) || ((uintptr_t)blocks & (prec == DDQ_F64 ? 15 : 7)))
+    return fail(DDQ_ERR_ARG, "misaligned blocks or packed array");
+  if (coarse_packed_bytes(cdims, nv) < 0)
+    return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  HIPCHK(launch_coarse_pack(cdims, nv, prec == DDQ_F64, blocks, packed, (hipStream_t)hip_stream));
+  return DDQ_OK;
+}
+
+int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
+                     int rhs_tiles_per_wave, void* hip_stream) {
+  if (!cdims || !packed || !v || !y) return fail(DDQ_ERR_ARG, "null argument");
+  if (coarse_packed_bytes(cdims, nv) < 0)
+    return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  if (nrhs < 1 || nrhs > 65535 * 16) return fail(DDQ_ERR_ARG, "nrhs must be in 1 .. 1048560");
+  if (rhs_tiles_per_wave < 0 || rhs_tiles_per_wave > 4) return fail(DDQ_ERR_ARG, "rhs_tiles_per_wave must be 0 .. 4");
+  if (((uintptr_t)packed & 15) || (((uintptr_t)v | (uintptr_t)y) & 7)) return fail(DDQ_ERR_ARG, "misaligned argument");
+  if (v == y) return fail(DDQ_ERR_ARG, "y must not overlap v");
+  HIPCHK(launch_coarse_apply(cdims, nv, nrhs, rhs_tiles_per_wave, packed, v, y, (hipStream_t)hip_stream));
   return DDQ_OK;
 }
 

@@ -1,0 +1,238 @@
+// coarse.hip -- the coarse-grid operator of Sect. 2.3 on several right-hand sides,
+//   y(x) = sum over d of A(x, d) v(x + d),
+// nine 2N_v x 2N_v complex blocks per coarse site (d = 0 the site's own, d = 1 + 2 mu + s
+// the neighbour in direction mu, forward s = 0 or backward s = 1, periodic), FP32
+// operands and accumulation, on the matrix cores.
+//
+// The contraction per block is a complex (2N_v x 2N_v) x (2N_v x nrhs) product: four
+// real products per 4-wide slice k of the contraction index and per 16 x 16 output tile
+// (Yr += Ar Vr - Ai Vi, Yi += Ar Vi + Ai Vr) with v_mfma_f32_16x16x4_f32, whose operand
+// lane l holds A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16] and whose
+// accumulator element e of lane l is C[4 (l / 16) + e][l % 16].
+//
+// Blocks are repacked once (k_coarse_pack) into that operand order, zero-padded to whole
+// tiles, two k-slices per 16-byte lane element:
+//   packed[x][d][kp][t][lane][4] = (Re, Im) A[16 t + l % 16][8 kp + l / 16]     (slice 2kp)
+//                                  (Re, Im) A[16 t + l % 16][8 kp + 4 + l / 16] (slice 2kp+1)
+// so a wave reads 1 KB contiguous per load.  A wave of the apply owns one coarse site and
+// up to TN tiles of 16 right-hand sides: every block element it loads feeds TN tiles, so a
+// launch reads the blocks ceil(nrhs / (16 TN)) times (once up to 16 TN right-hand sides).
+// Vectors are complex64 [site][row][rhs] (rhs innermost): the 16 lanes of one row read or
+// write 128 contiguous bytes.
+#include <hip/hip_runtime.h>
+
+#include "coarse_internal.h"
+
+namespace ddq {
+
+namespace {
+
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+struct CoarseGeo {
+  int cd[4];  // coarse extents
+  int n2;     // 2 N_v
+  int MT;     // row tiles: ceil(n2 / 16)
+  int KP;     // pairs of k-slices: ceil(n2 / 8)
+  int vc;     // coarse sites
+  int xcd_slab;  // 1: workgroup w -> site (w % 8) * (vc / 8) + w / 8 (vc % 8 == 0)
+};
+
+__device__ __forceinline__ int coarse_nbr(const CoarseGeo& g, int x, int d) {
+  if (d == 0) return x;
+  const int mu = (d - 1) >> 1;
+  int c[4], r = x;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    c[k] = r % g.cd[k];
+    r /= g.cd[k];
+  }
+  c[mu] += ((d - 1) & 1) ? g.cd[mu] - 1 : 1;
+  if (c[mu] >= g.cd[mu]) c[mu] -= g.cd[mu];
+  return c[0] + g.cd[0] * (c[1] + g.cd[1] * (c[2] + g.cd[2] * c[3]));
+}
+
+// one thread per 16-byte packed element; src complex [x][d][i][k] (row-major blocks)
+template <typename R>
+__global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __restrict__ src, f4v* __restrict__ dst,
+                                                     long long n_el) {
+  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n_el) return;
+  const int lane = (int)(e & 63);
+  long long r = e >> 6;
+  const int t = (int)(r % g.MT);
+  r /= g.MT;
+  const int kp = (int)(r % g.KP);
+  const long long xd = r / g.KP;  // x * 9 + d
+  const int i = 16 * t + (lane & 15);
+  const R* blk = src + xd * 2 * (long long)g.n2 * g.n2;
+  float o[4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = 8 * kp + 4 * h + (lane >> 4);
+    const bool in = i < g.n2 && k < g.n2;
+    o[2 * h] = in ? (float)blk[2 * ((long long)i * g.n2 + k)] : 0.f;
+    o[2 * h + 1] = in ? (float)blk[2 * ((long long)i * g.n2 + k) + 1] : 0.f;
+  }
+  dst[e] = f4v{o[0], o[1], o[2], o[3]};
+}
+
+// operands of one pair of k-slices: the packed block slice and the right-hand sides' rows
+template <int MT, int TN>
+struct CoarseSlice {
+  f4v a[MT];
+  float2 b[2][TN];
+};
+
+template <int MT, int TN>
+__device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* Akp, const float2* vn, int kp, int n2,
+                                            int nrhs, int lk, int j0) {
+#pragma unroll
+  for (int t = 0; t < MT; ++t) o.a[t] = __builtin_nontemporal_load(Akp + t * 64);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int k = 8 * kp + 4 * h + lk;
+#pragma unroll
+    for (int n = 0; n < TN; ++n) {
+      const int j = j0 + 16 * n;
+      o.b[h][n] = (k < n2 && j < nrhs) ? vn[(size_t)k * nrhs + j] : float2{0.f, 0.f};
+    }
+  }
+}
+
+template <int MT, int TN>
+__global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
+                                                     const float2* __restrict__ v, float2* __restrict__ y) {
+  const int w = (int)blockIdx.x;
+  const int x = g.xcd_slab ? (w & 7) * (g.vc >> 3) + (w >> 3) : w;
+  const int l = (int)threadIdx.x, li = l & 15, lk = l >> 4;
+  const int j0 = 16 * TN * (int)blockIdx.y + li;  // this lane's column in tile 0
+  const size_t vstride = (size_t)g.n2 * nrhs;
+  f4v yr[TN][MT], yi[TN][MT];
+#pragma unroll
+  for (int n = 0; n < TN; ++n)
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      yr[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
+      yi[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
+    }
+  // the (block, k-slice pair) sequence is walked in storage order; the loads of the
+  // next pair are issued before the products of the current one
+  const f4v* Ap = A + (size_t)x * 9 * g.KP * MT * 64 + l;
+  const float2* vcur = v + (size_t)x * vstride;
+  CoarseSlice<MT, TN> cur, nxt;
+  coarse_load<MT, TN>(cur, Ap, vcur, 0, g.n2, nrhs, lk, j0);
+  for (int d = 0; d < 9; ++d) {
+    const float2* vnext = d < 8 ? v + (size_t)coarse_nbr(g, x, d + 1) * vstride : vcur;
+    for (int kp = 0; kp < g.KP; ++kp) {
+      Ap += MT * 64;
+      if (kp + 1 < g.KP)
+        coarse_load<MT, TN>(nxt, Ap, vcur, kp + 1, g.n2, nrhs, lk, j0);
+      else if (d < 8)
+        coarse_load<MT, TN>(nxt, Ap, vnext, 0, g.n2, nrhs, lk, j0);
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int n = 0; n < TN; ++n) {
+          const float2 b = cur.b[h][n];
+#pragma unroll
+          for (int t = 0; t < MT; ++t) {
+            const float ar = cur.a[t][2 * h], ai = cur.a[t][2 * h + 1];
+            yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, yr[n][t], 0, 0, 0);
+            yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b.y, yr[n][t], 0, 0, 0);
+            yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, yi[n][t], 0, 0, 0);
+            yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.x, yi[n][t], 0, 0, 0);
+          }
+        }
+      cur = nxt;
+    }
+    vcur = vnext;
+  }
+  float2* yx = y + (size_t)x * vstride;
+#pragma unroll
+  for (int n = 0; n < TN; ++n) {
+    const int j = j0 + 16 * n;
+    if (j >= nrhs) continue;
+#pragma unroll
+    for (int t = 0; t < MT; ++t)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int i = 16 * t + 4 * lk + e;
+        if (i < g.n2) yx[(size_t)i * nrhs + j] = float2{yr[n][t][e], yi[n][t][e]};
+      }
+  }
+}
+
+hipError_t make_geo(const int cd[4], int nv, CoarseGeo& g) {
+  if (nv < 1 || nv > 32) return hipErrorInvalidValue;
+  long long vc = 1;
+  for (int k = 0; k < 4; ++k) {
+    if (cd[k] < 1) return hipErrorInvalidValue;
+    g.cd[k] = cd[k];
+    vc *= cd[k];
+  }
+  if (vc > (1LL << 25)) return hipErrorInvalidValue;  // grid.x * 64 work-items stays below 2^31
+  g.vc = (int)vc;
+  g.n2 = 2 * nv;
+  g.MT = (g.n2 + 15) / 16;
+  g.KP = (g.n2 + 7) / 8;
+  g.xcd_slab = (g.vc % 8 == 0) ? 1 : 0;
+  return hipSuccess;
+}
+
+template <int MT>
+hipError_t launch_mt(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
+  const int tiles = (nrhs + 15) / 16;
+  const dim3 grid((unsigned)g.vc, (unsigned)((tiles + tn - 1) / tn)), block(64);
+  switch (tn) {
+    case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 3: hipLaunchKernelGGL((k_coarse_apply<MT, 3>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    default: hipLaunchKernelGGL((k_coarse_apply<MT, 4>), grid, block, 0, s, g, nrhs, A, v, y); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+long long coarse_packed_bytes(const int cd[4], int nv) {
+  CoarseGeo g;
+  if (make_geo(cd, nv, g) != hipSuccess) return -1;
+  return (long long)g.vc * 9 * g.KP * g.MT * 64 * 16;
+}
+
+hipError_t launch_coarse_pack(const int cd[4], int nv, int src_f64, const void* src, void* dst, hipStream_t s) {
+  CoarseGeo g;
+  hipError_t e = make_geo(cd, nv, g);
+  if (e != hipSuccess) return e;
+  const long long n_el = (long long)g.vc * 9 * g.KP * g.MT * 64;
+  const dim3 grid((unsigned)((n_el + 255) / 256)), block(256);
+  if (src_f64)
+    hipLaunchKernelGGL(k_coarse_pack<double>, grid, block, 0, s, g, (const double*)src, (f4v*)dst, n_el);
+  else
+    hipLaunchKernelGGL(k_coarse_pack<float>, grid, block, 0, s, g, (const float*)src, (f4v*)dst, n_el);
+  return hipGetLastError();
+}
+
+hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, const void* packed,
+                               const void* v, void* y, hipStream_t s) {
+  CoarseGeo g;
+  hipError_t e = make_geo(cd, nv, g);
+  if (e != hipSuccess) return e;
+  const int tiles = (nrhs + 15) / 16;
+  if (nrhs < 1 || (tiles + 3) / 4 > 65535) return hipErrorInvalidValue;
+  int tn = rhs_tiles_per_wave > 0 ? rhs_tiles_per_wave : 4;
+  if (tn > 4) return hipErrorInvalidValue;
+  if (tn > tiles) tn = tiles;
+  const f4v* A = (const f4v*)packed;
+  const float2* vv = (const float2*)v;
+  float2* yy = (float2*)y;
+  switch (g.MT) {
+    case 1: return launch_mt<1>(g, nrhs, tn, A, vv, yy, s);
+    case 2: return launch_mt<2>(g, nrhs, tn, A, vv, yy, s);
+    case 3: return launch_mt<3>(g, nrhs, tn, A, vv, yy, s);
+    default: return launch_mt<4>(g, nrhs, tn, A, vv, yy, s);
+  }
+}
+
+}  // namespace ddq

@@ -1,0 +1,17 @@
+// coarse_internal.h -- launchers of the coarse-grid operator kernels (coarse.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace ddq {
+
+// bytes of the packed block array for coarse extents cd and N_v test vectors (-1 if out of range)
+long long coarse_packed_bytes(const int cd[4], int nv);
+// repack complex blocks [site][9][2 N_v][2 N_v] (row-major, complex128 if src_f64 else complex64)
+hipError_t launch_coarse_pack(const int cd[4], int nv, int src_f64, const void* src, void* dst, hipStream_t s);
+// y = D_c v on nrhs complex64 right-hand sides, vectors [site][2 N_v][nrhs];
+// rhs_tiles_per_wave in 0 (default 4) .. 4
+hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, const void* packed,
+                               const void* v, void* y, hipStream_t s);
+
+}  // namespace ddq

@@ -1,0 +1,145 @@
+"""The coarse-grid operator of Sect. 2.3 (nine 2N_v x 2N_v blocks per coarse site) on
+the matrix cores, through the C ABI, against the FP64 oracle.
+
+The device stores blocks and vectors in FP32 and accumulates in FP32; the oracle runs in
+FP64 on the same FP32-rounded inputs.  Each output element is a sum of 9 x 2N_v complex
+products, so its error is bounded by about 9 x 2N_v x 2^-24 times the sum of the
+magnitudes of its terms; the tests take 2e-6 of that sum (a small multiple of the
+bound's typical square-root growth) element by element.  Cases: random blocks with
+N_v = 4, 8, 10, 20, 24, 32 (2N_v = 8, 16, 20, 40, 48, 64: whole and ragged 16-row tiles
+and 8-column pairs of k-slices), 1 .. 80 right-hand sides (whole and ragged 16-wide
+tiles, one to four tiles per wave, several waves per site), coarse extents 1 and 2
+(neighbours coincide) and extents whose volume is or is not a multiple of 8 (the XCD
+site map is taken or not); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
+checked against P^H D P applied on the CPU; and a 12^3 x 24 coarse lattice (the
+coarsening of 48^3 x 96 by 4^4 aggregates) with N_v = 24 and 16 right-hand sides,
+sampled sites against the oracle's sum for those sites.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import coarse
+from oracle.dirac import Lattice, WilsonClover
+from paper_2407_08092_amd import api, synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rand(shape, seed):
+    return synth.gaussian_complex(shape, seed).astype(np.complex64)
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _term_bound(A, cd, v, sites=None):
+    """sum over d and k of |A[x, d, i, k]| |v[nbr, k, j]| for every output element"""
+    sites = range(A.shape[0]) if sites is None else sites
+    out = []
+    for x in sites:
+        acc = 0
+        for d in range(9):
+            acc = acc + np.abs(A[x, d]) @ np.abs(v[coarse.coarse_neighbour(cd, x, d)])
+        out.append(acc)
+    return np.stack(out)
+
+
+def _check(cd, nv, nrhs, seed, tn=0, blocks_f64=False):
+    Vc, n2 = int(np.prod(cd)), 2 * nv
+    A64 = synth.gaussian_complex((Vc, 9, n2, n2), seed)
+    A = A64.astype(np.complex64)
+    v = _rand((Vc, n2, nrhs), seed + 1)
+    op = api.CoarseOperator(cd, _dev(A64 if blocks_f64 else A))
+    y = op.apply(_dev(v), rhs_tiles_per_wave=tn).cpu().numpy()
+    ref = coarse.coarse_apply(A.astype(np.complex128), cd, v.astype(np.complex128))
+    tol = 2e-6 * _term_bound(A.astype(np.complex128), cd, v.astype(np.complex128))
+    err = np.abs(y - ref)
+    assert np.all(err <= tol), (err / tol).max()
+    return y
+
+
+@pytest.mark.parametrize("nv", [4, 8, 10, 20, 24, 32])
+def test_random_blocks_match_oracle(nv):
+    _check((3, 2, 3, 4), nv, 16, 701 + nv)
+
+
+@pytest.mark.parametrize("nrhs,tn", [(1, 0), (5, 0), (16, 1), (17, 0), (33, 2), (48, 3), (64, 4), (80, 0), (80, 1),
+                                     (50, 3)])
+def test_rhs_tiling_matches_oracle(nrhs, tn):
+    _check((2, 3, 2, 4), 10, nrhs, 711 + nrhs, tn)
+
+
+@pytest.mark.parametrize("cd", [(1, 1, 1, 1), (2, 2, 2, 2), (1, 3, 2, 5), (4, 4, 4, 4)])
+def test_extents_match_oracle(cd):
+    _check(cd, 8, 20, 731 + sum(cd))
+
+
+def test_complex128_blocks_are_rounded_once():
+    # FP64 blocks: the pack rounds them to FP32, the same as passing the rounded ones
+    cd, nv, nrhs = (2, 2, 3, 2), 6, 24
+    Vc, n2 = 24, 12
+    A64 = synth.gaussian_complex((Vc, 9, n2, n2), 741)
+    v = _dev(_rand((Vc, n2, nrhs), 742))
+    y64 = api.CoarseOperator(cd, _dev(A64)).apply(v)
+    y32 = api.CoarseOperator(cd, _dev(A64.astype(np.complex64))).apply(v)
+    torch.cuda.synchronize()
+    assert torch.equal(y64, y32)
+
+
+def test_single_vector_and_tiles_per_wave_agree():
+    cd, nv = (3, 3, 2, 2), 12
+    Vc, n2 = 36, 24
+    A = _rand((Vc, 9, n2, n2), 751)
+    op = api.CoarseOperator(cd, _dev(A))
+    v = _rand((Vc, n2, 64), 752)
+    ys = [op.apply(_dev(v), rhs_tiles_per_wave=tn).cpu().numpy() for tn in (1, 2, 3, 4)]
+    for y in ys[1:]:  # the same products in the same order whatever the grouping
+        assert np.array_equal(y, ys[0])
+    y1 = op.apply(_dev(v[:, :, 7].copy())).cpu().numpy()
+    assert np.array_equal(y1, ys[0][:, :, 7])
+
+
+def test_galerkin_operator_matches_restricted_fine_operator():
+    dims, agg, nv = (6, 6, 6, 6), (2, 2, 2, 2), 8
+    lat = Lattice(dims)
+    op = WilsonClover(lat, synth.gauge_field(dims, 0.3, 761), 1.0, -0.1)
+    P = coarse.Prolongation(lat, agg, [synth.gaussian_spinor(dims, 762 + k) for k in range(nv)])
+    A = coarse.galerkin_blocks(op, P)
+    vc = synth.gaussian_complex((P.Vc, 2, nv, 4), 770).astype(np.complex64)
+    y = api.CoarseOperator(P.cd, _dev(A)).apply(_dev(vc.reshape(P.Vc, 2 * nv, 4))).cpu().numpy()
+    for r in range(4):
+        ref = P.restrict(op.D(P.prolong(vc[..., r].astype(np.complex128)))).reshape(P.Vc, 2 * nv)
+        assert np.linalg.norm(y[:, :, r] - ref) <= 1e-5 * np.linalg.norm(ref)
+
+
+def test_full_size_coarse_lattice_sampled():
+    # 48^3 x 96 coarsened by 4^4 aggregates, N_v = 24, 16 right-hand sides (the benchmarked shape)
+    cd, nv, nrhs = (12, 12, 12, 24), 24, 16
+    Vc, n2 = 12 * 12 * 12 * 24, 48
+    g = torch.Generator(device="cuda").manual_seed(781)
+    A = torch.randn((Vc, 9, n2, n2), dtype=torch.complex64, device="cuda", generator=g)
+    v = torch.randn((Vc, n2, nrhs), dtype=torch.complex64, device="cuda", generator=g)
+    y = api.CoarseOperator(cd, A).apply(v)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(782)
+    sites = sorted(set(rng.integers(0, Vc, 40).tolist()) | {0, Vc - 1, 12 * 12 * 12 * 23, 11})
+    for x in sites:
+        nbr = [coarse.coarse_neighbour(cd, x, d) for d in range(9)]
+        Ax = A[x].cpu().numpy().astype(np.complex128)
+        vn = v[nbr].cpu().numpy().astype(np.complex128)
+        ref = sum(Ax[d] @ vn[d] for d in range(9))
+        bound = sum(np.abs(Ax[d]) @ np.abs(vn[d]) for d in range(9))
+        assert np.all(np.abs(y[x].cpu().numpy() - ref) <= 2e-6 * bound), x
+
+
+def test_bad_shapes_rejected():
+    A = torch.zeros((16, 9, 8, 8), dtype=torch.complex64, device="cuda")
+    with pytest.raises(ValueError):
+        api.CoarseOperator((2, 2, 2, 3), A)
+    op = api.CoarseOperator((2, 2, 2, 2), A)
+    with pytest.raises(TypeError):
+        op.apply(torch.zeros((16, 8, 4), dtype=torch.complex128, device="cuda"))
+    with pytest.raises(api.DDQError):
+        op.apply(torch.zeros((16, 8, 4), dtype=torch.complex64, device="cuda"), rhs_tiles_per_wave=7)

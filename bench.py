@@ -129,11 +129,22 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multi-rhs-only", action="store_true")
     ap.add_argument("--batch-only", action="store_true")
+    ap.add_argument("--coarse-only", action="store_true")
+    ap.add_argument("--coarse-nv", type=int, nargs="+", default=[24, 20])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the path is single-GPU; "
               f"multi-GPU sharding is design only)", file=sys.stderr)
         sys.exit(2)
+
+    if args.coarse_only:
+        import torch
+
+        from paper_2407_08092_amd import api
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"coarse": coarse_operator(api, torch, torch.device("cuda:0"), args.coarse_nv)}), flush=True)
+        return
 
     if args.multi_rhs_only or args.batch_only:
         import torch
@@ -343,6 +354,7 @@ def main():
     multi, batch = None, None
     if not args.no_batch:
         multi, batch = batched(api, synth, torch, dev)
+    coarse = coarse_operator(api, torch, dev, args.coarse_nv)
 
     out = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -363,10 +375,62 @@ def main():
         "mixed_vs_fp64": mixed,
         "multi_rhs": multi,
         "batched": batch,
+        "coarse": coarse,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
+    """The coarse-grid operator (Sect. 2.3) on the coarsening of 48^3 x 96 by 4^4
+    aggregates (12^3 x 24 coarse sites), random FP32 blocks, N_v = 24 and 20, 16 and 64
+    right-hand sides.  Algorithmic flops per site: 9 blocks x 8 (2 N_v)^2 per right-hand
+    side; algorithmic bytes: the nine FP32 blocks once per group of right-hand sides
+    sharing a wave (9 x (2 N_v)^2 x 8 B per site and group), the input vectors once and
+    the output once (2 N_v x nrhs x 8 B each per site)."""
+    cd = (12, 12, 12, 24)
+    vc = 12 * 12 * 12 * 24
+    out = {"workload": "coarse operator of 48^3x96 with 4^4 aggregates: 12^3x24 coarse sites, nine "
+                       "2N_v x 2N_v FP32 complex blocks per site, random blocks and vectors",
+           "coarse_dims": list(cd), "peak_TFLOPs_fp32_mfma": MFMA_F32_PEAK_TFLOPS}
+    for nv in nvs:
+        n2 = 2 * nv
+        g = torch.Generator(device=dev).manual_seed(900 + nv)
+        blocks = torch.randn((vc, 9, n2, n2), dtype=torch.complex64, device=dev, generator=g)
+        op = api.CoarseOperator(cd, blocks)
+        del blocks
+        for nrhs in (16, 64):
+            v = torch.randn((vc, n2, nrhs), dtype=torch.complex64, device=dev, generator=g)
+            y = torch.empty_like(v)
+            for _ in range(2):
+                op.apply(v, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                op.apply(v, y)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            tiles = (nrhs + 15) // 16
+            groups = (tiles + 3) // 4
+            flops = 8.0 * n2 * n2 * nrhs * 9 * vc
+            nbytes = groups * 9 * n2 * n2 * 8 * vc + 2 * n2 * nrhs * 8 * vc
+            tf = flops / (ms * 1e-3) / 1e12
+            gbs = nbytes / (ms * 1e-3) / 1e9
+            out[f"nv{nv}_rhs{nrhs}"] = {"ms": round(ms, 4), "TFLOPs": round(tf, 1),
+                                        "frac_mfma_peak": round(tf / MFMA_F32_PEAK_TFLOPS, 3), "GBs": round(gbs, 1),
+                                        "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 3),
+                                        "flop_per_byte": round(flops / nbytes, 2)}
+            log(f"coarse N_v={nv} nrhs={nrhs}: {out[f'nv{nv}_rhs{nrhs}']}")
+            del v, y
+        del op
+        torch.cuda.empty_cache()
+    return out
 
 
 def stencil_stream_ceiling(api, torch, lat, vin, x, b, out, reps):

@@ -426,8 +426,8 @@ int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, c
  * ddq_coarse_apply: y = D_c v for nrhs right-hand sides (1 .. 1048560); v and y are
  *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost),
  *   8-byte aligned, y not overlapping v.  One wavefront per coarse site and per group of
- *   rhs_tiles_per_wave tiles of 16 right-hand sides (0 = the default, 4); every group
- *   reads the packed blocks once.  Enqueued on hip_stream; allocates nothing.
+ *   rhs_tiles_per_wave tiles of 16 right-hand sides (1 .. 4; 0 = the default: the fewest
+ *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once.  Enqueued on hip_stream; allocates nothing.
  * Errors: DDQ_ERR_ARG for null or misaligned pointers and sizes out of range,
  * DDQ_ERR_HIP if a launch fails. */
 int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes);

@@ -28,6 +28,7 @@ namespace ddq {
 namespace {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef float f2v __attribute__((ext_vector_type(2)));
 
 struct CoarseGeo {
   int cd[4];  // coarse extents
@@ -84,9 +85,19 @@ struct CoarseSlice {
   float2 b[2][TN];
 };
 
+// buffer resource over one coarse site's vector (n2 x nrhs complex64); dword 3 is the
+// gfx9 default (32-bit data format, no swizzle)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t site_rsrc(const float2* vn, int bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void*)vn, (short)0, bytes, 0x00020000);
+}
+
+// Rows k >= 2 N_v and columns j >= nrhs read as zero: their offset lies past the
+// resource's extent, for which buffer loads return 0.  Every lane issues every load, so
+// the loads in flight are counted statically and the products of one slice wait only for
+// that slice's own operands.
 template <int MT, int TN>
-__device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* Akp, const float2* vn, int kp, int n2,
-                                            int nrhs, int lk, int j0) {
+__device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* Akp, __amdgpu_buffer_rsrc_t vr, int kp,
+                                            int n2, int nrhs, int lk, int j0) {
 #pragma unroll
   for (int t = 0; t < MT; ++t) o.a[t] = __builtin_nontemporal_load(Akp + t * 64);
 #pragma unroll
@@ -95,10 +106,36 @@ __device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* A
 #pragma unroll
     for (int n = 0; n < TN; ++n) {
       const int j = j0 + 16 * n;
-      o.b[h][n] = (k < n2 && j < nrhs) ? vn[(size_t)k * nrhs + j] : float2{0.f, 0.f};
+      const int off = (k < n2 && j < nrhs) ? (k * nrhs + j) * 8 : 0x7ffffff0;
+      const f2v t = __builtin_bit_cast(f2v, __builtin_amdgcn_raw_buffer_load_b64(vr, off, 0, 0));
+      o.b[h][n] = float2{t.x, t.y};
     }
   }
 }
+
+template <int MT, int TN>
+__device__ __forceinline__ void coarse_mma(const CoarseSlice<MT, TN>& c, f4v (&yr)[TN][MT], f4v (&yi)[TN][MT]) {
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int n = 0; n < TN; ++n) {
+      const float2 b = c.b[h][n];
+#pragma unroll
+      for (int t = 0; t < MT; ++t) {
+        const float ar = c.a[t][2 * h], ai = c.a[t][2 * h + 1];
+        yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, yr[n][t], 0, 0, 0);
+        yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b.y, yr[n][t], 0, 0, 0);
+        yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, yi[n][t], 0, 0, 0);
+        yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.x, yi[n][t], 0, 0, 0);
+      }
+    }
+}
+
+// position of the next load in the sequence of (block d, k-slice pair kp), storage order
+struct CoarseCursor {
+  int q, d, kp;  // linear step, block, slice pair; wraps to the start past the end
+  __amdgpu_buffer_rsrc_t vr;
+};
 
 template <int MT, int TN>
 __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
@@ -108,6 +145,7 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, cons
   const int l = (int)threadIdx.x, li = l & 15, lk = l >> 4;
   const int j0 = 16 * TN * (int)blockIdx.y + li;  // this lane's column in tile 0
   const size_t vstride = (size_t)g.n2 * nrhs;
+  const int vbytes = g.n2 * nrhs * 8;
   f4v yr[TN][MT], yi[TN][MT];
 #pragma unroll
   for (int n = 0; n < TN; ++n)
@@ -116,37 +154,27 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, cons
       yr[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
       yi[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
     }
-  // the (block, k-slice pair) sequence is walked in storage order; the loads of the
-  // next pair are issued before the products of the current one
-  const f4v* Ap = A + (size_t)x * 9 * g.KP * MT * 64 + l;
-  const float2* vcur = v + (size_t)x * vstride;
-  CoarseSlice<MT, TN> cur, nxt;
-  coarse_load<MT, TN>(cur, Ap, vcur, 0, g.n2, nrhs, lk, j0);
-  for (int d = 0; d < 9; ++d) {
-    const float2* vnext = d < 8 ? v + (size_t)coarse_nbr(g, x, d + 1) * vstride : vcur;
-    for (int kp = 0; kp < g.KP; ++kp) {
-      Ap += MT * 64;
-      if (kp + 1 < g.KP)
-        coarse_load<MT, TN>(nxt, Ap, vcur, kp + 1, g.n2, nrhs, lk, j0);
-      else if (d < 8)
-        coarse_load<MT, TN>(nxt, Ap, vnext, 0, g.n2, nrhs, lk, j0);
-#pragma unroll
-      for (int h = 0; h < 2; ++h)
-#pragma unroll
-        for (int n = 0; n < TN; ++n) {
-          const float2 b = cur.b[h][n];
-#pragma unroll
-          for (int t = 0; t < MT; ++t) {
-            const float ar = cur.a[t][2 * h], ai = cur.a[t][2 * h + 1];
-            yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, yr[n][t], 0, 0, 0);
-            yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b.y, yr[n][t], 0, 0, 0);
-            yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, yi[n][t], 0, 0, 0);
-            yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.x, yi[n][t], 0, 0, 0);
-          }
-        }
-      cur = nxt;
+  // two operand buffers in turn: the loads of step s + 1 are in flight during the
+  // products of step s; past the last step the cursor re-reads the first (unused)
+  const f4v* Ax = A + (size_t)x * 9 * g.KP * MT * 64 + l;
+  const int S = 9 * g.KP;
+  CoarseCursor c{0, 0, 0, site_rsrc(v + (size_t)x * vstride, vbytes)};
+  auto load_next = [&](CoarseSlice<MT, TN>& o) {
+    coarse_load<MT, TN>(o, Ax + (size_t)c.q * MT * 64, c.vr, c.kp, g.n2, nrhs, lk, j0);
+    if (++c.q == S) c.q = 0;
+    if (++c.kp == g.KP) {
+      c.kp = 0;
+      c.d = c.d == 8 ? 0 : c.d + 1;
+      c.vr = site_rsrc(v + (size_t)coarse_nbr(g, x, c.d) * vstride, vbytes);
     }
-    vcur = vnext;
+  };
+  CoarseSlice<MT, TN> b0, b1;
+  load_next(b0);
+  for (int s = 0; s < S; s += 2) {
+    load_next(b1);
+    coarse_mma<MT, TN>(b0, yr, yi);
+    load_next(b0);
+    if (s + 1 < S) coarse_mma<MT, TN>(b1, yr, yi);
   }
   float2* yx = y + (size_t)x * vstride;
 #pragma unroll
@@ -221,8 +249,10 @@ hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_
   if (e != hipSuccess) return e;
   const int tiles = (nrhs + 15) / 16;
   if (nrhs < 1 || (tiles + 3) / 4 > 65535) return hipErrorInvalidValue;
-  int tn = rhs_tiles_per_wave > 0 ? rhs_tiles_per_wave : 4;
-  if (tn > 4) return hipErrorInvalidValue;
+  if (rhs_tiles_per_wave > 4) return hipErrorInvalidValue;
+  // default: the fewest groups of at most 4 tiles, balanced (5 tiles: 3 + 2, not 4 + 1)
+  const int groups = (tiles + 3) / 4;
+  int tn = rhs_tiles_per_wave > 0 ? rhs_tiles_per_wave : (tiles + groups - 1) / groups;
   if (tn > tiles) tn = tiles;
   const f4v* A = (const f4v*)packed;
   const float2* vv = (const float2*)v;

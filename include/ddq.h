@@ -427,14 +427,19 @@ int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, c
  *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost),
  *   8-byte aligned, y not overlapping v.  One wavefront per coarse site and per group of
  *   rhs_tiles_per_wave tiles of 16 right-hand sides (1 .. 4; 0 = the default: the fewest
- *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once.  Enqueued on hip_stream; allocates nothing.
+ *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once.
+ *   product: how a complex product is formed on the matrix cores: 1 = four real products
+ *   (Re = ArVr - AiVi, Im = ArVi + AiVr), 2 = Gauss's three (P = Ar(Vr + Vi),
+ *   Q = (Ar + Ai)Vi, R = (Ai - Ar)Vr; Re = P - Q, Im = P + R: a quarter fewer products, the
+ *   sums rounded to FP32 first), 0 = the default (three).  Both stay within a small
+ *   multiple of 2^-24 x sum |A||v| per output element.  Enqueued on hip_stream; allocates nothing.
  * Errors: DDQ_ERR_ARG for null or misaligned pointers and sizes out of range,
  * DDQ_ERR_HIP if a launch fails. */
 int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes);
 int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blocks, void* packed,
                            void* hip_stream);
 int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
-                     int rhs_tiles_per_wave, void* hip_stream);
+                     int rhs_tiles_per_wave, int product, void* hip_stream);
 
 /* Thread-local message of the last error (empty string if none). */
 const char* ddq_last_error(void);

@@ -550,8 +550,10 @@ class CoarseOperator:
         check(lib().ddq_coarse_pack_blocks(self._cd, self.nv, _prec(blocks), _dev(blocks, "blocks"),
                                            _dev(self.packed, "packed"), C.c_void_p(s)), "ddq_coarse_pack_blocks")
 
-    def apply(self, v: torch.Tensor, out: torch.Tensor = None, rhs_tiles_per_wave: int = 0) -> torch.Tensor:
-        """y = D_c v; v complex64 [sites, 2 N_v] or [sites, 2 N_v, nrhs] (right-hand side innermost)"""
+    def apply(self, v: torch.Tensor, out: torch.Tensor = None, rhs_tiles_per_wave: int = 0,
+              product: int = 0) -> torch.Tensor:
+        """y = D_c v; v complex64 [sites, 2 N_v] or [sites, 2 N_v, nrhs] (right-hand side innermost);
+        product: 0 default, 1 four real products per complex one, 2 Gauss's three"""
         if v.dtype != torch.complex64:
             raise TypeError("coarse vectors are complex64")
         if v.dim() not in (2, 3) or v.shape[0] != self.vc or v.shape[1] != 2 * self.nv:
@@ -562,5 +564,6 @@ class CoarseOperator:
             raise ValueError("out must match v")
         s = torch.cuda.current_stream(self.device).cuda_stream
         check(lib().ddq_coarse_apply(self._cd, self.nv, nrhs, _dev(self.packed, "packed"), _dev(v, "v"),
-                                     _dev(y, "out"), int(rhs_tiles_per_wave), C.c_void_p(s)), "ddq_coarse_apply")
+                                     _dev(y, "out"), int(rhs_tiles_per_wave), int(product), C.c_void_p(s)),
+              "ddq_coarse_apply")
         return y

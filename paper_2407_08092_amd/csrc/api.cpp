@@ -908,15 +908,16 @@ int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blo
 }
 
 int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
-                     int rhs_tiles_per_wave, void* hip_stream) {
+                     int rhs_tiles_per_wave, int product, void* hip_stream) {
   if (!cdims || !packed || !v || !y) return fail(DDQ_ERR_ARG, "null argument");
   if (coarse_packed_bytes(cdims, nv) < 0)
     return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
   if (nrhs < 1 || nrhs > 65535 * 16) return fail(DDQ_ERR_ARG, "nrhs must be in 1 .. 1048560");
   if (rhs_tiles_per_wave < 0 || rhs_tiles_per_wave > 4) return fail(DDQ_ERR_ARG, "rhs_tiles_per_wave must be 0 .. 4");
+  if (product < 0 || product > 2) return fail(DDQ_ERR_ARG, "product must be 0 (default), 1 (four) or 2 (three real products)");
   if (((uintptr_t)packed & 15) || (((uintptr_t)v | (uintptr_t)y) & 7)) return fail(DDQ_ERR_ARG, "misaligned argument");
   if (v == y) return fail(DDQ_ERR_ARG, "y must not overlap v");
-  HIPCHK(launch_coarse_apply(cdims, nv, nrhs, rhs_tiles_per_wave, packed, v, y, (hipStream_t)hip_stream));
+  HIPCHK(launch_coarse_apply(cdims, nv, nrhs, rhs_tiles_per_wave, product, packed, v, y, (hipStream_t)hip_stream));
   return DDQ_OK;
 }
 

@@ -4,9 +4,9 @@
 // the neighbour in direction mu, forward s = 0 or backward s = 1, periodic), FP32
 // operands and accumulation, on the matrix cores.
 //
-// The contraction per block is a complex (2N_v x 2N_v) x (2N_v x nrhs) product: four
-// real products per 4-wide slice k of the contraction index and per 16 x 16 output tile
-// (Yr += Ar Vr - Ai Vi, Yi += Ar Vi + Ai Vr) with v_mfma_f32_16x16x4_f32, whose operand
+// The contraction per block is a complex (2N_v x 2N_v) x (2N_v x nrhs) product: per
+// 4-wide slice k of the contraction index and per 16 x 16 output tile, Gauss's three real
+// products (the default) or the four of the schoolbook form, with v_mfma_f32_16x16x4_f32, whose operand
 // lane l holds A[i = l % 16][k = l / 16] and B[k = l / 16][j = l % 16] and whose
 // accumulator element e of lane l is C[4 (l / 16) + e][l % 16].
 //
@@ -17,6 +17,9 @@
 // so a wave reads 1 KB contiguous per load.  A wave of the apply owns one coarse site and
 // up to TN tiles of 16 right-hand sides: every block element it loads feeds TN tiles, so a
 // launch reads the blocks ceil(nrhs / (16 TN)) times (once up to 16 TN right-hand sides).
+// Two waves per SIMD are asked for (amdgpu_waves_per_eu): the three-product form with 4
+// tiles then keeps its 144 accumulators and both operand buffers in the 256 registers
+// of a lane (at one wave per SIMD it ran 20% slower).
 // Vectors are complex64 [site][row][rhs] (rhs innermost): the 16 lanes of one row read or
 // write 128 contiguous bytes.
 #include <hip/hip_runtime.h>
@@ -113,22 +116,41 @@ __device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* A
   }
 }
 
-template <int MT, int TN>
-__device__ __forceinline__ void coarse_mma(const CoarseSlice<MT, TN>& c, f4v (&yr)[TN][MT], f4v (&yi)[TN][MT]) {
+// One step's products.  G3 = 0: four real products per complex one (Yr += Ar Vr - Ai Vi,
+// Yi += Ar Vi + Ai Vr) into acc[0] = Yr, acc[1] = Yi.  G3 = 1: Gauss's three real products,
+// P += Ar (Vr + Vi), Q += (Ar + Ai) Vi, R += (Ai - Ar) Vr into acc[0..2], with Yr = P - Q and
+// Yi = P + R formed once at the end (the sums are rounded to FP32 before the product).
+template <int MT, int TN, int G3>
+__device__ __forceinline__ void coarse_mma(const CoarseSlice<MT, TN>& c, f4v (&acc)[2 + G3][TN][MT]) {
 #pragma unroll
-  for (int h = 0; h < 2; ++h)
+  for (int h = 0; h < 2; ++h) {
+    float ar[MT], ai[MT], as[MT], ad[MT];
+#pragma unroll
+    for (int t = 0; t < MT; ++t) {
+      ar[t] = c.a[t][2 * h];
+      ai[t] = c.a[t][2 * h + 1];
+      as[t] = ar[t] + ai[t];
+      ad[t] = ai[t] - ar[t];
+    }
 #pragma unroll
     for (int n = 0; n < TN; ++n) {
       const float2 b = c.b[h][n];
+      const float bs = b.x + b.y;
 #pragma unroll
       for (int t = 0; t < MT; ++t) {
-        const float ar = c.a[t][2 * h], ai = c.a[t][2 * h + 1];
-        yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.x, yr[n][t], 0, 0, 0);
-        yr[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai, b.y, yr[n][t], 0, 0, 0);
-        yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar, b.y, yi[n][t], 0, 0, 0);
-        yi[n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai, b.x, yi[n][t], 0, 0, 0);
+        if constexpr (G3) {
+          acc[0][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[t], bs, acc[0][n][t], 0, 0, 0);
+          acc[1][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(as[t], b.y, acc[1][n][t], 0, 0, 0);
+          acc[2][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ad[t], b.x, acc[2][n][t], 0, 0, 0);
+        } else {
+          acc[0][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[t], b.x, acc[0][n][t], 0, 0, 0);
+          acc[0][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(-ai[t], b.y, acc[0][n][t], 0, 0, 0);
+          acc[1][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ar[t], b.y, acc[1][n][t], 0, 0, 0);
+          acc[1][n][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(ai[t], b.x, acc[1][n][t], 0, 0, 0);
+        }
       }
     }
+  }
 }
 
 // position of the next load in the sequence of (block d, k-slice pair kp), storage order
@@ -137,8 +159,8 @@ struct CoarseCursor {
   __amdgpu_buffer_rsrc_t vr;
 };
 
-template <int MT, int TN>
-__global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
+template <int MT, int TN, int G3>
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
                                                      const float2* __restrict__ v, float2* __restrict__ y) {
   const int w = (int)blockIdx.x;
   const int x = g.xcd_slab ? (w & 7) * (g.vc >> 3) + (w >> 3) : w;
@@ -146,14 +168,13 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, cons
   const int j0 = 16 * TN * (int)blockIdx.y + li;  // this lane's column in tile 0
   const size_t vstride = (size_t)g.n2 * nrhs;
   const int vbytes = g.n2 * nrhs * 8;
-  f4v yr[TN][MT], yi[TN][MT];
+  f4v acc[2 + G3][TN][MT];
 #pragma unroll
-  for (int n = 0; n < TN; ++n)
+  for (int q = 0; q < 2 + G3; ++q)
 #pragma unroll
-    for (int t = 0; t < MT; ++t) {
-      yr[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
-      yi[n][t] = f4v{0.f, 0.f, 0.f, 0.f};
-    }
+    for (int n = 0; n < TN; ++n)
+#pragma unroll
+      for (int t = 0; t < MT; ++t) acc[q][n][t] = f4v{0.f, 0.f, 0.f, 0.f};
   // two operand buffers in turn: the loads of step s + 1 are in flight during the
   // products of step s; past the last step the cursor re-reads the first (unused)
   const f4v* Ax = A + (size_t)x * 9 * g.KP * MT * 64 + l;
@@ -172,9 +193,9 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, cons
   load_next(b0);
   for (int s = 0; s < S; s += 2) {
     load_next(b1);
-    coarse_mma<MT, TN>(b0, yr, yi);
+    coarse_mma<MT, TN, G3>(b0, acc);
     load_next(b0);
-    if (s + 1 < S) coarse_mma<MT, TN>(b1, yr, yi);
+    if (s + 1 < S) coarse_mma<MT, TN, G3>(b1, acc);
   }
   float2* yx = y + (size_t)x * vstride;
 #pragma unroll
@@ -186,7 +207,11 @@ __global__ void __launch_bounds__(64) k_coarse_apply(CoarseGeo g, int nrhs, cons
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const int i = 16 * t + 4 * lk + e;
-        if (i < g.n2) yx[(size_t)i * nrhs + j] = float2{yr[n][t][e], yi[n][t][e]};
+        if (i >= g.n2) continue;
+        if constexpr (G3)
+          yx[(size_t)i * nrhs + j] = float2{acc[0][n][t][e] - acc[1][n][t][e], acc[0][n][t][e] + acc[2][n][t][e]};
+        else
+          yx[(size_t)i * nrhs + j] = float2{acc[0][n][t][e], acc[1][n][t][e]};
       }
   }
 }
@@ -208,17 +233,27 @@ hipError_t make_geo(const int cd[4], int nv, CoarseGeo& g) {
   return hipSuccess;
 }
 
-template <int MT>
+template <int MT, int G3>
 hipError_t launch_mt(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
   const int tiles = (nrhs + 15) / 16;
   const dim3 grid((unsigned)g.vc, (unsigned)((tiles + tn - 1) / tn)), block(64);
   switch (tn) {
-    case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    case 3: hipLaunchKernelGGL((k_coarse_apply<MT, 3>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    default: hipLaunchKernelGGL((k_coarse_apply<MT, 4>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 3: hipLaunchKernelGGL((k_coarse_apply<MT, 3, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    default: hipLaunchKernelGGL((k_coarse_apply<MT, 4, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
   }
   return hipGetLastError();
+}
+
+template <int G3>
+hipError_t launch_g(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
+  switch (g.MT) {
+    case 1: return launch_mt<1, G3>(g, nrhs, tn, A, v, y, s);
+    case 2: return launch_mt<2, G3>(g, nrhs, tn, A, v, y, s);
+    case 3: return launch_mt<3, G3>(g, nrhs, tn, A, v, y, s);
+    default: return launch_mt<4, G3>(g, nrhs, tn, A, v, y, s);
+  }
 }
 
 }  // namespace
@@ -242,27 +277,25 @@ hipError_t launch_coarse_pack(const int cd[4], int nv, int src_f64, const void* 
   return hipGetLastError();
 }
 
-hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, const void* packed,
-                               const void* v, void* y, hipStream_t s) {
+hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, int product,
+                               const void* packed, const void* v, void* y, hipStream_t s) {
   CoarseGeo g;
   hipError_t e = make_geo(cd, nv, g);
   if (e != hipSuccess) return e;
   const int tiles = (nrhs + 15) / 16;
   if (nrhs < 1 || (tiles + 3) / 4 > 65535) return hipErrorInvalidValue;
-  if (rhs_tiles_per_wave > 4) return hipErrorInvalidValue;
-  // default: the fewest groups of at most 4 tiles, balanced (5 tiles: 3 + 2, not 4 + 1)
-  const int groups = (tiles + 3) / 4;
+  if (rhs_tiles_per_wave > 4 || product < 0 || product > 2) return hipErrorInvalidValue;
+  const int g3 = product != 1;  // the default is Gauss's three products
+  // default grouping: the fewest groups of at most 4 tiles (3 for the three-product form
+  // with 4 row tiles, whose 4-tile kernel spills), balanced (5 tiles: 3 + 2, not 4 + 1)
+  const int max_tn = (g3 && g.MT == 4) ? 3 : 4;
+  const int groups = (tiles + max_tn - 1) / max_tn;
   int tn = rhs_tiles_per_wave > 0 ? rhs_tiles_per_wave : (tiles + groups - 1) / groups;
   if (tn > tiles) tn = tiles;
   const f4v* A = (const f4v*)packed;
   const float2* vv = (const float2*)v;
   float2* yy = (float2*)y;
-  switch (g.MT) {
-    case 1: return launch_mt<1>(g, nrhs, tn, A, vv, yy, s);
-    case 2: return launch_mt<2>(g, nrhs, tn, A, vv, yy, s);
-    case 3: return launch_mt<3>(g, nrhs, tn, A, vv, yy, s);
-    default: return launch_mt<4>(g, nrhs, tn, A, vv, yy, s);
-  }
+  return g3 ? launch_g<1>(g, nrhs, tn, A, vv, yy, s) : launch_g<0>(g, nrhs, tn, A, vv, yy, s);
 }
 
 }  // namespace ddq

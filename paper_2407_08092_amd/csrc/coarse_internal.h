@@ -10,8 +10,9 @@ long long coarse_packed_bytes(const int cd[4], int nv);
 // repack complex blocks [site][9][2 N_v][2 N_v] (row-major, complex128 if src_f64 else complex64)
 hipError_t launch_coarse_pack(const int cd[4], int nv, int src_f64, const void* src, void* dst, hipStream_t s);
 // y = D_c v on nrhs complex64 right-hand sides, vectors [site][2 N_v][nrhs];
-// rhs_tiles_per_wave in 0 (default 4) .. 4
-hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, const void* packed,
-                               const void* v, void* y, hipStream_t s);
+// rhs_tiles_per_wave in 0 (balanced default) .. 4; product 0 (default: three real
+// products), 1 (four real products) or 2 (three real products)
+hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, int product,
+                               const void* packed, const void* v, void* y, hipStream_t s);
 
 }  // namespace ddq

@@ -84,10 +84,12 @@ def test_coarse_sizes_and_bad_arguments_on_host():
     assert L.ddq_coarse_packed_bytes((C.c_int * 4)(3, 0, 3, 3), 8, C.byref(nb)) == -1
     assert L.ddq_coarse_packed_bytes((C.c_int * 4)(512, 512, 512, 1), 8, C.byref(nb)) == -1
     fake = C.c_void_p(1 << 20)  # never dereferenced: every call below fails its host checks
-    assert L.ddq_coarse_apply(cd, 8, 0, fake, fake, C.c_void_p((1 << 20) + 4096), 0, None) == -1
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, C.c_void_p((1 << 20) + 4096), 5, None) == -1
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, fake, 0, None) == -1  # y == v
-    assert L.ddq_coarse_apply(cd, 8, 16, C.c_void_p((1 << 20) + 8), fake, C.c_void_p((1 << 20) + 4096), 0,
+    y = C.c_void_p((1 << 20) + 4096)
+    assert L.ddq_coarse_apply(cd, 8, 0, fake, fake, y, 0, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 5, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 0, 3, None) == -1  # no such product form
+    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, fake, 0, 0, None) == -1  # y == v
+    assert L.ddq_coarse_apply(cd, 8, 16, C.c_void_p((1 << 20) + 8), fake, y, 0, 0,
                               None) == -1  # packed not 16-byte aligned
     assert L.ddq_coarse_pack_blocks(cd, 8, 2, fake, fake, None) == -1  # 16-bit blocks are not taken
-    assert L.ddq_coarse_apply(cd, 8, 16, None, fake, fake, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 16, None, fake, fake, 0, 0, None) == -1

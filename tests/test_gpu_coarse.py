@@ -13,7 +13,9 @@ tiles, one to four tiles per wave, several waves per site), coarse extents 1 and
 site map is taken or not); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
 checked against P^H D P applied on the CPU; and a 12^3 x 24 coarse lattice (the
 coarsening of 48^3 x 96 by 4^4 aggregates) with N_v = 24 and 16 right-hand sides,
-sampled sites against the oracle's sum for those sites.
+sampled sites against the oracle's sum for those sites.  Both product forms are covered:
+four real products per complex one, and Gauss's three (whose sums of real and imaginary
+parts are rounded to FP32 before the product, within the same bar).
 """
 import numpy as np
 import pytest
@@ -46,13 +48,13 @@ def _term_bound(A, cd, v, sites=None):
     return np.stack(out)
 
 
-def _check(cd, nv, nrhs, seed, tn=0, blocks_f64=False):
+def _check(cd, nv, nrhs, seed, tn=0, blocks_f64=False, product=0):
     Vc, n2 = int(np.prod(cd)), 2 * nv
     A64 = synth.gaussian_complex((Vc, 9, n2, n2), seed)
     A = A64.astype(np.complex64)
     v = _rand((Vc, n2, nrhs), seed + 1)
     op = api.CoarseOperator(cd, _dev(A64 if blocks_f64 else A))
-    y = op.apply(_dev(v), rhs_tiles_per_wave=tn).cpu().numpy()
+    y = op.apply(_dev(v), rhs_tiles_per_wave=tn, product=product).cpu().numpy()
     ref = coarse.coarse_apply(A.astype(np.complex128), cd, v.astype(np.complex128))
     tol = 2e-6 * _term_bound(A.astype(np.complex128), cd, v.astype(np.complex128))
     err = np.abs(y - ref)
@@ -60,15 +62,17 @@ def _check(cd, nv, nrhs, seed, tn=0, blocks_f64=False):
     return y
 
 
+@pytest.mark.parametrize("product", [1, 2], ids=["four", "gauss3"])
 @pytest.mark.parametrize("nv", [4, 8, 10, 20, 24, 32])
-def test_random_blocks_match_oracle(nv):
-    _check((3, 2, 3, 4), nv, 16, 701 + nv)
+def test_random_blocks_match_oracle(nv, product):
+    _check((3, 2, 3, 4), nv, 16, 701 + nv, product=product)
 
 
 @pytest.mark.parametrize("nrhs,tn", [(1, 0), (5, 0), (16, 1), (17, 0), (33, 2), (48, 3), (64, 4), (80, 0), (80, 1),
                                      (50, 3)])
 def test_rhs_tiling_matches_oracle(nrhs, tn):
     _check((2, 3, 2, 4), 10, nrhs, 711 + nrhs, tn)
+    _check((2, 3, 2, 4), 10, nrhs, 711 + nrhs, tn, product=2)
 
 
 @pytest.mark.parametrize("cd", [(1, 1, 1, 1), (2, 2, 2, 2), (1, 3, 2, 5), (4, 4, 4, 4)])
@@ -94,9 +98,11 @@ def test_single_vector_and_tiles_per_wave_agree():
     A = _rand((Vc, 9, n2, n2), 751)
     op = api.CoarseOperator(cd, _dev(A))
     v = _rand((Vc, n2, 64), 752)
+    for product in (1, 2):
+        ys = [op.apply(_dev(v), rhs_tiles_per_wave=tn, product=product).cpu().numpy() for tn in (1, 2, 3, 4)]
+        for y in ys[1:]:  # the same products in the same order whatever the grouping
+            assert np.array_equal(y, ys[0])
     ys = [op.apply(_dev(v), rhs_tiles_per_wave=tn).cpu().numpy() for tn in (1, 2, 3, 4)]
-    for y in ys[1:]:  # the same products in the same order whatever the grouping
-        assert np.array_equal(y, ys[0])
     y1 = op.apply(_dev(v[:, :, 7].copy())).cpu().numpy()
     assert np.array_equal(y1, ys[0][:, :, 7])
 
@@ -121,7 +127,9 @@ def test_full_size_coarse_lattice_sampled():
     g = torch.Generator(device="cuda").manual_seed(781)
     A = torch.randn((Vc, 9, n2, n2), dtype=torch.complex64, device="cuda", generator=g)
     v = torch.randn((Vc, n2, nrhs), dtype=torch.complex64, device="cuda", generator=g)
-    y = api.CoarseOperator(cd, A).apply(v)
+    op = api.CoarseOperator(cd, A)
+    y = op.apply(v)
+    y3 = op.apply(v, product=2)
     torch.cuda.synchronize()
     rng = np.random.default_rng(782)
     sites = sorted(set(rng.integers(0, Vc, 40).tolist()) | {0, Vc - 1, 12 * 12 * 12 * 23, 11})
@@ -132,6 +140,7 @@ def test_full_size_coarse_lattice_sampled():
         ref = sum(Ax[d] @ vn[d] for d in range(9))
         bound = sum(np.abs(Ax[d]) @ np.abs(vn[d]) for d in range(9))
         assert np.all(np.abs(y[x].cpu().numpy() - ref) <= 2e-6 * bound), x
+        assert np.all(np.abs(y3[x].cpu().numpy() - ref) <= 2e-6 * bound), x
 
 
 def test_bad_shapes_rejected():

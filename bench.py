@@ -355,6 +355,7 @@ def main():
     if not args.no_batch:
         multi, batch = batched(api, synth, torch, dev)
     coarse = coarse_operator(api, torch, dev, args.coarse_nv)
+    share = one_gpu_share(api, synth, torch, dev)
 
     out = {
         "metric": METRIC, "value": round(gbs, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
@@ -376,6 +377,7 @@ def main():
         "multi_rhs": multi,
         "batched": batch,
         "coarse": coarse,
+        "one_gpu_share": share,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -383,6 +385,44 @@ def main():
 
 
 MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def one_gpu_share(api, synth, torch, dev, reps=20):
+    """The FP32 Schur apply and Richardson sweep on 48^3 x 12: one GPU's share of 48^3 x 96
+    split over 8 GPUs in t.  The t wrap-around of this lattice stands in for the halo a
+    sharded run would receive (the same bytes per site); no exchange is made."""
+    dims = (48, 48, 48, 12)
+    lat = api.create_lattice(dims, device=dev)
+    api.set_gauge(lat, synth.gauge_field(dims, LARGE["eps"], LARGE["seed_gauge"] + 50, device=dev))
+    api.set_clover(lat, LARGE["c_sw"], LARGE["m0"])
+    vh = lat.Vh
+    g = synth.gaussian_complex((2, 12, vh), LARGE["seed_vec"] + 50)
+    x = api.convert_parity(lat, torch.from_numpy(g[0]).to(dev), torch.complex64)
+    b = api.convert_parity(lat, torch.from_numpy(g[1]).to(dev), torch.complex64)
+    del g
+    y = torch.empty_like(x)
+    xs = torch.zeros_like(x)
+    for _ in range(3):
+        api.apply_schur(lat, x, y)
+    e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        api.apply_schur(lat, x, y)
+    e1.record()
+    api.richardson_smooth(lat, xs, b, SWEEPS, 0.1)
+    e2.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    out = {"workload": "48^3x12 (one GPU's share of 48^3x96 over 8 GPUs in t), FP32 Schur apply and "
+                       "Richardson sweeps, no halo exchange", "dims": list(dims), "even_sites": vh,
+           "apply_ms": round(ms, 4), "apply_GBs": round(BYTES_APPLY_F32 * vh / (ms * 1e-3) / 1e9, 1),
+           "sweeps_per_s": round(SWEEPS / (e1.elapsed_time(e2) * 1e-3), 1)}
+    log(f"one GPU's share 48^3x12: {out}")
+    api.destroy_lattice(lat)
+    del x, b, y, xs
+    torch.cuda.empty_cache()
+    return out
 
 
 def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):

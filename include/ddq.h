@@ -427,7 +427,8 @@ int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, c
  *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost),
  *   8-byte aligned, y not overlapping v.  One wavefront per coarse site and per group of
  *   rhs_tiles_per_wave tiles of 16 right-hand sides (1 .. 4; 0 = the default: the fewest
- *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once.
+ *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once,
+ *   and up to four groups of one site run in one workgroup, sharing them through the caches.
  *   product: how a complex product is formed on the matrix cores: 1 = four real products
  *   (Re = ArVr - AiVi, Im = ArVi + AiVr), 2 = Gauss's three (P = Ar(Vr + Vi),
  *   Q = (Ar + Ai)Vi, R = (Ai - Ar)Vr; Re = P - Q, Im = P + R: a quarter fewer products, the

@@ -15,8 +15,10 @@
 //   packed[x][d][kp][t][lane][4] = (Re, Im) A[16 t + l % 16][8 kp + l / 16]     (slice 2kp)
 //                                  (Re, Im) A[16 t + l % 16][8 kp + 4 + l / 16] (slice 2kp+1)
 // so a wave reads 1 KB contiguous per load.  A wave of the apply owns one coarse site and
-// up to TN tiles of 16 right-hand sides: every block element it loads feeds TN tiles, so a
-// launch reads the blocks ceil(nrhs / (16 TN)) times (once up to 16 TN right-hand sides).
+// up to TN tiles of 16 right-hand sides: every block element it loads feeds TN tiles.  Up to
+// four such waves (consecutive groups of TN tiles of the same site) form one workgroup, so
+// that beyond 16 TN right-hand sides the site's further groups take its blocks from the
+// caches while the first wave brings them from memory.
 // Two waves per SIMD are asked for (amdgpu_waves_per_eu): the three-product form with 4
 // tiles then keeps its 144 accumulators and both operand buffers in the 256 registers
 // of a lane (at one wave per SIMD it ran 20% slower).
@@ -160,12 +162,15 @@ struct CoarseCursor {
 };
 
 template <int MT, int TN, int G3>
-__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
                                                      const float2* __restrict__ v, float2* __restrict__ y) {
   const int w = (int)blockIdx.x;
   const int x = g.xcd_slab ? (w & 7) * (g.vc >> 3) + (w >> 3) : w;
   const int l = (int)threadIdx.x, li = l & 15, lk = l >> 4;
-  const int j0 = 16 * TN * (int)blockIdx.y + li;  // this lane's column in tile 0
+  // the waves of a workgroup share the site and take consecutive groups of TN tiles
+  const int grp = (int)(blockIdx.y * blockDim.y + threadIdx.y);
+  if (grp * 16 * TN >= nrhs) return;  // a whole wave past the last group
+  const int j0 = 16 * TN * grp + li;  // this lane's column in tile 0
   const size_t vstride = (size_t)g.n2 * nrhs;
   const int vbytes = g.n2 * nrhs * 8;
   f4v acc[2 + G3][TN][MT];
@@ -236,7 +241,8 @@ hipError_t make_geo(const int cd[4], int nv, CoarseGeo& g) {
 template <int MT, int G3>
 hipError_t launch_mt(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
   const int tiles = (nrhs + 15) / 16;
-  const dim3 grid((unsigned)g.vc, (unsigned)((tiles + tn - 1) / tn)), block(64);
+  const int groups = (tiles + tn - 1) / tn, wpg = groups < 4 ? groups : 4;
+  const dim3 grid((unsigned)g.vc, (unsigned)((groups + wpg - 1) / wpg)), block(64, wpg);
   switch (tn) {
     case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
     case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;

@@ -35,13 +35,21 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
+#ifndef DDQ_COARSE_TMAP
+#define DDQ_COARSE_TMAP 2
+#endif
+
 struct CoarseGeo {
   int cd[4];  // coarse extents
   int n2;     // 2 N_v
   int MT;     // row tiles: ceil(n2 / 16)
   int KP;     // pairs of k-slices: ceil(n2 / 8)
   int vc;     // coarse sites
-  int xcd_slab;  // 1: workgroup w -> site (w % 8) * (vc / 8) + w / 8 (vc % 8 == 0)
+  int xcd_map;   // order of sites over workgroups w (one site per workgroup column):
+                 // 2 (T % 8 == 0): XCD w % 8 takes t-slices [(w % 8) T/8, (w % 8 + 1) T/8), walked
+                 //   t fastest, so that every neighbour of a site is a few hundred sites away;
+                 // 1 (vc % 8 == 0): XCD w % 8 takes the (w % 8)-th eighth of the sites in order;
+                 // 0: site w
 };
 
 __device__ __forceinline__ int coarse_nbr(const CoarseGeo& g, int x, int d) {
@@ -165,7 +173,14 @@ template <int MT, int TN, int G3>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
                                                      const float2* __restrict__ v, float2* __restrict__ y) {
   const int w = (int)blockIdx.x;
-  const int x = g.xcd_slab ? (w & 7) * (g.vc >> 3) + (w >> 3) : w;
+  int x = w;
+  if (g.xcd_map == 2) {
+    const int tc = g.cd[3] >> 3, q = w >> 3, r = q / tc;
+    const int t = (w & 7) * tc + (q - r * tc), xy = g.cd[0] * g.cd[1];
+    x = r % xy + xy * (r / xy + g.cd[2] * t);
+  } else if (g.xcd_map == 1) {
+    x = (w & 7) * (g.vc >> 3) + (w >> 3);
+  }
   const int l = (int)threadIdx.x, li = l & 15, lk = l >> 4;
   // the waves of a workgroup share the site and take consecutive groups of TN tiles
   const int grp = (int)(blockIdx.y * blockDim.y + threadIdx.y);
@@ -234,7 +249,7 @@ hipError_t make_geo(const int cd[4], int nv, CoarseGeo& g) {
   g.n2 = 2 * nv;
   g.MT = (g.n2 + 15) / 16;
   g.KP = (g.n2 + 7) / 8;
-  g.xcd_slab = (g.vc % 8 == 0) ? 1 : 0;
+  g.xcd_map = (g.cd[3] % 8 == 0) ? DDQ_COARSE_TMAP : (g.vc % 8 == 0) ? 1 : 0;
   return hipSuccess;
 }
 

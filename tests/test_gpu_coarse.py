@@ -9,8 +9,8 @@ bound's typical square-root growth) element by element.  Cases: random blocks wi
 N_v = 4, 8, 10, 20, 24, 32 (2N_v = 8, 16, 20, 40, 48, 64: whole and ragged 16-row tiles
 and 8-column pairs of k-slices), 1 .. 80 right-hand sides (whole and ragged 16-wide
 tiles, one to four tiles per wave, several waves per site), coarse extents 1 and 2
-(neighbours coincide) and extents whose volume is or is not a multiple of 8 (the XCD
-site map is taken or not); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
+(neighbours coincide) and extents whose t extent or volume is or is not a multiple of 8 (each
+of the three orders of sites over the XCDs is taken); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
 checked against P^H D P applied on the CPU; and a 12^3 x 24 coarse lattice (the
 coarsening of 48^3 x 96 by 4^4 aggregates) with N_v = 24 and 16 right-hand sides,
 sampled sites against the oracle's sum for those sites.  Both product forms are covered:
@@ -75,7 +75,7 @@ def test_rhs_tiling_matches_oracle(nrhs, tn):
     _check((2, 3, 2, 4), 10, nrhs, 711 + nrhs, tn, product=2)
 
 
-@pytest.mark.parametrize("cd", [(1, 1, 1, 1), (2, 2, 2, 2), (1, 3, 2, 5), (4, 4, 4, 4)])
+@pytest.mark.parametrize("cd", [(1, 1, 1, 1), (2, 2, 2, 2), (1, 3, 2, 5), (4, 4, 4, 4), (3, 2, 3, 8), (1, 1, 1, 16)])
 def test_extents_match_oracle(cd):
     _check(cd, 8, 20, 731 + sum(cd))
 

@@ -888,6 +888,11 @@ int ddq_stencil_stream(ddq_lattice* L, int prec, int kernel, const void* in, con
   return DDQ_OK;
 }
 
+bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
+  const uintptr_t pa = (uintptr_t)a, pb = (uintptr_t)b;
+  return pa < pb + nb && pb < pa + na;
+}
+
 int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes) {
   if (!cdims || !bytes) return fail(DDQ_ERR_ARG, "null argument");
   const long long n = coarse_packed_bytes(cdims, nv);
@@ -901,8 +906,12 @@ int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blo
   if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "blocks are complex128 (DDQ_F64) or complex64 (DDQ_F32)");
   if (((uintptr_t)packed & 15) || ((uintptr_t)blocks & (prec == DDQ_F64 ? 15 : 7)))
     return fail(DDQ_ERR_ARG, "misaligned blocks or packed array");
-  if (coarse_packed_bytes(cdims, nv) < 0)
+  const long long packed_bytes = coarse_packed_bytes(cdims, nv);
+  if (packed_bytes < 0)
     return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  const size_t sites = (size_t)cdims[0] * cdims[1] * cdims[2] * cdims[3];
+  if (ranges_overlap(blocks, sites * 9 * 4 * nv * nv * (prec == DDQ_F64 ? 16 : 8), packed, (size_t)packed_bytes))
+    return fail(DDQ_ERR_ARG, "packed must not overlap blocks");
   HIPCHK(launch_coarse_pack(cdims, nv, prec == DDQ_F64, blocks, packed, (hipStream_t)hip_stream));
   return DDQ_OK;
 }
@@ -916,7 +925,8 @@ int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, c
   if (rhs_tiles_per_wave < 0 || rhs_tiles_per_wave > 4) return fail(DDQ_ERR_ARG, "rhs_tiles_per_wave must be 0 .. 4");
   if (product < 0 || product > 2) return fail(DDQ_ERR_ARG, "product must be 0 (default), 1 (four) or 2 (three real products)");
   if (((uintptr_t)packed & 15) || (((uintptr_t)v | (uintptr_t)y) & 7)) return fail(DDQ_ERR_ARG, "misaligned argument");
-  if (v == y) return fail(DDQ_ERR_ARG, "y must not overlap v");
+  const size_t vbytes = (size_t)cdims[0] * cdims[1] * cdims[2] * cdims[3] * 2 * nv * nrhs * 8;
+  if (ranges_overlap(v, vbytes, y, vbytes)) return fail(DDQ_ERR_ARG, "y must not overlap v");
   HIPCHK(launch_coarse_apply(cdims, nv, nrhs, rhs_tiles_per_wave, product, packed, v, y, (hipStream_t)hip_stream));
   return DDQ_OK;
 }

@@ -89,7 +89,12 @@ def test_coarse_sizes_and_bad_arguments_on_host():
     assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 5, 0, None) == -1
     assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 0, 3, None) == -1  # no such product form
     assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, fake, 0, 0, None) == -1  # y == v
+    # y starting inside v (180 sites x 16 rows x 16 right-hand sides x 8 B = 368,640 B)
+    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, C.c_void_p((1 << 20) + 368640 - 8), 0, 0, None) == -1
+    assert b"overlap" in L.ddq_last_error()
     assert L.ddq_coarse_apply(cd, 8, 16, C.c_void_p((1 << 20) + 8), fake, y, 0, 0,
                               None) == -1  # packed not 16-byte aligned
     assert L.ddq_coarse_pack_blocks(cd, 8, 2, fake, fake, None) == -1  # 16-bit blocks are not taken
+    assert L.ddq_coarse_pack_blocks(cd, 8, 1, fake, C.c_void_p((1 << 20) + 1024), None) == -1  # overlap
+    assert b"overlap" in L.ddq_last_error()
     assert L.ddq_coarse_apply(cd, 8, 16, None, fake, fake, 0, 0, None) == -1

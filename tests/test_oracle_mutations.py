@@ -208,3 +208,71 @@ def test_coarse_direction_mutant_caught(monkeypatch):
     monkeypatch.setattr(coarse, "coarse_neighbour", _cnb_swapped)
     with pytest.raises(AssertionError):
         cpins.test_free_field_blocks_closed_form()
+
+
+# coarse operator: restriction with the transpose instead of the conjugate transpose
+def _restrict_transposed(self, f):
+    ff = np.asarray(f).reshape(self.lat.V, 4, 3)
+    vc = np.zeros((self.Vc, 2, self.nv), complex)
+    for a in range(self.Vc):
+        for c in range(2):
+            vc[a, c] = self.Q[a][c].T @ ff[self.sites[a], 2 * c:2 * c + 2, :].reshape(-1)
+    return vc
+
+
+def test_coarse_restriction_transpose_mutant_caught(monkeypatch):
+    monkeypatch.setattr(coarse.Prolongation, "restrict", _restrict_transposed)
+    with pytest.raises(AssertionError):
+        cpins.test_prolongation_orthonormal_and_spans_the_test_vectors()
+
+
+# coarse operator: test vectors orthonormalised over all four spins at once (no chirality split)
+_orig_pinit = coarse.Prolongation.__init__
+
+
+def _init_no_chirality_split(self, lat, agg, test_vectors):
+    _orig_pinit(self, lat, agg, test_vectors)
+    T = np.stack([np.asarray(t).reshape(lat.V, 4, 3) for t in test_vectors], axis=-1)
+    for a in range(self.Vc):
+        q, _ = np.linalg.qr(T[self.sites[a]].reshape(-1, self.nv))
+        q = q.reshape(len(self.sites[a]), 4, 3, self.nv)
+        self.Q[a] = [q[:, 0:2].reshape(-1, self.nv), q[:, 2:4].reshape(-1, self.nv)]
+
+
+def test_coarse_no_chirality_split_mutant_caught(monkeypatch):
+    monkeypatch.setattr(coarse.Prolongation, "__init__", _init_no_chirality_split)
+    with pytest.raises(AssertionError):
+        cpins.test_prolongation_orthonormal_and_spans_the_test_vectors()
+
+
+# coarse operator: Galerkin columns stored as rows
+_orig_gal = coarse.galerkin_blocks
+
+
+def _galerkin_transposed(op, P):
+    return np.swapaxes(_orig_gal(op, P), 2, 3)
+
+
+def test_coarse_galerkin_transposed_mutant_caught(monkeypatch):
+    monkeypatch.setattr(coarse, "galerkin_blocks", _galerkin_transposed)
+    with pytest.raises(AssertionError):
+        cpins.test_galerkin_identity_and_gamma5_hermiticity()
+
+
+# coarse operator: the apply leaves out the site's own block
+def _apply_no_self(A, cd, v):
+    y = np.zeros_like(v, dtype=complex)
+    for x in range(A.shape[0]):
+        for d in range(1, 9):
+            y[x] = y[x] + A[x, d] @ v[coarse.coarse_neighbour(cd, x, d)]
+    return y
+
+
+@pytest.mark.parametrize("pin", ["test_galerkin_identity_and_gamma5_hermiticity", "test_coarse_apply_plain_definition"])
+def test_coarse_apply_without_self_block_caught(monkeypatch, pin):
+    monkeypatch.setattr(coarse, "coarse_apply", _apply_no_self)
+    with pytest.raises(AssertionError):
+        if pin == "test_coarse_apply_plain_definition":
+            cpins.test_coarse_apply_plain_definition(3)
+        else:
+            cpins.test_galerkin_identity_and_gamma5_hermiticity()

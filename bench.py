@@ -442,6 +442,7 @@ def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
         g = torch.Generator(device=dev).manual_seed(900 + nv)
         blocks = torch.randn((vc, 9, n2, n2), dtype=torch.complex64, device=dev, generator=g)
         op = api.CoarseOperator(cd, blocks)
+        op16 = api.CoarseOperator(cd, blocks, storage=api.DDQ_F16) if nv == 24 else None
         del blocks
         for nrhs in (16, 64):
             v = torch.randn((vc, n2, nrhs), dtype=torch.complex64, device=dev, generator=g)
@@ -483,9 +484,24 @@ def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
                 out[f"nv{nv}_rhs{nrhs}"]["four_products"] = {
                     "ms": round(ms4, 4), "TFLOPs": round(flops / (ms4 * 1e-3) / 1e12, 1),
                     "frac_mfma_peak": round(flops / (ms4 * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS, 3)}
+            if op16 is not None:  # FP16 block storage: half the block bytes, FP32 arithmetic
+                for _ in range(2):
+                    op16.apply(v, y)
+                torch.cuda.synchronize()
+                e0.record()
+                for _ in range(reps):
+                    op16.apply(v, y)
+                e1.record()
+                torch.cuda.synchronize()
+                ms16 = e0.elapsed_time(e1) / reps
+                nbytes16 = groups * 9 * n2 * n2 * 4 * vc + 2 * n2 * nrhs * 8 * vc
+                out[f"nv{nv}_rhs{nrhs}"]["f16_blocks"] = {
+                    "ms": round(ms16, 4), "TFLOPs": round(flops / (ms16 * 1e-3) / 1e12, 1),
+                    "frac_mfma_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS, 3),
+                    "GBs": round(nbytes16 / (ms16 * 1e-3) / 1e9, 1)}
             log(f"coarse N_v={nv} nrhs={nrhs}: {out[f'nv{nv}_rhs{nrhs}']}")
             del v, y
-        del op
+        del op, op16
         torch.cuda.empty_cache()
     return out
 

@@ -413,18 +413,23 @@ int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, c
  * The coarse lattice is periodic in all directions (a fine antiperiodic boundary sign
  * is part of the blocks).  Coarse site index x + Cx*(y + Cy*(z + Cz*t)); a coarse
  * vector row q in 0 .. 2N_v-1 is chirality q / N_v, test vector q % N_v.  Blocks are
- * stored and applied in FP32 (Sect. 3.3 applies them in single precision), with FP32
- * accumulation on the matrix cores; the library does not build P or the blocks.
+ * stored in FP32 (Sect. 3.3 applies them in single precision) or, with `storage` =
+ * DDQ_F16 / DDQ_BF16, in 16 bits (the lower coarse-level precision the paper leaves to
+ * future work: half the block bytes; FP16 rounds once from the caller's values, BF16
+ * through FP32; FP16's range is the caller's to respect), and applied with FP32
+ * arithmetic and accumulation on the matrix cores; the library does not build P or the
+ * blocks.
  *
  * ddq_coarse_packed_bytes: bytes of the packed block array for coarse extents cdims
- *   (each >= 1, at most 2^25 sites) and N_v test vectors (1 .. 32).
+ *   (each >= 1, at most 2^25 sites), N_v test vectors (1 .. 32) and a storage.
  * ddq_coarse_pack_blocks: converts blocks[site][d][row i][column k] (row-major complex
  *   numbers, complex128 for prec = DDQ_F64 or complex64 for DDQ_F32) into the apply's
- *   packed FP32 operand order (zero-padded to 16 x 8 tiles) in `packed`, a caller-owned
+ *   packed operand order in the given storage (zero-padded to 16 x 8 tiles) in `packed`, a caller-owned
  *   device array of ddq_coarse_packed_bytes bytes, 16-byte aligned.  Enqueued on
  *   hip_stream; allocates nothing.
  * ddq_coarse_apply: y = D_c v for nrhs right-hand sides (1 .. 1048560); v and y are
- *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost),
+ *   complex64 device arrays [site][row 2N_v][rhs nrhs] (right-hand side innermost), and
+ *   `packed` the blocks as ddq_coarse_pack_blocks left them in the same storage,
  *   8-byte aligned, y not overlapping v.  One wavefront per coarse site and per group of
  *   rhs_tiles_per_wave tiles of 16 right-hand sides (1 .. 4; 0 = the default: the fewest
  *   groups of at most 4 tiles, of balanced size); every group reads the packed blocks once,
@@ -436,10 +441,10 @@ int ddq_stencil_stream(ddq_lattice* lat, int prec, int kernel, const void* in, c
  *   multiple of 2^-24 x sum |A||v| per output element.  Enqueued on hip_stream; allocates nothing.
  * Errors: DDQ_ERR_ARG for null or misaligned pointers and sizes out of range,
  * DDQ_ERR_HIP if a launch fails. */
-int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes);
-int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blocks, void* packed,
+int ddq_coarse_packed_bytes(const int cdims[4], int nv, int storage, int64_t* bytes);
+int ddq_coarse_pack_blocks(const int cdims[4], int nv, int storage, int prec, const void* blocks, void* packed,
                            void* hip_stream);
-int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
+int ddq_coarse_apply(const int cdims[4], int nv, int storage, int nrhs, const void* packed, const void* v, void* y,
                      int rhs_tiles_per_wave, int product, void* hip_stream);
 
 /* Thread-local message of the last error (empty string if none). */

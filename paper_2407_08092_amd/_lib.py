@@ -85,9 +85,9 @@ _SIGNATURES = {
     "ddq_fgmres_solve": [_P, _P, _P, _P, _P],
     "ddq_sap_smooth": [_P, C.c_int, _P, _P, C.c_int, C.c_int],
     "ddq_fgmres_sap_solve": [_P, _P, _P, _P, C.c_int, C.c_int, _P],
-    "ddq_coarse_packed_bytes": [C.POINTER(C.c_int), C.c_int, C.POINTER(C.c_int64)],
-    "ddq_coarse_pack_blocks": [C.POINTER(C.c_int), C.c_int, C.c_int, _P, _P, _P],
-    "ddq_coarse_apply": [C.POINTER(C.c_int), C.c_int, C.c_int, _P, _P, _P, C.c_int, C.c_int, _P],
+    "ddq_coarse_packed_bytes": [C.POINTER(C.c_int), C.c_int, C.c_int, C.POINTER(C.c_int64)],
+    "ddq_coarse_pack_blocks": [C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, _P, _P, _P],
+    "ddq_coarse_apply": [C.POINTER(C.c_int), C.c_int, C.c_int, C.c_int, _P, _P, _P, C.c_int, C.c_int, _P],
     "ddq_profile_begin": [_P],
     "ddq_profile_end": [_P, C.POINTER(KernelStats), C.c_int, C.POINTER(C.c_int)],
     "ddq_last_error": [],

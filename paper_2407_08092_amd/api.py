@@ -525,9 +525,10 @@ class CoarseOperator:
 
     blocks: complex128 or complex64 device tensor [sites, 9, 2 N_v, 2 N_v] (block d = 0
     the site's own, d = 1 + 2 mu + s the neighbour in direction mu, forward s = 0 or
-    backward s = 1); cdims: coarse extents (x, y, z, t), site index x fastest."""
+    backward s = 1); cdims: coarse extents (x, y, z, t), site index x fastest; storage:
+    DDQ_F32, DDQ_F16 or DDQ_BF16 for the packed blocks (FP32 arithmetic in all cases)."""
 
-    def __init__(self, cdims, blocks: torch.Tensor):
+    def __init__(self, cdims, blocks: torch.Tensor, storage: int = DDQ_F32):
         self.cdims = tuple(int(c) for c in cdims)
         if len(self.cdims) != 4:
             raise ValueError("cdims needs four extents")
@@ -543,11 +544,12 @@ class CoarseOperator:
         self.vc = vc
         self.device = blocks.device
         self._cd = (C.c_int * 4)(*self.cdims)
+        self.storage = int(storage)
         nb = C.c_int64()
-        check(lib().ddq_coarse_packed_bytes(self._cd, self.nv, C.byref(nb)), "ddq_coarse_packed_bytes")
+        check(lib().ddq_coarse_packed_bytes(self._cd, self.nv, self.storage, C.byref(nb)), "ddq_coarse_packed_bytes")
         self.packed = torch.empty(nb.value, dtype=torch.uint8, device=self.device)
         s = torch.cuda.current_stream(self.device).cuda_stream
-        check(lib().ddq_coarse_pack_blocks(self._cd, self.nv, _prec(blocks), _dev(blocks, "blocks"),
+        check(lib().ddq_coarse_pack_blocks(self._cd, self.nv, self.storage, _prec(blocks), _dev(blocks, "blocks"),
                                            _dev(self.packed, "packed"), C.c_void_p(s)), "ddq_coarse_pack_blocks")
 
     def apply(self, v: torch.Tensor, out: torch.Tensor = None, rhs_tiles_per_wave: int = 0,
@@ -563,7 +565,7 @@ class CoarseOperator:
         if y.shape != v.shape or y.dtype != v.dtype:
             raise ValueError("out must match v")
         s = torch.cuda.current_stream(self.device).cuda_stream
-        check(lib().ddq_coarse_apply(self._cd, self.nv, nrhs, _dev(self.packed, "packed"), _dev(v, "v"),
+        check(lib().ddq_coarse_apply(self._cd, self.nv, self.storage, nrhs, _dev(self.packed, "packed"), _dev(v, "v"),
                                      _dev(y, "out"), int(rhs_tiles_per_wave), int(product), C.c_void_p(s)),
               "ddq_coarse_apply")
         return y

@@ -893,41 +893,55 @@ bool ranges_overlap(const void* a, size_t na, const void* b, size_t nb) {
   return pa < pb + nb && pb < pa + na;
 }
 
-int ddq_coarse_packed_bytes(const int cdims[4], int nv, int64_t* bytes) {
-  if (!cdims || !bytes) return fail(DDQ_ERR_ARG, "null argument");
-  const long long n = coarse_packed_bytes(cdims, nv);
+int coarse_storage(int storage) {
+  return storage == DDQ_F32 ? COARSE_F32 : storage == DDQ_F16 ? COARSE_F16 : storage == DDQ_BF16 ? COARSE_BF16 : -1;
+}
+
+int check_coarse(const int cdims[4], int nv, int storage, long long* packed_bytes) {
+  if (coarse_storage(storage) < 0)
+    return fail(DDQ_ERR_ARG, "coarse blocks are stored as DDQ_F32, DDQ_F16 or DDQ_BF16");
+  const long long n = coarse_packed_bytes(cdims, nv, coarse_storage(storage));
   if (n < 0) return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  if (packed_bytes) *packed_bytes = n;
+  return DDQ_OK;
+}
+
+int ddq_coarse_packed_bytes(const int cdims[4], int nv, int storage, int64_t* bytes) {
+  if (!cdims || !bytes) return fail(DDQ_ERR_ARG, "null argument");
+  long long n = 0;
+  CHK(check_coarse(cdims, nv, storage, &n));
   *bytes = n;
   return DDQ_OK;
 }
 
-int ddq_coarse_pack_blocks(const int cdims[4], int nv, int prec, const void* blocks, void* packed, void* hip_stream) {
+int ddq_coarse_pack_blocks(const int cdims[4], int nv, int storage, int prec, const void* blocks, void* packed,
+                           void* hip_stream) {
   if (!cdims || !blocks || !packed) return fail(DDQ_ERR_ARG, "null argument");
   if (prec != DDQ_F64 && prec != DDQ_F32) return fail(DDQ_ERR_ARG, "blocks are complex128 (DDQ_F64) or complex64 (DDQ_F32)");
   if (((uintptr_t)packed & 15) || ((uintptr_t)blocks & (prec == DDQ_F64 ? 15 : 7)))
     return fail(DDQ_ERR_ARG, "misaligned blocks or packed array");
-  const long long packed_bytes = coarse_packed_bytes(cdims, nv);
-  if (packed_bytes < 0)
-    return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  long long packed_bytes = 0;
+  CHK(check_coarse(cdims, nv, storage, &packed_bytes));
   const size_t sites = (size_t)cdims[0] * cdims[1] * cdims[2] * cdims[3];
   if (ranges_overlap(blocks, sites * 9 * 4 * nv * nv * (prec == DDQ_F64 ? 16 : 8), packed, (size_t)packed_bytes))
     return fail(DDQ_ERR_ARG, "packed must not overlap blocks");
-  HIPCHK(launch_coarse_pack(cdims, nv, prec == DDQ_F64, blocks, packed, (hipStream_t)hip_stream));
+  HIPCHK(launch_coarse_pack(cdims, nv, coarse_storage(storage), prec == DDQ_F64, blocks, packed,
+                            (hipStream_t)hip_stream));
   return DDQ_OK;
 }
 
-int ddq_coarse_apply(const int cdims[4], int nv, int nrhs, const void* packed, const void* v, void* y,
+int ddq_coarse_apply(const int cdims[4], int nv, int storage, int nrhs, const void* packed, const void* v, void* y,
                      int rhs_tiles_per_wave, int product, void* hip_stream) {
   if (!cdims || !packed || !v || !y) return fail(DDQ_ERR_ARG, "null argument");
-  if (coarse_packed_bytes(cdims, nv) < 0)
-    return fail(DDQ_ERR_ARG, "coarse extents must be >= 1 with at most 2^25 sites, and 1 <= N_v <= 32");
+  CHK(check_coarse(cdims, nv, storage, nullptr));
   if (nrhs < 1 || nrhs > 65535 * 16) return fail(DDQ_ERR_ARG, "nrhs must be in 1 .. 1048560");
   if (rhs_tiles_per_wave < 0 || rhs_tiles_per_wave > 4) return fail(DDQ_ERR_ARG, "rhs_tiles_per_wave must be 0 .. 4");
   if (product < 0 || product > 2) return fail(DDQ_ERR_ARG, "product must be 0 (default), 1 (four) or 2 (three real products)");
   if (((uintptr_t)packed & 15) || (((uintptr_t)v | (uintptr_t)y) & 7)) return fail(DDQ_ERR_ARG, "misaligned argument");
   const size_t vbytes = (size_t)cdims[0] * cdims[1] * cdims[2] * cdims[3] * 2 * nv * nrhs * 8;
   if (ranges_overlap(v, vbytes, y, vbytes)) return fail(DDQ_ERR_ARG, "y must not overlap v");
-  HIPCHK(launch_coarse_apply(cdims, nv, nrhs, rhs_tiles_per_wave, product, packed, v, y, (hipStream_t)hip_stream));
+  HIPCHK(launch_coarse_apply(cdims, nv, coarse_storage(storage), nrhs, rhs_tiles_per_wave, product, packed, v, y,
+                             (hipStream_t)hip_stream));
   return DDQ_OK;
 }
 

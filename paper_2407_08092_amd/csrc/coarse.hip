@@ -35,6 +35,34 @@ namespace {
 typedef float f4v __attribute__((ext_vector_type(4)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 
+// packed block storage: 4 values per lane element (FP32: 16 bytes; FP16 / BF16: 8 bytes,
+// widened to FP32 in registers before the products)
+template <typename S>
+struct Store4 {
+  typedef S v __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Store4<float> {
+  typedef f4v v;
+};
+
+// FP16 rounds once from the caller's values; BF16 through FP32 (two roundings from FP64)
+template <typename S, typename R>
+__device__ __forceinline__ S to_store(R r) {
+  if constexpr (sizeof(S) == 2 && __is_same(S, __bf16))
+    return (S)(float)r;
+  else
+    return (S)r;
+}
+
+template <typename S>
+__device__ __forceinline__ f4v widen(typename Store4<S>::v q) {
+  if constexpr (sizeof(S) == 4)
+    return q;
+  else
+    return f4v{(float)q[0], (float)q[1], (float)q[2], (float)q[3]};
+}
+
 #ifndef DDQ_COARSE_TMAP
 #define DDQ_COARSE_TMAP 2
 #endif
@@ -66,10 +94,10 @@ __device__ __forceinline__ int coarse_nbr(const CoarseGeo& g, int x, int d) {
   return c[0] + g.cd[0] * (c[1] + g.cd[1] * (c[2] + g.cd[2] * c[3]));
 }
 
-// one thread per 16-byte packed element; src complex [x][d][i][k] (row-major blocks)
-template <typename R>
-__global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __restrict__ src, f4v* __restrict__ dst,
-                                                     long long n_el) {
+// one thread per packed lane element; src complex [x][d][i][k] (row-major blocks)
+template <typename R, typename S>
+__global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __restrict__ src,
+                                                     typename Store4<S>::v* __restrict__ dst, long long n_el) {
   const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
   if (e >= n_el) return;
   const int lane = (int)(e & 63);
@@ -80,15 +108,15 @@ __global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __res
   const long long xd = r / g.KP;  // x * 9 + d
   const int i = 16 * t + (lane & 15);
   const R* blk = src + xd * 2 * (long long)g.n2 * g.n2;
-  float o[4];
+  S o[4];
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k = 8 * kp + 4 * h + (lane >> 4);
     const bool in = i < g.n2 && k < g.n2;
-    o[2 * h] = in ? (float)blk[2 * ((long long)i * g.n2 + k)] : 0.f;
-    o[2 * h + 1] = in ? (float)blk[2 * ((long long)i * g.n2 + k) + 1] : 0.f;
+    o[2 * h] = to_store<S>(in ? blk[2 * ((long long)i * g.n2 + k)] : R(0));
+    o[2 * h + 1] = to_store<S>(in ? blk[2 * ((long long)i * g.n2 + k) + 1] : R(0));
   }
-  dst[e] = f4v{o[0], o[1], o[2], o[3]};
+  dst[e] = typename Store4<S>::v{o[0], o[1], o[2], o[3]};
 }
 
 // operands of one pair of k-slices: the packed block slice and the right-hand sides' rows
@@ -108,11 +136,11 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t site_rsrc(const float2* vn, in
 // resource's extent, for which buffer loads return 0.  Every lane issues every load, so
 // the loads in flight are counted statically and the products of one slice wait only for
 // that slice's own operands.
-template <int MT, int TN>
-__device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const f4v* Akp, __amdgpu_buffer_rsrc_t vr, int kp,
-                                            int n2, int nrhs, int lk, int j0) {
+template <int MT, int TN, typename S>
+__device__ __forceinline__ void coarse_load(CoarseSlice<MT, TN>& o, const typename Store4<S>::v* Akp,
+                                            __amdgpu_buffer_rsrc_t vr, int kp, int n2, int nrhs, int lk, int j0) {
 #pragma unroll
-  for (int t = 0; t < MT; ++t) o.a[t] = __builtin_nontemporal_load(Akp + t * 64);
+  for (int t = 0; t < MT; ++t) o.a[t] = widen<S>(__builtin_nontemporal_load(Akp + t * 64));
 #pragma unroll
   for (int h = 0; h < 2; ++h) {
     const int k = 8 * kp + 4 * h + lk;
@@ -169,8 +197,9 @@ struct CoarseCursor {
   __amdgpu_buffer_rsrc_t vr;
 };
 
-template <int MT, int TN, int G3>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs, const f4v* __restrict__ A,
+template <int MT, int TN, int G3, typename S>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k_coarse_apply(CoarseGeo g, int nrhs,
+                                                                                              const typename Store4<S>::v* __restrict__ A,
                                                      const float2* __restrict__ v, float2* __restrict__ y) {
   const int w = (int)blockIdx.x;
   int x = w;
@@ -197,12 +226,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
       for (int t = 0; t < MT; ++t) acc[q][n][t] = f4v{0.f, 0.f, 0.f, 0.f};
   // two operand buffers in turn: the loads of step s + 1 are in flight during the
   // products of step s; past the last step the cursor re-reads the first (unused)
-  const f4v* Ax = A + (size_t)x * 9 * g.KP * MT * 64 + l;
-  const int S = 9 * g.KP;
+  const typename Store4<S>::v* Ax = A + (size_t)x * 9 * g.KP * MT * 64 + l;
+  const int nsteps = 9 * g.KP;
   CoarseCursor c{0, 0, 0, site_rsrc(v + (size_t)x * vstride, vbytes)};
   auto load_next = [&](CoarseSlice<MT, TN>& o) {
-    coarse_load<MT, TN>(o, Ax + (size_t)c.q * MT * 64, c.vr, c.kp, g.n2, nrhs, lk, j0);
-    if (++c.q == S) c.q = 0;
+    coarse_load<MT, TN, S>(o, Ax + (size_t)c.q * MT * 64, c.vr, c.kp, g.n2, nrhs, lk, j0);
+    if (++c.q == nsteps) c.q = 0;
     if (++c.kp == g.KP) {
       c.kp = 0;
       c.d = c.d == 8 ? 0 : c.d + 1;
@@ -211,11 +240,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) k
   };
   CoarseSlice<MT, TN> b0, b1;
   load_next(b0);
-  for (int s = 0; s < S; s += 2) {
+  for (int s = 0; s < nsteps; s += 2) {
     load_next(b1);
     coarse_mma<MT, TN, G3>(b0, acc);
     load_next(b0);
-    if (s + 1 < S) coarse_mma<MT, TN, G3>(b1, acc);
+    if (s + 1 < nsteps) coarse_mma<MT, TN, G3>(b1, acc);
   }
   float2* yx = y + (size_t)x * vstride;
 #pragma unroll
@@ -253,52 +282,65 @@ hipError_t make_geo(const int cd[4], int nv, CoarseGeo& g) {
   return hipSuccess;
 }
 
-template <int MT, int G3>
-hipError_t launch_mt(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
+template <int MT, int G3, typename S>
+hipError_t launch_mt(const CoarseGeo& g, int nrhs, int tn, const void* A, const float2* v, float2* y, hipStream_t s) {
   const int tiles = (nrhs + 15) / 16;
   const int groups = (tiles + tn - 1) / tn, wpg = groups < 4 ? groups : 4;
   const dim3 grid((unsigned)g.vc, (unsigned)((groups + wpg - 1) / wpg)), block(64, wpg);
+  const typename Store4<S>::v* As = (const typename Store4<S>::v*)A;
   switch (tn) {
-    case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    case 3: hipLaunchKernelGGL((k_coarse_apply<MT, 3, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
-    default: hipLaunchKernelGGL((k_coarse_apply<MT, 4, G3>), grid, block, 0, s, g, nrhs, A, v, y); break;
+    case 1: hipLaunchKernelGGL((k_coarse_apply<MT, 1, G3, S>), grid, block, 0, s, g, nrhs, As, v, y); break;
+    case 2: hipLaunchKernelGGL((k_coarse_apply<MT, 2, G3, S>), grid, block, 0, s, g, nrhs, As, v, y); break;
+    case 3: hipLaunchKernelGGL((k_coarse_apply<MT, 3, G3, S>), grid, block, 0, s, g, nrhs, As, v, y); break;
+    default: hipLaunchKernelGGL((k_coarse_apply<MT, 4, G3, S>), grid, block, 0, s, g, nrhs, As, v, y); break;
   }
   return hipGetLastError();
 }
 
-template <int G3>
-hipError_t launch_g(const CoarseGeo& g, int nrhs, int tn, const f4v* A, const float2* v, float2* y, hipStream_t s) {
+template <int G3, typename S>
+hipError_t launch_g(const CoarseGeo& g, int nrhs, int tn, const void* A, const float2* v, float2* y, hipStream_t s) {
   switch (g.MT) {
-    case 1: return launch_mt<1, G3>(g, nrhs, tn, A, v, y, s);
-    case 2: return launch_mt<2, G3>(g, nrhs, tn, A, v, y, s);
-    case 3: return launch_mt<3, G3>(g, nrhs, tn, A, v, y, s);
-    default: return launch_mt<4, G3>(g, nrhs, tn, A, v, y, s);
+    case 1: return launch_mt<1, G3, S>(g, nrhs, tn, A, v, y, s);
+    case 2: return launch_mt<2, G3, S>(g, nrhs, tn, A, v, y, s);
+    case 3: return launch_mt<3, G3, S>(g, nrhs, tn, A, v, y, s);
+    default: return launch_mt<4, G3, S>(g, nrhs, tn, A, v, y, s);
   }
+}
+
+template <typename S>
+hipError_t launch_pack(const CoarseGeo& g, int src_f64, const void* src, void* dst, hipStream_t s) {
+  const long long n_el = (long long)g.vc * 9 * g.KP * g.MT * 64;
+  const dim3 grid((unsigned)((n_el + 255) / 256)), block(256);
+  typename Store4<S>::v* d = (typename Store4<S>::v*)dst;
+  if (src_f64)
+    hipLaunchKernelGGL((k_coarse_pack<double, S>), grid, block, 0, s, g, (const double*)src, d, n_el);
+  else
+    hipLaunchKernelGGL((k_coarse_pack<float, S>), grid, block, 0, s, g, (const float*)src, d, n_el);
+  return hipGetLastError();
 }
 
 }  // namespace
 
-long long coarse_packed_bytes(const int cd[4], int nv) {
+long long coarse_packed_bytes(const int cd[4], int nv, int storage) {
   CoarseGeo g;
-  if (make_geo(cd, nv, g) != hipSuccess) return -1;
-  return (long long)g.vc * 9 * g.KP * g.MT * 64 * 16;
+  if (make_geo(cd, nv, g) != hipSuccess || storage < COARSE_F32 || storage > COARSE_BF16) return -1;
+  return (long long)g.vc * 9 * g.KP * g.MT * 64 * (storage == COARSE_F32 ? 16 : 8);
 }
 
-hipError_t launch_coarse_pack(const int cd[4], int nv, int src_f64, const void* src, void* dst, hipStream_t s) {
+hipError_t launch_coarse_pack(const int cd[4], int nv, int storage, int src_f64, const void* src, void* dst,
+                              hipStream_t s) {
   CoarseGeo g;
   hipError_t e = make_geo(cd, nv, g);
   if (e != hipSuccess) return e;
-  const long long n_el = (long long)g.vc * 9 * g.KP * g.MT * 64;
-  const dim3 grid((unsigned)((n_el + 255) / 256)), block(256);
-  if (src_f64)
-    hipLaunchKernelGGL(k_coarse_pack<double>, grid, block, 0, s, g, (const double*)src, (f4v*)dst, n_el);
-  else
-    hipLaunchKernelGGL(k_coarse_pack<float>, grid, block, 0, s, g, (const float*)src, (f4v*)dst, n_el);
-  return hipGetLastError();
+  switch (storage) {
+    case COARSE_F32: return launch_pack<float>(g, src_f64, src, dst, s);
+    case COARSE_F16: return launch_pack<_Float16>(g, src_f64, src, dst, s);
+    case COARSE_BF16: return launch_pack<__bf16>(g, src_f64, src, dst, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
-hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_per_wave, int product,
+hipError_t launch_coarse_apply(const int cd[4], int nv, int storage, int nrhs, int rhs_tiles_per_wave, int product,
                                const void* packed, const void* v, void* y, hipStream_t s) {
   CoarseGeo g;
   hipError_t e = make_geo(cd, nv, g);
@@ -306,6 +348,7 @@ hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_
   const int tiles = (nrhs + 15) / 16;
   if (nrhs < 1 || (tiles + 3) / 4 > 65535) return hipErrorInvalidValue;
   if (rhs_tiles_per_wave > 4 || product < 0 || product > 2) return hipErrorInvalidValue;
+  if (storage < COARSE_F32 || storage > COARSE_BF16) return hipErrorInvalidValue;
   const int g3 = product != 1;  // the default is Gauss's three products
   // default grouping: the fewest groups of at most 4 tiles (3 for the three-product form
   // with 4 row tiles, whose 4-tile kernel spills), balanced (5 tiles: 3 + 2, not 4 + 1)
@@ -313,10 +356,16 @@ hipError_t launch_coarse_apply(const int cd[4], int nv, int nrhs, int rhs_tiles_
   const int groups = (tiles + max_tn - 1) / max_tn;
   int tn = rhs_tiles_per_wave > 0 ? rhs_tiles_per_wave : (tiles + groups - 1) / groups;
   if (tn > tiles) tn = tiles;
-  const f4v* A = (const f4v*)packed;
   const float2* vv = (const float2*)v;
   float2* yy = (float2*)y;
-  return g3 ? launch_g<1>(g, nrhs, tn, A, vv, yy, s) : launch_g<0>(g, nrhs, tn, A, vv, yy, s);
+  switch (storage) {
+    case COARSE_F16:
+      return g3 ? launch_g<1, _Float16>(g, nrhs, tn, packed, vv, yy, s) : launch_g<0, _Float16>(g, nrhs, tn, packed, vv, yy, s);
+    case COARSE_BF16:
+      return g3 ? launch_g<1, __bf16>(g, nrhs, tn, packed, vv, yy, s) : launch_g<0, __bf16>(g, nrhs, tn, packed, vv, yy, s);
+    default:
+      return g3 ? launch_g<1, float>(g, nrhs, tn, packed, vv, yy, s) : launch_g<0, float>(g, nrhs, tn, packed, vv, yy, s);
+  }
 }
 
 }  // namespace ddq

@@ -76,25 +76,30 @@ def test_coarse_sizes_and_bad_arguments_on_host():
     cd = (C.c_int * 4)(3, 4, 3, 5)
     nb = C.c_int64()
     # N_v = 24: 2N_v = 48 -> 3 row tiles x 6 pairs of k-slices x 1 KB per (site, block)
-    assert L.ddq_coarse_packed_bytes(cd, 24, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 6 * 1024
+    assert L.ddq_coarse_packed_bytes(cd, 24, 1, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 6 * 1024
     # N_v = 20: 2N_v = 40 padded to 48 rows and 40 columns (5 pairs of 4-wide k-slices)
-    assert L.ddq_coarse_packed_bytes(cd, 20, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 5 * 1024
-    assert L.ddq_coarse_packed_bytes(cd, 0, C.byref(nb)) == -1
-    assert L.ddq_coarse_packed_bytes(cd, 33, C.byref(nb)) == -1
-    assert L.ddq_coarse_packed_bytes((C.c_int * 4)(3, 0, 3, 3), 8, C.byref(nb)) == -1
-    assert L.ddq_coarse_packed_bytes((C.c_int * 4)(512, 512, 512, 1), 8, C.byref(nb)) == -1
+    assert L.ddq_coarse_packed_bytes(cd, 20, 1, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 5 * 1024
+    assert L.ddq_coarse_packed_bytes(cd, 0, 1, C.byref(nb)) == -1
+    assert L.ddq_coarse_packed_bytes(cd, 33, 1, C.byref(nb)) == -1
+    assert L.ddq_coarse_packed_bytes((C.c_int * 4)(3, 0, 3, 3), 8, 1, C.byref(nb)) == -1
+    assert L.ddq_coarse_packed_bytes((C.c_int * 4)(512, 512, 512, 1), 8, 1, C.byref(nb)) == -1
+    # FP16 / BF16 storage: half the bytes
+    assert L.ddq_coarse_packed_bytes(cd, 24, 2, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 6 * 512
+    assert L.ddq_coarse_packed_bytes(cd, 24, 3, C.byref(nb)) == 0 and nb.value == 180 * 9 * 3 * 6 * 512
+    assert L.ddq_coarse_packed_bytes(cd, 24, 0, C.byref(nb)) == -1  # no FP64 storage
     fake = C.c_void_p(1 << 20)  # never dereferenced: every call below fails its host checks
     y = C.c_void_p((1 << 20) + 4096)
-    assert L.ddq_coarse_apply(cd, 8, 0, fake, fake, y, 0, 0, None) == -1
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 5, 0, None) == -1
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, y, 0, 3, None) == -1  # no such product form
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, fake, 0, 0, None) == -1  # y == v
+    assert L.ddq_coarse_apply(cd, 8, 1, 0, fake, fake, y, 0, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, fake, fake, y, 5, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, fake, fake, y, 0, 3, None) == -1  # no such product form
+    assert L.ddq_coarse_apply(cd, 8, 0, 16, fake, fake, y, 0, 0, None) == -1  # no such storage
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, fake, fake, fake, 0, 0, None) == -1  # y == v
     # y starting inside v (180 sites x 16 rows x 16 right-hand sides x 8 B = 368,640 B)
-    assert L.ddq_coarse_apply(cd, 8, 16, fake, fake, C.c_void_p((1 << 20) + 368640 - 8), 0, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, fake, fake, C.c_void_p((1 << 20) + 368640 - 8), 0, 0, None) == -1
     assert b"overlap" in L.ddq_last_error()
-    assert L.ddq_coarse_apply(cd, 8, 16, C.c_void_p((1 << 20) + 8), fake, y, 0, 0,
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, C.c_void_p((1 << 20) + 8), fake, y, 0, 0,
                               None) == -1  # packed not 16-byte aligned
-    assert L.ddq_coarse_pack_blocks(cd, 8, 2, fake, fake, None) == -1  # 16-bit blocks are not taken
-    assert L.ddq_coarse_pack_blocks(cd, 8, 1, fake, C.c_void_p((1 << 20) + 1024), None) == -1  # overlap
+    assert L.ddq_coarse_pack_blocks(cd, 8, 1, 2, fake, fake, None) == -1  # 16-bit input blocks are not taken
+    assert L.ddq_coarse_pack_blocks(cd, 8, 1, 1, fake, C.c_void_p((1 << 20) + 1024), None) == -1  # overlap
     assert b"overlap" in L.ddq_last_error()
-    assert L.ddq_coarse_apply(cd, 8, 16, None, fake, fake, 0, 0, None) == -1
+    assert L.ddq_coarse_apply(cd, 8, 1, 16, None, fake, fake, 0, 0, None) == -1

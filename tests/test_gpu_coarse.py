@@ -13,7 +13,8 @@ tiles, one to four tiles per wave, several waves per site), coarse extents 1 and
 of the three orders of sites over the XCDs is taken); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
 checked against P^H D P applied on the CPU; and a 12^3 x 24 coarse lattice (the
 coarsening of 48^3 x 96 by 4^4 aggregates) with N_v = 24 and 16 right-hand sides,
-sampled sites against the oracle's sum for those sites.  Both product forms are covered:
+sampled sites against the oracle's sum for those sites; FP16 and BF16 block storage against
+the oracle on the same rounded blocks.  Both product forms are covered:
 four real products per complex one, and Gauss's three (whose sums of real and imaginary
 parts are rounded to FP32 before the product, within the same bar).
 """
@@ -152,3 +153,49 @@ def test_bad_shapes_rejected():
         op.apply(torch.zeros((16, 8, 4), dtype=torch.complex128, device="cuda"))
     with pytest.raises(api.DDQError):
         op.apply(torch.zeros((16, 8, 4), dtype=torch.complex64, device="cuda"), rhs_tiles_per_wave=7)
+
+
+def _bf16_round(x32):
+    """float32 -> nearest bfloat16 (ties to even), returned as float64 (finite inputs)"""
+    b = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    b = ((b + 0x7FFF + ((b >> 16) & 1)) >> 16) << 16
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _round_blocks(A, storage):
+    if storage == api.DDQ_F16:
+        return A.real.astype(np.float16).astype(np.float64) + 1j * A.imag.astype(np.float16).astype(np.float64)
+    return _bf16_round(A.real.astype(np.float32)) + 1j * _bf16_round(A.imag.astype(np.float32))
+
+
+@pytest.mark.parametrize("product", [1, 2], ids=["four", "gauss3"])
+@pytest.mark.parametrize("storage", [api.DDQ_F16, api.DDQ_BF16], ids=["f16", "bf16"])
+@pytest.mark.parametrize("nv,nrhs", [(4, 5), (10, 40), (24, 64)])
+def test_16bit_block_storage_matches_oracle(storage, product, nv, nrhs):
+    # the blocks are rounded once to 16 bits by the pack; the oracle applies the same rounded
+    # blocks in FP64, so the bar is the FP32 accumulation's
+    cd = (2, 3, 2, 4) if nv < 24 else (2, 2, 2, 8)
+    Vc, n2 = int(np.prod(cd)), 2 * nv
+    A = _rand((Vc, 9, n2, n2), 791 + nv)
+    v = _rand((Vc, n2, nrhs), 792 + nv)
+    y = api.CoarseOperator(cd, _dev(A), storage=storage).apply(_dev(v), product=product).cpu().numpy()
+    Ar = _round_blocks(A, storage)
+    ref = coarse.coarse_apply(Ar, cd, v.astype(np.complex128))
+    tol = 2e-6 * _term_bound(Ar, cd, v.astype(np.complex128))
+    assert np.all(np.abs(y - ref) <= tol), (np.abs(y - ref) / tol).max()
+    # the 16-bit rounding is visible: against the unrounded blocks the same output misses the bar
+    ref_full = coarse.coarse_apply(A.astype(np.complex128), cd, v.astype(np.complex128))
+    assert not np.all(np.abs(y - ref_full) <= tol)
+
+
+def test_16bit_storage_from_complex128_rounds_once():
+    # FP16 from complex128 blocks: one rounding, the same as numpy's float64 -> float16
+    cd, nv, nrhs = (2, 2, 3, 2), 6, 16
+    Vc, n2 = 24, 12
+    A64 = synth.gaussian_complex((Vc, 9, n2, n2), 801)
+    v = _rand((Vc, n2, nrhs), 802)
+    y = api.CoarseOperator(cd, _dev(A64), storage=api.DDQ_F16).apply(_dev(v)).cpu().numpy()
+    Ar = A64.real.astype(np.float16).astype(np.float64) + 1j * A64.imag.astype(np.float16).astype(np.float64)
+    ref = coarse.coarse_apply(Ar, cd, v.astype(np.complex128))
+    tol = 2e-6 * _term_bound(Ar, cd, v.astype(np.complex128))
+    assert np.all(np.abs(y - ref) <= tol)

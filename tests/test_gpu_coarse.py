@@ -13,7 +13,8 @@ tiles, one to four tiles per wave, several waves per site), coarse extents 1 and
 of the three orders of sites over the XCDs is taken); the Galerkin blocks of a 6^4 lattice with 2^4 aggregates,
 checked against P^H D P applied on the CPU; and a 12^3 x 24 coarse lattice (the
 coarsening of 48^3 x 96 by 4^4 aggregates) with N_v = 24 and 16 right-hand sides,
-sampled sites against the oracle's sum for those sites; FP16 and BF16 block storage against
+sampled sites against the oracle's sum for those sites; the largest right-hand-side count
+(1,048,560) and N_v = 32 on one site, sampled columns; FP16 and BF16 block storage against
 the oracle on the same rounded blocks.  Both product forms are covered:
 four real products per complex one, and Gauss's three (whose sums of real and imaginary
 parts are rounded to FP32 before the product, within the same bar).
@@ -199,3 +200,23 @@ def test_16bit_storage_from_complex128_rounds_once():
     ref = coarse.coarse_apply(Ar, cd, v.astype(np.complex128))
     tol = 2e-6 * _term_bound(Ar, cd, v.astype(np.complex128))
     assert np.all(np.abs(y - ref) <= tol)
+
+
+@pytest.mark.parametrize("tn", [0, 1])
+def test_maximum_rhs_count_single_site(tn):
+    # the largest nrhs the ABI takes (65535 tiles of 16), N_v = 32 (the largest), one coarse
+    # site (all eight neighbours are the site itself); sampled columns against the oracle
+    cd, nv, nrhs = (1, 1, 1, 1), 32, 65535 * 16
+    n2 = 2 * nv
+    A = _rand((1, 9, n2, n2), 811)
+    g = torch.Generator(device="cuda").manual_seed(812)
+    v = torch.randn((1, n2, nrhs), dtype=torch.complex64, device="cuda", generator=g)
+    y = api.CoarseOperator(cd, _dev(A)).apply(v, rhs_tiles_per_wave=tn)
+    torch.cuda.synchronize()
+    cols = np.array([0, 1, 15, 16, 17, 4095, 65536, nrhs // 2 + 3, nrhs - 17, nrhs - 16, nrhs - 1])
+    vs = v[0][:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.complex128)
+    Asum = A[0].astype(np.complex128).sum(axis=0)
+    ref = Asum @ vs
+    bound = np.abs(A[0].astype(np.complex128)).sum(axis=0) @ np.abs(vs)
+    got = y[0][:, torch.from_numpy(cols).cuda()].cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 2e-6 * bound)

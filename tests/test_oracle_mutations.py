@@ -180,8 +180,24 @@ def _sap_stale_residual(op, b, x0, n, m, block=(4, 4, 4, 4)):
     return x
 
 
+def _block_solve_unreduced(op, in_block, r, m):
+    # mistake: Minimal Residual on the whole block system D_kk e = r_k, without the
+    # odd-even reduction to the block's Schur complement (the converged limit is the same)
+    lat = op.lat
+    mask = in_block.astype(float)[..., None, None] * np.ones(lat.shape + (4, 3))
+
+    def D_kk(v):
+        return mask * op.D(mask * v)
+
+    return solvers.minimal_residual(D_kk, mask * r, m)
+
+
 @pytest.mark.parametrize("name,mutant,pin", [
     ("block_solve", _block_solve_leaky, lambda: pins.test_block_solve_converges_to_dense_block_inverse((2, 2, 2, 2))),
+    ("block_solve", _block_solve_unreduced,
+     lambda: pins.test_block_solve_at_few_mr_steps_is_block_odd_even_mr((4, 4, 2, 2), 1)),
+    ("block_solve", _block_solve_unreduced,
+     lambda: pins.test_block_solve_at_few_mr_steps_is_block_odd_even_mr((2, 2, 2, 2), 2)),
     ("minimal_residual", _mr_conj, pins.test_minimal_residual_closed_form_and_orthogonality),
     ("sap", _sap_stale_residual, pins.test_sap_is_multiplicative_schwarz),
 ])

@@ -676,3 +676,52 @@ def test_sap_is_multiplicative_schwarz():
     x1 = xh + B[1] @ (b - D @ xh)
     got = solvers.sap(op, b.reshape(lat.shape + (4, 3)), x0.reshape(lat.shape + (4, 3)), 1, 400, (2, 2, 2, 2))
     assert rel_err(got.ravel(), x1) < 1e-10
+
+
+def _block_parity_dofs(lat, in_block):
+    """dofs of the block's even and odd sites (a site is even when x + y + z + t is)"""
+    par = np.indices(lat.shape).sum(axis=0) % 2
+    return _block_dofs(lat, in_block & (par == 0)), _block_dofs(lat, in_block & (par == 1))
+
+
+@pytest.mark.parametrize("block,m", [((2, 2, 2, 2), 1), ((2, 2, 2, 2), 2), ((4, 4, 2, 2), 1),
+                                     ((4, 4, 2, 2), 2), ((4, 4, 2, 2), 3)])
+def test_block_solve_at_few_mr_steps_is_block_odd_even_mr(block, m):
+    """The block solve of SAP at the step counts a smoother uses (Sect. 2.4.5 on combining
+    odd-even with SAP: MR on the Schur complement of each block).  From the dense D of the
+    lattice: the block's four sub-blocks D_ee^k, D_eo^k, D_oe^k, D_oo^k (rows and columns of
+    the block's even and odd sites), the block Schur complement S = D_ee^k - D_eo^k
+    (D_oo^k)^-1 D_oe^k, m dense MR steps on S e_e = b~ from zero with b~ = r_e - D_eo^k
+    (D_oo^k)^-1 r_o, and e_o = (D_oo^k)^-1 (r_o - D_oe^k e_e).  Also what holds for any m:
+    the block's odd rows are solved exactly, and after one step the block's even residual
+    is orthogonal to S b~ (the MR step's minimisation)."""
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 149), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    idx, colour, nblk = solvers.sap_blocks(lat, block)
+    r = _full_vec(lat, 150)
+    rv = r.ravel()
+    for k in range(nblk):
+        e_d, o_d = _block_parity_dofs(lat, idx == k)
+        Dee, Deo = D[np.ix_(e_d, e_d)], D[np.ix_(e_d, o_d)]
+        Doe, Doo = D[np.ix_(o_d, e_d)], D[np.ix_(o_d, o_d)]
+        Doo_inv = np.linalg.inv(Doo)
+        S = Dee - Deo @ Doo_inv @ Doe
+        bt = rv[e_d] - Deo @ (Doo_inv @ rv[o_d])
+        xe, res = np.zeros_like(bt), bt.copy()
+        for _ in range(m):
+            q = S @ res
+            alpha = np.vdot(q, res) / np.vdot(q, q)
+            xe, res = xe + alpha * res, res - alpha * q
+        xo = Doo_inv @ (rv[o_d] - Doe @ xe)
+        e = solvers.block_solve(op, idx == k, r, m).ravel()
+        assert rel_err(e[e_d], xe) < 1e-12 and rel_err(e[o_d], xo) < 1e-12
+        # odd rows of the block system hold exactly, for any m
+        assert rel_err(Doe @ e[e_d] + Doo @ e[o_d], rv[o_d]) < 1e-12
+        if m == 1:
+            # one step: e_e = alpha b~ with alpha = (S b~)^H b~ / |S b~|^2, whose residual is
+            # orthogonal to S b~
+            sb = S @ bt
+            assert rel_err(e[e_d], (np.vdot(sb, bt) / np.vdot(sb, sb)) * bt) < 1e-12
+            ree = rv[e_d] - Dee @ e[e_d] - Deo @ e[o_d]
+            assert abs(np.vdot(sb, ree)) < 1e-12 * np.linalg.norm(sb) * np.linalg.norm(bt)

@@ -34,10 +34,15 @@
  *
  * Ownership: every field pointer is a device pointer owned by the caller, except
  * the gauge input of ddq_set_gauge, which may be a host pointer.  The library owns
- * its packed copies of links and clover blocks and its work buffers; it allocates
- * them in ddq_create_lattice / ddq_set_gauge / ddq_set_clover and, for GMRES
- * bases, on the first solve that needs a larger basis; ddq_destroy_lattice frees
- * them.  Apply and smooth calls allocate nothing.
+ * its packed copies of links and clover blocks and its work buffers.  It allocates
+ * device and pinned host memory only in ddq_create_lattice, ddq_set_gauge,
+ * ddq_set_clover, ddq_reserve, ddq_tune_multi_rhs, ddq_autotune (through the tuner
+ * it does not call: it only reads and writes the cache) and, for a batch, in
+ * ddq_batch_create and ddq_batch_reserve; ddq_destroy_lattice / ddq_batch_destroy
+ * free it.  Every other call -- apply, smooth, prepare, reconstruct, the solvers,
+ * the force -- allocates nothing: when its work space exceeds what was reserved it
+ * returns DDQ_ERR_STATE and does nothing.  ddq_set_gauge / ddq_set_clover reserve
+ * one right-hand side of apply and smooth in every stored precision.
  *
  * Streams: every call enqueues its work on the lattice's stream and returns
  * without waiting, except ddq_set_clover, ddq_get_clover, ddq_estimate_lambda_max
@@ -62,7 +67,7 @@ typedef struct ddq_lattice ddq_lattice;
  * DDQ_F32: complex64 vectors, FP32 links and clover (blocks inverted in FP64,
  * then rounded).  DDQ_F16 / DDQ_BF16: 16-bit storage of vectors, links (12-real)
  * and clover blocks (rounded from FP64) with FP32 arithmetic: the lower-precision
- * storage the paper leaves to future work (Sect. 6).  16-bit parity vectors are
+ * storage the paper leaves to future work (Sect. 4).  16-bit parity vectors are
  * [rhs][sc/4][i][sc%4] complex pairs of 16-bit values (four complex numbers per
  * 16-byte element); FP16's range (normal numbers 6.1e-5 .. 65504) is the
  * caller's to respect.  Narrowing from FP64 rounds to nearest even: FP16 in one
@@ -89,8 +94,12 @@ enum ddq_status {
  * 16-bit 12-real links (and, at ddq_set_clover, 16-bit clover blocks). */
 enum { DDQ_STORE_F64 = 1, DDQ_STORE_F32 = 2, DDQ_STORE_F32_LINK12 = 4, DDQ_STORE_F16 = 8, DDQ_STORE_BF16 = 16 };
 
-/* Lattice of extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2, with
- * V = Lx*Ly*Lz*Lt < 2^31.  t_antiperiodic != 0 selects antiperiodic t.
+/* Lattice of extents dims = {Lx, Ly, Lz, Lt}, each even and >= 2.  The kernels
+ * address every field through 32-bit buffer descriptors; the largest field, the
+ * FP64 clover blocks of one parity (576 bytes a site), must stay below 4 GiB, so
+ * V/2 (rounded up to a multiple of 64) must not exceed 7,456,512 sites (48^3 x 96
+ * has 5,308,416); larger lattices are refused with DDQ_ERR_ARG before anything is
+ * allocated.  t_antiperiodic != 0 selects antiperiodic t.
  * hip_stream: a hipStream_t (NULL = the null stream). */
 int ddq_create_lattice(const int dims[4], int t_antiperiodic, void* hip_stream,
                        ddq_lattice** out);
@@ -98,6 +107,29 @@ int ddq_destroy_lattice(ddq_lattice* lat);
 int ddq_set_stream(ddq_lattice* lat, void* hip_stream);
 /* volume V and half volume V/2 */
 int ddq_lattice_size(const ddq_lattice* lat, int64_t* volume, int64_t* half_volume);
+
+/* Work space of the calls that follow (they allocate nothing themselves).  The
+ * reservation only grows: every call raises it to at least these limits and
+ * allocates what the lattice's stored precisions then need; ddq_set_gauge applies it
+ * to precisions stored later.
+ *   max_nrhs  right-hand sides of ddq_apply_schur, ddq_richardson_smooth,
+ *             ddq_backward_apply (u_o in every stored precision), ddq_oe_prepare /
+ *             ddq_oe_reconstruct and, with DDQ_RESERVE_FULL, ddq_apply_dirac /
+ *             ddq_oe_smoother (1 .. 4096)
+ *   max_m     GMRES / FGMRES cycle length (0 .. 128)
+ *   what      DDQ_RESERVE_SOLVE: ddq_oe_gmres_solve (2 max_m + 4 FP64 and 3 FP32
+ *             parity vectors; several right-hand sides are solved one after the
+ *             other in this space);  DDQ_RESERVE_FULL: the full operator, the
+ *             odd-even smoother and ddq_fgmres_solve (8 FP64 and 2 FP32 parity
+ *             vectors per right-hand side, 2 max_m + 2 full FP64 vectors);
+ *             DDQ_RESERVE_SAP: ddq_sap_smooth / ddq_fgmres_sap_solve (SAP-ordered
+ *             copies of links and clover, the residual work space, FGMRES);
+ *             DDQ_RESERVE_FORCE: ddq_backward_link_force (V x 54 complex128
+ *             insertions and two parity vectors)
+ * Returns DDQ_ERR_OOM when the device memory does not suffice (the reservation then
+ * keeps what it had). */
+enum { DDQ_RESERVE_SOLVE = 1, DDQ_RESERVE_FULL = 2, DDQ_RESERVE_SAP = 4, DDQ_RESERVE_FORCE = 8 };
+int ddq_reserve(ddq_lattice* lat, int max_nrhs, int max_m, unsigned what);
 
 /* Gauge links U (canonical layout, SU(3), complex128; host pointer when
  * U_on_device == 0).  Packs them into the library's per-parity layout in the
@@ -141,7 +173,7 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
  * and ddq_richardson_smooth, not daggered).  The operator is that of Sect. 2.4.5
  * applied to nrhs vectors that share the links and clover blocks; the paper applies
  * one vector at a time and names several right-hand sides as a way to make the
- * block applications cache-friendly (Sect. 5); the tiling is this library's.
+ * block applications cache-friendly (Sect. 3.3); the tiling is this library's.
  *   nb       right-hand sides per thread (links and clover slots loaded once for
  *            nb spinors); 1..4 and dividing nrhs.  0: one right-hand side per
  *            thread, 64 sites x 4 right-hand sides per workgroup, the workgroups
@@ -178,6 +210,18 @@ int ddq_set_multi_rhs_tile(ddq_lattice* lat, int nrhs, const ddq_mr_tile* tile);
 int ddq_tune_multi_rhs(ddq_lattice* lat, int nrhs, int reps, ddq_mr_tile* results, int max_results,
                        int* n_results, ddq_mr_tile* chosen);
 
+/* Persisted tiles.  cache_json_path names a JSON file {"ddq_autotune": 1, "tiles":
+ * [{"key", "nrhs", "nb", "waves", "xcd_map", "ms"}, ...]} (created when absent), one
+ * entry per line; the key is the device (architecture name and compute-unit count),
+ * the lattice extents and the FP32 link storage ("link12" / "link18").  The call sets
+ * every cached tile of the lattice's key for a right-hand-side count the lattice has
+ * no tile for yet, then writes the lattice's tiles (tuned or set, with the tuner's
+ * time where known) back under its key, keeping the other keys' entries; the file
+ * is replaced through a temporary file.  Timing is left to ddq_tune_multi_rhs: a
+ * first run tunes and saves, later runs load.  DDQ_ERR_ARG when the file cannot be
+ * written or holds an invalid tile for this key. */
+int ddq_autotune(ddq_lattice* lat, const char* cache_json_path);
+
 /* |lambda_max(D_S)| by power iteration in FP64 (Sect. 2.4.4):
  * out = (|D_S^iters v0| / |v0|)^(1/iters).  v0: FP64 parity vector (device,
  * not modified).  Synchronises the stream. */
@@ -188,11 +232,16 @@ int ddq_estimate_lambda_max(ddq_lattice* lat, int iters, const void* v0, double*
 int ddq_oe_prepare(ddq_lattice* lat, int nrhs, const void* b, void* bt_e);
 int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* b, void* x);
 
-/* Restarted GMRES(m) of Alg. 2 on D_S with eq. 2 around it.
+/* Restarted GMRES(m) of Alg. 2 on D_S with eq. 2 around it, for nrhs systems
+ * D x_r = b_r solved one after the other (ddq_batch_solve runs several in lock-step).
  *   m            cycle length (1 <= m <= 128)
  *   max_cycles   restarts before giving up (DDQ_NOT_CONVERGED)
- *   tol          stop when |b~_e - D_S x_e| <= tol * |b| (b the full right-hand
- *                side); the same as the full residual |b - D x| in exact arithmetic
+ *   tol          the full residual |b - D x| <= tol * |b| (the fine-level tolerance
+ *                of the paper's parameter table is 1e-10).  The restarts run until
+ *                |b~_e - D_S x_e| <= tol |b|, the same in exact arithmetic; then x is
+ *                reconstructed (eq. 2) and |b - D x| formed in FP64 (eq. 1 on both
+ *                parities); if rounding left it above tol |b|, the Schur target is
+ *                lowered by the observed ratio and the restarts continue
  *   inner_prec   DDQ_F64: every operator apply in FP64.  DDQ_F32: inside a cycle
  *                the operator and the smoother run in FP32 on FP64 Arnoldi
  *                vectors (iterative refinement: the residual at every restart,
@@ -219,9 +268,12 @@ int ddq_oe_reconstruct(ddq_lattice* lat, int nrhs, const void* x_e, const void* 
  *                default; 0 means 2) or 1 (one pass: half the reads of the basis;
  *                enough where the cycle's own target, 1e-5 with an FP32 operator,
  *                lies far above the FP64 loss of orthogonality)
- * x: full vector, in the initial guess, out the solution; b: full vector;
- * both complex128.  info (may be NULL) receives counts and the final residual
- * (FP64, recomputed).  Synchronises the stream. */
+ * x: nrhs full vectors [nrhs][t][z][y][x][4][3], in the initial guesses, out the
+ * solutions; b: nrhs full vectors; both complex128, not overlapping.  info (may be
+ * NULL) receives one record per right-hand side: counts and the final full residual
+ * (FP64, recomputed).  Work space: DDQ_RESERVE_SOLVE of ddq_reserve with max_m >= m
+ * (else DDQ_ERR_STATE).  Returns DDQ_NOT_CONVERGED when any system missed tol.
+ * Synchronises the stream. */
 typedef struct {
   int m;
   int max_cycles;
@@ -240,20 +292,19 @@ typedef struct {
   int iters;             /* Arnoldi steps */
   int applies_f64;       /* D_S applications in FP64 (smoother sweeps included) */
   int applies_lo;        /* D_S applications in FP32 (smoother sweeps included) */
-  double true_relres;    /* |b~_e - D_S x_e| / |b|, FP64, after the last update */
+  double true_relres;    /* |b - D x| / |b|, FP64, recomputed after the last update */
   double t_total_ms;     /* wall time of the call */
 } ddq_solve_info;
 
-int ddq_oe_gmres_solve(ddq_lattice* lat, void* x, const void* b,
+int ddq_oe_gmres_solve(ddq_lattice* lat, int nrhs, void* x, const void* b,
                        const ddq_gmres_params* params, ddq_solve_info* info);
 
 /* The full Wilson-clover operator D of eq. 1 (nine 12x12 blocks per block row, Sect.
  * 2.3): y = D x for nrhs full FP64 vectors (the layout of ddq_pack_parity's full
  * vectors).  Kernel B's apply mode on each parity: y_e = A_ee x_e - H_eo x_o and
  * y_o = A_oo x_o - H_oe x_e, with the undivided odd clover blocks A_oo that
- * ddq_set_clover keeps for this.  x, y: device, not overlapping.  Allocates 8 FP64
- * parity vectors per right-hand side of work space on first use (kept until the
- * lattice is destroyed). */
+ * ddq_set_clover keeps for this.  x, y: device, not overlapping.  Work space: 8 FP64
+ * parity vectors per right-hand side (DDQ_RESERVE_FULL of ddq_reserve). */
 int ddq_apply_dirac(ddq_lattice* lat, int nrhs, const void* x, void* y);
 
 /* The odd-even smoother M_nu of Sect. 2.4.5 (the right panel of Fig. 1): z = M_nu r for
@@ -280,7 +331,9 @@ int ddq_oe_smoother(ddq_lattice* lat, int nrhs, const void* r, void* z, int nswe
  * DDQ_F64, or in DDQ_F32 with the FP32 links (12-real if stored so) and clover blocks
  * (their dot products accumulated in FP64); the residuals b - D x and the update of x
  * are FP64 either way.  x: initial guess in, iterate out; b: right-hand side (device,
- * not overlapping).  One workgroup per block, the block's half vectors in LDS.
+ * not overlapping).  One workgroup per block, the block's half vectors in LDS.  Work
+ * space: DDQ_RESERVE_SAP of ddq_reserve (the links and clover blocks are copied into
+ * SAP block order there on the first call after ddq_set_gauge / ddq_set_clover).
  * Synchronises the stream. */
 int ddq_sap_smooth(ddq_lattice* lat, int prec, void* x, const void* b, int n, int m);
 
@@ -292,7 +345,8 @@ int ddq_sap_smooth(ddq_lattice* lat, int prec, void* x, const void* b, int n, in
  * <= tol |b| on the FP64 residual recomputed at a restart; inner_reduction > 0 ends a
  * cycle once its residual estimate has fallen by that factor (0: at the target).
  * cycle_graph is ignored.  x: initial guess in, solution out (device).  Work space:
- * 2m + 2 full FP64 vectors plus the smoother's.  Returns DDQ_NOT_CONVERGED when
+ * 2m + 2 full FP64 vectors plus the smoother's (DDQ_RESERVE_FULL of ddq_reserve with
+ * max_m >= m; DDQ_RESERVE_SAP for the SAP form below).  Returns DDQ_NOT_CONVERGED when
  * max_cycles restarts did not reach the target (x holds the last iterate). */
 int ddq_fgmres_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmres_params* params,
                      ddq_solve_info* info);
@@ -323,22 +377,33 @@ int ddq_fgmres_sap_solve(ddq_lattice* lat, void* x, const void* b, const ddq_gmr
  * ddq_batch_create: lats[nlat] distinct lattice handles, each with FP64 and FP32
  *   links (ddq_set_gauge) and clover (ddq_set_clover); nrhs[l] >= 1 right-hand
  *   sides for lattice l.  The batch keeps the handles (destroy it before them) and
- *   owns its own stream (default priority) and work buffers, allocated on the first
- *   solve: per lattice (2m + 5) FP64 and 3 FP32 batched parity vectors.
+ *   owns its own stream (default priority) and work buffers.
  *   hip_stream: the caller's stream; a solve starts after the work enqueued on it.
+ * ddq_batch_reserve: allocates the batch's work space for cycle lengths up to max_m
+ *   (1 .. 127; cycle_graph != 0 adds the cycle mode's coefficient arrays): per
+ *   lattice (2 max_m + 5) FP64 and 3 FP32 batched parity vectors, u_o of nrhs[l]
+ *   right-hand sides in every precision the lattice stores, the pinned host
+ *   buffers; and tunes (ddq_tune_multi_rhs) every lattice with no tile for its
+ *   count.  Synchronises.  A solve needs it (else DDQ_ERR_STATE) and allocates
+ *   nothing.
  * ddq_batch_solve: x[l], b[l] complex128 full vectors [nrhs[l]][t][z][y][x][4][3]
  *   on the device (x in: initial guess, out: solution; b not modified).  params as
  *   for ddq_oe_gmres_solve (m <= 127, inner_prec must be DDQ_F32); omegas[l] (or
  *   NULL: params->omega for all) the Richardson weight of lattice l.  info (may be
  *   NULL) receives one record per system in (lattice, right-hand side) order; the
- *   counts are those of the lock-step run.  Synchronises; returns DDQ_OK when
- *   every system met |b~_e - D_S x_e| <= tol |b|, DDQ_NOT_CONVERGED otherwise.
+ *   counts are those of the lock-step run.  The stopping rule is that of
+ *   ddq_oe_gmres_solve: after the restarts have brought every system to
+ *   |b~_e - D_S x_e| <= tol |b|, its full residual |b - D x| is formed in FP64 and a
+ *   system above tol |b| continues with a lowered Schur target.  Synchronises;
+ *   returns DDQ_OK when every system met |b - D x| <= tol |b|, DDQ_NOT_CONVERGED
+ *   otherwise.
  *   Graphs are captured on the first solve and again when m, nu, an omega or a
  *   lattice's buffers change.  One thread at a time per batch; a lattice in a
  *   batch must not be used by other calls while a batch solve runs. */
 typedef struct ddq_batch ddq_batch;
 
 int ddq_batch_create(ddq_lattice* const* lats, const int* nrhs, int nlat, void* hip_stream, ddq_batch** out);
+int ddq_batch_reserve(ddq_batch* batch, int max_m, int cycle_graph);
 int ddq_batch_solve(ddq_batch* batch, void* const* x, const void* const* b, const ddq_gmres_params* params,
                     const double* omegas, ddq_solve_info* info);
 int ddq_batch_destroy(ddq_batch* batch);
@@ -355,8 +420,8 @@ int ddq_batch_destroy(ddq_batch* batch);
  *   Both the hopping term and the clover term (its leaves and the inverse A_oo^-1)
  *   are differentiated.  accumulate != 0 adds to G / F instead of overwriting.
  *   chi_e, phi_e: FP64 parity vectors.  Needs the canonical links set by
- *   ddq_set_gauge and the clover of ddq_set_clover.  Work buffers (two parity
- *   vectors and V x 54 complex128 insertions) grow on first use. */
+ *   ddq_set_gauge and the clover of ddq_set_clover.  Work space (two parity
+ *   vectors and V x 54 complex128 insertions): DDQ_RESERVE_FORCE of ddq_reserve. */
 int ddq_backward_apply(ddq_lattice* lat, int prec, int nrhs, const void* grad_y_e, void* grad_x_e);
 int ddq_backward_link_force(ddq_lattice* lat, const void* chi_e, const void* phi_e, void* G, void* F,
                             int accumulate);

@@ -14,6 +14,7 @@ LIB_PATH = os.environ.get("DDQ_LIBRARY") or os.path.join(PKG, "libddq.so")
 
 DDQ_F64, DDQ_F32, DDQ_F16, DDQ_BF16 = 0, 1, 2, 3
 DDQ_STORE_F64, DDQ_STORE_F32, DDQ_STORE_F32_LINK12, DDQ_STORE_F16, DDQ_STORE_BF16 = 1, 2, 4, 8, 16
+DDQ_RESERVE_SOLVE, DDQ_RESERVE_FULL, DDQ_RESERVE_SAP, DDQ_RESERVE_FORCE = 1, 2, 4, 8
 STATUS = {
     0: "DDQ_OK", 1: "DDQ_NOT_CONVERGED", -1: "DDQ_ERR_ARG", -2: "DDQ_ERR_STATE", -3: "DDQ_ERR_HIP",
     -4: "DDQ_ERR_OOM", -5: "DDQ_ERR_NOT_PD", -6: "DDQ_ERR_NONFINITE",
@@ -71,7 +72,10 @@ _SIGNATURES = {
     "ddq_tune_multi_rhs": [_P, C.c_int, C.c_int, C.POINTER(MrTile), C.c_int, C.POINTER(C.c_int), C.POINTER(MrTile)],
     "ddq_oe_prepare": [_P, C.c_int, _P, _P],
     "ddq_oe_reconstruct": [_P, C.c_int, _P, _P, _P],
-    "ddq_oe_gmres_solve": [_P, _P, _P, C.POINTER(GmresParams), C.POINTER(SolveInfo)],
+    "ddq_oe_gmres_solve": [_P, C.c_int, _P, _P, C.POINTER(GmresParams), C.POINTER(SolveInfo)],
+    "ddq_reserve": [_P, C.c_int, C.c_int, C.c_uint],
+    "ddq_autotune": [_P, C.c_char_p],
+    "ddq_batch_reserve": [_P, C.c_int, C.c_int],
     "ddq_batch_create": [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, _P, C.POINTER(_P)],
     "ddq_batch_solve": [_P, C.POINTER(_P), C.POINTER(_P), C.POINTER(GmresParams), C.POINTER(C.c_double),
                         C.POINTER(SolveInfo)],

@@ -11,6 +11,11 @@ Tensor layouts (see include/ddq.h):
                 site, (re, im) in the last axis (16-bit storage, FP32 arithmetic)
 The arithmetic of a call follows the dtype: complex128 -> FP64, complex64 -> FP32,
 float16 / bfloat16 -> 16-bit storage with FP32 arithmetic.
+
+Work space: the library allocates only in its set-up and reservation calls.  The
+helpers below call ``reserve`` with what the call needs before making it (a no-op
+once the lattice holds that much), so Python users need not; callers of the C ABI
+reserve themselves.
 """
 from __future__ import annotations
 
@@ -19,8 +24,9 @@ import ctypes as C
 import torch
 
 from . import _lib
-from ._lib import (DDQ_BF16, DDQ_F16, DDQ_F32, DDQ_F64, DDQ_STORE_BF16, DDQ_STORE_F16, DDQ_STORE_F32,
-                   DDQ_STORE_F32_LINK12, DDQ_STORE_F64, DDQError, GmresParams, SolveInfo, check, lib)
+from ._lib import (DDQ_BF16, DDQ_F16, DDQ_F32, DDQ_F64, DDQ_RESERVE_FORCE, DDQ_RESERVE_FULL, DDQ_RESERVE_SAP,
+                   DDQ_RESERVE_SOLVE, DDQ_STORE_BF16, DDQ_STORE_F16, DDQ_STORE_F32, DDQ_STORE_F32_LINK12,
+                   DDQ_STORE_F64, DDQError, GmresParams, SolveInfo, check, lib)
 
 __all__ = [
     "Lattice", "DDQError", "create_lattice", "destroy_lattice", "set_gauge", "set_clover", "get_clover",
@@ -28,7 +34,9 @@ __all__ = [
     "oe_prepare", "oe_reconstruct", "oe_gmres_solve", "parity_vector", "profile_begin", "profile_end",
     "stream_copy", "stencil_stream", "apply_dirac", "oe_smoother", "sap_smooth", "fgmres_solve", "fgmres_sap_solve", "backward_apply", "backward_link_force", "convert_parity",
     "CoarseOperator",
-    "Batch", "batch_create", "batch_solve", "batch_destroy", "set_multi_rhs_tile", "tune_multi_rhs",
+    "Batch", "batch_create", "batch_reserve", "batch_solve", "batch_destroy", "set_multi_rhs_tile",
+    "tune_multi_rhs", "autotune", "reserve", "DDQ_RESERVE_SOLVE", "DDQ_RESERVE_FULL", "DDQ_RESERVE_SAP",
+    "DDQ_RESERVE_FORCE",
     "DDQ_F64", "DDQ_F32", "DDQ_F16", "DDQ_BF16",
 ]
 
@@ -124,6 +132,18 @@ def set_gauge(lat: Lattice, U: torch.Tensor, store=(DDQ_F64, DDQ_F32), link12: b
         torch.cuda.current_stream(lat.device).synchronize()
 
 
+def reserve(lat: Lattice, max_nrhs: int = 1, max_m: int = 0, what: int = 0) -> None:
+    """Work space for later calls (grown, never shrunk): max_nrhs right-hand sides,
+    cycle length max_m, what = DDQ_RESERVE_* flags."""
+    check(lib().ddq_reserve(lat.handle, int(max_nrhs), int(max_m), int(what)), "ddq_reserve")
+
+
+def autotune(lat: Lattice, cache_json_path: str) -> None:
+    """Load the cached multi-right-hand-side tiles of this lattice and device, then
+    save the lattice's tiles (see ddq_autotune)."""
+    check(lib().ddq_autotune(lat.handle, str(cache_json_path).encode()), "ddq_autotune")
+
+
 def set_clover(lat: Lattice, c_sw: float, m0: float) -> None:
     lat.sync_stream()
     check(lib().ddq_set_clover(lat.handle, float(c_sw), float(m0)), "ddq_set_clover")
@@ -206,6 +226,7 @@ def apply_schur(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor = None, dagge
     n = _nrhs_parity(lat, x_e)
     if y_e is None:
         y_e = torch.empty_like(x_e)
+    reserve(lat, n)
     lat.sync_stream()
     check(lib().ddq_apply_schur(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(y_e, "y_e"), int(bool(dagger))),
           "ddq_apply_schur")
@@ -217,6 +238,7 @@ def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweep
     n = _nrhs_parity(lat, x_e)
     if b_e.dtype != x_e.dtype or b_e.shape != x_e.shape:
         raise ValueError("x_e and b_e must match in dtype and shape")
+    reserve(lat, n)
     lat.sync_stream()
     check(lib().ddq_richardson_smooth(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(b_e, "b_e"),
                                       int(nsweeps), float(omega)), "ddq_richardson_smooth")
@@ -259,6 +281,7 @@ def oe_prepare(lat: Lattice, b: torch.Tensor) -> torch.Tensor:
     if b.dtype != torch.complex128:
         raise TypeError("b must be complex128")
     bt = parity_vector(lat, None if b.dim() == 6 else n)
+    reserve(lat, n)
     lat.sync_stream()
     check(lib().ddq_oe_prepare(lat.handle, n, _dev(b, "b"), _dev(bt, "bt_e")), "ddq_oe_prepare")
     return bt
@@ -269,6 +292,7 @@ def oe_reconstruct(lat: Lattice, x_e: torch.Tensor, b: torch.Tensor) -> torch.Te
     if b.dtype != torch.complex128 or x_e.dtype != torch.complex128:
         raise TypeError("x_e and b must be complex128")
     x = torch.empty_like(b)
+    reserve(lat, n)
     lat.sync_stream()
     check(lib().ddq_oe_reconstruct(lat.handle, n, _dev(x_e, "x_e"), _dev(b, "b"), _dev(x, "x")),
           "ddq_oe_reconstruct")
@@ -278,18 +302,22 @@ def oe_reconstruct(lat: Lattice, x_e: torch.Tensor, b: torch.Tensor) -> torch.Te
 def oe_gmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int = 30, max_cycles: int = 100,
                    tol: float = 1e-10, inner_prec: int = DDQ_F64, smoother_sweeps: int = 0, omega: float = 0.0,
                    inner_reduction: float = 0.0, smoother_prec: int = None, orth_passes: int = 2):
-    """Odd-even GMRES(m) of Alg. 2 with eq. 2 around it.  Returns (x, info, converged)."""
-    if b.dtype != torch.complex128 or tuple(b.shape) != lat.full_shape:
-        raise ValueError(f"b must be complex128 of shape {lat.full_shape}")
+    """Odd-even GMRES(m) of Alg. 2 with eq. 2 around it, to |b - D x| <= tol |b|.  b: one
+    full vector or [nrhs, ...] (solved one after the other).  Returns (x, info,
+    converged): info a dict (one right-hand side) or a list of dicts, converged True
+    when every system met tol."""
+    n = _full_nrhs(lat, b, "b")
     x = torch.zeros_like(b) if x0 is None else x0.clone()
     p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
                     float(inner_reduction), int(inner_prec if smoother_prec is None else smoother_prec),
                     int(orth_passes))
-    info = SolveInfo()
+    info = (SolveInfo * n)()
+    reserve(lat, 1, m, DDQ_RESERVE_SOLVE)
     lat.sync_stream()
-    st = check(lib().ddq_oe_gmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
+    st = check(lib().ddq_oe_gmres_solve(lat.handle, n, _dev(x, "x"), _dev(b, "b"), C.byref(p), info),
                "ddq_oe_gmres_solve", allow=(0, 1))
-    return x, info.as_dict(), st == 0
+    infos = [i.as_dict() for i in info]
+    return x, (infos[0] if b.dim() == 6 else infos), st == 0
 
 
 def _full_nrhs(lat, v, name):
@@ -307,6 +335,7 @@ def apply_dirac(lat: Lattice, x: torch.Tensor, y: torch.Tensor = None) -> torch.
     n = _full_nrhs(lat, x, "x")
     if y is None:
         y = torch.empty_like(x)
+    reserve(lat, n, 0, DDQ_RESERVE_FULL)
     lat.sync_stream()
     check(lib().ddq_apply_dirac(lat.handle, n, _dev(x, "x"), _dev(y, "y")), "ddq_apply_dirac")
     return y
@@ -319,6 +348,7 @@ def oe_smoother(lat: Lattice, r: torch.Tensor, nsweeps: int, omega: float, prec:
     n = _full_nrhs(lat, r, "r")
     if z is None:
         z = torch.empty_like(r)
+    reserve(lat, n, 0, DDQ_RESERVE_FULL)
     lat.sync_stream()
     check(lib().ddq_oe_smoother(lat.handle, n, _dev(r, "r"), _dev(z, "z"), int(nsweeps), float(omega), int(prec)),
           "ddq_oe_smoother")
@@ -330,6 +360,7 @@ def sap_smooth(lat: Lattice, b: torch.Tensor, x: torch.Tensor, n: int, m: int, p
     block solves in prec (DDQ_F64 or DDQ_F32)."""
     if _full_nrhs(lat, b, "b") != 1 or _full_nrhs(lat, x, "x") != 1:
         raise ValueError("one right-hand side")
+    reserve(lat, 1, 0, DDQ_RESERVE_SAP)
     lat.sync_stream()
     check(lib().ddq_sap_smooth(lat.handle, int(prec), _dev(x, "x"), _dev(b, "b"), int(n), int(m)), "ddq_sap_smooth")
     return x
@@ -346,6 +377,7 @@ def fgmres_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: int 
     p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), int(smoother_sweeps), float(omega),
                     float(inner_reduction), int(inner_prec), int(orth_passes))
     info = SolveInfo()
+    reserve(lat, 1, m, DDQ_RESERVE_FULL)
     lat.sync_stream()
     st = check(lib().ddq_fgmres_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), C.byref(info)),
                "ddq_fgmres_solve", allow=(0, 1))
@@ -363,6 +395,7 @@ def fgmres_sap_solve(lat: Lattice, b: torch.Tensor, x0: torch.Tensor = None, m: 
     p = GmresParams(int(m), int(max_cycles), float(tol), int(inner_prec), 0, 0.0, float(inner_reduction),
                     int(inner_prec), int(orth_passes))
     info = SolveInfo()
+    reserve(lat, 1, m, DDQ_RESERVE_SAP)
     lat.sync_stream()
     st = check(lib().ddq_fgmres_sap_solve(lat.handle, _dev(x, "x"), _dev(b, "b"), C.byref(p), int(sap_n),
                                           int(sap_m), C.byref(info)), "ddq_fgmres_sap_solve", allow=(0, 1))
@@ -403,6 +436,11 @@ def batch_create(lats, nrhs) -> Batch:
     return Batch(h, lats, nrhs)
 
 
+def batch_reserve(batch: Batch, max_m: int, cycle_graph: bool = False) -> None:
+    """Work space of later solves with m <= max_m (and the tuning of untuned lattices)."""
+    check(lib().ddq_batch_reserve(batch.handle, int(max_m), int(bool(cycle_graph))), "ddq_batch_reserve")
+
+
 def batch_destroy(batch: Batch) -> None:
     if batch.handle is not None:
         check(lib().ddq_batch_destroy(batch.handle), "ddq_batch_destroy")
@@ -432,6 +470,7 @@ def batch_solve(batch: Batch, bs, x0s=None, m: int = 50, max_cycles: int = 100, 
     p = GmresParams(int(m), int(max_cycles), float(tol), DDQ_F32, int(smoother_sweeps), om[0],
                     float(inner_reduction), int(smoother_prec), int(orth_passes), int(bool(cycle_graph)))
     infos = (SolveInfo * sum(batch.nrhs))()
+    batch_reserve(batch, m, cycle_graph)
     st = check(lib().ddq_batch_solve(batch.handle, xp, bp, C.byref(p), op, infos), "ddq_batch_solve", allow=(0, 1))
     return xs, [i.as_dict() for i in infos], st == 0
 
@@ -489,6 +528,7 @@ def backward_apply(lat: Lattice, grad_y_e: torch.Tensor, out: torch.Tensor = Non
     n = _nrhs_parity(lat, grad_y_e)
     if out is None:
         out = torch.empty_like(grad_y_e)
+    reserve(lat, n)
     lat.sync_stream()
     check(lib().ddq_backward_apply(lat.handle, _prec(grad_y_e), n, _dev(grad_y_e, "grad_y_e"), _dev(out, "grad_x_e")),
           "ddq_backward_apply")
@@ -512,6 +552,7 @@ def backward_link_force(lat: Lattice, chi_e: torch.Tensor, phi_e: torch.Tensor, 
         G = torch.empty(shp + (3, 3), dtype=torch.complex128, device=lat.device)
     if want_F and F is None:
         F = torch.empty(shp + (8,), dtype=torch.float64, device=lat.device)
+    reserve(lat, 1, 0, DDQ_RESERVE_FORCE)
     lat.sync_stream()
     check(lib().ddq_backward_link_force(lat.handle, _dev(chi_e, "chi_e"), _dev(phi_e, "phi_e"),
                                         _dev(G, "G") if want_G else None, _dev(F, "F") if want_F else None,

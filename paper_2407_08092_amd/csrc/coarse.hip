@@ -98,8 +98,8 @@ __device__ __forceinline__ int coarse_nbr(const CoarseGeo& g, int x, int d) {
 template <typename R, typename S>
 __global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __restrict__ src,
                                                      typename Store4<S>::v* __restrict__ dst, long long n_el) {
-  const long long e = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (e >= n_el) return;
+  // grid-stride: the grid is capped so that a dispatch stays below 2^32 work-items
+  for (long long e = (long long)blockIdx.x * 256 + threadIdx.x; e < n_el; e += (long long)gridDim.x * 256) {
   const int lane = (int)(e & 63);
   long long r = e >> 6;
   const int t = (int)(r % g.MT);
@@ -117,6 +117,11 @@ __global__ void __launch_bounds__(256) k_coarse_pack(CoarseGeo g, const R* __res
     o[2 * h + 1] = to_store<S>(in ? blk[2 * ((long long)i * g.n2 + k) + 1] : R(0));
   }
   dst[e] = typename Store4<S>::v{o[0], o[1], o[2], o[3]};
+  // the store reads its data registers after issue; the next iteration rewrites them
+  __builtin_amdgcn_sched_barrier(0);
+  __builtin_amdgcn_s_waitcnt(0xCF0F);  // expcnt(0)
+  __builtin_amdgcn_sched_barrier(0);
+  }
 }
 
 // operands of one pair of k-slices: the packed block slice and the right-hand sides' rows
@@ -310,7 +315,8 @@ hipError_t launch_g(const CoarseGeo& g, int nrhs, int tn, const void* A, const f
 template <typename S>
 hipError_t launch_pack(const CoarseGeo& g, int src_f64, const void* src, void* dst, hipStream_t s) {
   const long long n_el = (long long)g.vc * 9 * g.KP * g.MT * 64;
-  const dim3 grid((unsigned)((n_el + 255) / 256)), block(256);
+  const long long blocks = (n_el + 255) / 256;
+  const dim3 grid((unsigned)(blocks < (1LL << 20) ? blocks : (1LL << 20))), block(256);
   typename Store4<S>::v* d = (typename Store4<S>::v*)dst;
   if (src_f64)
     hipLaunchKernelGGL((k_coarse_pack<double, S>), grid, block, 0, s, g, (const double*)src, d, n_el);

@@ -103,3 +103,30 @@ def test_coarse_sizes_and_bad_arguments_on_host():
     assert L.ddq_coarse_pack_blocks(cd, 8, 1, 1, fake, C.c_void_p((1 << 20) + 1024), None) == -1  # overlap
     assert b"overlap" in L.ddq_last_error()
     assert L.ddq_coarse_apply(cd, 8, 1, 16, None, fake, fake, 0, 0, None) == -1
+
+
+def test_lattice_beyond_the_descriptor_limit_refused():
+    # 56^3 x 112: V/2 = 9,834,496 sites, the FP64 clover field of a parity would need
+    # 5.7 GB in one 32-bit buffer descriptor
+    L = _lib.lib()
+    h = C.c_void_p()
+    assert L.ddq_create_lattice((C.c_int * 4)(56, 56, 56, 112), 1, None, C.byref(h)) == -1
+    assert h.value is None
+    assert b"4 GiB" in L.ddq_last_error()
+
+
+def test_reservation_and_cache_calls_reject_null_on_host():
+    L = _lib.lib()
+    assert L.ddq_reserve(None, 1, 0, 0) == -1
+    assert L.ddq_autotune(None, b"/tmp/x.json") == -1
+    assert L.ddq_batch_reserve(None, 10, 0) == -1
+    assert L.ddq_oe_gmres_solve(None, 1, None, None, None, None) == -1
+
+
+def test_coarse_pack_of_many_sites_is_accepted_on_host():
+    # 2^22 coarse sites at N_v = 32: the pack has 2^22 * 9 * 8 * 4 * 64 > 2^32 lane elements,
+    # which the grid-stride pack kernel covers; only the site bound (2^25) limits the size
+    L = _lib.lib()
+    nb = C.c_int64()
+    assert L.ddq_coarse_packed_bytes((C.c_int * 4)(64, 64, 32, 32), 32, 1, C.byref(nb)) == 0
+    assert nb.value == (1 << 22) * 9 * 8 * 4 * 64 * 16

@@ -5,7 +5,9 @@ through closed forms that hold at any size, so no oracle run is needed:
   plane waves, and after k Richardson sweeps from zero on an eigenvector with
   eigenvalue mu, x_k = (1 - (1 - omega mu)^k) / mu * b (Alg. 4, Sect. 2.4.5);
 * pure gauge U_mu(x) = Om(x) Om(x + mu)^H: D_S (Om psi_e) = Om (closed form psi_e),
-  which checks link placement, daggering and the clover vanishing at full size.
+  which checks link placement, daggering and the clover vanishing at full size;
+* gauge covariance with random links and a non-trivial clover: the clover blocks
+  and D_S rotate with a random site field Om.
 The even-site coordinates are recomputed here in torch, independently of the
 library's indexing.
 """
@@ -119,3 +121,60 @@ def test_pure_gauge_fullsize():
 
     got = api.apply_schur(lat, rot(psi))
     assert relerr(got, rot(expect)) < 1e-12
+
+
+def test_gauge_covariance_random_links_fullsize():
+    """Random links (eps 0.5, c_sw 1.2, m0 -0.25) at the benchmarked size: under
+    U'_mu(x) = Om(x) U_mu(x) Om(x + mu)^H the clover blocks rotate, A' = Om A Om^H, and
+    D_S'(Om psi) = Om (D_S psi) (eq. 3 with the 6x6 clover blocks of Sect. 2.4.5), so
+    the link and clover-slot indexing of every site is exercised with a non-trivial
+    clover, in FP64 (1e-12) and FP32 (1e-5)."""
+    dev = "cuda"
+    x, y, z, t = even_coords(DIMS, dev)
+    lx, ly, lz, lt = DIMS
+    lexi = x + lx * (y + ly * (z + lz * t))
+    del x, y, z, t
+    psi = torch.from_numpy(synth.gaussian_complex((12, lexi.numel()), 303)).to(dev)
+    U = synth.gauge_field(DIMS, 0.5, 301, device=dev)
+    every = 4099  # sampled sites of the clover comparison
+
+    def applies(lat, v):
+        y64 = api.apply_schur(lat, v)
+        y32 = api.apply_schur(lat, api.convert_parity(lat, v, torch.complex64))
+        return y64, api.convert_parity(lat, y32, torch.complex128)
+
+    lat = api.create_lattice(DIMS)
+    api.set_gauge(lat, U)
+    api.set_clover(lat, 1.2, M0)
+    y64, y32 = applies(lat, psi)
+    A_ee, _ = api.get_clover(lat)
+    A_sample = A_ee[::every].clone()
+    del A_ee, lat
+    torch.cuda.empty_cache()
+    Om = synth.random_su3_sites(DIMS, 304, device=dev)
+    for mu, axis in enumerate((3, 2, 1, 0)):
+        U[..., mu, :, :] = Om @ U[..., mu, :, :] @ torch.roll(Om, -1, dims=axis).conj().transpose(-1, -2)
+    Om_e = Om.reshape(-1, 3, 3)[lexi]  # [V/2, 3, 3]
+    del Om
+
+    def rot(v):  # Om(x) on the colour index of an ABI-layout vector [12, V/2]
+        w = v.reshape(4, 3, -1).permute(2, 0, 1)
+        return torch.einsum("nab,nsb->nsa", Om_e, w).permute(1, 2, 0).reshape(12, -1).contiguous()
+
+    lat = api.create_lattice(DIMS)
+    api.set_gauge(lat, U)
+    del U
+    api.set_clover(lat, 1.2, M0)
+    # A' = Om A Om^H on both 6x6 blocks (Om on the colour index of each spin)
+    A2, _ = api.get_clover(lat)
+    Os = Om_e[::every]
+    O6 = torch.zeros((Os.shape[0], 1, 6, 6), dtype=torch.complex128, device=dev)
+    O6[:, 0, :3, :3] = Os
+    O6[:, 0, 3:, 3:] = Os
+    expect_A = O6 @ A_sample @ O6.conj().transpose(-1, -2)
+    assert ((A2[::every] - expect_A).abs().max() / A_sample.abs().max()).item() < 1e-13
+    del A2
+    y64b, y32b = applies(lat, rot(psi))
+    assert relerr(y64b, rot(y64)) < 1e-12
+    assert relerr(y32b, rot(y64)) < 1e-5
+    assert relerr(rot(y32), y64b) < 1e-5

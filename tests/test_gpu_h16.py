@@ -99,7 +99,7 @@ def test_gmres_with_16bit_smoother(dtype):
                                      smoother_prec=PREC[dtype])
     assert ok, info
     res = solvers.vnorm(b - c.op.D(x.cpu().numpy())) / solvers.vnorm(b)
-    assert res <= 1.5e-10
+    assert res <= 1e-10
 
 
 def test_batch_with_16bit_smoother():
@@ -113,7 +113,7 @@ def test_batch_with_16bit_smoother():
     for c, b, x in ((c1, bs[0], xs[0]), (c2, bs[1], xs[1])):
         xh = x.cpu().numpy()
         for r in range(b.shape[0]):
-            assert solvers.vnorm(b[r] - c.op.D(xh[r])) / solvers.vnorm(b[r]) <= 1.5e-10
+            assert solvers.vnorm(b[r] - c.op.D(xh[r])) / solvers.vnorm(b[r]) <= 1e-10
 
 
 def test_16bit_errors():

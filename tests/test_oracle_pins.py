@@ -437,7 +437,7 @@ def test_oe_solve_matches_full_solve():
     b = synth.gaussian_spinor(dims, 142)
     x, res = solvers.oe_solve(op, b, 30, 100, 1e-10)
     assert res.converged
-    assert solvers.vnorm(b - op.D(x)) <= 1.5e-10 * solvers.vnorm(b)
+    assert solvers.vnorm(b - op.D(x)) <= 1e-10 * solvers.vnorm(b)
     x_ref = np.linalg.solve(sparse_D(op).toarray(), b.ravel()).reshape(b.shape)
     assert rel_err(x, x_ref) < 1e-8
 

@@ -463,12 +463,17 @@ def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
             nbytes = groups * 9 * n2 * n2 * 8 * vc + 2 * n2 * nrhs * 8 * vc
             tf = flops / (ms * 1e-3) / 1e12
             gbs = nbytes / (ms * 1e-3) / 1e9
-            # the default product form is Gauss's: 3 real products (6 flops) per complex
-            # multiply-add on the matrix cores, against the 8 algorithmic flops
-            out[f"nv{nv}_rhs{nrhs}"] = {"ms": round(ms, 4), "TFLOPs": round(tf, 1),
-                                        "frac_mfma_peak": round(tf / MFMA_F32_PEAK_TFLOPS, 3),
-                                        "mfma_TFLOPs_executed": round(tf * 6 / 8, 1),
-                                        "frac_mfma_peak_executed": round(tf * 6 / 8 / MFMA_F32_PEAK_TFLOPS, 3),
+            # the matrix-core work actually issued: per site, 9 blocks x (16-row tiles) x
+            # (4-wide k-slices) x (16-column right-hand-side tiles) x real products per
+            # complex one (Gauss's 3 by default, 4 in the schoolbook form) x 2048 flops of
+            # one v_mfma_f32_16x16x4_f32, padding included; its fraction of the FP32 matrix
+            # peak cannot exceed 1
+            def issued(ms_, products):
+                per_site = 9 * ((n2 + 15) // 16) * 2 * ((n2 + 7) // 8) * tiles * products * 2048
+                return per_site * vc / (ms_ * 1e-3) / 1e12
+            out[f"nv{nv}_rhs{nrhs}"] = {"ms": round(ms, 4), "TFLOPs_algorithmic": round(tf, 1),
+                                        "mfma_TFLOPs_issued": round(issued(ms, 3), 1),
+                                        "frac_mfma_peak": round(issued(ms, 3) / MFMA_F32_PEAK_TFLOPS, 3),
                                         "GBs": round(gbs, 1), "frac_hbm_peak": round(gbs / HBM_PEAK_GBS, 3),
                                         "flop_per_byte": round(flops / nbytes, 2)}
             if nrhs == 64:  # the schoolbook form (4 real products) for comparison
@@ -482,8 +487,9 @@ def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
                 torch.cuda.synchronize()
                 ms4 = e0.elapsed_time(e1) / reps
                 out[f"nv{nv}_rhs{nrhs}"]["four_products"] = {
-                    "ms": round(ms4, 4), "TFLOPs": round(flops / (ms4 * 1e-3) / 1e12, 1),
-                    "frac_mfma_peak": round(flops / (ms4 * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS, 3)}
+                    "ms": round(ms4, 4), "TFLOPs_algorithmic": round(flops / (ms4 * 1e-3) / 1e12, 1),
+                    "mfma_TFLOPs_issued": round(issued(ms4, 4), 1),
+                    "frac_mfma_peak": round(issued(ms4, 4) / MFMA_F32_PEAK_TFLOPS, 3)}
             if op16 is not None:  # FP16 block storage: half the block bytes, FP32 arithmetic
                 for _ in range(2):
                     op16.apply(v, y)
@@ -496,8 +502,9 @@ def coarse_operator(api, torch, dev, nvs=(24, 20), reps=10):
                 ms16 = e0.elapsed_time(e1) / reps
                 nbytes16 = groups * 9 * n2 * n2 * 4 * vc + 2 * n2 * nrhs * 8 * vc
                 out[f"nv{nv}_rhs{nrhs}"]["f16_blocks"] = {
-                    "ms": round(ms16, 4), "TFLOPs": round(flops / (ms16 * 1e-3) / 1e12, 1),
-                    "frac_mfma_peak": round(flops / (ms16 * 1e-3) / 1e12 / MFMA_F32_PEAK_TFLOPS, 3),
+                    "ms": round(ms16, 4), "TFLOPs_algorithmic": round(flops / (ms16 * 1e-3) / 1e12, 1),
+                    "mfma_TFLOPs_issued": round(issued(ms16, 3), 1),
+                    "frac_mfma_peak": round(issued(ms16, 3) / MFMA_F32_PEAK_TFLOPS, 3),
                     "GBs": round(nbytes16 / (ms16 * 1e-3) / 1e9, 1)}
             log(f"coarse N_v={nv} nrhs={nrhs}: {out[f'nv{nv}_rhs{nrhs}']}")
             del v, y
@@ -609,7 +616,7 @@ def mixed_vs_fp64(api, synth, torch, dev):
     fp64_best = min(v["time_s"] for k, v in runs.items() if k.startswith("fp64") and v["converged"])
     mixed_best = min(v["time_s"] for k, v in runs.items() if k.startswith("mixed") and v["converged"])
     api.destroy_lattice(lat)
-    return {"workload": "16^3x32, eps 0.5, c_sw 1.0, m0 -0.2, Gaussian b, tol 1e-10 (|b~_e - D_S x_e| / |b|)",
+    return {"workload": "16^3x32, eps 0.5, c_sw 1.0, m0 -0.2, Gaussian b, tol 1e-10 (|b - D x| / |b|, FP64)",
             "runs": runs, "fp64_best_s": fp64_best, "mixed_best_s": mixed_best,
             "speedup": round(fp64_best / mixed_best, 3),
             "fgmres_full_oe_smoother": full}

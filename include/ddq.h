@@ -190,6 +190,13 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
  *            L2; the order of the one-right-hand-side kernels).  The 16-bit
  *            kernels use the xcd_map of the tile set for the same nrhs, slab
  *            order if none.
+ *   passes   (nb >= 1) the right-hand sides are split into this many consecutive
+ *            groups, one launch each: links and clover are read once per pass while
+ *            the neighbour rows of fewer right-hand sides compete for the L2; must
+ *            divide nrhs, with nb dividing nrhs / passes
+ *   lds_kb   (nb >= 1) LDS requested per workgroup (0 .. 160 KB; the kernel uses none):
+ *            caps the workgroups resident on a compute unit, and so the sites whose
+ *            neighbour rows are in flight on an XCD at once
  *   ms       (tuner output) mean time of one Richardson sweep with this tile
  * ddq_set_multi_rhs_tile: use `tile` for launches with nrhs right-hand sides.
  * ddq_tune_multi_rhs: the autotuner.  Times one FP32 Richardson sweep (kernel A +
@@ -204,6 +211,8 @@ typedef struct {
   int waves;
   int xcd_map;
   double ms;
+  int passes;
+  int lds_kb;
 } ddq_mr_tile;
 
 int ddq_set_multi_rhs_tile(ddq_lattice* lat, int nrhs, const ddq_mr_tile* tile);
@@ -211,7 +220,7 @@ int ddq_tune_multi_rhs(ddq_lattice* lat, int nrhs, int reps, ddq_mr_tile* result
                        int* n_results, ddq_mr_tile* chosen);
 
 /* Persisted tiles.  cache_json_path names a JSON file {"ddq_autotune": 1, "tiles":
- * [{"key", "nrhs", "nb", "waves", "xcd_map", "ms"}, ...]} (created when absent), one
+ * [{"key", "nrhs", "nb", "waves", "xcd_map", "passes", "lds_kb", "ms"}, ...]} (created when absent), one
  * entry per line; the key is the device (architecture name and compute-unit count),
  * the lattice extents and the FP32 link storage ("link12" / "link18").  The call sets
  * every cached tile of the lattice's key for a right-hand-side count the lattice has

@@ -42,7 +42,8 @@ class SolveInfo(C.Structure):
 
 
 class MrTile(C.Structure):
-    _fields_ = [("nb", C.c_int), ("waves", C.c_int), ("xcd_map", C.c_int), ("ms", C.c_double)]
+    _fields_ = [("nb", C.c_int), ("waves", C.c_int), ("xcd_map", C.c_int), ("ms", C.c_double),
+                ("passes", C.c_int), ("lds_kb", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -245,24 +245,27 @@ def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweep
     return x_e
 
 
-def set_multi_rhs_tile(lat: Lattice, nrhs: int, nb: int, waves: int = 4, xcd_map: int = 0) -> None:
+def set_multi_rhs_tile(lat: Lattice, nrhs: int, nb: int, waves: int = 4, xcd_map: int = 0, passes: int = 1,
+                       lds_kb: int = 0) -> None:
     """Tile of the FP32 multi-right-hand-side stencil for launches of nrhs right-hand
     sides (nb = 0: one right-hand side per thread; xcd_map: 0 dispatcher order, c > 0
-    chunks of c site blocks per XCD, -1 slab order)."""
-    t = _lib.MrTile(int(nb), int(waves), int(xcd_map), 0.0)
+    chunks of c site blocks per XCD, -1 slab order; passes: launches over consecutive
+    groups of right-hand sides; lds_kb: LDS per workgroup capping the resident ones)."""
+    t = _lib.MrTile(int(nb), int(waves), int(xcd_map), 0.0, int(passes), int(lds_kb))
     check(lib().ddq_set_multi_rhs_tile(lat.handle, int(nrhs), C.byref(t)), "ddq_set_multi_rhs_tile")
 
 
 def tune_multi_rhs(lat: Lattice, nrhs: int, reps: int = 5):
     """Time every tile for nrhs right-hand sides and keep the fastest.  Returns
     (chosen, candidates) as dicts."""
-    arr = (_lib.MrTile * 64)()
+    arr = (_lib.MrTile * 512)()
     n = C.c_int()
     best = _lib.MrTile()
+    reserve(lat, nrhs)
     lat.sync_stream()
-    check(lib().ddq_tune_multi_rhs(lat.handle, int(nrhs), int(reps), arr, 64, C.byref(n), C.byref(best)),
+    check(lib().ddq_tune_multi_rhs(lat.handle, int(nrhs), int(reps), arr, 512, C.byref(n), C.byref(best)),
           "ddq_tune_multi_rhs")
-    return best.as_dict(), [arr[k].as_dict() for k in range(min(n.value, 64))]
+    return best.as_dict(), [arr[k].as_dict() for k in range(min(n.value, 512))]
 
 
 def estimate_lambda_max(lat: Lattice, iters: int, v0: torch.Tensor) -> float:

@@ -294,7 +294,8 @@ hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int 
   if (prec == DDQ_F32 && nrhs > 1) {
     const MrTile* t = L->tile_for(nrhs);
     if (t && hop_rb_supported(mode, dag, nrhs, *t))
-      tile = "_nb" + std::to_string(t->nb) + "g" + std::to_string(t->g) + (t->xmap ? "x" + std::to_string(t->xmap) : "");
+      tile = "_nb" + std::to_string(t->nb) + "g" + std::to_string(t->g) + (t->xmap ? "x" + std::to_string(t->xmap) : "") +
+             (t->passes > 1 ? "p" + std::to_string(t->passes) : "") + (t->lds_kb ? "l" + std::to_string(t->lds_kb) : "");
   }
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
                      (dag ? "_dag" : "") + (nrhs > 1 ? "_x" + std::to_string(nrhs) : "") + tile;
@@ -771,8 +772,12 @@ int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
   t.nb = tile->nb;
   t.g = tile->waves;
   t.xmap = tile->xcd_map;
-  if ((t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t)) || t.xmap < XMAP_SLAB || t.xmap > 1024)
-    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs with nb <= 4, waves 1 or 4, xcd_map -1..1024");
+  t.passes = tile->passes < 1 ? 1 : tile->passes;
+  t.lds_kb = tile->lds_kb;
+  if ((t.nb != 0 && !hop_rb_supported(M_RICH, false, nrhs, t)) || t.xmap < XMAP_SLAB || t.xmap > 1024 ||
+      (t.nb == 0 && (t.passes != 1 || t.lds_kb != 0)))
+    return fail(DDQ_ERR_ARG, "tile: nb must be 0 or divide nrhs / passes with nb <= 4, waves 1 or 4, xcd_map "
+                             "-1..1024, passes dividing nrhs, lds_kb 0..160 (passes 1, lds_kb 0 for nb = 0)");
   for (auto& e : L->tiles)
     if (e.first == nrhs) {
       e.second = t;
@@ -796,11 +801,19 @@ int ddq_tune_multi_rhs(ddq_lattice* L, int nrhs, int reps, ddq_mr_tile* results,
   HIPCHK(hipMemsetAsync(x, 0, 2 * N * 8, L->stream));
   std::vector<ddq_mr_tile> cand;
   for (int xm : {XMAP_SLAB, 0})  // one right-hand side per thread, the 64-site x 4 mapping
-    cand.push_back({0, 4, xm, 0.0});
+    cand.push_back({0, 4, xm, 0.0, 1, 0});
   for (int nb = 1; nb <= MR_MAX_NB; ++nb)
     if (nrhs % nb == 0)
       for (int g : {1, 4})
-        for (int xm : {XMAP_SLAB, 0, 1, 8, 32}) cand.push_back({nb, g, xm, 0.0});
+        for (int xm : {XMAP_SLAB, 0, 1, 8, 32}) cand.push_back({nb, g, xm, 0.0, 1, 0});
+  // fewer right-hand sides or fewer workgroups in flight: slab order, RHS passes and an
+  // LDS cap on the resident workgroups
+  for (int nb = 1; nb <= MR_MAX_NB; ++nb)
+    for (int passes : {1, 2, 3, 4})
+      if (nrhs % passes == 0 && (nrhs / passes) % nb == 0 && nrhs / passes >= 2)
+        for (int g : {1, 4})
+          for (int lds : {0, 48, 64, 96})
+            if (passes > 1 || lds > 0) cand.push_back({nb, g, XMAP_SLAB, 0.0, passes, lds});
   hipEvent_t e0 = nullptr, e1 = nullptr;
   HIPCHK(hipEventCreate(&e0));
   hipError_t he = hipEventCreate(&e1);
@@ -866,6 +879,12 @@ bool parse_tile_line(const std::string& line, TileEntry& e) {
   const size_t b = line.find('"', a + k0.size());
   if (b == std::string::npos) return false;
   e.key = line.substr(a + k0.size(), b - a - k0.size());
+  e.t.passes = 1;
+  e.t.lds_kb = 0;
+  if (std::sscanf(line.c_str() + b + 1,
+                  ", \"nrhs\": %d, \"nb\": %d, \"waves\": %d, \"xcd_map\": %d, \"passes\": %d, \"lds_kb\": %d, \"ms\": %lf",
+                  &e.nrhs, &e.t.nb, &e.t.waves, &e.t.xcd_map, &e.t.passes, &e.t.lds_kb, &e.t.ms) == 7)
+    return true;
   return std::sscanf(line.c_str() + b + 1, ", \"nrhs\": %d, \"nb\": %d, \"waves\": %d, \"xcd_map\": %d, \"ms\": %lf",
                      &e.nrhs, &e.t.nb, &e.t.waves, &e.t.xcd_map, &e.t.ms) == 5;
 }
@@ -906,7 +925,7 @@ int ddq_autotune(ddq_lattice* L, const char* cache_json_path) {
     TileEntry e;
     e.key = key;
     e.nrhs = t.first;
-    e.t = {t.second.nb, t.second.g, t.second.xmap, 0.0};
+    e.t = {t.second.nb, t.second.g, t.second.xmap, 0.0, t.second.passes, t.second.lds_kb};
     for (const auto& m : L->tile_ms)
       if (m.first == t.first) e.t.ms = m.second;
     out.push_back(e);
@@ -916,9 +935,11 @@ int ddq_autotune(ddq_lattice* L, const char* cache_json_path) {
   if (!f) return fail(DDQ_ERR_ARG, std::string("cannot write ") + tmp);
   std::fprintf(f, "{\"ddq_autotune\": 1, \"tiles\": [\n");
   for (size_t k = 0; k < out.size(); ++k)
-    std::fprintf(f, " {\"key\": \"%s\", \"nrhs\": %d, \"nb\": %d, \"waves\": %d, \"xcd_map\": %d, \"ms\": %.6g}%s\n",
-                 out[k].key.c_str(), out[k].nrhs, out[k].t.nb, out[k].t.waves, out[k].t.xcd_map, out[k].t.ms,
-                 k + 1 < out.size() ? "," : "");
+    std::fprintf(f,
+                 " {\"key\": \"%s\", \"nrhs\": %d, \"nb\": %d, \"waves\": %d, \"xcd_map\": %d, \"passes\": %d, "
+                 "\"lds_kb\": %d, \"ms\": %.6g}%s\n",
+                 out[k].key.c_str(), out[k].nrhs, out[k].t.nb, out[k].t.waves, out[k].t.xcd_map, out[k].t.passes,
+                 out[k].t.lds_kb, out[k].t.ms, k + 1 < out.size() ? "," : "");
   std::fprintf(f, "]}\n");
   const bool ok = std::fclose(f) == 0;
   if (!ok || std::rename(tmp.c_str(), cache_json_path) != 0)
@@ -1883,6 +1904,7 @@ std::vector<uintptr_t> batch_key(const ddq_batch* B, int m, int nu) {
       key.push_back(v);
     const MrTile* t = L->tile_for(S.nrhs);
     key.push_back(t ? (uintptr_t)(1 + t->nb + 8 * t->g + 64 * t->xmap) : 0);
+    key.push_back(t ? (uintptr_t)(t->passes + 16 * t->lds_kb) : 0);
   }
   return key;
 }

@@ -30,10 +30,16 @@ enum HopMode {
 // all right-hand-side groups of a block together, so a block's neighbour rows
 // (+-z, +-t) are mostly read through the same L2 (xmap = 0: the dispatcher's
 // round-robin order; xmap = XMAP_SLAB: slab order, slab_group).
+// passes > 1 splits the right-hand sides into that many consecutive groups, one launch
+// each (links and clover read once per pass, the neighbour rows of fewer right-hand
+// sides in flight); lds_kb > 0 requests that much (unused) LDS per workgroup, which caps
+// the workgroups resident on a compute unit and with them the sites in flight per XCD.
 struct MrTile {
   int nb = 0;
   int g = 1;
   int xmap = 0;
+  int passes = 1;
+  int lds_kb = 0;
 };
 
 // workgroup blk -> (site block sb, right-hand-side group rg) of a launch with gr

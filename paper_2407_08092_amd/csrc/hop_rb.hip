@@ -129,7 +129,8 @@ hop_kernel_rb(HopArgs<float> a) {
 bool hop_rb_supported(int mode, bool dagger, int nrhs, const MrTile& t) {
   if (dagger || nrhs < 2) return false;
   if (mode != M_HOP_CLINV && mode != M_APPLY && mode != M_RICH) return false;
-  if (t.nb < 1 || t.nb > MR_MAX_NB || nrhs % t.nb != 0) return false;
+  if (t.passes < 1 || nrhs % t.passes != 0 || t.lds_kb < 0 || t.lds_kb > 160) return false;
+  if (t.nb < 1 || t.nb > MR_MAX_NB || (nrhs / t.passes) % t.nb != 0) return false;
   if (t.xmap < XMAP_SLAB || t.xmap > 1024) return false;
   return t.g == 1 || t.g == 4;
 }
@@ -140,10 +141,11 @@ static hipError_t rb_launch_g(const HopArgs<float>& a, hipStream_t s) {
   const int gr = (a.nrhs + NB * G - 1) / (NB * G);
   const long long nb = tile_grid_sites(a.g, HOP_BLOCK / G, gr, a.tile.xmap);
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  const unsigned lds = (unsigned)a.tile.lds_kb * 1024u;  // occupancy cap only: the kernel uses no LDS
   if (G == 1)
-    hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 1>), dim3((unsigned)nb), dim3(HOP_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 1>), dim3((unsigned)nb), dim3(HOP_BLOCK), lds, s, a);
   else
-    hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 4>), dim3((unsigned)nb), dim3(HOP_BLOCK), 0, s, a);
+    hipLaunchKernelGGL((hop_kernel_rb<MODE, L12, NB, 4>), dim3((unsigned)nb), dim3(HOP_BLOCK), lds, s, a);
   return hipGetLastError();
 }
 
@@ -165,14 +167,25 @@ static hipError_t rb_launch_mode(const HopArgs<float>& a, hipStream_t s) {
 
 hipError_t launch_hop_rb(const HopArgs<float>& a0, int mode, int nrhs, hipStream_t s) {
   if (!hop_rb_supported(mode, false, nrhs, a0.tile)) return hipErrorInvalidValue;
-  HopArgs<float> a = a0;
-  a.nrhs = nrhs;
-  switch (mode) {
-    case M_HOP_CLINV: return rb_launch_mode<M_HOP_CLINV>(a, s);
-    case M_APPLY: return rb_launch_mode<M_APPLY>(a, s);
-    case M_RICH: return rb_launch_mode<M_RICH>(a, s);
+  const int per = nrhs / a0.tile.passes;
+  for (int p = 0; p < a0.tile.passes; ++p) {
+    // pass p: right-hand sides [p per, (p + 1) per), every vector offset alike
+    HopArgs<float> a = a0;
+    const size_t off = (size_t)p * per * (size_t)a0.rhs_stride;
+    a.in = a0.in + off;
+    a.out = a0.out + off;
+    if (a0.x) a.x = a0.x + off;
+    if (a0.b) a.b = a0.b + off;
+    a.nrhs = per;
+    hipError_t e = hipErrorInvalidValue;
+    switch (mode) {
+      case M_HOP_CLINV: e = rb_launch_mode<M_HOP_CLINV>(a, s); break;
+      case M_APPLY: e = rb_launch_mode<M_APPLY>(a, s); break;
+      case M_RICH: e = rb_launch_mode<M_RICH>(a, s); break;
+    }
+    if (e != hipSuccess) return e;
   }
-  return hipErrorInvalidValue;
+  return hipSuccess;
 }
 
 }  // namespace ddq

@@ -6,7 +6,8 @@ Every tile is covered: nb (right-hand sides per thread) 0..4, one or four
 wavefronts per site block, XCD order off, in chunks of 1, 8, 32 site blocks
 (more chunks than the small lattices have blocks: the padded grid) or slab order
 (t-slices cut into eight pieces of 64-site groups: on these lattices some XCDs get
-none), 18- and 12-real links.
+none), 18- and 12-real links; and tiles that split the right-hand sides into passes or
+request LDS to cap the resident workgroups.
 Lattices 4x6x8x10 (V/2 = 960: 15 blocks of 64 sites, 3.75 of 256) and 6x6x6x10
 (V/2 = 1080: ragged for both) with 12 right-hand sides (divisible by 1, 2, 3, 4).
 """
@@ -25,6 +26,9 @@ pytestmark = pytest.mark.gpu
 NRHS = 12
 DIMS = [(4, 6, 8, 10), (6, 6, 6, 10)]
 TILES = [(0, 4, 0), (0, 4, -1)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
+# right-hand sides split into passes and workgroups capped by an LDS request
+PASS_TILES = [(1, 4, -1, 2, 64), (2, 1, -1, 3, 48), (3, 4, -1, 2, 96), (4, 4, -1, 3, 0), (1, 1, -1, 4, 0),
+              (2, 4, 0, 2, 160)]
 _cache = {}
 
 
@@ -50,7 +54,8 @@ def per_rhs_err(got, ref):
 
 @pytest.mark.parametrize("dims", DIMS)
 @pytest.mark.parametrize("link12", [False, True])
-@pytest.mark.parametrize("tile", TILES, ids=lambda t: f"nb{t[0]}w{t[1]}x{t[2]}")
+@pytest.mark.parametrize("tile", TILES + PASS_TILES, ids=lambda t: "nb{}w{}x{}".format(*t[:3]) +
+                         ("p{}l{}".format(*t[3:]) if len(t) > 3 else ""))
 def test_tile_apply_and_richardson(dims, link12, tile):
     c, lat12, x, b, omega, y_ref, x_rich = setup(dims)
     lat = lat12 if link12 else c.lat
@@ -81,12 +86,15 @@ def test_tile_reaches_uneven_rhs_counts():
 def test_autotuner_picks_the_fastest_valid_tile():
     c, lat12, x, b, omega, y_ref, x_rich = setup(DIMS[1])
     best, cands = api.tune_multi_rhs(c.lat, NRHS, reps=3)
-    assert len(cands) == len(TILES)
+    seen = [(t["nb"], t["waves"], t["xcd_map"], t["passes"], t["lds_kb"]) for t in cands]
+    assert all(tuple(t) + (1, 0) in seen for t in TILES)
+    assert any(t[3] > 1 for t in seen) and any(t[4] > 0 for t in seen)
     assert all(t["ms"] > 0 for t in cands)
     assert best["ms"] == min(t["ms"] for t in cands)
-    assert (best["nb"], best["waves"], best["xcd_map"]) in [(t["nb"], t["waves"], t["xcd_map"]) for t in cands]
+    assert (best["nb"], best["waves"], best["xcd_map"], best["passes"], best["lds_kb"]) in seen
     y = api.apply_schur(c.lat, to_dev(x, torch.complex64))
     assert per_rhs_err(to_host(y), y_ref) < 1e-5
-    # 7 right-hand sides: only nb = 1 tiles and the default are candidates
+    # 7 right-hand sides: only nb = 1 tiles in one pass and the default are candidates
     best7, cands7 = api.tune_multi_rhs(c.lat, 7, reps=2)
     assert {t["nb"] for t in cands7} == {0, 1}
+    assert {t["passes"] for t in cands7} == {1}

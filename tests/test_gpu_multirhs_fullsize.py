@@ -20,7 +20,8 @@ from paper_2407_08092_amd import api, synth
 pytestmark = pytest.mark.gpu
 
 DIMS = (24, 24, 24, 48)
-TILES = [(0, 4, 0), (0, 4, -1)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32)))
+TILES = [(0, 4, 0), (0, 4, -1)] + list(itertools.product((1, 2, 3, 4), (1, 4), (-1, 0, 1, 8, 32))) + \
+    [(1, 4, -1, 2, 64), (2, 4, -1, 2, 48), (3, 4, -1, 2, 96), (4, 1, -1, 2, 0), (2, 1, -1, 4, 64)]
 OMEGA = 0.15
 
 
@@ -54,7 +55,8 @@ def test_fp32_tiles_match_single_and_repeat(lat, n):
     b = api.convert_parity(lat, torch.from_numpy(g[1]).cuda(), torch.complex64)
     y1, x1 = singles(lat, x, b, 2)
     for tile in TILES:
-        if tile[0] and n % tile[0]:
+        passes = tile[3] if len(tile) > 3 else 1
+        if tile[0] and (n % passes or (n // passes) % tile[0]):
             continue
         api.set_multi_rhs_tile(lat, n, *tile)
         runs = []

@@ -622,6 +622,52 @@ def mixed_vs_fp64(api, synth, torch, dev):
             "fgmres_full_oe_smoother": full}
 
 
+def mrhs_layout(api, torch, lat, x_planar, n, timed):
+    """The interleaved-layout stencil (right-hand sides contiguous per site) on the same
+    vectors: apply and Richardson sweep per engine, workgroup order and LDS cap; the
+    per-kernel mean durations of the fastest setting from the library's profiler."""
+    vh = lat.Vh
+    xm = api.mrhs_pack(lat, x_planar)
+    ym = torch.empty_like(xm)
+    bm = xm.flip(2).contiguous()
+    wm = xm.clone()
+    bytes_apply = (12 * 5 * n + 144 + 72) * 8 * vh
+    bytes_sweep = (12 * 6 * n + 144 + 72) * 8 * vh
+    res = {"layout": "[V/2][6][nrhs][2] complex64", "bytes_per_apply": bytes_apply, "bytes_per_sweep": bytes_sweep,
+           "settings": {}}
+    best = None
+    for engine, ename in ((api.DDQ_ENGINE_VALU, "valu"), (api.DDQ_ENGINE_MFMA, "mfma")):
+        for order in (1, 0):
+            for lds in (0, 32, 64):
+                api.mrhs_set_launch(lat, order, lds)
+                ta = timed(lambda: api.mrhs_apply_schur(lat, xm, ym, engine=engine))
+                ts = timed(lambda: api.mrhs_richardson_smooth(lat, wm, bm, 1, 0.1, engine=engine))
+                key = f"{ename}_order{order}_lds{lds}"
+                res["settings"][key] = {"apply_ms": round(ta, 4), "apply_GBs": round(bytes_apply / (ta * 1e-3) / 1e9, 1),
+                                        "sweep_ms": round(ts, 4)}
+                if best is None or ta < best[0]:
+                    best = (ta, engine, order, lds, key)
+    ta, engine, order, lds, key = best
+    api.mrhs_set_launch(lat, order, lds)
+    api.profile_begin(lat)
+    for _ in range(10):
+        api.mrhs_apply_schur(lat, xm, ym, engine=engine)
+        api.mrhs_richardson_smooth(lat, wm, bm, 1, 0.1, engine=engine)
+    torch.cuda.synchronize()
+    kstats = api.profile_end(lat)
+    api.mrhs_set_launch(lat, 1, 0)
+    res.update({"best": key, "apply_ms": round(ta, 4), "apply_GBs": round(bytes_apply / (ta * 1e-3) / 1e9, 1),
+                "frac_of_8TBs": round(bytes_apply / (ta * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                "kernels": {name: {"mean_ms": round(k["mean_ms"], 4),
+                                   "GBs": round(k["bytes_per_launch"] / (k["mean_ms"] * 1e-3) / 1e9, 1),
+                                   "frac_of_8TBs": round(k["bytes_per_launch"] / (k["mean_ms"] * 1e-3) / 1e9 /
+                                                         HBM_PEAK_GBS, 4)}
+                            for name, k in kstats.items()}})
+    log(f"mrhs layout: best {key}: {res['apply_ms']} ms = {res['apply_GBs']} GB/s")
+    del xm, ym, bm, wm
+    return res
+
+
 def batched(api, synth, torch, dev, solve=True):
     """Multi-right-hand-side apply and (solve) the batched solve of uneven lattices."""
     lats, bs, oms = [], [], []
@@ -664,6 +710,7 @@ def batched(api, synth, torch, dev, solve=True):
              "speedup_vs_single_loop": round(n * t_one / t_multi, 3)}
     log(f"multi-rhs: {multi['apply_ms']} ms = {multi['apply_GBs']} GB/s, x{multi['speedup_vs_single_loop']} "
         f"vs {n} single applies, tile {best}")
+    multi["mrhs_layout"] = mrhs_layout(api, torch, lat, x, n, timed)
     del x, y, x1, y1
     if not solve:
         for lat in lats:

@@ -219,6 +219,36 @@ int ddq_set_multi_rhs_tile(ddq_lattice* lat, int nrhs, const ddq_mr_tile* tile);
 int ddq_tune_multi_rhs(ddq_lattice* lat, int nrhs, int reps, ddq_mr_tile* results, int max_results,
                        int* n_results, ddq_mr_tile* chosen);
 
+/* Several right-hand sides in the interleaved ("mrhs") layout, FP32 (DDQ_F32 links
+ * and clover; 12-real when the lattice stores them so).  The operator is D_S of eq. 3
+ * on nrhs vectors that share the links and clover blocks; the paper names several
+ * right-hand sides as the way to make block applications cache-friendly (Sect. 3.3).
+ * Layout of an mrhs parity vector (complex64, device): [V/2][6][nrhs][2], i.e. the
+ * 16-byte element holding rows 2k, 2k+1 (row = 3 spin + colour) of right-hand side r
+ * at checkerboard site i sits at element (6 i + k) nrhs + r: all right-hand sides of a
+ * site are one contiguous run.  nrhs in 1..256, and V/2 x 96 x nrhs bytes below 4 GiB.
+ *   engine  DDQ_ENGINE_VALU: the SU(3) products on the vector units;
+ *           DDQ_ENGINE_MFMA: on the matrix cores (v_mfma_f32_4x4x1_16b_f32, one 4 x 4
+ *           outer-product block per four right-hand sides of a site); both give the same
+ *           operator to FP32 rounding.
+ * ddq_mrhs_pack / ddq_mrhs_unpack: FP32 parity vectors [nrhs][6][V/2][2] (the layout of
+ *   ddq_apply_schur) to and from the mrhs layout (data movement only; src and dst must not
+ *   overlap).
+ * ddq_mrhs_apply_schur: y = D_S x (x and y must not overlap).
+ * ddq_mrhs_richardson_smooth: Alg. 4, nsweeps times x <- x + omega (b - D_S x), in place.
+ *   Both need the work space of ddq_reserve with max_nrhs >= nrhs (u_o in FP32).
+ * ddq_mrhs_set_launch: workgroup order (0: plain site order, 1: slab order, the default:
+ *   every t-slice cut into eight pieces, XCD k walking piece k of each slice in t order)
+ *   and LDS requested per workgroup (0..160 KB; the kernels use none: it caps the
+ *   workgroups resident on a compute unit). */
+enum { DDQ_ENGINE_VALU = 0, DDQ_ENGINE_MFMA = 1 };
+int ddq_mrhs_pack(ddq_lattice* lat, int nrhs, const void* src, void* dst);
+int ddq_mrhs_unpack(ddq_lattice* lat, int nrhs, const void* src, void* dst);
+int ddq_mrhs_apply_schur(ddq_lattice* lat, int nrhs, const void* x_e, void* y_e, int engine);
+int ddq_mrhs_richardson_smooth(ddq_lattice* lat, int nrhs, void* x_e, const void* b_e, int nsweeps, double omega,
+                               int engine);
+int ddq_mrhs_set_launch(ddq_lattice* lat, int order, int lds_kb);
+
 /* Persisted tiles.  cache_json_path names a JSON file {"ddq_autotune": 1, "tiles":
  * [{"key", "nrhs", "nb", "waves", "xcd_map", "passes", "lds_kb", "ms"}, ...]} (created when absent), one
  * entry per line; the key is the device (architecture name and compute-unit count),

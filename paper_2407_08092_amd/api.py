@@ -233,6 +233,77 @@ def apply_schur(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor = None, dagge
     return y_e
 
 
+DDQ_ENGINE_VALU = 0
+DDQ_ENGINE_MFMA = 1
+
+
+def _mrhs_shape(lat: Lattice, nrhs: int):
+    return (int(lat.Vh), 6, int(nrhs), 2)
+
+
+def _nrhs_mrhs(lat: Lattice, v: torch.Tensor) -> int:
+    if v.dtype != torch.complex64 or v.dim() != 4 or tuple(v.shape[:2]) != (lat.Vh, 6) or v.shape[3] != 2:
+        raise ValueError(f"an mrhs vector is complex64 [V/2, 6, nrhs, 2], got {v.dtype} {tuple(v.shape)}")
+    if not v.is_contiguous():
+        raise ValueError("mrhs vectors must be contiguous")
+    return int(v.shape[2])
+
+
+def mrhs_vector(lat: Lattice, nrhs: int) -> torch.Tensor:
+    """An uninitialised mrhs-layout vector of nrhs right-hand sides."""
+    return torch.empty(_mrhs_shape(lat, nrhs), dtype=torch.complex64, device=lat.device)
+
+
+def mrhs_pack(lat: Lattice, v: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    """FP32 parity vectors [nrhs, 6, V/2, 2] -> mrhs layout [V/2, 6, nrhs, 2]."""
+    n = _nrhs_parity(lat, v)
+    if v.dtype != torch.complex64:
+        raise ValueError("mrhs vectors are FP32 (complex64)")
+    if out is None:
+        out = mrhs_vector(lat, n)
+    lat.sync_stream()
+    check(lib().ddq_mrhs_pack(lat.handle, n, _dev(v, "v"), _dev(out, "out")), "ddq_mrhs_pack")
+    return out
+
+
+def mrhs_unpack(lat: Lattice, v: torch.Tensor, out: torch.Tensor = None) -> torch.Tensor:
+    """mrhs layout [V/2, 6, nrhs, 2] -> FP32 parity vectors [nrhs, 6, V/2, 2]."""
+    n = _nrhs_mrhs(lat, v)
+    if out is None:
+        out = torch.empty((n,) + _parity_shape(lat, torch.complex64), dtype=torch.complex64, device=lat.device)
+    lat.sync_stream()
+    check(lib().ddq_mrhs_unpack(lat.handle, n, _dev(v, "v"), _dev(out, "out")), "ddq_mrhs_unpack")
+    return out
+
+
+def mrhs_apply_schur(lat: Lattice, x: torch.Tensor, y: torch.Tensor = None, engine: int = DDQ_ENGINE_MFMA) -> torch.Tensor:
+    """y = D_S x on mrhs-layout vectors."""
+    n = _nrhs_mrhs(lat, x)
+    if y is None:
+        y = torch.empty_like(x)
+    reserve(lat, n)
+    lat.sync_stream()
+    check(lib().ddq_mrhs_apply_schur(lat.handle, n, _dev(x, "x"), _dev(y, "y"), int(engine)), "ddq_mrhs_apply_schur")
+    return y
+
+
+def mrhs_richardson_smooth(lat: Lattice, x: torch.Tensor, b: torch.Tensor, nsweeps: int, omega: float,
+                           engine: int = DDQ_ENGINE_MFMA) -> torch.Tensor:
+    """Alg. 4 on D_S, in place on the mrhs-layout x."""
+    n = _nrhs_mrhs(lat, x)
+    if b.shape != x.shape or b.dtype != x.dtype:
+        raise ValueError("x and b must match in dtype and shape")
+    reserve(lat, n)
+    lat.sync_stream()
+    check(lib().ddq_mrhs_richardson_smooth(lat.handle, n, _dev(x, "x"), _dev(b, "b"), int(nsweeps), float(omega),
+                                           int(engine)), "ddq_mrhs_richardson_smooth")
+    return x
+
+
+def mrhs_set_launch(lat: Lattice, order: int = 1, lds_kb: int = 0) -> None:
+    check(lib().ddq_mrhs_set_launch(lat.handle, int(order), int(lds_kb)), "ddq_mrhs_set_launch")
+
+
 def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweeps: int, omega: float) -> torch.Tensor:
     """Alg. 4 on D_S, in place on x_e."""
     n = _nrhs_parity(lat, x_e)

@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libddq.so")
 ARCH = os.environ.get("DDQ_OFFLOAD_ARCH", "gfx950")
 
-SOURCES = ["hop.hip", "hop_rb.hip", "hop_h16.hip", "sap.hip", "coarse.hip", "fields.hip", "blas.hip", "force.hip", "api.cpp"]
+SOURCES = ["hop.hip", "hop_rb.hip", "hop_mrhs.hip", "hop_h16.hip", "sap.hip", "coarse.hip", "fields.hip", "blas.hip", "force.hip", "api.cpp"]
 
 FLAGS = [
     "-x", "hip", f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC",

@@ -136,6 +136,9 @@ struct ddq_lattice {
   std::vector<double> kind_ms, kind_bytes;
   std::vector<int> kind_n;
 
+  // launch settings of the mrhs-layout stencil (ddq_mrhs_set_launch)
+  int mrhs_order = MRHS_ORDER_SLAB, mrhs_lds_kb = 0;
+
   // FP32 multi-right-hand-side tiles by right-hand-side count (ddq_tune_multi_rhs)
   std::vector<std::pair<int, MrTile>> tiles;
   std::vector<std::pair<int, double>> tile_ms;  // the tuner's time of the chosen tile
@@ -341,6 +344,31 @@ int sweeps16(ddq_lattice* L, int prec, int nrhs, void* x, const void* b, int n, 
     HIPCHK(run_hop16(L, prec, nrhs, M_RICH, u, x, b, x, omega));
   }
   return DDQ_OK;
+}
+
+// the mrhs-layout stencil: kernel A (M_HOP_CLINV) or kernel B (M_APPLY / M_RICH)
+hipError_t run_mrhs(ddq_lattice* L, int nrhs, int mode, int engine, const void* in, const void* x, const void* b,
+                    void* out, float omega) {
+  MrhsArgs a{};
+  const int p_out = mode == M_HOP_CLINV ? 1 : 0;
+  a.g = L->geo;
+  a.p_out = p_out;
+  a.in = (const f2_t*)in;
+  a.links = (const f2_t*)L->links[DDQ_F32][p_out];
+  a.clov = (const f2_t*)L->clov[DDQ_F32][p_out];
+  a.x = (const f2_t*)x;
+  a.b = (const f2_t*)b;
+  a.out = (f2_t*)out;
+  a.omega = omega;
+  a.link12 = L->link12 ? 1 : 0;
+  a.nrhs = nrhs;
+  a.engine = engine;
+  a.order = L->mrhs_order;
+  a.lds_kb = L->mrhs_lds_kb;
+  if (!L->prof_on) return launch_hop_mrhs(a, mode, L->stream);
+  std::string name = std::string(mode_name(mode)) + (a.link12 ? "_f32l12" : "_f32") + "_mrhs" +
+                     std::to_string(nrhs) + (engine == MRHS_ENGINE_MFMA ? "_mfma" : "_valu");
+  return prof_launch(L, name, hop_bytes(L, DDQ_F32, mode, nrhs), [&]() { return launch_hop_mrhs(a, mode, L->stream); });
 }
 
 template <typename R>
@@ -763,6 +791,74 @@ int ddq_richardson_smooth(ddq_lattice* L, int prec, int nrhs, void* x_e, const v
   if (is16(prec)) return sweeps16(L, prec, nrhs, x_e, b_e, nsweeps, (float)omega);
   if (prec == DDQ_F64) return sweeps<double>(L, prec, nrhs, (d2_t*)x_e, (const d2_t*)b_e, nsweeps, omega);
   return sweeps<float>(L, prec, nrhs, (f2_t*)x_e, (const f2_t*)b_e, nsweeps, (float)omega);
+}
+
+namespace {
+int check_mrhs(ddq_lattice* L, int nrhs) {
+  CHK(check_ready(L, DDQ_F32));
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS)
+    return fail(DDQ_ERR_ARG, "nrhs must be in [1, " + std::to_string(MRHS_MAX_NRHS) + "]");
+  if ((uint64_t)L->Vh * 96u * (uint64_t)nrhs >= (1ULL << 32))
+    return fail(DDQ_ERR_ARG, "an mrhs vector (V/2 x 96 x nrhs bytes) must stay below 4 GiB");
+  return DDQ_OK;
+}
+int check_engine(int engine) {
+  if (engine != DDQ_ENGINE_VALU && engine != DDQ_ENGINE_MFMA)
+    return fail(DDQ_ERR_ARG, "engine must be DDQ_ENGINE_VALU or DDQ_ENGINE_MFMA");
+  return DDQ_OK;
+}
+}  // namespace
+
+int ddq_mrhs_pack(ddq_lattice* L, int nrhs, const void* src, void* dst) {
+  CHK(check_lat(L));
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS || !src || !dst) return fail(DDQ_ERR_ARG, "bad mrhs pack arguments");
+  if (src == dst) return fail(DDQ_ERR_ARG, "src and dst must not overlap");
+  HIPCHK(launch_mrhs_layout(src, dst, nrhs, (int)L->Vh, true, L->stream));
+  return DDQ_OK;
+}
+
+int ddq_mrhs_unpack(ddq_lattice* L, int nrhs, const void* src, void* dst) {
+  CHK(check_lat(L));
+  if (nrhs < 1 || nrhs > MRHS_MAX_NRHS || !src || !dst) return fail(DDQ_ERR_ARG, "bad mrhs unpack arguments");
+  if (src == dst) return fail(DDQ_ERR_ARG, "src and dst must not overlap");
+  HIPCHK(launch_mrhs_layout(src, dst, nrhs, (int)L->Vh, false, L->stream));
+  return DDQ_OK;
+}
+
+int ddq_mrhs_set_launch(ddq_lattice* L, int order, int lds_kb) {
+  CHK(check_lat(L));
+  if (order != MRHS_ORDER_PLAIN && order != MRHS_ORDER_SLAB) return fail(DDQ_ERR_ARG, "order must be 0 or 1");
+  if (lds_kb < 0 || lds_kb > 160) return fail(DDQ_ERR_ARG, "lds_kb must be in [0, 160]");
+  L->mrhs_order = order;
+  L->mrhs_lds_kb = lds_kb;
+  return DDQ_OK;
+}
+
+int ddq_mrhs_apply_schur(ddq_lattice* L, int nrhs, const void* x_e, void* y_e, int engine) {
+  CHK(check_mrhs(L, nrhs));
+  CHK(check_engine(engine));
+  if (!x_e || !y_e) return fail(DDQ_ERR_ARG, "bad apply arguments");
+  if (x_e == y_e) return fail(DDQ_ERR_ARG, "x_e and y_e must not overlap");
+  CHK(ensure_tmp(L, DDQ_F32, nrhs));
+  void* u = L->tmp[DDQ_F32].p;
+  HIPCHK(run_mrhs(L, nrhs, M_HOP_CLINV, engine, x_e, nullptr, nullptr, u, 0.f));
+  HIPCHK(run_mrhs(L, nrhs, M_APPLY, engine, u, x_e, nullptr, y_e, 0.f));
+  return DDQ_OK;
+}
+
+int ddq_mrhs_richardson_smooth(ddq_lattice* L, int nrhs, void* x_e, const void* b_e, int nsweeps, double omega,
+                               int engine) {
+  CHK(check_mrhs(L, nrhs));
+  CHK(check_engine(engine));
+  if (!x_e || !b_e || nsweeps < 0) return fail(DDQ_ERR_ARG, "bad smoother arguments");
+  if (x_e == b_e) return fail(DDQ_ERR_ARG, "x_e and b_e must not overlap");
+  CHK(ensure_tmp(L, DDQ_F32, nrhs));
+  void* u = L->tmp[DDQ_F32].p;
+  for (int k = 0; k < nsweeps; ++k) {
+    HIPCHK(run_mrhs(L, nrhs, M_HOP_CLINV, engine, x_e, nullptr, nullptr, u, 0.f));
+    HIPCHK(run_mrhs(L, nrhs, M_RICH, engine, u, x_e, b_e, x_e, (float)omega));
+  }
+  return DDQ_OK;
 }
 
 int ddq_set_multi_rhs_tile(ddq_lattice* L, int nrhs, const ddq_mr_tile* tile) {
@@ -1383,6 +1479,9 @@ int oe_solve_one(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params*
   auto t0 = std::chrono::steady_clock::now();
   const int m = P->m;
   if (m < 1 || m > 128) return fail(DDQ_ERR_ARG, "cycle length m must be in [1, 128]");
+  if (!(L->res_what & DDQ_RESERVE_SOLVE) || m > L->res_m)
+    return fail(DDQ_ERR_STATE, "the solver's work space is reserved for m <= " + std::to_string(L->res_m) +
+                                   " (ddq_reserve with DDQ_RESERVE_SOLVE and max_m >= " + std::to_string(m) + ")");
   if (P->max_cycles < 0 || !(P->tol >= 0.0) || P->smoother_sweeps < 0)
     return fail(DDQ_ERR_ARG, "bad max_cycles, tol or smoother_sweeps");
   if (P->inner_prec != DDQ_F64 && P->inner_prec != DDQ_F32)
@@ -1611,6 +1710,9 @@ int fgmres_full(ddq_lattice* L, void* x, const void* b, const ddq_gmres_params* 
   auto t0 = std::chrono::steady_clock::now();
   const int m = P->m;
   if (P->orth_passes < 0 || P->orth_passes > 2) return fail(DDQ_ERR_ARG, "orth_passes must be 0, 1 or 2");
+  if (m > L->res_m)
+    return fail(DDQ_ERR_STATE, "the FGMRES work space is reserved for m <= " + std::to_string(L->res_m) +
+                                   " (ddq_reserve with max_m >= " + std::to_string(m) + ")");
   const int passes = P->orth_passes == 1 ? 1 : 2;
   const long long n = 2 * L->nvec();  // complex numbers of a full vector
   const size_t vb = (size_t)n * 16;

@@ -127,6 +127,38 @@ hipError_t launch_hop_stream(const HopArgs<R>& a, int mode, hipStream_t s);
 bool hop_rb_supported(int mode, bool dagger, int nrhs, const MrTile& t);
 hipError_t launch_hop_rb(const HopArgs<float>& a, int mode, int nrhs, hipStream_t s);
 
+// FP32 stencil on the mrhs layout (hop_mrhs.hip): right-hand sides interleaved per site,
+// element (i, k, r) at (6 i + k) nrhs + r; modes M_HOP_CLINV, M_APPLY, M_RICH, not
+// daggered.  The host fills everything up to lds_kb; launch_hop_mrhs derives the rest.
+enum { MRHS_ENGINE_VALU = 0, MRHS_ENGINE_MFMA = 1 };
+enum { MRHS_ORDER_PLAIN = 0, MRHS_ORDER_SLAB = 1 };
+constexpr int MRHS_MAX_NRHS = 256;
+struct MrhsArgs {
+  Geo g;
+  int p_out;
+  const f2_t* in;
+  const f2_t* links;
+  const f2_t* clov;
+  const f2_t* x;
+  const f2_t* b;
+  f2_t* out;
+  float omega;
+  int link12;
+  int nrhs;
+  int engine;   // MRHS_ENGINE_*: SU(3) products on the vector units or the matrix cores
+  int order;    // MRHS_ORDER_*: workgroup order
+  int lds_kb;   // LDS requested per workgroup (unused; caps resident workgroups)
+  // derived by mrhs_geometry
+  int ngroups;  // right-hand-side groups (one workgroup each per site group)
+  int rgs;      // right-hand sides per group (<= 16)
+  int lps;      // lanes per site: rgs rounded up to a multiple of 4
+  int spw;      // sites per wavefront: 64 / lps
+};
+bool mrhs_geometry(int nrhs, MrhsArgs& a);
+hipError_t launch_hop_mrhs(const MrhsArgs& a, int mode, hipStream_t s);
+// FP32 parity vectors [nrhs][6][V/2] <-> mrhs layout (to_mrhs selects the direction)
+hipError_t launch_mrhs_layout(const void* src, void* dst, int nrhs, int vh, bool to_mrhs, hipStream_t s);
+
 // 16-bit storage (FP16 or BF16 values, FP32 arithmetic): modes M_HOP_CLINV, M_APPLY,
 // M_RICH, not daggered.  Parity vectors are [nrhs][3][V/2] 16-byte elements of four
 // complex numbers; links 12-real; clover padded to 20 slots per block.

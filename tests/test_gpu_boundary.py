@@ -143,7 +143,8 @@ def test_autotune_cache_round_trip(tmp_path):
     # a fresh lattice of the same extents takes the cached tile (here replaced by a known
     # one), and an entry of another lattice survives the rewrite
     mine[0].update(nb=2, waves=4, xcd_map=8)
-    other = {"key": "other/1cu/2x2x2x2/link18", "nrhs": 2, "nb": 1, "waves": 1, "xcd_map": 0, "ms": 1.0}
+    other = {"key": "other/1cu/2x2x2x2/link18", "nrhs": 2, "nb": 1, "waves": 1, "xcd_map": 0, "passes": 1,
+             "lds_kb": 0, "ms": 1.0}
     entries = [e for e in doc["tiles"] if e is not mine[0]] + [mine[0], other]
     path.write_text('{"ddq_autotune": 1, "tiles": [\n' + ",\n".join(json.dumps(e) for e in entries) + "\n]}\n")
     lat2 = api.create_lattice(dims)

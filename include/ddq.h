@@ -162,6 +162,22 @@ int ddq_convert_parity(ddq_lattice* lat, int nrhs, int src_prec, const void* src
 int ddq_apply_schur(ddq_lattice* lat, int prec, int nrhs, const void* x_e, void* y_e,
                     int dagger);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ddq_apply_schur with the same
+ * arguments, result and kernels, whose work space for u_o comes from a fixed 64 MiB
+ * device array built into the library (one copy per GPU, held until the process ends)
+ * instead of the lattice's reservation.  It calls no hipMalloc, hipFree or other
+ * allocating routine, and the per-kernel profiler does not record it.  Limit:
+ * nrhs * V/2 * 12 * (16, 8 or 4 bytes for DDQ_F64, DDQ_F32 or 16-bit) <= 64 MiB, e.g.
+ * one FP64 or two FP32 right-hand sides of 24^3 x 48; larger requests return
+ * DDQ_ERR_ARG.  Call it on the device the lattice was created on (else
+ * DDQ_ERR_STATE).  Every call on one GPU shares that array: calls that overlap in time
+ * on one GPU (two streams, two threads, two lattices) race and must be ordered by the
+ * caller; nothing in the array needs to start at zero (u_o is written in full before
+ * it is read). */
+int ddq_apply_schur_noalloc(ddq_lattice* lat, int prec, int nrhs, const void* x_e, void* y_e,
+                            int dagger);
+
 /* Alg. 4 on D_S: nsweeps times x_e <- x_e + omega (b_e - D_S x_e), in place
  * (x_e: in x^(0), out x^(n)).  omega is used as given; Alg. 4's
  * omega = delta / |lambda_max| is formed by the caller (see

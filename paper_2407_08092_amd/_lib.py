@@ -67,6 +67,7 @@ _SIGNATURES = {
     "ddq_unpack_parity": [_P, C.c_int, C.c_int, C.c_int, _P, _P],
     "ddq_convert_parity": [_P, C.c_int, C.c_int, _P, C.c_int, _P],
     "ddq_apply_schur": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
+    "ddq_apply_schur_noalloc": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_mrhs_pack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_unpack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_apply_schur": [_P, C.c_int, _P, _P, C.c_int],

@@ -304,6 +304,18 @@ def mrhs_set_launch(lat: Lattice, order: int = 1, lds_kb: int = 0) -> None:
     check(lib().ddq_mrhs_set_launch(lat.handle, int(order), int(lds_kb)), "ddq_mrhs_set_launch")
 
 
+def apply_schur_noalloc(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor, dagger: bool = False) -> torch.Tensor:
+    """y_e = D_S x_e (or D_S^H x_e) with the library's fixed work space: the call itself
+    allocates nothing, so the caller passes y_e."""
+    n = _nrhs_parity(lat, x_e)
+    if y_e.dtype != x_e.dtype or y_e.shape != x_e.shape:
+        raise ValueError("x_e and y_e must match in dtype and shape")
+    lat.sync_stream()
+    check(lib().ddq_apply_schur_noalloc(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(y_e, "y_e"),
+                                        int(bool(dagger))), "ddq_apply_schur_noalloc")
+    return y_e
+
+
 def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweeps: int, omega: float) -> torch.Tensor:
     """Alg. 4 on D_S, in place on x_e."""
     n = _nrhs_parity(lat, x_e)

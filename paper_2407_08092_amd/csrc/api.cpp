@@ -11,6 +11,7 @@
 #include <cstring>
 #include <string>
 #include <functional>
+#include <mutex>
 #include <vector>
 
 #include "../../include/ddq.h"
@@ -90,6 +91,39 @@ struct Grow {
   }
 };
 
+// Fixed work space of ddq_apply_schur_noalloc: a file-scope device array, one copy per
+// GPU, alive until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in symbol); it uses the device address that
+// hipGetSymbolAddress returns, looked up once per device by ddq_create_lattice with the
+// lattice's device current.
+constexpr size_t NOALLOC_SCRATCH_BYTES = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device (resolved on first use)
+int scratch_address(int* device, void** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(DDQ_ERR_HIP, "device ordinal out of range");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(DDQ_ERR_HIP, "hipGetSymbolAddress returned a null address for the work space");
+    g_scratch_dev[dev] = p;
+  }
+  *device = dev;
+  *out = g_scratch_dev[dev];
+  return DDQ_OK;
+}
+
+// set while a call that must not allocate runs: the per-kernel profiler (which creates
+// HIP events) stands aside
+thread_local bool g_no_alloc_call = false;
+
 }  // namespace
 
 struct ddq_lattice {
@@ -125,6 +159,9 @@ struct ddq_lattice {
   // the reservation of ddq_reserve (grown, never shrunk): right-hand sides, cycle length
   // and the DDQ_RESERVE_* call families whose work space is kept
   int res_nrhs = 1, res_m = 0;
+  // the lattice's device and that device's copy of the fixed work space
+  int device = -1;
+  void* noalloc_ws = nullptr;
   unsigned res_what = 0;
 
   // per-kernel timing (ddq_profile_begin / ddq_profile_end)
@@ -254,7 +291,7 @@ hipError_t launch_any(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, i
 // its time booked under `name` with `bytes` algorithmic bytes per launch
 template <typename F>
 hipError_t prof_launch(ddq_lattice* L, const std::string& name, double bytes, F launch) {
-  if (!L->prof_on) return launch();
+  if (!L->prof_on || g_no_alloc_call) return launch();
   int kind = -1;
   for (size_t k = 0; k < L->kind_name.size(); ++k)
     if (L->kind_name[k] == name) kind = (int)k;
@@ -291,7 +328,7 @@ hipError_t prof_launch(ddq_lattice* L, const std::string& name, double bytes, F 
 // launch a stencil kernel, bracketed by events while profiling
 template <typename R>
 hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int nrhs) {
-  if (!L->prof_on) return launch_any<R>(L, a, mode, dag, nrhs);
+  if (!L->prof_on || g_no_alloc_call) return launch_any<R>(L, a, mode, dag, nrhs);
   const int prec = sizeof(R) == 8 ? DDQ_F64 : DDQ_F32;
   std::string tile;
   if (prec == DDQ_F32 && nrhs > 1) {
@@ -324,14 +361,16 @@ hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* i
   // workgroup order: that of the lattice's FP32 tile for this count, else slab order
   const MrTile* t = nrhs > 1 ? L->tile_for(nrhs) : nullptr;
   a.chunk = t ? t->xmap : XMAP_SLAB;
+  if (!L->prof_on || g_no_alloc_call) return launch_hop16(h16_kind(prec), a, mode, L->stream);
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_BF16 ? "_bf16" : "_f16") +
                      (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
   return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
                      [&]() { return launch_hop16(h16_kind(prec), a, mode, L->stream); });
 }
 
-int schur16(ddq_lattice* L, int prec, int nrhs, const void* x, void* y) {
-  void* u = L->tmp[prec].p;
+// u: work space for u_o (nrhs parity vectors of prec); null selects the lattice's own
+int schur16(ddq_lattice* L, int prec, int nrhs, const void* x, void* y, void* u = nullptr) {
+  if (!u) u = L->tmp[prec].p;
   HIPCHK(run_hop16(L, prec, nrhs, M_HOP_CLINV, x, nullptr, nullptr, u, 0.f));
   HIPCHK(run_hop16(L, prec, nrhs, M_APPLY, u, x, nullptr, y, 0.f));
   return DDQ_OK;
@@ -365,7 +404,7 @@ hipError_t run_mrhs(ddq_lattice* L, int nrhs, int mode, int engine, const void* 
   a.engine = engine;
   a.order = L->mrhs_order;
   a.lds_kb = L->mrhs_lds_kb;
-  if (!L->prof_on) return launch_hop_mrhs(a, mode, L->stream);
+  if (!L->prof_on || g_no_alloc_call) return launch_hop_mrhs(a, mode, L->stream);
   std::string name = std::string(mode_name(mode)) + (a.link12 ? "_f32l12" : "_f32") + "_mrhs" +
                      std::to_string(nrhs) + (engine == MRHS_ENGINE_MFMA ? "_mfma" : "_valu");
   return prof_launch(L, name, hop_bytes(L, DDQ_F32, mode, nrhs), [&]() { return launch_hop_mrhs(a, mode, L->stream); });
@@ -405,9 +444,10 @@ hipError_t kernel_B(ddq_lattice* L, int prec, int nrhs, int mode, const pair<R>*
   return run_hop<R>(L, a, mode, dag, nrhs);
 }
 
+// u: work space for u_o (nrhs parity vectors of prec); null selects the lattice's own
 template <typename R>
-int schur(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, pair<R>* y, bool dag) {
-  pair<R>* u = (pair<R>*)L->tmp[prec].p;
+int schur(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, pair<R>* y, bool dag, pair<R>* u = nullptr) {
+  if (!u) u = (pair<R>*)L->tmp[prec].p;
   HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, dag));
   HIPCHK(kernel_B<R>(L, prec, nrhs, M_APPLY, u, x, nullptr, y, R(0), dag));
   return DDQ_OK;
@@ -559,6 +599,13 @@ int ddq_create_lattice(const int dims[4], int t_antiperiodic, void* hip_stream, 
   g.sT = g.Lxh * dims[1] * dims[2];
   g.antiperiodic = L->anti;
   L->stream = (hipStream_t)hip_stream;
+  {
+    const int r0 = scratch_address(&L->device, &L->noalloc_ws);
+    if (r0 != DDQ_OK) {
+      delete L;
+      return r0;
+    }
+  }
   long long nb = (L->nvec() + 255) / 256;
   L->nbx = (int)(nb > 1024 ? 1024 : nb);
   int r = L->partial.ensure((size_t)L->nbx * 256 * sizeof(d2_t));
@@ -780,6 +827,33 @@ int ddq_apply_schur(ddq_lattice* L, int prec, int nrhs, const void* x_e, void* y
   }
   if (prec == DDQ_F64) return schur<double>(L, prec, nrhs, (const d2_t*)x_e, (d2_t*)y_e, dagger != 0);
   return schur<float>(L, prec, nrhs, (const f2_t*)x_e, (f2_t*)y_e, dagger != 0);
+}
+
+int ddq_apply_schur_noalloc(ddq_lattice* L, int prec, int nrhs, const void* x_e, void* y_e, int dagger) {
+  CHK(check_ready(L, prec));
+  if (nrhs < 1 || !x_e || !y_e) return fail(DDQ_ERR_ARG, "bad apply arguments");
+  if (x_e == y_e) return fail(DDQ_ERR_ARG, "x_e and y_e must not overlap");
+  const size_t need = (size_t)nrhs * (size_t)L->nvec() * elem_bytes(prec);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(DDQ_ERR_ARG, "ddq_apply_schur_noalloc: u_o needs " + std::to_string(need) +
+                                 " bytes, more than the fixed work space of " + std::to_string(NOALLOC_SCRATCH_BYTES) +
+                                 " bytes (nrhs x V/2 x 12 x " + std::to_string(elem_bytes(prec)) + " bytes)");
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev != L->device || !L->noalloc_ws)
+    return fail(DDQ_ERR_STATE, "ddq_apply_schur_noalloc: the lattice was created on device " +
+                                   std::to_string(L->device) + ", the current device is " + std::to_string(dev));
+  struct Guard {
+    Guard() { g_no_alloc_call = true; }
+    ~Guard() { g_no_alloc_call = false; }
+  } guard;
+  void* u = L->noalloc_ws;
+  if (is16(prec)) {
+    if (dagger) return fail(DDQ_ERR_ARG, "the 16-bit path has no daggered apply");
+    return schur16(L, prec, nrhs, x_e, y_e, u);
+  }
+  if (prec == DDQ_F64) return schur<double>(L, prec, nrhs, (const d2_t*)x_e, (d2_t*)y_e, dagger != 0, (d2_t*)u);
+  return schur<float>(L, prec, nrhs, (const f2_t*)x_e, (f2_t*)y_e, dagger != 0, (f2_t*)u);
 }
 
 int ddq_richardson_smooth(ddq_lattice* L, int prec, int nrhs, void* x_e, const void* b_e, int nsweeps,

@@ -27,6 +27,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-ba
        python bench.py --multi-rhs-only   (profiling run: only the 12-right-hand-side apply on 24^3 x 48,
                                            prints its own JSON, not the benchmark line)
        python bench.py --batch-only       (profiling run: that apply and the batched solves, own JSON)
+       python bench.py --mrhs-only        (profiling run: only the interleaved-layout 12-right-hand-side stencil)
 """
 from __future__ import annotations
 
@@ -51,6 +52,7 @@ BYTES_APPLY_F32 = 2208    # per even site, FP32 links/spinors/clover, every fiel
 BYTES_APPLY_F64 = 4416
 BYTES_APPLY_F32_L12 = 1824  # 12-real FP32 links
 BYTES_APPLY_H16 = 944       # 16-bit spinors, 12-real links, clover padded to 40 slots
+BYTES_APPLY_H16_C32 = 1200  # 16-bit spinors, 12-real 16-bit links, FP32 clover blocks
 
 
 MODE_CODE = {"clinv": 0, "recon": 1, "apply": 2, "richardson": 3, "resid": 4, "prep": 5}
@@ -128,6 +130,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multi-rhs-only", action="store_true")
+    ap.add_argument("--mrhs-only", action="store_true")
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--coarse-only", action="store_true")
     ap.add_argument("--coarse-nv", type=int, nargs="+", default=[24, 20])
@@ -144,6 +147,15 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"coarse": coarse_operator(api, torch, torch.device("cuda:0"), args.coarse_nv)}), flush=True)
+        return
+
+    if args.mrhs_only:
+        import torch
+
+        from paper_2407_08092_amd import api, synth
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"mrhs_layout": mrhs_only(api, synth, torch, torch.device("cuda:0"))}), flush=True)
         return
 
     if args.multi_rhs_only or args.batch_only:
@@ -266,7 +278,10 @@ def main():
     torch.cuda.empty_cache()
     api.set_clover(lat, cfg["c_sw"], cfg["m0"])
     h16 = {}
-    for label, dt in (("fp16", torch.float16), ("bf16", torch.bfloat16)):
+    for label, dt, c32 in (("fp16", torch.float16, False), ("bf16", torch.bfloat16, False),
+                           ("fp16_clover32", torch.float16, True), ("bf16_clover32", torch.bfloat16, True)):
+        api.set_h16_clover(lat, c32)
+        bps = BYTES_APPLY_H16_C32 if c32 else BYTES_APPLY_H16
         x16 = api.convert_parity(lat, x64, dt)
         b16 = api.convert_parity(lat, b64, dt)
         y16, xs16 = torch.empty_like(x16), torch.empty_like(x16)
@@ -293,11 +308,12 @@ def main():
         tsw = sum(e[1].elapsed_time(e[2]) for e in ev16) / args.steps
         ref = api.convert_parity(lat, y32, torch.complex128)
         got = api.convert_parity(lat, y16, torch.complex128)
-        h16[label] = {"apply_ms": round(ta, 4), "apply_GBs": round(BYTES_APPLY_H16 * vh / (ta * 1e-3) / 1e9, 1),
-                      "bytes_per_even_site": BYTES_APPLY_H16, "sweeps_per_s": round(SWEEPS / (tsw * 1e-3), 1),
+        h16[label] = {"apply_ms": round(ta, 4), "apply_GBs": round(bps * vh / (ta * 1e-3) / 1e9, 1),
+                      "bytes_per_even_site": bps, "sweeps_per_s": round(SWEEPS / (tsw * 1e-3), 1),
                       "rel_diff_vs_fp32_apply": float((got - ref).norm() / ref.norm())}
         log(f"{label} storage: apply {ta:.3f} ms, {h16[label]['sweeps_per_s']} sweeps/s")
         del x16, b16, y16, xs16, ref, got
+    api.set_h16_clover(lat, False)
 
     # FP64 apply and sweeps on the same lattice (context)
     y64 = torch.empty_like(x64)
@@ -622,6 +638,30 @@ def mixed_vs_fp64(api, synth, torch, dev):
             "fgmres_full_oe_smoother": full}
 
 
+def timed_events(torch, fn, reps=20):
+    for _ in range(3):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def mrhs_only(api, synth, torch, dev):
+    """Profiling run: only the interleaved-layout stencil on the batching workload's
+    24^3 x 48 lattice with 12 right-hand sides."""
+    dims, n, seed = BATCH[0]
+    lat = api.create_lattice(dims, device=dev)
+    api.set_gauge(lat, synth.gauge_field(dims, 0.5, seed, device=dev))
+    api.set_clover(lat, 1.0, -0.2)
+    x = api.convert_parity(lat, torch.from_numpy(synth.gaussian_complex((n, 12, lat.Vh), 405)).to(dev), torch.complex64)
+    return mrhs_layout(api, torch, lat, x, n, lambda fn, reps=20: timed_events(torch, fn, reps))
+
+
 def mrhs_layout(api, torch, lat, x_planar, n, timed):
     """The interleaved-layout stencil (right-hand sides contiguous per site) on the same
     vectors: apply and Richardson sweep per engine, workgroup order and LDS cap; the
@@ -636,19 +676,21 @@ def mrhs_layout(api, torch, lat, x_planar, n, timed):
     res = {"layout": "[V/2][6][nrhs][2] complex64", "bytes_per_apply": bytes_apply, "bytes_per_sweep": bytes_sweep,
            "settings": {}}
     best = None
+    lt = lat.dims[3]
+    launches = [(o, lds, 0, st) for st in (0, 1) for o in (1, 0) for lds in (0, 64)] + \
+               [(2, lds, ts, st) for st in (0, 1) for ts in sorted({2, 4, lt // 2}) if ts <= lt // 2 for lds in (0, 64)]
     for engine, ename in ((api.DDQ_ENGINE_VALU, "valu"), (api.DDQ_ENGINE_MFMA, "mfma")):
-        for order in (1, 0):
-            for lds in (0, 32, 64):
-                api.mrhs_set_launch(lat, order, lds)
-                ta = timed(lambda: api.mrhs_apply_schur(lat, xm, ym, engine=engine))
-                ts = timed(lambda: api.mrhs_richardson_smooth(lat, wm, bm, 1, 0.1, engine=engine))
-                key = f"{ename}_order{order}_lds{lds}"
-                res["settings"][key] = {"apply_ms": round(ta, 4), "apply_GBs": round(bytes_apply / (ta * 1e-3) / 1e9, 1),
-                                        "sweep_ms": round(ts, 4)}
-                if best is None or ta < best[0]:
-                    best = (ta, engine, order, lds, key)
-    ta, engine, order, lds, key = best
-    api.mrhs_set_launch(lat, order, lds)
+        for order, lds, tsteps, stage in launches:
+            api.mrhs_set_launch(lat, order, lds, tsteps, stage)
+            ta = timed(lambda: api.mrhs_apply_schur(lat, xm, ym, engine=engine))
+            ts = timed(lambda: api.mrhs_richardson_smooth(lat, wm, bm, 1, 0.1, engine=engine))
+            key = f"{ename}_order{order}_lds{lds}" + (f"_t{tsteps}" if order == 2 else "") + ("_staged" if stage else "")
+            res["settings"][key] = {"apply_ms": round(ta, 4), "apply_GBs": round(bytes_apply / (ta * 1e-3) / 1e9, 1),
+                                    "sweep_ms": round(ts, 4)}
+            if best is None or ta < best[0]:
+                best = (ta, engine, order, lds, tsteps, stage, key)
+    ta, engine, order, lds, tsteps, stage, key = best
+    api.mrhs_set_launch(lat, order, lds, tsteps, stage)
     api.profile_begin(lat)
     for _ in range(10):
         api.mrhs_apply_schur(lat, xm, ym, engine=engine)

@@ -185,6 +185,14 @@ int ddq_apply_schur_noalloc(ddq_lattice* lat, int prec, int nrhs, const void* x_
 int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const void* b_e,
                           int nsweeps, double omega);
 
+/* Clover blocks of the 16-bit (DDQ_F16 / DDQ_BF16) stencil: fp32 = 0 reads the 16-bit
+ * copies of A_ee and A_oo^-1 (rounded from FP64, 944 bytes per even site per Schur
+ * apply in all), fp32 = 1 the FP32 blocks (links and spinors stay 16-bit: 1,200 bytes
+ * per even site); needs DDQ_STORE_F32 (else DDQ_ERR_STATE), and a later ddq_set_gauge
+ * without it returns to 0.  Half precision is the lower precision the paper names as
+ * future work (Sect. 4). */
+int ddq_set_h16_clover(ddq_lattice* lat, int fp32);
+
 /* Tiles of the FP32 multi-right-hand-side stencil (nrhs >= 2 in ddq_apply_schur
  * and ddq_richardson_smooth, not daggered).  The operator is that of Sect. 2.4.5
  * applied to nrhs vectors that share the links and clover blocks; the paper applies
@@ -254,16 +262,23 @@ int ddq_tune_multi_rhs(ddq_lattice* lat, int nrhs, int reps, ddq_mr_tile* result
  * ddq_mrhs_richardson_smooth: Alg. 4, nsweeps times x <- x + omega (b - D_S x), in place.
  *   Both need the work space of ddq_reserve with max_nrhs >= nrhs (u_o in FP32).
  * ddq_mrhs_set_launch: workgroup order (0: plain site order, 1: slab order, the default:
- *   every t-slice cut into eight pieces, XCD k walking piece k of each slice in t order)
- *   and LDS requested per workgroup (0..160 KB; the kernels use none: it caps the
- *   workgroups resident on a compute unit). */
+ *   every t-slice cut into eight pieces, XCD k walking piece k of each slice in t order;
+ *   2: t walk: a wavefront keeps its sites' x, y, z and walks tsteps slices of one parity
+ *   of t (t, t + 2, ...; 1 <= tsteps <= Lt / 2), carrying the forward-t neighbour it
+ *   loaded as the next slice's backward-t neighbour, the XCDs owning the pieces of slab
+ *   order) and LDS requested per workgroup (0..160 KB; the kernels use none: it caps the
+ *   workgroups resident on a compute unit).  tsteps is ignored unless order = 2.
+ *   stage = 1 (the default) stages each site's links and clover slots in LDS: the lanes of
+ *   a site load every 16-byte element once between them and read it from LDS, instead of
+ *   each lane loading all of them (stage = 0; the LDS of the slots, 864 bytes per site of
+ *   a workgroup, counts towards lds_kb).  Defaults: order 1, lds_kb 0, stage 1. */
 enum { DDQ_ENGINE_VALU = 0, DDQ_ENGINE_MFMA = 1 };
 int ddq_mrhs_pack(ddq_lattice* lat, int nrhs, const void* src, void* dst);
 int ddq_mrhs_unpack(ddq_lattice* lat, int nrhs, const void* src, void* dst);
 int ddq_mrhs_apply_schur(ddq_lattice* lat, int nrhs, const void* x_e, void* y_e, int engine);
 int ddq_mrhs_richardson_smooth(ddq_lattice* lat, int nrhs, void* x_e, const void* b_e, int nsweeps, double omega,
                                int engine);
-int ddq_mrhs_set_launch(ddq_lattice* lat, int order, int lds_kb);
+int ddq_mrhs_set_launch(ddq_lattice* lat, int order, int lds_kb, int tsteps, int stage);
 
 /* Persisted tiles.  cache_json_path names a JSON file {"ddq_autotune": 1, "tiles":
  * [{"key", "nrhs", "nb", "waves", "xcd_map", "passes", "lds_kb", "ms"}, ...]} (created when absent), one

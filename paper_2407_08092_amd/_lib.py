@@ -68,11 +68,12 @@ _SIGNATURES = {
     "ddq_convert_parity": [_P, C.c_int, C.c_int, _P, C.c_int, _P],
     "ddq_apply_schur": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_apply_schur_noalloc": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
+    "ddq_set_h16_clover": [_P, C.c_int],
     "ddq_mrhs_pack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_unpack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_apply_schur": [_P, C.c_int, _P, _P, C.c_int],
     "ddq_mrhs_richardson_smooth": [_P, C.c_int, _P, _P, C.c_int, C.c_double, C.c_int],
-    "ddq_mrhs_set_launch": [_P, C.c_int, C.c_int],
+    "ddq_mrhs_set_launch": [_P, C.c_int, C.c_int, C.c_int, C.c_int],
     "ddq_richardson_smooth": [_P, C.c_int, C.c_int, _P, _P, C.c_int, C.c_double],
     "ddq_estimate_lambda_max": [_P, C.c_int, _P, C.POINTER(C.c_double)],
     "ddq_set_multi_rhs_tile": [_P, C.c_int, C.POINTER(MrTile)],

@@ -233,6 +233,23 @@ def apply_schur(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor = None, dagge
     return y_e
 
 
+def apply_schur_noalloc(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor, dagger: bool = False) -> torch.Tensor:
+    """y_e = D_S x_e (or D_S^H x_e) with the library's fixed work space: the call itself
+    allocates nothing, so the caller passes y_e."""
+    n = _nrhs_parity(lat, x_e)
+    if y_e.dtype != x_e.dtype or y_e.shape != x_e.shape:
+        raise ValueError("x_e and y_e must match in dtype and shape")
+    lat.sync_stream()
+    check(lib().ddq_apply_schur_noalloc(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(y_e, "y_e"),
+                                        int(bool(dagger))), "ddq_apply_schur_noalloc")
+    return y_e
+
+
+def set_h16_clover(lat: Lattice, fp32: bool) -> None:
+    """The 16-bit stencil reads FP32 clover blocks (fp32) or their 16-bit copies."""
+    check(lib().ddq_set_h16_clover(lat.handle, int(bool(fp32))), "ddq_set_h16_clover")
+
+
 DDQ_ENGINE_VALU = 0
 DDQ_ENGINE_MFMA = 1
 
@@ -300,20 +317,11 @@ def mrhs_richardson_smooth(lat: Lattice, x: torch.Tensor, b: torch.Tensor, nswee
     return x
 
 
-def mrhs_set_launch(lat: Lattice, order: int = 1, lds_kb: int = 0) -> None:
-    check(lib().ddq_mrhs_set_launch(lat.handle, int(order), int(lds_kb)), "ddq_mrhs_set_launch")
-
-
-def apply_schur_noalloc(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor, dagger: bool = False) -> torch.Tensor:
-    """y_e = D_S x_e (or D_S^H x_e) with the library's fixed work space: the call itself
-    allocates nothing, so the caller passes y_e."""
-    n = _nrhs_parity(lat, x_e)
-    if y_e.dtype != x_e.dtype or y_e.shape != x_e.shape:
-        raise ValueError("x_e and y_e must match in dtype and shape")
-    lat.sync_stream()
-    check(lib().ddq_apply_schur_noalloc(lat.handle, _prec(x_e), n, _dev(x_e, "x_e"), _dev(y_e, "y_e"),
-                                        int(bool(dagger))), "ddq_apply_schur_noalloc")
-    return y_e
+def mrhs_set_launch(lat: Lattice, order: int = 1, lds_kb: int = 0, tsteps: int = 0, stage: int = 1) -> None:
+    """Workgroup order of the mrhs stencil (0 plain, 1 slab, 2 t walk of tsteps slices),
+    the LDS requested per workgroup (an occupancy cap) and LDS staging of links and clover."""
+    check(lib().ddq_mrhs_set_launch(lat.handle, int(order), int(lds_kb), int(tsteps), int(stage)),
+          "ddq_mrhs_set_launch")
 
 
 def richardson_smooth(lat: Lattice, x_e: torch.Tensor, b_e: torch.Tensor, nsweeps: int, omega: float) -> torch.Tensor:

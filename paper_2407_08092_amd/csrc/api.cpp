@@ -174,7 +174,9 @@ struct ddq_lattice {
   std::vector<int> kind_n;
 
   // launch settings of the mrhs-layout stencil (ddq_mrhs_set_launch)
-  int mrhs_order = MRHS_ORDER_SLAB, mrhs_lds_kb = 0;
+  int mrhs_order = MRHS_ORDER_SLAB, mrhs_lds_kb = 0, mrhs_tsteps = 0, mrhs_stage = 1;
+  // the 16-bit stencil reads the FP32 clover blocks (ddq_set_h16_clover)
+  bool h16_clover32 = false;
 
   // FP32 multi-right-hand-side tiles by right-hand-side count (ddq_tune_multi_rhs)
   std::vector<std::pair<int, MrTile>> tiles;
@@ -243,8 +245,10 @@ double hop_bytes(const ddq_lattice* L, int prec, int mode, int nrhs) {
     case M_RESID: spin = 4; break;                // in, x, b, out
     case M_PREP: spin = 3; clover = false; break; // in, b, out
   }
-  if (is16(prec))  // 12-real links, clover padded to 40 slots, 4 bytes per complex
-    return (double)(12 * spin * nrhs + 48 + (clover ? 40 : 0)) * 4 * (double)L->Vh;
+  if (is16(prec)) {  // 12-real links, 4 bytes per complex; clover: 40 padded 16-bit slots or 36 FP32 pairs
+    const double cl = !clover ? 0.0 : (L->h16_clover32 ? 36.0 * 8 : 40.0 * 4);
+    return ((double)(12 * spin * nrhs + 48) * 4 + cl) * (double)L->Vh;
+  }
   const int link = (prec == DDQ_F32 && L->link12) ? 48 : 72;
   const double per_site = (double)(12 * spin * nrhs + link + (clover ? 36 : 0)) * (prec == DDQ_F64 ? 16 : 8);
   return per_site * (double)L->Vh;
@@ -353,6 +357,7 @@ hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* i
   a.in = (const u4_t*)in;
   a.links = (const u4_t*)L->links[prec][p_out];
   a.clov = (const u4_t*)L->clov[prec][p_out];
+  a.clov32 = L->h16_clover32 ? (const f2_t*)L->clov[DDQ_F32][p_out] : nullptr;
   a.x = (const u4_t*)x;
   a.b = (const u4_t*)b;
   a.out = (u4_t*)out;
@@ -363,6 +368,7 @@ hipError_t run_hop16(ddq_lattice* L, int prec, int nrhs, int mode, const void* i
   a.chunk = t ? t->xmap : XMAP_SLAB;
   if (!L->prof_on || g_no_alloc_call) return launch_hop16(h16_kind(prec), a, mode, L->stream);
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_BF16 ? "_bf16" : "_f16") +
+                     (L->h16_clover32 ? "_c32" : "") +
                      (nrhs > 1 ? "_x" + std::to_string(nrhs) : "");
   return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
                      [&]() { return launch_hop16(h16_kind(prec), a, mode, L->stream); });
@@ -404,9 +410,11 @@ hipError_t run_mrhs(ddq_lattice* L, int nrhs, int mode, int engine, const void* 
   a.engine = engine;
   a.order = L->mrhs_order;
   a.lds_kb = L->mrhs_lds_kb;
+  a.tsteps = L->mrhs_order == MRHS_ORDER_TWALK ? L->mrhs_tsteps : 0;
+  a.stage = L->mrhs_stage;
   if (!L->prof_on || g_no_alloc_call) return launch_hop_mrhs(a, mode, L->stream);
   std::string name = std::string(mode_name(mode)) + (a.link12 ? "_f32l12" : "_f32") + "_mrhs" +
-                     std::to_string(nrhs) + (engine == MRHS_ENGINE_MFMA ? "_mfma" : "_valu");
+                     std::to_string(nrhs) + (engine == MRHS_ENGINE_MFMA ? "_mfma" : "_valu") + (a.stage ? "_st" : "");
   return prof_launch(L, name, hop_bytes(L, DDQ_F32, mode, nrhs), [&]() { return launch_hop_mrhs(a, mode, L->stream); });
 }
 
@@ -710,6 +718,7 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
     }
   } else {
     for (int q = 0; q < 2; ++q) dfree(L->links[DDQ_F32][q]);
+    L->h16_clover32 = false;  // no FP32 clover blocks without FP32 storage
   }
   // 16-bit storage: 12-real links, 3 element rows per direction
   const size_t n16 = (size_t)4 * 3 * field_vh((int)L->Vh) * 16;
@@ -883,6 +892,14 @@ int check_engine(int engine) {
 }
 }  // namespace
 
+int ddq_set_h16_clover(ddq_lattice* L, int fp32) {
+  CHK(check_lat(L));
+  if (fp32 != 0 && fp32 != 1) return fail(DDQ_ERR_ARG, "fp32 must be 0 or 1");
+  if (fp32 && !L->links[DDQ_F32][0]) return fail(DDQ_ERR_STATE, "FP32 clover blocks need DDQ_STORE_F32");
+  L->h16_clover32 = fp32 != 0;
+  return DDQ_OK;
+}
+
 int ddq_mrhs_pack(ddq_lattice* L, int nrhs, const void* src, void* dst) {
   CHK(check_lat(L));
   if (nrhs < 1 || nrhs > MRHS_MAX_NRHS || !src || !dst) return fail(DDQ_ERR_ARG, "bad mrhs pack arguments");
@@ -899,12 +916,18 @@ int ddq_mrhs_unpack(ddq_lattice* L, int nrhs, const void* src, void* dst) {
   return DDQ_OK;
 }
 
-int ddq_mrhs_set_launch(ddq_lattice* L, int order, int lds_kb) {
+int ddq_mrhs_set_launch(ddq_lattice* L, int order, int lds_kb, int tsteps, int stage) {
   CHK(check_lat(L));
-  if (order != MRHS_ORDER_PLAIN && order != MRHS_ORDER_SLAB) return fail(DDQ_ERR_ARG, "order must be 0 or 1");
+  if (order != MRHS_ORDER_PLAIN && order != MRHS_ORDER_SLAB && order != MRHS_ORDER_TWALK)
+    return fail(DDQ_ERR_ARG, "order must be 0, 1 or 2");
   if (lds_kb < 0 || lds_kb > 160) return fail(DDQ_ERR_ARG, "lds_kb must be in [0, 160]");
+  if (order == MRHS_ORDER_TWALK && (tsteps < 1 || tsteps > L->dims[3] / 2))
+    return fail(DDQ_ERR_ARG, "tsteps must be in [1, Lt / 2] for the t walk");
+  if (stage != 0 && stage != 1) return fail(DDQ_ERR_ARG, "stage must be 0 or 1");
+  L->mrhs_stage = stage;
   L->mrhs_order = order;
   L->mrhs_lds_kb = lds_kb;
+  L->mrhs_tsteps = order == MRHS_ORDER_TWALK ? tsteps : 0;
   return DDQ_OK;
 }
 

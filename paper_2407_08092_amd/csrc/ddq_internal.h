@@ -131,7 +131,7 @@ hipError_t launch_hop_rb(const HopArgs<float>& a, int mode, int nrhs, hipStream_
 // element (i, k, r) at (6 i + k) nrhs + r; modes M_HOP_CLINV, M_APPLY, M_RICH, not
 // daggered.  The host fills everything up to lds_kb; launch_hop_mrhs derives the rest.
 enum { MRHS_ENGINE_VALU = 0, MRHS_ENGINE_MFMA = 1 };
-enum { MRHS_ORDER_PLAIN = 0, MRHS_ORDER_SLAB = 1 };
+enum { MRHS_ORDER_PLAIN = 0, MRHS_ORDER_SLAB = 1, MRHS_ORDER_TWALK = 2 };
 constexpr int MRHS_MAX_NRHS = 256;
 struct MrhsArgs {
   Geo g;
@@ -148,6 +148,8 @@ struct MrhsArgs {
   int engine;   // MRHS_ENGINE_*: SU(3) products on the vector units or the matrix cores
   int order;    // MRHS_ORDER_*: workgroup order
   int lds_kb;   // LDS requested per workgroup (unused; caps resident workgroups)
+  int tsteps;   // > 0: t walk, each wavefront takes that many slices of one parity of t
+  int stage;    // 1: links and clover slots staged in LDS, shared by the lanes of a site
   // derived by mrhs_geometry
   int ngroups;  // right-hand-side groups (one workgroup each per site group)
   int rgs;      // right-hand sides per group (<= 16)
@@ -169,6 +171,7 @@ struct Hop16Args {
   const u4_t* in;
   const u4_t* links;
   const u4_t* clov;
+  const f2_t* clov32;  // non-null: read the FP32 clover blocks (CLOVER_ROWS rows) instead of clov
   const u4_t* x;
   const u4_t* b;
   u4_t* out;

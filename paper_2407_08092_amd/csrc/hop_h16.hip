@@ -154,7 +154,9 @@ __device__ __forceinline__ void set_block_rows(Spinor<float>& s, int b, const cp
 // One thread per output site and NB right-hand sides; workgroup blk covers 256 sites
 // of one group of NB right-hand sides (tile_site); the links and clover slots of the
 // site are loaded once for the NB spinors.
-template <typename S, int MODE, int NB>
+// C32: the clover blocks come from the FP32 field (CLOVER_ROWS complex rows, two per
+// 16-byte element) instead of the 16-bit one
+template <typename S, int MODE, int NB, bool C32>
 __global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(NB > 1 ? 2 : 4)))
 hop16_kernel(Hop16Args a) {
   const int vh = a.g.Vh;
@@ -182,15 +184,22 @@ hop16_kernel(Hop16Args a) {
     steps16<0, S, NB>(acc, r, ub, c, in);
   }
 
-  const Field cl = bfield(a.clov, CL16_E, vh);
-  const uint32_t coff = boff(i, CL16_E);
+  constexpr int CL_E = C32 ? CLOVER_ROWS / CPE<float> : CL16_E;
+  const Field cl = bfield(C32 ? (const void*)a.clov32 : (const void*)a.clov, CL_E, vh);
+  const uint32_t coff = boff(i, CL_E);
   const uint32_t off = voff(i);
+  auto slots = [&](int b, cpx<float>(&sl)[20]) {
+    if constexpr (C32)
+      load_rows<float, DDQ_STREAM_AUX>(cl, 18 * b, 18, coff, sl);
+    else
+      clover_slots16<S>(cl, coff, b, sl);
+  };
   // epilogue: per right-hand side, both clover blocks (their slots loaded once
   // for the NB spinors; with one right-hand side, block by block)
   cpx<float> sl[2][20];
   if constexpr (NB > 1) {
-    clover_slots16<S>(cl, coff, 0, sl[0]);
-    clover_slots16<S>(cl, coff, 1, sl[1]);
+    slots(0, sl[0]);
+    slots(1, sl[1]);
   }
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
@@ -201,7 +210,7 @@ hop16_kernel(Hop16Args a) {
     Spinor<float> res;
 #pragma unroll
     for (int b = 0; b < 2; ++b) {
-      if constexpr (NB == 1) clover_slots16<S>(cl, coff, b, sl[b]);
+      if constexpr (NB == 1) slots(b, sl[b]);
       cpx<float> h[6], o[6];
       block_rows(acc[q], b, h);
 #pragma unroll
@@ -228,18 +237,23 @@ hop16_kernel(Hop16Args a) {
   }
 }
 
+template <typename S, int NB, bool C32>
+static hipError_t launch16_c(const Hop16Args& a, int mode, dim3 grid, dim3 block, hipStream_t s) {
+  switch (mode) {
+    case M_HOP_CLINV: hipLaunchKernelGGL((hop16_kernel<S, M_HOP_CLINV, NB, C32>), grid, block, 0, s, a); break;
+    case M_APPLY: hipLaunchKernelGGL((hop16_kernel<S, M_APPLY, NB, C32>), grid, block, 0, s, a); break;
+    case M_RICH: hipLaunchKernelGGL((hop16_kernel<S, M_RICH, NB, C32>), grid, block, 0, s, a); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename S, int NB>
 static hipError_t launch16_nb(const Hop16Args& a, int mode, hipStream_t s) {
   const long long nb = tile_grid_sites(a.g, HOP_BLOCK, a.nrhs / NB, a.chunk);
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(HOP_BLOCK);
-  switch (mode) {
-    case M_HOP_CLINV: hipLaunchKernelGGL((hop16_kernel<S, M_HOP_CLINV, NB>), grid, block, 0, s, a); break;
-    case M_APPLY: hipLaunchKernelGGL((hop16_kernel<S, M_APPLY, NB>), grid, block, 0, s, a); break;
-    case M_RICH: hipLaunchKernelGGL((hop16_kernel<S, M_RICH, NB>), grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-  }
-  return hipGetLastError();
+  return a.clov32 ? launch16_c<S, NB, true>(a, mode, grid, block, s) : launch16_c<S, NB, false>(a, mode, grid, block, s);
 }
 
 template <typename S>

@@ -136,3 +136,42 @@ def test_16bit_errors():
     with pytest.raises(api.DDQError):  # a 16-bit smoother under an FP64 inner solve
         api.oe_gmres_solve(c.lat, b, m=8, inner_prec=api.DDQ_F64, smoother_sweeps=2, omega=omega,
                            smoother_prec=api.DDQ_F16)
+
+
+@pytest.mark.parametrize("dims", DIMS)
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f16", "bf16"])
+def test_fp32_clover_variant(dims, dtype):
+    # 16-bit links and spinors with the FP32 clover blocks: the same bars (one rounding
+    # fewer per apply), and the profiler counts 36 FP32 slot pairs per site
+    c, omega = case(dims)
+    x, b = c.vec(92, 2), c.vec(93, 2)
+    api.set_h16_clover(c.lat, True)
+    try:
+        api.profile_begin(c.lat)
+        y = api.apply_schur(c.lat, to_dev16(x, dtype))
+        stats = api.profile_end(c.lat)
+        xs = to_dev16(x, dtype)
+        api.richardson_smooth(c.lat, xs, to_dev16(b, dtype), 3, omega)
+        torch.cuda.synchronize()
+    finally:
+        api.set_h16_clover(c.lat, False)
+    ref = np.stack([c.op.schur(x[r]) for r in range(2)])
+    assert per_rhs_err(to_host(y), ref) < 10 * U_ROUND[dtype]
+    ref = np.stack([solvers.richardson(c.op.schur, b[r], x[r], 3, omega) for r in range(2)])
+    assert per_rhs_err(to_host(xs), ref) < 30 * U_ROUND[dtype]
+    tag = "bf16" if dtype == torch.bfloat16 else "f16"
+    vh = c.olat.Vh
+    per_site = {f"hop_clinv_{tag}_c32_x2": (2 * 24 + 48) * 4 + 36 * 8, f"hop_apply_{tag}_c32_x2": (2 * 36 + 48) * 4 + 36 * 8}
+    for name, bps in per_site.items():
+        assert name in stats, list(stats)
+        assert stats[name]["bytes_per_launch"] == bps * vh
+
+
+def test_fp32_clover_needs_fp32_storage():
+    c, _ = case((4, 4, 4, 4))
+    lat = api.create_lattice((4, 4, 4, 4))
+    api.set_gauge(lat, torch.from_numpy(c.U).cuda(), store=(api.DDQ_F64, api.DDQ_F16))
+    api.set_clover(lat, 1.0, -0.2)
+    with pytest.raises(api.DDQError) as e:
+        api.set_h16_clover(lat, True)
+    assert e.value.status == -2

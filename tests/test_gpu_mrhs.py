@@ -74,24 +74,34 @@ APPLY_CASES = [((4, 4, 4, 4), 1), ((4, 4, 4, 4), 12), ((4, 6, 8, 10), 2), ((4, 6
                ((8, 8, 8, 16), 8), ((8, 8, 8, 16), 13), ((8, 8, 8, 16), 32), ((2, 2, 2, 2), 4)]
 
 
+@pytest.mark.parametrize("stage", [0, 1], ids=["direct", "staged"])
 @pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
 @pytest.mark.parametrize("dims,n", APPLY_CASES)
-def test_apply_matches_oracle(dims, n, engine):
+def test_apply_matches_oracle(dims, n, engine, stage):
     c = case(dims)
     x = c.vec(302, n)
-    y = api.mrhs_apply_schur(c.lat, to_mrhs(x), engine=engine)
-    torch.cuda.synchronize()
+    api.mrhs_set_launch(c.lat, 1, 0, 0, stage)
+    try:
+        y = api.mrhs_apply_schur(c.lat, to_mrhs(x), engine=engine)
+        torch.cuda.synchronize()
+    finally:
+        api.mrhs_set_launch(c.lat, 1, 0)
     ref = np.stack([c.op.schur(x[r]) for r in range(n)])
     assert per_rhs(from_mrhs(y), ref) < 1e-5
 
 
+@pytest.mark.parametrize("stage", [0, 1], ids=["direct", "staged"])
 @pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
 @pytest.mark.parametrize("n", [4, 12])
-def test_apply_link12(n, engine):
+def test_apply_link12(n, engine, stage):
     c = case((6, 6, 6, 10), link12=True)
     x = c.vec(303, n)
-    y = api.mrhs_apply_schur(c.lat, to_mrhs(x), engine=engine)
-    torch.cuda.synchronize()
+    api.mrhs_set_launch(c.lat, 1, 0, 0, stage)
+    try:
+        y = api.mrhs_apply_schur(c.lat, to_mrhs(x), engine=engine)
+        torch.cuda.synchronize()
+    finally:
+        api.mrhs_set_launch(c.lat, 1, 0)
     ref = np.stack([c.op.schur(x[r]) for r in range(n)])
     assert per_rhs(from_mrhs(y), ref) < 1e-5
 
@@ -110,26 +120,53 @@ def test_richardson_matches_oracle(dims, n, engine):
     assert per_rhs(from_mrhs(x), ref) < 1e-5
 
 
+LAUNCHES = [(0, 0, 0, 0), (0, 48, 0, 0), (1, 0, 0, 0), (1, 48, 0, 0), (2, 0, 1, 0), (2, 0, 2, 0), (2, 32, 3, 0),
+            (2, 0, 5, 0), (1, 0, 0, 1), (0, 0, 0, 1), (2, 0, 3, 1), (2, 64, 5, 1)]
+
+
 @pytest.mark.parametrize("n", [3, 12, 24])
 def test_engines_agree_and_orders_are_bitwise_equal(n):
+    # plain, slab and t-walk orders (walks of 1, 2, 3 and 5 = Lt / 2 slices) with and
+    # without an LDS cap: every lane's arithmetic is the same, so results are bitwise equal
     c = case((6, 6, 6, 10))
     x = to_mrhs(c.vec(306, n))
     ys = {}
     for engine in ENGINES:
-        for order in (0, 1):
-            for lds in (0, 48):
-                api.mrhs_set_launch(c.lat, order, lds)
-                ys[(engine, order, lds)] = api.mrhs_apply_schur(c.lat, x, engine=engine)
+        for order, lds, ts, stage in LAUNCHES:
+            api.mrhs_set_launch(c.lat, order, lds, ts, stage)
+            ys[(engine, order, lds, ts, stage)] = api.mrhs_apply_schur(c.lat, x, engine=engine)
     api.mrhs_set_launch(c.lat, 1, 0)
     torch.cuda.synchronize()
     for engine in ENGINES:
-        ref = ys[(engine, 1, 0)]
+        ref = ys[(engine, 1, 0, 0, 0)]
         for key, y in ys.items():
             if key[0] == engine:
                 assert torch.equal(y, ref), key  # the arithmetic of a lane does not depend on the order
-    a = from_mrhs(ys[(0, 1, 0)])
-    b = from_mrhs(ys[(1, 1, 0)])
+    a = from_mrhs(ys[(0, 1, 0, 0, 0)])
+    b = from_mrhs(ys[(1, 1, 0, 0, 0)])
     assert per_rhs(b, a) < 2e-6  # two FP32 summation orders of the same sums
+
+
+@pytest.mark.parametrize("stage", [0, 1], ids=["direct", "staged"])
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+@pytest.mark.parametrize("dims,n,ts", [((4, 6, 8, 10), 12, 1), ((4, 6, 8, 10), 5, 3), ((8, 8, 8, 16), 12, 8),
+                                       ((8, 8, 8, 16), 20, 3), ((2, 2, 2, 2), 4, 1)])
+def test_twalk_matches_oracle(dims, n, ts, engine, stage):
+    c = case(dims)
+    api.mrhs_set_launch(c.lat, 2, 0, ts, stage)
+    try:
+        x = c.vec(310, n)
+        y = api.mrhs_apply_schur(c.lat, to_mrhs(x), engine=engine)
+        b = c.vec(311, n)
+        z = to_mrhs(x)
+        api.mrhs_richardson_smooth(c.lat, z, to_mrhs(b), 3, 0.12, engine=engine)
+        torch.cuda.synchronize()
+    finally:
+        api.mrhs_set_launch(c.lat, 1, 0)
+    ref = np.stack([c.op.schur(x[r]) for r in range(n)])
+    assert per_rhs(from_mrhs(y), ref) < 1e-5
+    ref = np.stack([solvers.richardson(c.op.schur, b[r], x[r], 3, 0.12) for r in range(n)])
+    assert per_rhs(from_mrhs(z), ref) < 1e-5
 
 
 def test_matches_planar_multi_rhs_kernels():
@@ -154,8 +191,11 @@ def test_argument_errors():
     assert L.ddq_mrhs_apply_schur(c.lat.handle, 0, px, py, 0) == -1
     assert L.ddq_mrhs_apply_schur(c.lat.handle, 4, px, px, 0) == -1  # x and y overlap
     assert L.ddq_mrhs_richardson_smooth(c.lat.handle, 4, px, px, 1, 0.1, 0) == -1
-    assert L.ddq_mrhs_set_launch(c.lat.handle, 2, 0) == -1
-    assert L.ddq_mrhs_set_launch(c.lat.handle, 1, 161) == -1
+    assert L.ddq_mrhs_set_launch(c.lat.handle, 3, 0, 0, 0) == -1
+    assert L.ddq_mrhs_set_launch(c.lat.handle, 1, 161, 0, 0) == -1
+    assert L.ddq_mrhs_set_launch(c.lat.handle, 2, 0, 0, 0) == -1  # a t walk of no slices
+    assert L.ddq_mrhs_set_launch(c.lat.handle, 2, 0, 3, 0) == -1  # more than Lt / 2 = 2
+    assert L.ddq_mrhs_set_launch(c.lat.handle, 1, 0, 0, 2) == -1
     assert L.ddq_mrhs_pack(c.lat.handle, 4, px, px) == -1
     # beyond the reservation: DDQ_ERR_STATE, nothing allocated
     big = to_mrhs(c.vec(309, 200))

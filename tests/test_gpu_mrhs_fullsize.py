@@ -37,9 +37,14 @@ def per_rhs(a, b):
     return max(rel(a[r].cpu().numpy(), b[r].cpu().numpy()) for r in range(b.shape[0]))
 
 
+LAUNCH = [(1, 0, 0, 0), (2, 0, 6, 0), (2, 64, 24, 0), (1, 0, 0, 1), (2, 0, 2, 1)]
+
+
+@pytest.mark.parametrize("launch", LAUNCH, ids=["slab", "twalk6", "twalk24_lds64", "slab_staged", "twalk2_staged"])
 @pytest.mark.parametrize("engine", [api.DDQ_ENGINE_VALU, api.DDQ_ENGINE_MFMA], ids=["valu", "mfma"])
-def test_fullsize_apply_matches_single_rhs_kernel(engine):
+def test_fullsize_apply_matches_single_rhs_kernel(engine, launch):
     lat, x = _setup()
+    api.mrhs_set_launch(lat, *launch)
     ref = torch.stack([api.apply_schur(lat, x[r].contiguous()) for r in range(N)])
     xm = api.mrhs_pack(lat, x)
     y1 = api.mrhs_apply_schur(lat, xm, engine=engine)
@@ -47,12 +52,15 @@ def test_fullsize_apply_matches_single_rhs_kernel(engine):
     torch.cuda.synchronize()
     assert torch.equal(y1, y2)
     got = api.mrhs_unpack(lat, y1)
+    api.mrhs_set_launch(lat, 1, 0)
     assert per_rhs(got, ref) < 2e-6
 
 
+@pytest.mark.parametrize("launch", LAUNCH, ids=["slab", "twalk6", "twalk24_lds64", "slab_staged", "twalk2_staged"])
 @pytest.mark.parametrize("engine", [api.DDQ_ENGINE_VALU, api.DDQ_ENGINE_MFMA], ids=["valu", "mfma"])
-def test_fullsize_sweeps_match_single_rhs_kernel(engine):
+def test_fullsize_sweeps_match_single_rhs_kernel(engine, launch):
     lat, x = _setup()
+    api.mrhs_set_launch(lat, *launch)
     b = x.flip(0).contiguous()
     omega = 0.15
     ref = x.clone()
@@ -61,4 +69,5 @@ def test_fullsize_sweeps_match_single_rhs_kernel(engine):
     xm = api.mrhs_pack(lat, x)
     api.mrhs_richardson_smooth(lat, xm, api.mrhs_pack(lat, b), 3, omega, engine=engine)
     torch.cuda.synchronize()
+    api.mrhs_set_launch(lat, 1, 0)
     assert per_rhs(api.mrhs_unpack(lat, xm), ref) < 5e-6

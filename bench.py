@@ -28,6 +28,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-solve] [--no-ba
                                            prints its own JSON, not the benchmark line)
        python bench.py --batch-only       (profiling run: that apply and the batched solves, own JSON)
        python bench.py --mrhs-only        (profiling run: only the interleaved-layout 12-right-hand-side stencil)
+       python bench.py --headline-only    (profiling run: only the timed FP32 step on 48^3 x 96, own JSON)
 """
 from __future__ import annotations
 
@@ -59,13 +60,14 @@ MODE_CODE = {"clinv": 0, "recon": 1, "apply": 2, "richardson": 3, "resid": 4, "p
 KERNEL_SOURCES = ("paper_2407_08092_amd/csrc/hop.hip", "paper_2407_08092_amd/csrc/hop_common.h",
                   "paper_2407_08092_amd/csrc/ddq_device.h",
                   "paper_2407_08092_amd/csrc/ddq_internal.h")
-PROFILE = "profiles/hop_kernels_48x96.md"
+PROFILE = "profiles/hop_fp32_step_48x96.md"
 
 
-def measured_traffic(kernel_name: str):
-    """HBM traffic per launch of a stencil kernel from the committed rocprofv3 counter
-    summary (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a copy kernel), or None when
-    the kernel sources changed since the counters were taken."""
+def measured_traffic(kernel_name: str, bytes_per_launch: float):
+    """Traffic past L2 per launch of a stencil kernel: its algorithmic bytes times the ratio
+    of counter traffic (FETCH_SIZE x 2 + WRITE_SIZE, calibrated on a copy kernel) to
+    algorithmic bytes in the committed rocprofv3 summary; None when the kernel sources
+    changed since the counters were taken."""
     import hashlib
 
     h = hashlib.sha1()
@@ -85,8 +87,8 @@ def measured_traffic(kernel_name: str):
         return None
     for ln in lines:
         f = ln.split()
-        if len(f) == 4 and f[0] == "traffic_bytes_per_launch" and f[1] == key and f[3] == cur:
-            return float(f[2])
+        if len(f) == 4 and f[0] == "traffic_over_algorithmic" and f[1] == key and f[3] == cur:
+            return float(f[2]) * bytes_per_launch
     return None
 
 
@@ -131,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multi-rhs-only", action="store_true")
     ap.add_argument("--mrhs-only", action="store_true")
+    ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--coarse-only", action="store_true")
     ap.add_argument("--coarse-nv", type=int, nargs="+", default=[24, 20])
@@ -217,14 +220,19 @@ def main():
         step()
     torch.cuda.synchronize()
     evs = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
-    api.profile_begin(lat)
+    # the library's per-kernel profiler brackets every launch of the first timed step with
+    # HIP events on the lattice's stream (an event pair per launch costs a few microseconds,
+    # which over the 546 launches of a step would slow every step by ~10%)
     torch.cuda.synchronize()
     t_start = time.perf_counter()
     for k in range(args.steps):
+        if k == 0:
+            api.profile_begin(lat)
         step(evs[k])
+        if k == 0:
+            prof = api.profile_end(lat)
     torch.cuda.synchronize()
     t_wall = time.perf_counter() - t_start
-    prof = api.profile_end(lat)
     t_apply = sum(e[0].elapsed_time(e[1]) for e in evs) / args.steps  # ms
     t_sweeps = sum(e[1].elapsed_time(e[2]) for e in evs) / args.steps
     gbs = BYTES_APPLY_F32 * vh / (t_apply * 1e-3) / 1e9
@@ -235,7 +243,7 @@ def main():
     # dominant kernel of the timed region
     name, st = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
     ach = st["bytes_per_launch"] / (st["mean_ms"] * 1e-3) / 1e9
-    traffic = measured_traffic(name)
+    traffic = measured_traffic(name, st["bytes_per_launch"])
     roof = {"bound": "hbm", "kernel": name, "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "traffic_over_algorithmic": round(traffic / st["bytes_per_launch"], 3) if traffic else None,
@@ -244,6 +252,28 @@ def main():
             "all_kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
                                 "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
                             for k, v in prof.items()}}
+
+    if args.headline_only:  # profiling run: the timed FP32 step only, its own JSON
+        print(json.dumps({"apply_ms": round(t_apply, 4), "apply_GBs": round(gbs, 1),
+                          "sweeps_per_s": round(sweeps_per_s, 1), "roofline": roof}), flush=True)
+        return
+
+    # the same apply and sweeps as one launch per kernel (no t-chunks): what the chunked
+    # launches gain by reading u_o back from the Infinity Cache
+    api.set_sweep_chunks(lat, 1)
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    ev1 = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        step(ev1[k])
+    torch.cuda.synchronize()
+    api.set_sweep_chunks(lat, 0)
+    t1a = sum(e[0].elapsed_time(e[1]) for e in ev1) / args.steps
+    t1s = sum(e[1].elapsed_time(e[2]) for e in ev1) / args.steps
+    one_launch = {"apply_ms": round(t1a, 4), "apply_GBs": round(BYTES_APPLY_F32 * vh / (t1a * 1e-3) / 1e9, 1),
+                  "sweeps_per_s": round(SWEEPS / (t1s * 1e-3), 1)}
+    log(f"one launch per kernel (no t-chunks): {one_launch}")
 
     # the streaming ceiling of each stencil kernel's byte mix on the same fields
     mix = stencil_stream_ceiling(api, torch, lat, x32, xs, b32, y32, args.steps)
@@ -386,6 +416,10 @@ def main():
         "pct_of_stream_copy": round(100 * gbs / stream_gbs, 2),
         "schur_apply_ms": round(t_apply, 4),
         "sweeps_per_s": round(sweeps_per_s, 1),
+        "t_chunks": "FP32 one-right-hand-side apply and sweeps launched per range of t-slices (13 ranges, "
+                    "u_o of a range about 40 MiB, read back from the Infinity Cache); one_launch: the same "
+                    "with one launch per kernel",
+        "one_launch": one_launch,
         "fp32_link12": link12,
         "storage_16bit": h16,
         "fp64": fp64,

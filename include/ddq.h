@@ -185,6 +185,17 @@ int ddq_apply_schur_noalloc(ddq_lattice* lat, int prec, int nrhs, const void* x_
 int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const void* b_e,
                           int nsweeps, double omega);
 
+/* One-right-hand-side Richardson sweeps and Schur applies (FP64 / FP32
+ * ddq_richardson_smooth and ddq_apply_schur with nrhs = 1, daggered too) on nc ranges of
+ * t-slices (1 <= nc <= Lt; 0, the default, chooses nc so that one range's u_o is about
+ * 40 MiB: 13 for FP32 at 48^3 x 96, 1 up to 28^3 x 56): each launches kernel A and kernel
+ * B per range, ordered so that the result is that of eq. 3 / Alg. 4 bit for bit (every B
+ * reads u_o of the old x; every A reads x before its neighbour range is updated) while the
+ * u_o rows of a range are read one launch after they were written, from the Infinity
+ * Cache instead of HBM.  The interleaved multi-right-hand-side calls (ddq_mrhs_*) use the
+ * ranges only when nc > 0 is set here, and never with their t walk. */
+int ddq_set_sweep_chunks(ddq_lattice* lat, int nc);
+
 /* Clover blocks of the 16-bit (DDQ_F16 / DDQ_BF16) stencil: fp32 = 0 reads the 16-bit
  * copies of A_ee and A_oo^-1 (rounded from FP64, 944 bytes per even site per Schur
  * apply in all), fp32 = 1 the FP32 blocks (links and spinors stay 16-bit: 1,200 bytes

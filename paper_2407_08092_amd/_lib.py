@@ -69,6 +69,7 @@ _SIGNATURES = {
     "ddq_apply_schur": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_apply_schur_noalloc": [_P, C.c_int, C.c_int, _P, _P, C.c_int],
     "ddq_set_h16_clover": [_P, C.c_int],
+    "ddq_set_sweep_chunks": [_P, C.c_int],
     "ddq_mrhs_pack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_unpack": [_P, C.c_int, _P, _P],
     "ddq_mrhs_apply_schur": [_P, C.c_int, _P, _P, C.c_int],

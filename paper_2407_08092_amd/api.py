@@ -245,6 +245,11 @@ def apply_schur_noalloc(lat: Lattice, x_e: torch.Tensor, y_e: torch.Tensor, dagg
     return y_e
 
 
+def set_sweep_chunks(lat: Lattice, nc: int) -> None:
+    """One-right-hand-side Richardson sweeps launched on nc ranges of t-slices."""
+    check(lib().ddq_set_sweep_chunks(lat.handle, int(nc)), "ddq_set_sweep_chunks")
+
+
 def set_h16_clover(lat: Lattice, fp32: bool) -> None:
     """The 16-bit stencil reads FP32 clover blocks (fp32) or their 16-bit copies."""
     check(lib().ddq_set_h16_clover(lat.handle, int(bool(fp32))), "ddq_set_h16_clover")

@@ -177,6 +177,9 @@ struct ddq_lattice {
   int mrhs_order = MRHS_ORDER_SLAB, mrhs_lds_kb = 0, mrhs_tsteps = 0, mrhs_stage = 1;
   // the 16-bit stencil reads the FP32 clover blocks (ddq_set_h16_clover)
   bool h16_clover32 = false;
+  // one-right-hand-side sweeps and applies on this many t-chunks (ddq_set_sweep_chunks;
+  // 0: chosen from the lattice size)
+  int sweep_chunks = 0;
 
   // FP32 multi-right-hand-side tiles by right-hand-side count (ddq_tune_multi_rhs)
   std::vector<std::pair<int, MrTile>> tiles;
@@ -304,8 +307,9 @@ hipError_t prof_launch(ddq_lattice* L, const std::string& name, double bytes, F 
     L->kind_name.push_back(name);
     L->kind_ms.push_back(0.0);
     L->kind_n.push_back(0);
-    L->kind_bytes.push_back(bytes);
+    L->kind_bytes.push_back(0.0);
   }
+  L->kind_bytes[kind] += bytes;  // summed over launches (chunked launches differ in size)
   if (L->ev_used * 2 == (int)L->ev.size()) {
     if (L->ev.size() < 2048) {
       hipEvent_t e0, e1;
@@ -343,7 +347,8 @@ hipError_t run_hop(ddq_lattice* L, const HopArgs<R>& a, int mode, bool dag, int 
   }
   std::string name = std::string(mode_name(mode)) + (prec == DDQ_F64 ? "_f64" : (a.link12 ? "_f32l12" : "_f32")) +
                      (dag ? "_dag" : "") + (nrhs > 1 ? "_x" + std::to_string(nrhs) : "") + tile;
-  return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs),
+  const double share = a.t_cnt > 0 ? (double)a.t_cnt / L->dims[3] : 1.0;  // a chunk of t-slices
+  return prof_launch(L, name, hop_bytes(L, prec, mode, nrhs) * share,
                      [&]() { return launch_any<R>(L, a, mode, dag, nrhs); });
 }
 
@@ -391,9 +396,10 @@ int sweeps16(ddq_lattice* L, int prec, int nrhs, void* x, const void* b, int n, 
   return DDQ_OK;
 }
 
-// the mrhs-layout stencil: kernel A (M_HOP_CLINV) or kernel B (M_APPLY / M_RICH)
+// the mrhs-layout stencil: kernel A (M_HOP_CLINV) or kernel B (M_APPLY / M_RICH), on the
+// output sites of slices [t_lo, t_lo + t_cnt) when t_cnt > 0
 hipError_t run_mrhs(ddq_lattice* L, int nrhs, int mode, int engine, const void* in, const void* x, const void* b,
-                    void* out, float omega) {
+                    void* out, float omega, int t_lo = 0, int t_cnt = 0) {
   MrhsArgs a{};
   const int p_out = mode == M_HOP_CLINV ? 1 : 0;
   a.g = L->geo;
@@ -412,10 +418,14 @@ hipError_t run_mrhs(ddq_lattice* L, int nrhs, int mode, int engine, const void* 
   a.lds_kb = L->mrhs_lds_kb;
   a.tsteps = L->mrhs_order == MRHS_ORDER_TWALK ? L->mrhs_tsteps : 0;
   a.stage = L->mrhs_stage;
+  a.t_lo = t_lo;
+  a.t_cnt = t_cnt;
   if (!L->prof_on || g_no_alloc_call) return launch_hop_mrhs(a, mode, L->stream);
   std::string name = std::string(mode_name(mode)) + (a.link12 ? "_f32l12" : "_f32") + "_mrhs" +
                      std::to_string(nrhs) + (engine == MRHS_ENGINE_MFMA ? "_mfma" : "_valu") + (a.stage ? "_st" : "");
-  return prof_launch(L, name, hop_bytes(L, DDQ_F32, mode, nrhs), [&]() { return launch_hop_mrhs(a, mode, L->stream); });
+  const double share = t_cnt > 0 ? (double)t_cnt / L->dims[3] : 1.0;
+  return prof_launch(L, name, hop_bytes(L, DDQ_F32, mode, nrhs) * share,
+                     [&]() { return launch_hop_mrhs(a, mode, L->stream); });
 }
 
 template <typename R>
@@ -452,10 +462,63 @@ hipError_t kernel_B(ddq_lattice* L, int prec, int nrhs, int mode, const pair<R>*
   return run_hop<R>(L, a, mode, dag, nrhs);
 }
 
+// Chunks of t-slices for the one-right-hand-side sweeps and applies: the number set by
+// ddq_set_sweep_chunks, or (0, the default) enough that one chunk's u_o (V/2 x 12 complex
+// numbers of the precision) stays near 40 MiB, a small part of the 256 MB Infinity Cache.
+int chunks_for(const ddq_lattice* L, int prec) {
+  int nc = L->sweep_chunks;
+  if (nc == 0) {
+    const double u_bytes = (double)L->nvec() * (prec == DDQ_F64 ? 16.0 : 8.0);
+    nc = (int)std::ceil(u_bytes / (40.0 * 1024 * 1024));
+  }
+  return std::max(1, std::min(nc, L->dims[3]));
+}
+
+// One Richardson sweep (mode M_RICH: out = x in place) or Schur apply (M_APPLY: out = y) on
+// t-chunks: kernels A and B on the output sites of nc ranges of t-slices, ordered so that
+// every B reads only u_o of the old x and every A reads x before the B of the chunk next to
+// it updates it: A(nc-1), A(0), then per chunk c: A(c+1), B(c).  u_o of a chunk is read by
+// its B one launch after its A wrote it.
+template <typename R>
+int sweep_chunked(ddq_lattice* L, int prec, const pair<R>* x, const pair<R>* b, pair<R>* u, pair<R>* out, R omega,
+                  int nc, int mode, bool dag) {
+  const int lt = L->dims[3];
+  auto lo = [&](int c) { return (int)((long long)c * lt / nc); };
+  auto runA = [&](int c) -> hipError_t {
+    HopArgs<R> a = hop_args<R>(L, prec, 1);
+    a.in = x;
+    a.out = u;
+    a.t_lo = lo(c);
+    a.t_cnt = lo(c + 1) - lo(c);
+    return run_hop<R>(L, a, M_HOP_CLINV, dag, 1);
+  };
+  auto runB = [&](int c) -> hipError_t {
+    HopArgs<R> a = hop_args<R>(L, prec, 0);
+    a.in = u;
+    a.x = x;
+    a.b = b;
+    a.out = out;
+    a.omega = omega;
+    a.t_lo = lo(c);
+    a.t_cnt = lo(c + 1) - lo(c);
+    return run_hop<R>(L, a, mode, dag, 1);
+  };
+  HIPCHK(runA(nc - 1));
+  HIPCHK(runA(0));
+  for (int c = 0; c + 1 < nc; ++c) {
+    if (c + 1 < nc - 1) HIPCHK(runA(c + 1));
+    HIPCHK(runB(c));
+  }
+  HIPCHK(runB(nc - 1));
+  return DDQ_OK;
+}
+
 // u: work space for u_o (nrhs parity vectors of prec); null selects the lattice's own
 template <typename R>
 int schur(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, pair<R>* y, bool dag, pair<R>* u = nullptr) {
   if (!u) u = (pair<R>*)L->tmp[prec].p;
+  const int nc = nrhs == 1 ? chunks_for(L, prec) : 1;
+  if (nc > 1) return sweep_chunked<R>(L, prec, x, nullptr, u, y, R(0), nc, M_APPLY, dag);
   HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, dag));
   HIPCHK(kernel_B<R>(L, prec, nrhs, M_APPLY, u, x, nullptr, y, R(0), dag));
   return DDQ_OK;
@@ -472,7 +535,12 @@ int resid(ddq_lattice* L, int prec, int nrhs, const pair<R>* x, const pair<R>* b
 template <typename R>
 int sweeps(ddq_lattice* L, int prec, int nrhs, pair<R>* x, const pair<R>* b, int n, R omega) {
   pair<R>* u = (pair<R>*)L->tmp[prec].p;
+  const int nc = chunks_for(L, prec);
   for (int k = 0; k < n; ++k) {
+    if (nrhs == 1 && nc > 1) {
+      CHK(sweep_chunked<R>(L, prec, x, b, u, x, omega, nc, M_RICH, false));
+      continue;
+    }
     HIPCHK(kernel_A<R>(L, prec, nrhs, x, u, false));
     HIPCHK(kernel_B<R>(L, prec, nrhs, M_RICH, u, x, b, x, omega, false));
   }
@@ -892,6 +960,13 @@ int check_engine(int engine) {
 }
 }  // namespace
 
+int ddq_set_sweep_chunks(ddq_lattice* L, int nc) {
+  CHK(check_lat(L));
+  if (nc < 0 || nc > L->dims[3]) return fail(DDQ_ERR_ARG, "nc must be in [0, Lt]");
+  L->sweep_chunks = nc;
+  return DDQ_OK;
+}
+
 int ddq_set_h16_clover(ddq_lattice* L, int fp32) {
   CHK(check_lat(L));
   if (fp32 != 0 && fp32 != 1) return fail(DDQ_ERR_ARG, "fp32 must be 0 or 1");
@@ -931,16 +1006,41 @@ int ddq_mrhs_set_launch(ddq_lattice* L, int order, int lds_kb, int tsteps, int s
   return DDQ_OK;
 }
 
+// kernels A and B of the mrhs stencil on t-chunks in the order of sweep_chunked when
+// ddq_set_sweep_chunks asked for them (the default here is one range: at 24^3 x 48 with 12
+// right-hand sides, ranges measured slower — their launches are too small for the chip),
+// never with the t walk
+static int mrhs_pass(ddq_lattice* L, int nrhs, int engine, const void* x, const void* b, void* u, void* out,
+                     float omega, int mode) {
+  int nc = L->sweep_chunks > 0 ? L->sweep_chunks : 1;
+  nc = std::max(1, std::min(nc, L->dims[3]));
+  if (L->mrhs_order == MRHS_ORDER_TWALK) nc = 1;
+  if (nc == 1) {
+    HIPCHK(run_mrhs(L, nrhs, M_HOP_CLINV, engine, x, nullptr, nullptr, u, 0.f));
+    HIPCHK(run_mrhs(L, nrhs, mode, engine, u, x, b, out, omega));
+    return DDQ_OK;
+  }
+  const int lt = L->dims[3];
+  auto lo = [&](int c) { return (int)((long long)c * lt / nc); };
+  auto A = [&](int c) { return run_mrhs(L, nrhs, M_HOP_CLINV, engine, x, nullptr, nullptr, u, 0.f, lo(c), lo(c + 1) - lo(c)); };
+  auto B = [&](int c) { return run_mrhs(L, nrhs, mode, engine, u, x, b, out, omega, lo(c), lo(c + 1) - lo(c)); };
+  HIPCHK(A(nc - 1));
+  HIPCHK(A(0));
+  for (int c = 0; c + 1 < nc; ++c) {
+    if (c + 1 < nc - 1) HIPCHK(A(c + 1));
+    HIPCHK(B(c));
+  }
+  HIPCHK(B(nc - 1));
+  return DDQ_OK;
+}
+
 int ddq_mrhs_apply_schur(ddq_lattice* L, int nrhs, const void* x_e, void* y_e, int engine) {
   CHK(check_mrhs(L, nrhs));
   CHK(check_engine(engine));
   if (!x_e || !y_e) return fail(DDQ_ERR_ARG, "bad apply arguments");
   if (x_e == y_e) return fail(DDQ_ERR_ARG, "x_e and y_e must not overlap");
   CHK(ensure_tmp(L, DDQ_F32, nrhs));
-  void* u = L->tmp[DDQ_F32].p;
-  HIPCHK(run_mrhs(L, nrhs, M_HOP_CLINV, engine, x_e, nullptr, nullptr, u, 0.f));
-  HIPCHK(run_mrhs(L, nrhs, M_APPLY, engine, u, x_e, nullptr, y_e, 0.f));
-  return DDQ_OK;
+  return mrhs_pass(L, nrhs, engine, x_e, nullptr, L->tmp[DDQ_F32].p, y_e, 0.f, M_APPLY);
 }
 
 int ddq_mrhs_richardson_smooth(ddq_lattice* L, int nrhs, void* x_e, const void* b_e, int nsweeps, double omega,
@@ -951,10 +1051,7 @@ int ddq_mrhs_richardson_smooth(ddq_lattice* L, int nrhs, void* x_e, const void* 
   if (x_e == b_e) return fail(DDQ_ERR_ARG, "x_e and b_e must not overlap");
   CHK(ensure_tmp(L, DDQ_F32, nrhs));
   void* u = L->tmp[DDQ_F32].p;
-  for (int k = 0; k < nsweeps; ++k) {
-    HIPCHK(run_mrhs(L, nrhs, M_HOP_CLINV, engine, x_e, nullptr, nullptr, u, 0.f));
-    HIPCHK(run_mrhs(L, nrhs, M_RICH, engine, u, x_e, b_e, x_e, (float)omega));
-  }
+  for (int k = 0; k < nsweeps; ++k) CHK(mrhs_pass(L, nrhs, engine, x_e, b_e, u, x_e, (float)omega, M_RICH));
   return DDQ_OK;
 }
 
@@ -1346,7 +1443,7 @@ int ddq_profile_end(ddq_lattice* L, ddq_kernel_stats* out, int max_entries, int*
     std::strncpy(out[k].name, L->kind_name[k].c_str(), sizeof(out[k].name) - 1);
     out[k].launches = L->kind_n[k];
     out[k].total_ms = L->kind_ms[k];
-    out[k].bytes_per_launch = L->kind_bytes[k];
+    out[k].bytes_per_launch = L->kind_n[k] > 0 ? L->kind_bytes[k] / L->kind_n[k] : 0.0;
   }
   return DDQ_OK;
 }

@@ -107,6 +107,7 @@ struct HopArgs {
   int nrhs;                  // right-hand sides of the launch
   long long rhs_stride;      // complex elements between right-hand sides
   MrTile tile;               // FP32 multi-right-hand-side tile (nb = 0: one right-hand side per thread)
+  int t_lo, t_cnt;           // one right-hand side: only output sites of slices [t_lo, t_lo + t_cnt) (t_cnt 0: all)
 };
 
 #ifndef DDQ_HOP_BLOCK
@@ -150,6 +151,7 @@ struct MrhsArgs {
   int lds_kb;   // LDS requested per workgroup (unused; caps resident workgroups)
   int tsteps;   // > 0: t walk, each wavefront takes that many slices of one parity of t
   int stage;    // 1: links and clover slots staged in LDS, shared by the lanes of a site
+  int t_lo, t_cnt;  // slab and plain order: only output sites of slices [t_lo, t_lo + t_cnt) (t_cnt 0: all)
   // derived by mrhs_geometry
   int ngroups;  // right-hand-side groups (one workgroup each per site group)
   int rgs;      // right-hand sides per group (<= 16)

@@ -26,10 +26,17 @@ namespace ddq {
 template <typename R> struct HOP_WAVES { static constexpr int value = DDQ_WAVES_F32; };
 template <> struct HOP_WAVES<double> { static constexpr int value = DDQ_WAVES_F64; };
 
-// site of this thread in a one-right-hand-side launch (grid: one_rhs_grid); false if none
-__device__ __forceinline__ bool one_rhs_site(const Geo& g, int nblk, int& i) {
+// site of this thread in a one-right-hand-side launch (grid: one_rhs_grid); false if none.
+// t_cnt > 0 restricts the launch to the output sites of slices [t_lo, t_lo + t_cnt).
+__device__ __forceinline__ bool one_rhs_site(const Geo& g, int nblk, int& i, int t_lo = 0, int t_cnt = 0) {
 #if DDQ_SITE_ORDER
-  const int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  if (t_cnt > 0) {
+    const int ng = (g.sT + 63) >> 6, xcd = (int)(blockIdx.x & 7);
+    const int n = (((xcd + 1) * ng) >> 3) - ((xcd * ng) >> 3);  // this XCD's groups per slice
+    if (n <= 0 || q >= t_cnt * n) return false;
+    q += t_lo * n;
+  }
   int base, end;
   if (!slab_group(g, (int)(blockIdx.x & 7), q, base, end)) return false;
   i = base + ((int)threadIdx.x & 63);
@@ -39,9 +46,10 @@ __device__ __forceinline__ bool one_rhs_site(const Geo& g, int nblk, int& i) {
   return i < g.Vh;
 #endif
 }
-static int one_rhs_grid(const Geo& g) {
+static int one_rhs_grid(const Geo& g, int t_cnt = 0) {
 #if DDQ_SITE_ORDER
-  const long long per = (slab_groups_per_xcd(g) + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
+  const long long groups = t_cnt > 0 ? (long long)t_cnt * (((g.sT + 63) / 64 + 7) / 8) : slab_groups_per_xcd(g);
+  const long long per = (groups + HOP_BLOCK / 64 - 1) / (HOP_BLOCK / 64);
   return 8 * per > 0x7fffffffLL ? -1 : (int)(8 * per);
 #else
   int nb = (g.Vh + HOP_BLOCK - 1) / HOP_BLOCK;
@@ -56,7 +64,7 @@ hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
   int i, rhs;
   if constexpr (!MR) {
-    if (!one_rhs_site(a.g, a.nblk, i)) return;
+    if (!one_rhs_site(a.g, a.nblk, i, a.t_lo, a.t_cnt)) return;
     rhs = 0;
   } else {
     // several right-hand sides: a workgroup is 64 sites x (HOP_BLOCK / 64) right-hand
@@ -156,10 +164,34 @@ hop_kernel(HopArgs<R> a) {
 // neighbours'), the four link fields, the clover field, x and b where the mode reads
 // them, the output rows -- with the same layouts, workgroup order and cache
 // policies, combined by XOR without arithmetic.
+// sites per thread of the streaming probe: with 2, a wavefront streams two consecutive
+// 64-site groups (an experiment on run lengths; the stencil kernels use one)
+#ifndef DDQ_STREAM_SPL
+#define DDQ_STREAM_SPL 1
+#endif
+template <typename R, int MODE, bool L12>
+__device__ __forceinline__ void stream_site(const HopArgs<R>& a, int i);
+
 template <typename R, int MODE, bool L12>
 __global__ void __launch_bounds__(HOP_BLOCK) hop_stream_kernel(HopArgs<R> a) {
+#if DDQ_STREAM_SPL == 2
+  const int q = (int)(blockIdx.x >> 3) * (HOP_BLOCK / 64) + __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
+  int base0, end0, base1, end1;
+  const bool ok0 = slab_group(a.g, (int)(blockIdx.x & 7), 2 * q, base0, end0);
+  const bool ok1 = slab_group(a.g, (int)(blockIdx.x & 7), 2 * q + 1, base1, end1);
+  const int i0 = base0 + ((int)threadIdx.x & 63), i1 = base1 + ((int)threadIdx.x & 63);
+  if (ok0 && i0 < end0) stream_site<R, MODE, L12>(a, i0);
+  if (ok1 && i1 < end1) stream_site<R, MODE, L12>(a, i1);
+}
+#else
   int i;
   if (!one_rhs_site(a.g, a.nblk, i)) return;
+  stream_site<R, MODE, L12>(a, i);
+}
+#endif
+
+template <typename R, int MODE, bool L12>
+__device__ __forceinline__ void stream_site(const HopArgs<R>& a, int i) {
   const int vh = a.g.Vh;
   constexpr int SP_E = SPINOR_ROWS / CPE<R>;
   constexpr int LR = L12 ? LINK12_ROWS : LINK_ROWS;
@@ -206,7 +238,7 @@ hipError_t launch_hop_stream(const HopArgs<R>& a0, int mode, hipStream_t s) {
   if (a.nblk < 0) return hipErrorInvalidValue;
   const bool l12 = sizeof(R) == 4 && a.link12;
   constexpr bool F32 = sizeof(R) == 4;
-  dim3 grid(a.nblk), block(HOP_BLOCK);
+  dim3 grid(DDQ_STREAM_SPL == 2 ? ((a.nblk / 8 + 1) / 2) * 8 : a.nblk), block(HOP_BLOCK);
 #define DDQ_STREAM_LAUNCH(M)                                                    \
   if (l12)                                                                      \
     hipLaunchKernelGGL((hop_stream_kernel<R, M, F32>), grid, block, 0, s, a);   \
@@ -259,7 +291,9 @@ template <typename R>
 hipError_t launch_hop(const HopArgs<R>& a0, int mode, bool dagger, int nrhs, hipStream_t s) {
   HopArgs<R> a = a0;
   a.nrhs = nrhs;
-  a.nblk = one_rhs_grid(a.g);
+  if (a.t_cnt < 0 || a.t_lo < 0 || a.t_lo + a.t_cnt > a.g.L[3] || (a.t_cnt > 0 && nrhs != 1))
+    return hipErrorInvalidValue;
+  a.nblk = one_rhs_grid(a.g, a.t_cnt);
   if (a.nblk < 0) return hipErrorInvalidValue;
   switch (mode) {
     case M_HOP_CLINV: return launch_mode<R, M_HOP_CLINV>(a, dagger, nrhs, s);

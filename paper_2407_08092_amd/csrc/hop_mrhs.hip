@@ -418,16 +418,24 @@ hop_mrhs_kernel(MrhsArgs a) {
   const int w = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 6);
   const int blk = (int)blockIdx.x;
   const int gs = (HOP_BLOCK / 64) * a.spw;  // sites of a workgroup
+  // sites of the launch: the whole lattice, or slices [t_lo, t_lo + t_cnt) when t_cnt > 0
+  const int t_cnt = a.t_cnt > 0 ? a.t_cnt : a.g.L[3];
   int rg, base, end;
   if (a.order == MRHS_ORDER_SLAB) {
-    const int local = blk >> 3;
+    const int local = blk >> 3, xcd = blk & 7;
     rg = local % a.ngroups;
-    if (!slab_group_n(a.g, blk & 7, local / a.ngroups, gs, base, end)) return;
+    int q = local / a.ngroups;
+    const int ng = (a.g.sT + gs - 1) / gs;
+    const int n = (((xcd + 1) * ng) >> 3) - ((xcd * ng) >> 3);  // this XCD's groups per slice
+    if (n <= 0 || q >= t_cnt * n) return;
+    q += a.t_lo * n;
+    if (!slab_group_n(a.g, xcd, q, gs, base, end)) return;
   } else {
     rg = blk % a.ngroups;
-    base = (blk / a.ngroups) * gs;
-    if (base >= a.g.Vh) return;
-    end = min(base + gs, a.g.Vh);
+    base = a.t_lo * a.g.sT + (blk / a.ngroups) * gs;
+    const int lim = (a.t_lo + t_cnt) * a.g.sT;
+    if (base >= lim) return;
+    end = min(base + gs, lim);
   }
   const int first = base + w * a.spw;
   if (first >= end) return;  // wavefront-uniform
@@ -503,11 +511,12 @@ long long mrhs_grid(const MrhsArgs& a) {
     const long long nseg = (a.g.L[3] / 2 + a.tsteps - 1) / a.tsteps;
     return 8LL * nseg * 2 * ((ng + 7) / 8) * a.ngroups;
   }
+  const long long nt = a.t_cnt > 0 ? a.t_cnt : a.g.L[3];
   if (a.order == MRHS_ORDER_SLAB) {
     const long long ng = (a.g.sT + gs - 1) / gs;
-    return 8LL * (long long)a.g.L[3] * ((ng + 7) / 8) * a.ngroups;
+    return 8LL * nt * ((ng + 7) / 8) * a.ngroups;
   }
-  return ((long long)a.g.Vh + gs - 1) / gs * a.ngroups;
+  return (nt * a.g.sT + gs - 1) / gs * a.ngroups;
 }
 
 template <int MODE, bool MF, bool ST>
@@ -546,6 +555,8 @@ hipError_t launch_hop_mrhs(const MrhsArgs& a0, int mode, hipStream_t s) {
   MrhsArgs a = a0;
   if (!mrhs_geometry(a.nrhs, a)) return hipErrorInvalidValue;
   if (a.lds_kb < 0 || a.lds_kb > 160 || a.tsteps < 0 || a.tsteps > 4096) return hipErrorInvalidValue;
+  if (a.t_lo < 0 || a.t_cnt < 0 || a.t_lo + a.t_cnt > a.g.L[3] || (a.t_cnt > 0 && a.tsteps > 0))
+    return hipErrorInvalidValue;
   if ((uint64_t)a.g.Vh * 96u * (uint64_t)a.nrhs >= (1ULL << 32)) return hipErrorInvalidValue;
   switch (mode) {
     case M_HOP_CLINV: return mrhs_launch_e<M_HOP_CLINV>(a, s);

@@ -203,3 +203,27 @@ def test_argument_errors():
     st = L.ddq_mrhs_apply_schur(c.lat.handle, 200, ctypes.c_void_p(big.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), 1)
     assert st == -2
+
+
+@pytest.mark.parametrize("engine", ENGINES, ids=ENGINE_IDS)
+@pytest.mark.parametrize("order", [1, 0], ids=["slab", "plain"])
+def test_chunked_launches_are_bitwise_equal(engine, order):
+    # kernels A and B launched per range of t-slices (ddq_set_sweep_chunks) give the one-launch
+    # apply and sweeps bit for bit
+    c = case((6, 6, 6, 10))
+    x = to_mrhs(c.vec(312, 12))
+    b = to_mrhs(c.vec(313, 12))
+    outs = {}
+    for nc in (1, 2, 3, 7, 10):
+        api.set_sweep_chunks(c.lat, nc)
+        api.mrhs_set_launch(c.lat, order)
+        y = api.mrhs_apply_schur(c.lat, x, engine=engine)
+        z = x.clone()
+        api.mrhs_richardson_smooth(c.lat, z, b, 3, 0.12, engine=engine)
+        torch.cuda.synchronize()
+        outs[nc] = (y, z)
+    api.set_sweep_chunks(c.lat, 0)
+    api.mrhs_set_launch(c.lat, 1)
+    for nc in (2, 3, 7, 10):
+        assert torch.equal(outs[nc][0], outs[1][0]), nc
+        assert torch.equal(outs[nc][1], outs[1][1]), nc

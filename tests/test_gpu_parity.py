@@ -281,3 +281,60 @@ def test_call_order_errors():
         api.apply_schur(lat, x)
     with pytest.raises(api.DDQError):
         api.set_clover(lat, float("nan"), 0.0)
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (6, 6, 6, 10), (8, 8, 8, 16)])
+@pytest.mark.parametrize("nc", [2, 3, 4, 10])
+def test_chunked_sweeps_equal_plain_sweeps(dims, nc):
+    # Richardson sweeps launched per range of t-slices give the plain sweep's result bit for
+    # bit (every site computes the same sums from the same inputs), FP64 and FP32
+    c = case(dims)
+    nc = min(nc, dims[3])
+    b, x0 = c.vec(131), c.vec(132)
+    omega = 0.12
+    outs = {}
+    for dt in (torch.complex128, torch.complex64):
+        for k in (1, nc):
+            api.set_sweep_chunks(c.lat, k)
+            x = to_dev(x0, dt)
+            api.richardson_smooth(c.lat, x, to_dev(b, dt), 4, omega)
+            torch.cuda.synchronize()
+            outs[(dt, k)] = x
+    api.set_sweep_chunks(c.lat, 0)
+    for dt in (torch.complex128, torch.complex64):
+        assert torch.equal(outs[(dt, 1)], outs[(dt, nc)])
+    ref = solvers.richardson(c.op.schur, b, x0, 4, omega)
+    assert rel(to_host(outs[(torch.complex128, nc)]), ref) < 1e-12
+    assert rel(to_host(outs[(torch.complex64, nc)]), ref) < 1e-5
+
+
+@pytest.mark.parametrize("dims", [(4, 6, 8, 10), (8, 8, 8, 16)])
+@pytest.mark.parametrize("nc", [2, 5, 16])
+@pytest.mark.parametrize("dagger", [False, True], ids=["plain", "dagger"])
+def test_chunked_apply_equals_plain_apply(dims, nc, dagger):
+    # the Schur apply launched per range of t-slices: bit for bit the one-launch apply
+    c = case(dims)
+    nc = min(nc, dims[3])
+    x = c.vec(133)
+    outs = {}
+    for dt in (torch.complex128, torch.complex64):
+        for k in (1, nc):
+            api.set_sweep_chunks(c.lat, k)
+            outs[(dt, k)] = api.apply_schur(c.lat, to_dev(x, dt), dagger=dagger)
+            torch.cuda.synchronize()
+    api.set_sweep_chunks(c.lat, 0)
+    for dt in (torch.complex128, torch.complex64):
+        assert torch.equal(outs[(dt, 1)], outs[(dt, nc)])
+    ref = c.op.schur_adjoint(x) if dagger else c.op.schur(x)
+    assert rel(to_host(outs[(torch.complex128, nc)]), ref) < 1e-12
+    assert rel(to_host(outs[(torch.complex64, nc)]), ref) < 1e-5
+
+
+def test_chunk_count_arguments():
+    c = case((4, 4, 4, 4))
+    with pytest.raises(api.DDQError):
+        api.set_sweep_chunks(c.lat, -1)
+    with pytest.raises(api.DDQError):
+        api.set_sweep_chunks(c.lat, 5)  # more ranges than t-slices
+    api.set_sweep_chunks(c.lat, 4)
+    api.set_sweep_chunks(c.lat, 0)

@@ -187,9 +187,10 @@ int ddq_richardson_smooth(ddq_lattice* lat, int prec, int nrhs, void* x_e, const
 
 /* One-right-hand-side Richardson sweeps and Schur applies (FP64 / FP32
  * ddq_richardson_smooth and ddq_apply_schur with nrhs = 1, daggered too) on nc ranges of
- * t-slices (1 <= nc <= Lt; 0, the default, chooses nc so that one range's u_o is about
- * 40 MiB: 13 for FP32 at 48^3 x 96, 1 up to 28^3 x 56): each launches kernel A and kernel
- * B per range, ordered so that the result is that of eq. 3 / Alg. 4 bit for bit (every B
+ * t-slices (1 <= nc <= Lt; 0, the default, chooses for FP32 lattices whose u_o exceeds 128
+ * MiB nc ranges of about 40 MiB of u_o each (13 at 48^3 x 96), else one): each launches
+ * kernel A and kernel B per range, ordered so that the result is that of eq. 3 / Alg. 4
+ * bit for bit (every B
  * reads u_o of the old x; every A reads x before its neighbour range is updated) while the
  * u_o rows of a range are read one launch after they were written, from the Infinity
  * Cache instead of HBM.  The interleaved multi-right-hand-side calls (ddq_mrhs_*) use the

@@ -463,13 +463,16 @@ hipError_t kernel_B(ddq_lattice* L, int prec, int nrhs, int mode, const pair<R>*
 }
 
 // Chunks of t-slices for the one-right-hand-side sweeps and applies: the number set by
-// ddq_set_sweep_chunks, or (0, the default) enough that one chunk's u_o (V/2 x 12 complex
-// numbers of the precision) stays near 40 MiB, a small part of the 256 MB Infinity Cache.
+// ddq_set_sweep_chunks, or (0, the default) for FP32 whose u_o (V/2 x 12 complex64) exceeds
+// 128 MiB, enough chunks that one chunk's u_o stays near 40 MiB, a small part of the 256 MB
+// Infinity Cache; else one launch.  Measured: 48^3 x 96 FP32 (509 MB of u_o) gains 5-7 %
+// with 10-13 chunks; 48^3 x 12 (64 MB, cached anyway) loses 5 % with 2; FP64 at 48^3 x 96
+// with 25 chunks is 1 % slower than one launch.
 int chunks_for(const ddq_lattice* L, int prec) {
   int nc = L->sweep_chunks;
   if (nc == 0) {
-    const double u_bytes = (double)L->nvec() * (prec == DDQ_F64 ? 16.0 : 8.0);
-    nc = (int)std::ceil(u_bytes / (40.0 * 1024 * 1024));
+    const double u_bytes = (double)L->nvec() * 8.0;
+    nc = (prec == DDQ_F32 && u_bytes > 128.0 * 1024 * 1024) ? (int)std::ceil(u_bytes / (40.0 * 1024 * 1024)) : 1;
   }
   return std::max(1, std::min(nc, L->dims[3]));
 }

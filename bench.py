@@ -133,6 +133,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--multi-rhs-only", action="store_true")
     ap.add_argument("--mrhs-only", action="store_true")
+    ap.add_argument("--sap-only", action="store_true")
     ap.add_argument("--headline-only", action="store_true")
     ap.add_argument("--batch-only", action="store_true")
     ap.add_argument("--coarse-only", action="store_true")
@@ -150,6 +151,15 @@ def main():
 
         torch.cuda.set_device(0)
         print(json.dumps({"coarse": coarse_operator(api, torch, torch.device("cuda:0"), args.coarse_nv)}), flush=True)
+        return
+
+    if args.sap_only:
+        import torch
+
+        from paper_2407_08092_amd import api, synth
+
+        torch.cuda.set_device(0)
+        print(json.dumps({"sap": sap_only(api, synth, torch, torch.device("cuda:0"))}), flush=True)
         return
 
     if args.mrhs_only:
@@ -366,25 +376,7 @@ def main():
             "stream_mix_GBs": stencil_stream_ceiling(api, torch, lat, x64, xs64, b64, y64, 5)}
     # SAP(1, 4) sweeps (Alg. 1, 4^4 blocks; block solves in FP64 and in FP32) on the same
     # lattice: the block kernel's live profile and the sweep time
-    bf = torch.from_numpy(synth.gaussian_spinor(dims, cfg["seed_vec"] + 7)).to(dev)
-    xf = torch.zeros_like(bf)
-    for label, prec in (("sap_1x4_f64", api.DDQ_F64), ("sap_1x4_f32", api.DDQ_F32)):
-        api.sap_smooth(lat, bf, xf, 1, 4, prec=prec)
-        torch.cuda.synchronize()
-        api.profile_begin(lat)
-        e0.record(stream)
-        nsap = 3
-        api.sap_smooth(lat, bf, xf, nsap, 4, prec=prec)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        sprof = api.profile_end(lat)
-        sap = {"sweep_ms": round(e0.elapsed_time(e1) / nsap, 3),
-               "kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
-                               "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
-                           for k, v in sprof.items()}}
-        fp64[label] = sap
-        log(f"SAP(1, 4) on 48^3x96, {label}: {sap}")
-    del bf, xf
+    fp64.update(sap_sweeps(api, synth, torch, lat, dims, cfg["seed_vec"] + 7))
     del y64, xs64, x64, b64
     api.destroy_lattice(lat)
     del lat
@@ -435,6 +427,45 @@ def main():
 
 
 MFMA_F32_PEAK_TFLOPS = 157.3
+
+
+def sap_sweeps(api, synth, torch, lat, dims, seed, nsap=3):
+    """SAP(1, 4) sweeps on D x = b (Alg. 1, 4^4 blocks) with FP64 and with FP32 block
+    solves: the sweep time and the library profiler's figures of the block kernels."""
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    bf = torch.from_numpy(synth.gaussian_spinor(dims, seed)).to(lat.device)
+    xf = torch.zeros_like(bf)
+    out = {}
+    for label, prec in (("sap_1x4_f64", api.DDQ_F64), ("sap_1x4_f32", api.DDQ_F32)):
+        api.sap_smooth(lat, bf, xf, 1, 4, prec=prec)
+        torch.cuda.synchronize()
+        api.profile_begin(lat)
+        e0.record(stream)
+        api.sap_smooth(lat, bf, xf, nsap, 4, prec=prec)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        sprof = api.profile_end(lat)
+        sap = {"sweep_ms": round(e0.elapsed_time(e1) / nsap, 3),
+               "kernels": {k: {"mean_ms": round(v["mean_ms"], 4), "launches": v["launches"],
+                               "GBs": round(v["bytes_per_launch"] / (v["mean_ms"] * 1e-3) / 1e9, 1)}
+                           for k, v in sprof.items()}}
+        out[label] = sap
+        log(f"SAP(1, 4) on {'x'.join(map(str, dims))}, {label}: {sap}")
+    return out
+
+
+def sap_only(api, synth, torch, dev):
+    """--sap-only: the SAP sweeps of the full run on the 48^3x96 lattice, FP32 block
+    solves with 12-real links."""
+    cfg = LARGE
+    dims = cfg["dims"]
+    lat = api.create_lattice(dims, device=dev)
+    api.set_gauge(lat, synth.gauge_field(dims, cfg["eps"], cfg["seed_gauge"], device=dev), link12=True)
+    api.set_clover(lat, cfg["c_sw"], cfg["m0"])
+    out = sap_sweeps(api, synth, torch, lat, dims, cfg["seed_vec"] + 7)
+    api.destroy_lattice(lat)
+    return out
 
 
 def one_gpu_share(api, synth, torch, dev, reps=20):

@@ -8,13 +8,20 @@
 // block's hopping terms) and m Minimal Residual steps on the block's Schur complement
 // from zero; then x += e on the block's sites.  The residual and the iterate are FP64
 // full vectors; the block solve runs in R (FP64, or FP32 with FP32 links and clover),
-// its dot products accumulated in FP64.  Thread j of the 128 owns the j-th even and
-// the j-th odd site of the block (the checkerboard half index of the block's
-// lexicographic site order); the hopping terms read the other parity's half-block
-// vector from one LDS buffer, the links and clover blocks from HBM in SAP order: a copy
-// of the link and clover fields with the 128 sites of one parity of each block at
-// consecutive positions blockIdx * 128 + j (k_sap_reorder), so that every row a
-// wavefront loads is one contiguous run.
+// its dot products accumulated in FP64.  The links and clover blocks are read in SAP
+// order: a copy of the link and clover fields with the 128 sites of one parity of each
+// block at consecutive positions blockIdx * 128 + j (k_sap_reorder), so that every row
+// a wavefront loads is one contiguous run.
+//
+// Two kernels:
+// * k_sap_block (FP64; FP32 with 18-real links): 128 threads, thread j owns the j-th
+//   even and the j-th odd site of the block (the checkerboard half index of the block's
+//   lexicographic site order); the hopping terms read the other parity's half-block
+//   vector from one LDS buffer, the links and clover blocks from memory at every use.
+// * k_sap_block_split (FP32 with 12-real links): everything the MR steps touch stays on
+//   chip -- the block's links in LDS, the clover blocks in registers -- and each site
+//   pair is split over two threads so that two workgroups give every SIMD two
+//   wavefronts (see the kernel).
 #include "hop_common.h"
 
 namespace ddq {
@@ -36,7 +43,7 @@ __device__ __forceinline__ void sap_local(int j, int p, int lc[4]) {
 // the 8 hops of (1 -/+ g_mu) U p(neighbour), p read from the other parity's half-block
 // vector v[12][128] in LDS (zero for neighbours outside the block); `c` carries the
 // site's links and the t-boundary signs
-template <typename R, bool L12>
+template <typename R>
 __device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cpx<R> (*v)[SAP_HALF],
                                          const HopCtx<R>& c, Spinor<R>& acc) {
   zero(acc);
@@ -65,13 +72,9 @@ __device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cp
     if constexpr (CPE<R> == 1) {
       u = load_link_half<R>(link_field(c, mu), H & 1, c.loff);
     } else if ((H & 1) == 0) {
-      if constexpr (L12)
-        load_link_pair12<R>(link_field(c, mu), c.loff, u, ub);
-      else
-        load_link_pair<R>(link_field(c, mu), c.loff, u, ub);
+      load_link_pair<R>(link_field(c, mu), c.loff, u, ub);
     } else {
       u = ub;
-      if constexpr (L12) su3_third_row(u);
     }
     switch (H) {
       case 0: hop_compute<0, R>(acc, p, u, c); break;
@@ -87,8 +90,8 @@ __device__ __forceinline__ void sap_hops(const Geo& g, const int lc[4], const cp
   }
 }
 
-template <typename R>
-__device__ __forceinline__ void sap_put(cpx<R> (*v)[SAP_HALF], int j, const Spinor<R>& s) {
+template <typename R, int N>
+__device__ __forceinline__ void sap_put(cpx<R> (*v)[N], int j, const Spinor<R>& s) {
 #pragma unroll
   for (int sp = 0; sp < 4; ++sp)
 #pragma unroll
@@ -149,7 +152,7 @@ struct SapArgs {
   int m;  // Minimal Residual steps
 };
 
-template <typename R, bool L12>
+template <typename R>
 __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
   __shared__ cpx<R> vb[12][SAP_HALF];  // the other parity's half-block vector of the current hop
   __shared__ cpx<R> vx[12][SAP_HALF];  // the even half of the block correction (own slot only)
@@ -182,7 +185,7 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
   }
   const int ss = (int)blockIdx.x * SAP_HALF + j;  // SAP-order position of both sites
   const int vh = g.Vh;
-  constexpr int LR = L12 ? LINK12_ROWS : LINK_ROWS;
+  constexpr int LR = LINK_ROWS;
   constexpr int CL_E = CLOVER_ROWS / CPE<R>;
   // hopping context of each of the thread's two sites: links, signs of the t hops
   HopCtx<R> ce, co;
@@ -207,7 +210,7 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
   // eq. 2 on the block: b~_e = r_e - D_eo A_oo^-1 r_o = r_e + H_eo (A_oo^-1 r_o)
   sap_put(vb, j, clover_mul<R>(Co, cofo, sap_load_full<R>(a.r, site_o)));
   __syncthreads();
-  sap_hops<R, L12>(g, le, vb, ce, acc);
+  sap_hops<R>(g, le, vb, ce, acc);
   rr = sap_load_full<R>(a.r, site_e);
 #pragma unroll
   for (int s = 0; s < 4; ++s)
@@ -221,7 +224,7 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
     __syncthreads();  // every thread is done reading vb
     sap_put(vb, j, rr);
     __syncthreads();
-    sap_hops<R, L12>(g, lo, vb, co, acc);  // H_oe r
+    sap_hops<R>(g, lo, vb, co, acc);  // H_oe r
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
@@ -230,7 +233,7 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
     __syncthreads();  // every thread is done reading r from vb
     sap_put(vb, j, t);
     __syncthreads();
-    sap_hops<R, L12>(g, le, vb, ce, acc);  // H_eo A_oo^-1 H_oe r
+    sap_hops<R>(g, le, vb, ce, acc);  // H_eo A_oo^-1 H_oe r
     q = clover_mul<R>(Ce, cofe, rr);
     double d[3] = {0.0, 0.0, 0.0};  // q^H r, |q|^2
 #pragma unroll
@@ -265,13 +268,313 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
     }
   sap_add_full(a.x, site_e, q);
   __syncthreads();
-  sap_hops<R, L12>(g, lo, vb, co, acc);
+  sap_hops<R>(g, lo, vb, co, acc);
   rr = sap_load_full<R>(a.r, site_o);
 #pragma unroll
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc.c[s][c] = rr.c[s][c] + R(0.5) * acc.c[s][c];
   sap_add_full(a.x, site_o, clover_mul<R>(Co, cofo, acc));
+}
+
+// ---------------------------------------------------------------------------
+// FP32 block solve with 12-real links, all operands on chip across the MR steps.
+// The block's 1,024 forward links U_mu(x) (first two rows, 48 KB) are copied into LDS
+// once; every hop of the block reads its link there: the forward hop of site x takes
+// U_mu(x), the backward hop U_mu(x - mu)^H, the forward link of the neighbour.  Each
+// thread keeps the clover slots of its two sites (A_ee of the even one, A_oo^-1 of the
+// odd one: 72 complex numbers) in registers.  Per workgroup 60 KB of LDS, so two
+// blocks share a compute unit, one wavefront per SIMD.
+// ---------------------------------------------------------------------------
+constexpr int SAP_LK = 6;  // complex entries of a link kept in LDS (rows 0, 1)
+
+// LDS index of entry e of the forward link of direction mu at (parity q, half index j)
+__device__ __forceinline__ int sap_lk_idx(int e, int mu, int q, int j) {
+  return (e * 8 + 2 * mu + q) * SAP_HALF + j;
+}
+
+// half index of hop H's neighbour of the site at local coordinates lc (wrapping inside
+// a block that spans the direction); SAP_HALF, the index of the zero column of the LDS
+// half-block vector, when the neighbour lies outside the block
+__device__ __forceinline__ int sap_nbr(const Geo& g, const int lc[4], int H) {
+  const int mu = H >> 1;
+  int nc[4] = {lc[0], lc[1], lc[2], lc[3]};
+  nc[mu] += (H & 1) ? -1 : 1;
+  bool inside = (unsigned)nc[mu] < (unsigned)SAP_B;
+  if (g.L[mu] == SAP_B) {  // uniform
+    nc[mu] &= SAP_B - 1;
+    inside = true;
+  }
+  return inside ? (nc[0] + SAP_B * (nc[1] + SAP_B * (nc[2] + SAP_B * nc[3]))) >> 1 : SAP_HALF;
+}
+
+// operands of hop H of the site (parity p, half index j): the neighbour's spinor from
+// the half-block vector v (its zero column outside the block) and the two stored rows
+// of the link; every lane reads, so the reads go out together
+template <int H>
+__device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int p, int j,
+                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
+                                              Spinor<float>& nb, Link<float>& u) {
+  constexpr int MU = H >> 1;
+  const int jn = sap_nbr(g, lc, H);
+#pragma unroll
+  for (int s = 0; s < 4; ++s)
+#pragma unroll
+    for (int a = 0; a < 3; ++a) nb.c[s][a] = v[3 * s + a][jn];
+  // forward: the site's own link; backward: the neighbour's (any link outside the block,
+  // where the spinor is zero)
+  const int q = (H & 1) ? 1 - p : p, jl = (H & 1) ? (jn & (SAP_HALF - 1)) : j;
+#pragma unroll
+  for (int e = 0; e < SAP_LK; ++e) u.u[e] = lk[sap_lk_idx(e, MU, q, jl)];
+}
+
+template <int H>
+__device__ __forceinline__ void sap_lds_hop(Spinor<float>& acc, const Spinor<float>& nb, Link<float> u,
+                                            const HopCtx<float>& c) {
+  su3_third_row(u);
+  if constexpr (H & 1) {
+    Link<float> d;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) d.u[3 * a + b] = conj(u.u[3 * b + a]);
+    hop_compute<H, float>(acc, nb, d, c);
+  } else {
+    hop_compute<H, float>(acc, nb, u, c);
+  }
+}
+
+// hops H..HE-1, the operands of hop H + 1 read before hop H's arithmetic
+template <int H, int HE>
+__device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int p, int j,
+                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
+                                              const HopCtx<float>& c, Spinor<float>& acc, const Spinor<float>& nb,
+                                              const Link<float>& u) {
+  if constexpr (H + 1 < HE) {
+    Spinor<float> nn;
+    Link<float> un;
+    sap_lds_loads<H + 1>(g, lc, p, j, v, lk, nn, un);
+    sap_lds_hop<H>(acc, nb, u, c);
+    hop_fence<float>(acc);
+    sap_lds_steps<H + 1, HE>(g, lc, p, j, v, lk, c, acc, nn, un);
+  } else {
+    sap_lds_hop<H>(acc, nb, u, c);
+    hop_fence<float>(acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// The kernel has two threads per site pair: 256 threads, thread (h, j) with
+// h = threadIdx / 128 (uniform over a wavefront) and j = threadIdx mod 128.  Thread h
+// sums the hops of directions 2h and 2h + 1 into a partial spinor; the partials meet in
+// LDS, after which thread h owns spins 2h, 2h + 1 of its two sites: the rows clover
+// block h acts on, the rows of the Minimal Residual vectors it updates.  Per workgroup
+// 72 KB of LDS (links, the hop input, the exchange buffer): two blocks share a compute
+// unit with two wavefronts per SIMD.
+// ---------------------------------------------------------------------------
+constexpr int SAP_SPLIT = 2 * SAP_HALF;  // threads of a workgroup
+
+// the hops of directions 2h, 2h + 1 (h uniform over the wavefront)
+__device__ __forceinline__ void sap_hops_half(const Geo& g, const int lc[4], int p, int j, int h,
+                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
+                                              const HopCtx<float>& c, Spinor<float>& acc) {
+  zero(acc);
+  Spinor<float> nb;
+  Link<float> u;
+  if (h == 0) {
+    sap_lds_loads<0>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<0, 4>(g, lc, p, j, v, lk, c, acc, nb, u);
+  } else {
+    sap_lds_loads<4>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<4, 8>(g, lc, p, j, v, lk, c, acc, nb, u);
+  }
+}
+
+// own[k] (k = 3 s + c: spin 2h + s, colour c) = the sum of both threads' partials;
+// xb: exchange rows, row 6 h' + k written by the thread that does not own them
+__device__ __forceinline__ void sap_exchange(cpx<float> (*xb)[SAP_HALF], int h, int j, const Spinor<float>& acc,
+                                             cpx<float> own[6]) {
+  if (h == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xb[6 + k][j] = acc.c[2 + k / 3][k % 3];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) xb[k][j] = acc.c[k / 3][k % 3];
+  }
+  __syncthreads();
+  if (h == 0) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) own[k] = acc.c[k / 3][k % 3] + xb[k][j];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) own[k] = acc.c[2 + k / 3][k % 3] + xb[6 + k][j];
+  }
+}
+
+// rows 6 h .. 6 h + 5 of a site of a full FP64 vector
+__device__ __forceinline__ void sap_load_rows6(const d2_t* f, long long site, int h, cpx<float> o[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    const d2_t q = f[site * 12 + 6 * h + k];
+    o[k] = {(float)q.x, (float)q.y};
+  }
+}
+__device__ __forceinline__ void sap_add_rows6(d2_t* f, long long site, int h, const cpx<float> s[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    d2_t q = f[site * 12 + 6 * h + k];
+    q.x += (double)s[k].r;
+    q.y += (double)s[k].i;
+    f[site * 12 + 6 * h + k] = q;
+  }
+  store_fence();
+}
+
+__device__ __forceinline__ void sap_put6(cpx<float> (*v)[SAP_HALF + 1], int h, int j, const cpx<float> s[6]) {
+#pragma unroll
+  for (int k = 0; k < 6; ++k) v[6 * h + k][j] = s[k];
+}
+
+// sum over the workgroup's 256 threads of three doubles (four wavefronts)
+__device__ __forceinline__ void sap_sum3_4(double v[3], double* red /* [4][3] */) {
+#pragma unroll
+  for (int k = 0; k < 3; ++k)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[k] += __shfl_xor(v[k], off, 64);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) red[3 * w + k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 3; ++k) v[k] = (red[k] + red[3 + k]) + (red[6 + k] + red[9 + k]);
+}
+
+__global__ void __launch_bounds__(SAP_SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
+k_sap_block_split(SapArgs a) {
+  __shared__ cpx<float> lk[SAP_LK * 8 * SAP_HALF];  // the block's forward links, rows 0 and 1
+  __shared__ cpx<float> vb[12][SAP_HALF + 1];      // hop input; column SAP_HALF zero
+  __shared__ cpx<float> xb[12][SAP_HALF];          // partial sums in exchange
+  __shared__ double red[12];
+  const Geo& g = a.g;
+  int bc[4];
+  {
+    const int hx = (a.nb[0] + 1) >> 1;
+    const int k = (int)blockIdx.x;
+    int row = k / hx;
+    bc[1] = row % a.nb[1];
+    row /= a.nb[1];
+    bc[2] = row % a.nb[2];
+    bc[3] = row / a.nb[2];
+    bc[0] = 2 * (k - (k / hx) * hx) + ((a.colour + bc[1] + bc[2] + bc[3]) & 1);
+  }
+  if (bc[0] >= a.nb[0]) return;  // uniform over the workgroup
+  const int blk = bc[0] + a.nb[0] * (bc[1] + a.nb[1] * (bc[2] + a.nb[2] * bc[3]));
+  const int j = (int)threadIdx.x & (SAP_HALF - 1);
+  const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 7);
+  int le[4], lo[4];
+  sap_local(j, 0, le);
+  sap_local(j, 1, lo);
+  long long site_e, site_o;
+  {
+    int ge[4], go[4];
+    for (int mu = 0; mu < 4; ++mu) {
+      ge[mu] = SAP_B * bc[mu] + le[mu];
+      go[mu] = SAP_B * bc[mu] + lo[mu];
+    }
+    site_e = ge[0] + (long long)g.L[0] * (ge[1] + (long long)g.L[1] * (ge[2] + (long long)g.L[2] * ge[3]));
+    site_o = go[0] + (long long)g.L[0] * (go[1] + (long long)g.L[1] * (go[2] + (long long)g.L[2] * go[3]));
+  }
+  cpx<float> ro[6], re[6];  // the thread's rows of the residual (r_o kept for the reconstruction)
+  sap_load_rows6(a.r, site_o, h, ro);
+  sap_load_rows6(a.r, site_e, h, re);
+  const int ss = blk * SAP_HALF + j;
+  const int vh = g.Vh;
+  constexpr int LE = LINK12_ROWS / 2;
+  constexpr int CL_E = CLOVER_ROWS / 2;
+  const uint32_t loff = boff(ss, LE), coff = boff(ss, CL_E);
+  // the forward links of directions 2h, 2h + 1 of both parities into LDS
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int mu = 2 * h + d;
+      const Field U = bfield((const pair<float>*)a.links[q] + (size_t)mu * LINK12_ROWS * field_vh(vh), LE, vh);
+      cpx<float> c6[SAP_LK];
+      load_rows<float, DDQ_STREAM_AUX>(U, 0, SAP_LK, loff, c6);
+#pragma unroll
+      for (int e = 0; e < SAP_LK; ++e) lk[sap_lk_idx(e, mu, q, j)] = c6[e];
+    }
+  if (threadIdx.x < 12) vb[threadIdx.x][SAP_HALF] = {0.f, 0.f};
+  cpx<float> cle[18], clo[18];  // clover block h of A_ee (even site) and of A_oo^-1 (odd site)
+  load_rows<float, DDQ_STREAM_AUX>(bfield(a.clov_e, CL_E, vh), 18 * h, 18, coff, cle);
+  load_rows<float, DDQ_STREAM_AUX>(bfield(a.clov_oi, CL_E, vh), 18 * h, 18, coff, clo);
+  HopCtx<float> ce, co;
+  ce.sf = co.sf = -1.f;
+  ce.sb = co.sb = 1.f;
+  const bool wrap_t = g.L[3] == SAP_B && g.antiperiodic;
+  ce.nb.sgn_tf = (wrap_t && le[3] == SAP_B - 1) ? -1.f : 1.f;
+  ce.nb.sgn_tb = (wrap_t && le[3] == 0) ? -1.f : 1.f;
+  co.nb.sgn_tf = (wrap_t && lo[3] == SAP_B - 1) ? -1.f : 1.f;
+  co.nb.sgn_tb = (wrap_t && lo[3] == 0) ? -1.f : 1.f;
+
+  Spinor<float> acc;
+  cpx<float> rr[6], ex[6], t6[6], q6[6];
+  // eq. 2 on the block: b~_e = r_e + H_eo (A_oo^-1 r_o)
+  clover_block_apply<float>(clo, ro, t6);
+  sap_put6(vb, h, j, t6);
+  __syncthreads();  // the links and vb written
+  sap_hops_half(g, le, 0, j, h, vb, lk, ce, acc);
+  sap_exchange(xb, h, j, acc, t6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) {
+    rr[k] = re[k] + 0.5f * t6[k];
+    ex[k] = {0.f, 0.f};
+  }
+  // Minimal Residual on the block Schur complement S = A_ee - H_eo A_oo^-1 H_oe
+  for (int it = 0; it < a.m; ++it) {
+    __syncthreads();  // every thread is done reading vb
+    sap_put6(vb, h, j, rr);
+    __syncthreads();
+    sap_hops_half(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
+    sap_exchange(xb, h, j, acc, q6);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) q6[k] = 0.5f * q6[k];
+    clover_block_apply<float>(clo, q6, t6);  // A_oo^-1 H_oe r
+    sap_put6(vb, h, j, t6);  // vb's readers passed the exchange's barrier
+    __syncthreads();
+    sap_hops_half(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
+    sap_exchange(xb, h, j, acc, t6);
+    clover_block_apply<float>(cle, rr, q6);
+    double d[3] = {0.0, 0.0, 0.0};  // q^H r, |q|^2
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      q6[k] = q6[k] - 0.5f * t6[k];
+      const double qr = q6[k].r, qi = q6[k].i, rr_ = rr[k].r, ri = rr[k].i;
+      d[0] += qr * rr_ + qi * ri;
+      d[1] += qr * ri - qi * rr_;
+      d[2] += qr * qr + qi * qi;
+    }
+    sap_sum3_4(d, red);
+    if (d[2] == 0.0) break;  // uniform: every thread holds the same sums
+    const cpx<float> alpha = {(float)(d[0] / d[2]), (float)(d[1] / d[2])};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      ex[k] = ex[k] + alpha * rr[k];
+      rr[k] = rr[k] - alpha * q6[k];
+    }
+  }
+  // eq. 2 on the block: e_o = A_oo^-1 (r_o + H_oe e_e)
+  __syncthreads();
+  sap_put6(vb, h, j, ex);
+  sap_add_rows6(a.x, site_e, h, ex);
+  __syncthreads();
+  sap_hops_half(g, lo, 1, j, h, vb, lk, co, acc);
+  sap_exchange(xb, h, j, acc, t6);
+#pragma unroll
+  for (int k = 0; k < 6; ++k) t6[k] = ro[k] + 0.5f * t6[k];
+  clover_block_apply<float>(clo, t6, q6);
+  sap_add_rows6(a.x, site_o, h, q6);
 }
 
 // dst = src with its sites of parity p in SAP order: element row e of SAP position
@@ -331,12 +634,14 @@ hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t*
   a.colour = colour & 1;
   a.m = m;
   const dim3 grid((unsigned)nblk), block(SAP_HALF);
+  // the LDS kernel's grid: the blocks of one colour, (nb[0] + 1) / 2 of them per row in x
+  const dim3 grid_c((unsigned)(nblk / a.nb[0] * ((a.nb[0] + 1) / 2)));
   if (!prec_f32)
-    hipLaunchKernelGGL((k_sap_block<double, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL(k_sap_block<double>, grid, block, 0, s, a);
   else if (link12)
-    hipLaunchKernelGGL((k_sap_block<float, true>), grid, block, 0, s, a);
+    hipLaunchKernelGGL(k_sap_block_split, grid_c, dim3(SAP_SPLIT), 0, s, a);
   else
-    hipLaunchKernelGGL((k_sap_block<float, false>), grid, block, 0, s, a);
+    hipLaunchKernelGGL(k_sap_block<float>, grid, block, 0, s, a);
   return hipGetLastError();
 }
 

@@ -43,17 +43,22 @@ def test_sap_matches_oracle(dims, m):
         assert rel(x.cpu().numpy(), ref) < tol, prec
 
 
-def test_sap_f32_with_twelve_real_links():
-    dims = (8, 4, 4, 4)
+# FP32 block solves with 12-real links keep the block's links in LDS and the clover
+# slots in registers; 8^4 has no direction that a block spans (no wrap-around hop)
+@pytest.mark.parametrize("m", [1, 4])
+@pytest.mark.parametrize("dims", DIMS + [(8, 8, 8, 8)], ids=lambda d: "x".join(map(str, d)))
+def test_sap_f32_with_twelve_real_links(dims, m):
     c = case(dims)
     lat = api.create_lattice(dims)
     api.set_gauge(lat, torch.from_numpy(c.U).cuda(), link12=True)
     api.set_clover(lat, 1.0, -0.2)
     b = c.full(504)
-    ref = solvers.sap(c.op, b, np.zeros_like(b), 2, 4)
-    x = torch.zeros((1,) + lat.full_shape, dtype=torch.complex128, device="cuda")[0]
-    api.sap_smooth(lat, torch.from_numpy(b).cuda(), x, 2, 4, prec=api.DDQ_F32)
+    x0 = c.full(505) * 0.1
+    ref = solvers.sap(c.op, b, x0, 2, m)
+    x = torch.from_numpy(x0.copy()).cuda()
+    api.sap_smooth(lat, torch.from_numpy(b).cuda(), x, 2, m, prec=api.DDQ_F32)
     torch.cuda.synchronize()
+    api.destroy_lattice(lat)
     assert rel(x.cpu().numpy(), ref) < 1e-5
 
 

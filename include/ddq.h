@@ -412,10 +412,13 @@ int ddq_oe_smoother(ddq_lattice* lat, int nrhs, const void* r, void* z, int nswe
  * Schur complement from zero, then added to x on the block.  prec: the block solves in
  * DDQ_F64, or in DDQ_F32 with the FP32 links (12-real if stored so) and clover blocks
  * (their dot products accumulated in FP64); the residuals b - D x and the update of x
- * are FP64 either way.  x: initial guess in, iterate out; b: right-hand side (device,
- * not overlapping).  One workgroup per block, the block's half vectors in LDS.  Work
- * space: DDQ_RESERVE_SAP of ddq_reserve (the links and clover blocks are copied into
- * SAP block order there on the first call after ddq_set_gauge / ddq_set_clover).
+ * are FP64 either way; a colour's residual is computed on that colour's blocks only (the
+ * sites its block solves read).  x: initial guess in, iterate out; b: right-hand side
+ * (device, not overlapping).  One workgroup per block, the block's half vectors in LDS
+ * (FP32 with 12-real links: also the block's links).  Work space: DDQ_RESERVE_SAP of
+ * ddq_reserve (the links and clover blocks of the block solves, and the FP64 links and
+ * clover blocks of the residual, are copied into SAP block order there on the first
+ * call after ddq_set_gauge / ddq_set_clover).
  * Synchronises the stream. */
 int ddq_sap_smooth(ddq_lattice* lat, int prec, void* x, const void* b, int n, int m);
 

@@ -151,6 +151,8 @@ struct ddq_lattice {
   Grow oe_ws32;       // the smoother's FP32 parity vectors
   Grow sap_links[2], sap_clov[2];  // links and clover blocks per parity in SAP order
   int sap_prec = -1;               // their precision; -1: not built for the current fields
+  Grow sap_rlinks[2], sap_rclov[2];  // FP64 links and A_ee, A_oo in SAP order (SAP residual)
+  bool sap_res_ok = false;           // built for the current fields
   Grow partial;       // reduction partials
   Grow small;         // device scalars: h (2 x 256 complex), norms
   double* host = nullptr;  // pinned host mirror of `small`
@@ -586,6 +588,8 @@ int reserve_impl(ddq_lattice* L) {
     for (int q = 0; q < 2; ++q) {  // the FP64 sizes cover the FP32 copies
       CHK(L->sap_links[q].ensure(4 * (size_t)LINK_ROWS * fvh * 16));
       CHK(L->sap_clov[q].ensure((size_t)CLOVER_ROWS * fvh * 16));
+      CHK(L->sap_rlinks[q].ensure(4 * (size_t)LINK_ROWS * fvh * 16));
+      CHK(L->sap_rclov[q].ensure((size_t)CLOVER_ROWS * fvh * 16));
     }
   }
   if (what & DDQ_RESERVE_FORCE) CHK(L->force_ws.ensure((2 * nv + (size_t)L->V * 54) * 16));
@@ -716,6 +720,8 @@ int ddq_destroy_lattice(ddq_lattice* L) {
   for (int q = 0; q < 2; ++q) {
     L->sap_links[q].release();
     L->sap_clov[q].release();
+    L->sap_rlinks[q].release();
+    L->sap_rclov[q].release();
   }
   L->force_ws.release();
   L->partial.release();
@@ -764,6 +770,7 @@ int ddq_set_gauge(ddq_lattice* L, const void* U, int U_on_device, unsigned stora
   L->have_gauge = false;
   L->have_clover = false;
   L->sap_prec = -1;
+  L->sap_res_ok = false;
   const size_t ubytes = (size_t)L->V * 4 * 9 * 16;
   if (!L->U) CHK(dalloc(&L->U, ubytes));
   HIPCHK(hipMemcpyAsync(L->U, U, ubytes, U_on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
@@ -822,6 +829,7 @@ int ddq_set_clover(ddq_lattice* L, double c_sw, double m0) {
   if (!std::isfinite(c_sw) || !std::isfinite(m0)) return fail(DDQ_ERR_ARG, "c_sw and m0 must be finite");
   L->have_clover = false;
   L->sap_prec = -1;
+  L->sap_res_ok = false;
   const size_t n = (size_t)36 * field_vh((int)L->Vh);  // (re, im) slots per parity
   for (int q = 0; q < 2; ++q)
     if (!L->clov[DDQ_F64][q]) {
@@ -1853,18 +1861,17 @@ extern "C" int ddq_oe_smoother(ddq_lattice* L, int nrhs, const void* r, void* z,
 namespace {
 
 // SAP(n, m) of Alg. 1 on D x = b (full FP64 vectors), x updated in place: every sweep
-// recomputes r = b - D x (FP64) before each colour's block solves, which run in prec
-// (DDQ_F64 or DDQ_F32).  ws64: the workspace of oe_workspace (the residual uses its
-// upper half).
+// recomputes r = b - D x (FP64) on the blocks of a colour before that colour's block
+// solves, which run in prec (DDQ_F64 or DDQ_F32).  ws64: the workspace of oe_workspace
+// (r uses its upper half).
 int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64) {
-  const long long nf = 2 * L->nvec();  // complex numbers of a full vector
   d2_t* r = ws64 + 4 * (size_t)L->nvec();
   const bool f32 = prec == DDQ_F32;
   const bool l12 = f32 && L->link12;
+  const size_t fvh = (size_t)field_vh((int)L->Vh);
   if (L->sap_prec != prec) {  // links and clover in SAP order, built once per gauge field and clover
     const int cpe = f32 ? 2 : 1;
     const int lrows = (l12 ? LINK12_ROWS : LINK_ROWS) / cpe, crows = CLOVER_ROWS / cpe;
-    const size_t fvh = (size_t)field_vh((int)L->Vh);
     for (int q = 0; q < 2; ++q) {
       CHK(L->sap_links[q].ensure(4 * (size_t)lrows * fvh * 16));
       CHK(L->sap_clov[q].ensure((size_t)crows * fvh * 16));
@@ -1875,16 +1882,34 @@ int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_
     }
     L->sap_prec = prec;
   }
-  // algorithmic bytes of one colour's launch: per site of that colour's blocks, the FP64
-  // residual, the FP64 iterate (read and written), the links and the clover blocks once
+  if (!L->sap_res_ok) {  // the residual's FP64 links and undivided clover blocks in SAP order
+    for (int q = 0; q < 2; ++q) {
+      CHK(L->sap_rlinks[q].ensure(4 * (size_t)LINK_ROWS * fvh * 16));
+      CHK(L->sap_rclov[q].ensure((size_t)CLOVER_ROWS * fvh * 16));
+      for (int mu = 0; mu < 4; ++mu)
+        HIPCHK(launch_sap_reorder(L->geo, q,
+                                  (const char*)L->links[DDQ_F64][q] + (size_t)mu * LINK_ROWS * fvh * 16,
+                                  (char*)L->sap_rlinks[q].p + (size_t)mu * LINK_ROWS * fvh * 16, LINK_ROWS,
+                                  L->stream));
+    }
+    HIPCHK(launch_sap_reorder(L->geo, 0, L->clov[DDQ_F64][0], L->sap_rclov[0].p, CLOVER_ROWS, L->stream));
+    HIPCHK(launch_sap_reorder(L->geo, 1, L->clov_oo, L->sap_rclov[1].p, CLOVER_ROWS, L->stream));
+    L->sap_res_ok = true;
+  }
+  // algorithmic bytes of one colour's launches, per site of that colour's blocks:
+  // block solve -- the FP64 residual, the FP64 iterate (read and written), the links and
+  // the clover blocks once; residual -- x (its own sites and, once, the other colour's),
+  // b, r, the FP64 links and clover blocks
   const double per_site = 192 + 384 + (f32 ? (l12 ? 384 : 576) + 288 : 1152 + 576);
   const double bytes = (double)L->V / 2 * per_site;
+  const double bytes_res = (double)L->V / 2 * (2 * 192 + 192 + 192 + 1152 + 576);
   const std::string name = "sap_block_mr" + std::to_string(m) + (f32 ? (l12 ? "_f32l12" : "_f32") : "_f64");
   for (int it = 0; it < n; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      CHK(dirac_impl(L, 1, x, r, ws64));  // r = b - D x
-      HIPCHK(launch_scale(r, r, -1.0, nf, L->stream));
-      HIPCHK(launch_axpy(r, 1.0, 0.0, b, nf, L->stream));
+      HIPCHK(prof_launch(L, "sap_residual_f64", bytes_res, [&]() {  // r = b - D x on the colour's blocks
+        return launch_sap_residual(L->geo, b, x, r, L->sap_rlinks[0].p, L->sap_rlinks[1].p, L->sap_rclov[0].p,
+                                   L->sap_rclov[1].p, colour, L->stream);
+      }));
       HIPCHK(prof_launch(L, name, bytes, [&]() {
         return launch_sap_blocks(L->geo, f32, l12, r, x, L->sap_links[0].p, L->sap_links[1].p, L->sap_clov[0].p,
                                  L->sap_clov[1].p, colour, m, L->stream);

@@ -239,6 +239,11 @@ hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStr
 hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t* r, d2_t* x, const void* links_e,
                              const void* links_o, const void* clov_e, const void* clov_oi, int colour, int m,
                              hipStream_t s);
+// r = b - D x (FP64 full vectors) at the sites of every 4^4 block of `colour`; FP64
+// links and undivided clover blocks A_ee, A_oo in SAP order
+hipError_t launch_sap_residual(const Geo& g, const d2_t* b, const d2_t* x, d2_t* r, const void* links_e,
+                               const void* links_o, const void* clov_ee, const void* clov_oo, int colour,
+                               hipStream_t s);
 // copy of a blocked field of parity `parity` (erows element rows) into SAP order (the
 // 128 sites of that parity of every 4^4 block consecutive), as launch_sap_blocks reads
 // its links and clover

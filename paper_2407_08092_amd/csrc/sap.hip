@@ -321,9 +321,9 @@ __device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int
   for (int s = 0; s < 4; ++s)
 #pragma unroll
     for (int a = 0; a < 3; ++a) nb.c[s][a] = v[3 * s + a][jn];
-  // forward: the site's own link; backward: the neighbour's (any link outside the block,
-  // where the spinor is zero)
-  const int q = (H & 1) ? 1 - p : p, jl = (H & 1) ? (jn & (SAP_HALF - 1)) : j;
+  // forward: the site's own link; backward: the neighbour's (outside the block, where
+  // the spinor is zero, any link: the one at the site's own index)
+  const int q = (H & 1) ? 1 - p : p, jl = ((H & 1) && jn < SAP_HALF) ? jn : j;
 #pragma unroll
   for (int e = 0; e < SAP_LK; ++e) u.u[e] = lk[sap_lk_idx(e, MU, q, jl)];
 }
@@ -575,6 +575,124 @@ k_sap_block_split(SapArgs a) {
   for (int k = 0; k < 6; ++k) t6[k] = ro[k] + 0.5f * t6[k];
   clover_block_apply<float>(clo, t6, q6);
   sap_add_rows6(a.x, site_o, h, q6);
+}
+
+// ---------------------------------------------------------------------------
+// The residual of Alg. 1 on the blocks of one colour: r = b - D x at every site of the
+// colour's blocks (the sites the block solves read), FP64, one workgroup of 256
+// threads per block (thread t: parity t / 128, half index t mod 128).  D x at a site
+// is A x - 1/2 sum over the 8 hops of (1 -/+ g_mu) U x(neighbour) with the lattice's
+// boundary conditions, the neighbours anywhere in the lattice.  Links and clover blocks
+// (A_ee, A_oo: the undivided blocks) come from FP64 copies in SAP order, so each
+// wavefront reads them as contiguous runs; x, b and r are the full vectors.
+// ---------------------------------------------------------------------------
+struct SapResArgs {
+  Geo g;
+  const d2_t* b;
+  const d2_t* x;
+  d2_t* r;
+  const void* links[2];  // FP64 links per parity in SAP order (LINK_ROWS rows a direction)
+  const void* clov[2];   // FP64 A_ee, A_oo in SAP order
+  int nb[4];
+  int colour;
+};
+
+__global__ void __launch_bounds__(256) k_sap_residual(SapResArgs a) {
+  const Geo& g = a.g;
+  int bc[4];
+  {
+    const int hx = (a.nb[0] + 1) >> 1;
+    const int k = (int)blockIdx.x;
+    int row = k / hx;
+    bc[1] = row % a.nb[1];
+    row /= a.nb[1];
+    bc[2] = row % a.nb[2];
+    bc[3] = row / a.nb[2];
+    bc[0] = 2 * (k - (k / hx) * hx) + ((a.colour + bc[1] + bc[2] + bc[3]) & 1);
+  }
+  if (bc[0] >= a.nb[0]) return;  // uniform over the workgroup
+  const int blk = bc[0] + a.nb[0] * (bc[1] + a.nb[1] * (bc[2] + a.nb[2] * bc[3]));
+  const int q = (int)threadIdx.x >> 7, j = (int)threadIdx.x & (SAP_HALF - 1);
+  int lc[4], gc[4];
+  sap_local(j, q, lc);
+  for (int mu = 0; mu < 4; ++mu) gc[mu] = SAP_B * bc[mu] + lc[mu];
+  auto lex = [&](const int c[4]) {
+    return c[0] + (long long)g.L[0] * (c[1] + (long long)g.L[1] * (c[2] + (long long)g.L[2] * c[3]));
+  };
+  const long long site = lex(gc);
+  const int ss = blk * SAP_HALF + j;
+  HopCtx<double> c;
+  c.links = (const pair<double>*)a.links[q];
+  c.lrows = LINK_ROWS;
+  c.vh = g.Vh;
+  c.loff = boff(ss, LINK_ROWS);
+  c.sf = -1.0;  // D: forward (1 - g), backward (1 + g)
+  c.sb = 1.0;
+  c.nb.sgn_tf = (g.antiperiodic && gc[3] == g.L[3] - 1) ? -1.f : 1.f;
+  c.nb.sgn_tb = (g.antiperiodic && gc[3] == 0) ? -1.f : 1.f;
+  long long nsite[8];
+#pragma unroll
+  for (int H = 0; H < 8; ++H) {
+    const int mu = H >> 1;
+    int nc[4] = {gc[0], gc[1], gc[2], gc[3]};
+    nc[mu] += (H & 1) ? -1 : 1;
+    if (nc[mu] < 0) nc[mu] += g.L[mu];
+    if (nc[mu] >= g.L[mu]) nc[mu] -= g.L[mu];
+    nsite[H] = lex(nc);
+  }
+  Spinor<double> acc;
+  zero(acc);
+#pragma unroll
+  for (int H = 0; H < 8; ++H) {
+    const Spinor<double> p = sap_load_full<double>(a.x, nsite[H]);
+    const Link<double> u = load_link_half<double>(link_field(c, H >> 1), H & 1, c.loff);
+    switch (H) {
+      case 0: hop_compute<0, double>(acc, p, u, c); break;
+      case 1: hop_compute<1, double>(acc, p, u, c); break;
+      case 2: hop_compute<2, double>(acc, p, u, c); break;
+      case 3: hop_compute<3, double>(acc, p, u, c); break;
+      case 4: hop_compute<4, double>(acc, p, u, c); break;
+      case 5: hop_compute<5, double>(acc, p, u, c); break;
+      case 6: hop_compute<6, double>(acc, p, u, c); break;
+      default: hop_compute<7, double>(acc, p, u, c); break;
+    }
+    hop_fence<double>(acc);
+  }
+  const Spinor<double> ax = clover_mul<double>(bfield(a.clov[q], CLOVER_ROWS, g.Vh), boff(ss, CLOVER_ROWS),
+                                               sap_load_full<double>(a.x, site));
+  const Spinor<double> bb = sap_load_full<double>(a.b, site);
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const cpx<double> v = bb.c[sp][cc] - (ax.c[sp][cc] - 0.5 * acc.c[sp][cc]);
+      a.r[site * 12 + 3 * sp + cc] = d2_t{v.r, v.i};
+    }
+}
+
+hipError_t launch_sap_residual(const Geo& g, const d2_t* b, const d2_t* x, d2_t* r, const void* links_e,
+                               const void* links_o, const void* clov_ee, const void* clov_oo, int colour,
+                               hipStream_t s) {
+  SapResArgs a;
+  a.g = g;
+  a.b = b;
+  a.x = x;
+  a.r = r;
+  a.links[0] = links_e;
+  a.links[1] = links_o;
+  a.clov[0] = clov_ee;
+  a.clov[1] = clov_oo;
+  long long rows = 1;
+  for (int mu = 0; mu < 4; ++mu) {
+    if (g.L[mu] % SAP_B != 0) return hipErrorInvalidValue;
+    a.nb[mu] = g.L[mu] / SAP_B;
+    if (mu > 0) rows *= a.nb[mu];
+  }
+  const long long nwg = rows * ((a.nb[0] + 1) / 2);
+  if (nwg > 0x7fffffffLL) return hipErrorInvalidValue;
+  a.colour = colour & 1;
+  hipLaunchKernelGGL(k_sap_residual, dim3((unsigned)nwg), dim3(256), 0, s, a);
+  return hipGetLastError();
 }
 
 // dst = src with its sites of parity p in SAP order: element row e of SAP position

@@ -278,19 +278,38 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 block solve with 12-real links, all operands on chip across the MR steps.
-// The block's 1,024 forward links U_mu(x) (first two rows, 48 KB) are copied into LDS
-// once; every hop of the block reads its link there: the forward hop of site x takes
-// U_mu(x), the backward hop U_mu(x - mu)^H, the forward link of the neighbour.  Each
-// thread keeps the clover slots of its two sites (A_ee of the even one, A_oo^-1 of the
-// odd one: 72 complex numbers) in registers.  Per workgroup 60 KB of LDS, so two
-// blocks share a compute unit, one wavefront per SIMD.
+// FP32 block solves with the block's links in LDS across the MR steps: the forward hop
+// of site x reads U_mu(x), the backward hop the neighbour's U_mu(x - mu) and applies
+// its adjoint.  Two LDS forms of the links:
+// * 12-real storage: rows 0 and 1 of all 1,024 forward links (48 KB), the third row
+//   rebuilt at each hop; entry e of (direction mu, parity q, half index j) at
+//   (e * 8 + 2 mu + q) * 128 + j;
+// * 18-real storage (L18; no block spans y, z or t): the whole matrices of the 832
+//   links a hop can use (59 KB) -- all of x, and of y, z, t those whose site is not at
+//   the block's last coordinate in the direction (that link leaves the block); entry e
+//   of (mu, q, compact index c) at e * SAP_L18 + sap_l18_base(mu, q) + c.
 // ---------------------------------------------------------------------------
-constexpr int SAP_LK = 6;  // complex entries of a link kept in LDS (rows 0, 1)
+constexpr int SAP_LK = 6;                        // entries of a link in the 12-real form
+constexpr int SAP_L18 = 2 * (SAP_HALF + 3 * 96);  // links of the 18-real form
 
-// LDS index of entry e of the forward link of direction mu at (parity q, half index j)
 __device__ __forceinline__ int sap_lk_idx(int e, int mu, int q, int j) {
   return (e * 8 + 2 * mu + q) * SAP_HALF + j;
+}
+__device__ __forceinline__ int sap_l18_base(int mu, int q) {
+  return mu == 0 ? q * SAP_HALF : 2 * SAP_HALF + (mu - 1) * 192 + q * 96;
+}
+// compact index of the link of direction mu at half index j (of a site whose coordinate
+// in mu is at most 2, or mu = 0); clamped to a valid index for the others
+__device__ __forceinline__ int sap_l18_c(int mu, int j) {
+  if (mu == 0) return j;
+  int c;
+  if (mu == 1)
+    c = (j & 1) + 2 * ((j >> 1) & 3) + 6 * (j >> 3);
+  else if (mu == 2)
+    c = (j & 7) + 8 * ((j >> 3) & 3) + 24 * (j >> 5);
+  else
+    c = j;
+  return c < 95 ? c : 95;
 }
 
 // half index of hop H's neighbour of the site at local coordinates lc (wrapping inside
@@ -309,9 +328,9 @@ __device__ __forceinline__ int sap_nbr(const Geo& g, const int lc[4], int H) {
 }
 
 // operands of hop H of the site (parity p, half index j): the neighbour's spinor from
-// the half-block vector v (its zero column outside the block) and the two stored rows
-// of the link; every lane reads, so the reads go out together
-template <int H>
+// the half-block vector v (its zero column outside the block) and the link's stored
+// entries; every lane reads, so the reads go out together
+template <int H, bool L18>
 __device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int p, int j,
                                               const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
                                               Spinor<float>& nb, Link<float>& u) {
@@ -324,14 +343,20 @@ __device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int
   // forward: the site's own link; backward: the neighbour's (outside the block, where
   // the spinor is zero, any link: the one at the site's own index)
   const int q = (H & 1) ? 1 - p : p, jl = ((H & 1) && jn < SAP_HALF) ? jn : j;
+  if constexpr (L18) {
+    const int o = sap_l18_base(MU, q) + sap_l18_c(MU, jl);
 #pragma unroll
-  for (int e = 0; e < SAP_LK; ++e) u.u[e] = lk[sap_lk_idx(e, MU, q, jl)];
+    for (int e = 0; e < 9; ++e) u.u[e] = lk[e * SAP_L18 + o];
+  } else {
+#pragma unroll
+    for (int e = 0; e < SAP_LK; ++e) u.u[e] = lk[sap_lk_idx(e, MU, q, jl)];
+  }
 }
 
-template <int H>
+template <int H, bool L18>
 __device__ __forceinline__ void sap_lds_hop(Spinor<float>& acc, const Spinor<float>& nb, Link<float> u,
                                             const HopCtx<float>& c) {
-  su3_third_row(u);
+  if constexpr (!L18) su3_third_row(u);
   if constexpr (H & 1) {
     Link<float> d;
 #pragma unroll
@@ -345,7 +370,7 @@ __device__ __forceinline__ void sap_lds_hop(Spinor<float>& acc, const Spinor<flo
 }
 
 // hops H..HE-1, the operands of hop H + 1 read before hop H's arithmetic
-template <int H, int HE>
+template <int H, int HE, bool L18>
 __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int p, int j,
                                               const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
                                               const HopCtx<float>& c, Spinor<float>& acc, const Spinor<float>& nb,
@@ -353,12 +378,12 @@ __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int
   if constexpr (H + 1 < HE) {
     Spinor<float> nn;
     Link<float> un;
-    sap_lds_loads<H + 1>(g, lc, p, j, v, lk, nn, un);
-    sap_lds_hop<H>(acc, nb, u, c);
+    sap_lds_loads<H + 1, L18>(g, lc, p, j, v, lk, nn, un);
+    sap_lds_hop<H, L18>(acc, nb, u, c);
     hop_fence<float>(acc);
-    sap_lds_steps<H + 1, HE>(g, lc, p, j, v, lk, c, acc, nn, un);
+    sap_lds_steps<H + 1, HE, L18>(g, lc, p, j, v, lk, c, acc, nn, un);
   } else {
-    sap_lds_hop<H>(acc, nb, u, c);
+    sap_lds_hop<H, L18>(acc, nb, u, c);
     hop_fence<float>(acc);
   }
 }
@@ -369,12 +394,14 @@ __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int
 // sums the hops of directions 2h and 2h + 1 into a partial spinor; the partials meet in
 // LDS, after which thread h owns spins 2h, 2h + 1 of its two sites: the rows clover
 // block h acts on, the rows of the Minimal Residual vectors it updates.  Per workgroup
-// 72 KB of LDS (links, the hop input, the exchange buffer): two blocks share a compute
+// 72 KB of LDS (12-real: links, the hop input, an exchange buffer; 18-real: links and
+// the hop input, which then also carries the exchange): two blocks share a compute
 // unit with two wavefronts per SIMD.
 // ---------------------------------------------------------------------------
 constexpr int SAP_SPLIT = 2 * SAP_HALF;  // threads of a workgroup
 
 // the hops of directions 2h, 2h + 1 (h uniform over the wavefront)
+template <bool L18>
 __device__ __forceinline__ void sap_hops_half(const Geo& g, const int lc[4], int p, int j, int h,
                                               const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
                                               const HopCtx<float>& c, Spinor<float>& acc) {
@@ -382,17 +409,19 @@ __device__ __forceinline__ void sap_hops_half(const Geo& g, const int lc[4], int
   Spinor<float> nb;
   Link<float> u;
   if (h == 0) {
-    sap_lds_loads<0>(g, lc, p, j, v, lk, nb, u);
-    sap_lds_steps<0, 4>(g, lc, p, j, v, lk, c, acc, nb, u);
+    sap_lds_loads<0, L18>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<0, 4, L18>(g, lc, p, j, v, lk, c, acc, nb, u);
   } else {
-    sap_lds_loads<4>(g, lc, p, j, v, lk, nb, u);
-    sap_lds_steps<4, 8>(g, lc, p, j, v, lk, c, acc, nb, u);
+    sap_lds_loads<4, L18>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<4, 8, L18>(g, lc, p, j, v, lk, c, acc, nb, u);
   }
 }
 
 // own[k] (k = 3 s + c: spin 2h + s, colour c) = the sum of both threads' partials;
-// xb: exchange rows, row 6 h' + k written by the thread that does not own them
-__device__ __forceinline__ void sap_exchange(cpx<float> (*xb)[SAP_HALF], int h, int j, const Spinor<float>& acc,
+// xb: exchange rows, row 6 h' + k written by the thread that does not own them (the
+// caller orders the writes after every read of xb's previous contents)
+template <int N>
+__device__ __forceinline__ void sap_exchange(cpx<float> (*xb)[N], int h, int j, const Spinor<float>& acc,
                                              cpx<float> own[6]) {
   if (h == 0) {
 #pragma unroll
@@ -450,11 +479,12 @@ __device__ __forceinline__ void sap_sum3_4(double v[3], double* red /* [4][3] */
   for (int k = 0; k < 3; ++k) v[k] = (red[k] + red[3 + k]) + (red[6 + k] + red[9 + k]);
 }
 
+template <bool L18>
 __global__ void __launch_bounds__(SAP_SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
 k_sap_block_split(SapArgs a) {
-  __shared__ cpx<float> lk[SAP_LK * 8 * SAP_HALF];  // the block's forward links, rows 0 and 1
-  __shared__ cpx<float> vb[12][SAP_HALF + 1];      // hop input; column SAP_HALF zero
-  __shared__ cpx<float> xb[12][SAP_HALF];          // partial sums in exchange
+  __shared__ cpx<float> lk[L18 ? 9 * SAP_L18 : SAP_LK * 8 * SAP_HALF];  // the block's links
+  __shared__ cpx<float> vb[12][SAP_HALF + 1];  // hop input; column SAP_HALF zero
+  __shared__ cpx<float> xb[L18 ? 1 : 12][SAP_HALF];  // partial sums in exchange (12-real form)
   __shared__ double red[12];
   const Geo& g = a.g;
   int bc[4];
@@ -490,20 +520,32 @@ k_sap_block_split(SapArgs a) {
   sap_load_rows6(a.r, site_e, h, re);
   const int ss = blk * SAP_HALF + j;
   const int vh = g.Vh;
-  constexpr int LE = LINK12_ROWS / 2;
   constexpr int CL_E = CLOVER_ROWS / 2;
-  const uint32_t loff = boff(ss, LE), coff = boff(ss, CL_E);
+  const uint32_t loff = boff(ss, (L18 ? LINK_ROWS : LINK12_ROWS) / 2), coff = boff(ss, CL_E);
   // the forward links of directions 2h, 2h + 1 of both parities into LDS
+  constexpr int LR = L18 ? LINK_ROWS : LINK12_ROWS;  // complex rows of a direction's field
 #pragma unroll
   for (int q = 0; q < 2; ++q)
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int mu = 2 * h + d;
-      const Field U = bfield((const pair<float>*)a.links[q] + (size_t)mu * LINK12_ROWS * field_vh(vh), LE, vh);
-      cpx<float> c6[SAP_LK];
-      load_rows<float, DDQ_STREAM_AUX>(U, 0, SAP_LK, loff, c6);
+      const Field U = bfield((const pair<float>*)a.links[q] + (size_t)mu * LR * field_vh(vh), LR / 2, vh);
+      if constexpr (L18) {
+        int lq[4];
+        sap_local(j, q, lq);
+        if (mu == 0 || lq[mu] < SAP_B - 1) {  // the links a hop inside the block uses
+          cpx<float> c10[10];  // rows 0..8: U_mu(x)
+          load_rows<float, DDQ_STREAM_AUX>(U, 0, 10, loff, c10);
+          const int o = sap_l18_base(mu, q) + sap_l18_c(mu, j);
 #pragma unroll
-      for (int e = 0; e < SAP_LK; ++e) lk[sap_lk_idx(e, mu, q, j)] = c6[e];
+          for (int e = 0; e < 9; ++e) lk[e * SAP_L18 + o] = c10[e];
+        }
+      } else {
+        cpx<float> c6[SAP_LK];
+        load_rows<float, DDQ_STREAM_AUX>(U, 0, SAP_LK, loff, c6);
+#pragma unroll
+        for (int e = 0; e < SAP_LK; ++e) lk[sap_lk_idx(e, mu, q, j)] = c6[e];
+      }
     }
   if (threadIdx.x < 12) vb[threadIdx.x][SAP_HALF] = {0.f, 0.f};
   cpx<float> cle[18], clo[18];  // clover block h of A_ee (even site) and of A_oo^-1 (odd site)
@@ -520,12 +562,22 @@ k_sap_block_split(SapArgs a) {
 
   Spinor<float> acc;
   cpx<float> rr[6], ex[6], t6[6], q6[6];
+  // the partials of acc summed into the thread's rows; in the 18-real form through vb,
+  // once every thread has read vb for its hops
+  auto exchange = [&](cpx<float> own[6]) {
+    if constexpr (L18) {
+      __syncthreads();
+      sap_exchange(vb, h, j, acc, own);
+    } else {
+      sap_exchange(xb, h, j, acc, own);
+    }
+  };
   // eq. 2 on the block: b~_e = r_e + H_eo (A_oo^-1 r_o)
   clover_block_apply<float>(clo, ro, t6);
   sap_put6(vb, h, j, t6);
   __syncthreads();  // the links and vb written
-  sap_hops_half(g, le, 0, j, h, vb, lk, ce, acc);
-  sap_exchange(xb, h, j, acc, t6);
+  sap_hops_half<L18>(g, le, 0, j, h, vb, lk, ce, acc);
+  exchange(t6);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     rr[k] = re[k] + 0.5f * t6[k];
@@ -536,15 +588,16 @@ k_sap_block_split(SapArgs a) {
     __syncthreads();  // every thread is done reading vb
     sap_put6(vb, h, j, rr);
     __syncthreads();
-    sap_hops_half(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
-    sap_exchange(xb, h, j, acc, q6);
+    sap_hops_half<L18>(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
+    exchange(q6);
 #pragma unroll
     for (int k = 0; k < 6; ++k) q6[k] = 0.5f * q6[k];
     clover_block_apply<float>(clo, q6, t6);  // A_oo^-1 H_oe r
-    sap_put6(vb, h, j, t6);  // vb's readers passed the exchange's barrier
+    if constexpr (L18) __syncthreads();  // every thread has read its partials from vb
+    sap_put6(vb, h, j, t6);  // (12-real: vb's readers passed the exchange's barrier)
     __syncthreads();
-    sap_hops_half(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
-    sap_exchange(xb, h, j, acc, t6);
+    sap_hops_half<L18>(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
+    exchange(t6);
     clover_block_apply<float>(cle, rr, q6);
     double d[3] = {0.0, 0.0, 0.0};  // q^H r, |q|^2
 #pragma unroll
@@ -569,8 +622,8 @@ k_sap_block_split(SapArgs a) {
   sap_put6(vb, h, j, ex);
   sap_add_rows6(a.x, site_e, h, ex);
   __syncthreads();
-  sap_hops_half(g, lo, 1, j, h, vb, lk, co, acc);
-  sap_exchange(xb, h, j, acc, t6);
+  sap_hops_half<L18>(g, lo, 1, j, h, vb, lk, co, acc);
+  exchange(t6);
 #pragma unroll
   for (int k = 0; k < 6; ++k) t6[k] = ro[k] + 0.5f * t6[k];
   clover_block_apply<float>(clo, t6, q6);
@@ -757,7 +810,9 @@ hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t*
   if (!prec_f32)
     hipLaunchKernelGGL(k_sap_block<double>, grid, block, 0, s, a);
   else if (link12)
-    hipLaunchKernelGGL(k_sap_block_split, grid_c, dim3(SAP_SPLIT), 0, s, a);
+    hipLaunchKernelGGL(k_sap_block_split<false>, grid_c, dim3(SAP_SPLIT), 0, s, a);
+  else if (g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B)  // 18-real: no block spans y, z, t
+    hipLaunchKernelGGL(k_sap_block_split<true>, grid_c, dim3(SAP_SPLIT), 0, s, a);
   else
     hipLaunchKernelGGL(k_sap_block<float>, grid, block, 0, s, a);
   return hipGetLastError();

@@ -330,10 +330,10 @@ __device__ __forceinline__ int sap_nbr(const Geo& g, const int lc[4], int H) {
 // operands of hop H of the site (parity p, half index j): the neighbour's spinor from
 // the half-block vector v (its zero column outside the block) and the link's stored
 // entries; every lane reads, so the reads go out together
-template <int H, bool L18>
+template <int H, bool L18, typename R>
 __device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int p, int j,
-                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
-                                              Spinor<float>& nb, Link<float>& u) {
+                                              const cpx<R> (*v)[SAP_HALF + 1], const cpx<R>* lk,
+                                              Spinor<R>& nb, Link<R>& u) {
   constexpr int MU = H >> 1;
   const int jn = sap_nbr(g, lc, H);
 #pragma unroll
@@ -353,38 +353,38 @@ __device__ __forceinline__ void sap_lds_loads(const Geo& g, const int lc[4], int
   }
 }
 
-template <int H, bool L18>
-__device__ __forceinline__ void sap_lds_hop(Spinor<float>& acc, const Spinor<float>& nb, Link<float> u,
-                                            const HopCtx<float>& c) {
+template <int H, bool L18, typename R>
+__device__ __forceinline__ void sap_lds_hop(Spinor<R>& acc, const Spinor<R>& nb, Link<R> u,
+                                            const HopCtx<R>& c) {
   if constexpr (!L18) su3_third_row(u);
   if constexpr (H & 1) {
-    Link<float> d;
+    Link<R> d;
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
       for (int b = 0; b < 3; ++b) d.u[3 * a + b] = conj(u.u[3 * b + a]);
-    hop_compute<H, float>(acc, nb, d, c);
+    hop_compute<H, R>(acc, nb, d, c);
   } else {
-    hop_compute<H, float>(acc, nb, u, c);
+    hop_compute<H, R>(acc, nb, u, c);
   }
 }
 
 // hops H..HE-1, the operands of hop H + 1 read before hop H's arithmetic
-template <int H, int HE, bool L18>
+template <int H, int HE, bool L18, typename R>
 __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int p, int j,
-                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
-                                              const HopCtx<float>& c, Spinor<float>& acc, const Spinor<float>& nb,
-                                              const Link<float>& u) {
+                                              const cpx<R> (*v)[SAP_HALF + 1], const cpx<R>* lk,
+                                              const HopCtx<R>& c, Spinor<R>& acc, const Spinor<R>& nb,
+                                              const Link<R>& u) {
   if constexpr (H + 1 < HE) {
-    Spinor<float> nn;
-    Link<float> un;
-    sap_lds_loads<H + 1, L18>(g, lc, p, j, v, lk, nn, un);
-    sap_lds_hop<H, L18>(acc, nb, u, c);
-    hop_fence<float>(acc);
-    sap_lds_steps<H + 1, HE, L18>(g, lc, p, j, v, lk, c, acc, nn, un);
+    Spinor<R> nn;
+    Link<R> un;
+    sap_lds_loads<H + 1, L18, R>(g, lc, p, j, v, lk, nn, un);
+    sap_lds_hop<H, L18, R>(acc, nb, u, c);
+    hop_fence<R>(acc);
+    sap_lds_steps<H + 1, HE, L18, R>(g, lc, p, j, v, lk, c, acc, nn, un);
   } else {
-    sap_lds_hop<H, L18>(acc, nb, u, c);
-    hop_fence<float>(acc);
+    sap_lds_hop<H, L18, R>(acc, nb, u, c);
+    hop_fence<R>(acc);
   }
 }
 
@@ -401,28 +401,28 @@ __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int
 constexpr int SAP_SPLIT = 2 * SAP_HALF;  // threads of a workgroup
 
 // the hops of directions 2h, 2h + 1 (h uniform over the wavefront)
-template <bool L18>
+template <bool L18, typename R>
 __device__ __forceinline__ void sap_hops_half(const Geo& g, const int lc[4], int p, int j, int h,
-                                              const cpx<float> (*v)[SAP_HALF + 1], const cpx<float>* lk,
-                                              const HopCtx<float>& c, Spinor<float>& acc) {
+                                              const cpx<R> (*v)[SAP_HALF + 1], const cpx<R>* lk,
+                                              const HopCtx<R>& c, Spinor<R>& acc) {
   zero(acc);
-  Spinor<float> nb;
-  Link<float> u;
+  Spinor<R> nb;
+  Link<R> u;
   if (h == 0) {
-    sap_lds_loads<0, L18>(g, lc, p, j, v, lk, nb, u);
-    sap_lds_steps<0, 4, L18>(g, lc, p, j, v, lk, c, acc, nb, u);
+    sap_lds_loads<0, L18, R>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<0, 4, L18, R>(g, lc, p, j, v, lk, c, acc, nb, u);
   } else {
-    sap_lds_loads<4, L18>(g, lc, p, j, v, lk, nb, u);
-    sap_lds_steps<4, 8, L18>(g, lc, p, j, v, lk, c, acc, nb, u);
+    sap_lds_loads<4, L18, R>(g, lc, p, j, v, lk, nb, u);
+    sap_lds_steps<4, 8, L18, R>(g, lc, p, j, v, lk, c, acc, nb, u);
   }
 }
 
 // own[k] (k = 3 s + c: spin 2h + s, colour c) = the sum of both threads' partials;
 // xb: exchange rows, row 6 h' + k written by the thread that does not own them (the
 // caller orders the writes after every read of xb's previous contents)
-template <int N>
-__device__ __forceinline__ void sap_exchange(cpx<float> (*xb)[N], int h, int j, const Spinor<float>& acc,
-                                             cpx<float> own[6]) {
+template <int N, typename R>
+__device__ __forceinline__ void sap_exchange(cpx<R> (*xb)[N], int h, int j, const Spinor<R>& acc,
+                                             cpx<R> own[6]) {
   if (h == 0) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) xb[6 + k][j] = acc.c[2 + k / 3][k % 3];
@@ -441,14 +441,16 @@ __device__ __forceinline__ void sap_exchange(cpx<float> (*xb)[N], int h, int j, 
 }
 
 // rows 6 h .. 6 h + 5 of a site of a full FP64 vector
-__device__ __forceinline__ void sap_load_rows6(const d2_t* f, long long site, int h, cpx<float> o[6]) {
+template <typename R>
+__device__ __forceinline__ void sap_load_rows6(const d2_t* f, long long site, int h, cpx<R> o[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     const d2_t q = f[site * 12 + 6 * h + k];
-    o[k] = {(float)q.x, (float)q.y};
+    o[k] = {(R)q.x, (R)q.y};
   }
 }
-__device__ __forceinline__ void sap_add_rows6(d2_t* f, long long site, int h, const cpx<float> s[6]) {
+template <typename R>
+__device__ __forceinline__ void sap_add_rows6(d2_t* f, long long site, int h, const cpx<R> s[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
     d2_t q = f[site * 12 + 6 * h + k];
@@ -459,7 +461,8 @@ __device__ __forceinline__ void sap_add_rows6(d2_t* f, long long site, int h, co
   store_fence();
 }
 
-__device__ __forceinline__ void sap_put6(cpx<float> (*v)[SAP_HALF + 1], int h, int j, const cpx<float> s[6]) {
+template <typename R>
+__device__ __forceinline__ void sap_put6(cpx<R> (*v)[SAP_HALF + 1], int h, int j, const cpx<R> s[6]) {
 #pragma unroll
   for (int k = 0; k < 6; ++k) v[6 * h + k][j] = s[k];
 }
@@ -479,12 +482,12 @@ __device__ __forceinline__ void sap_sum3_4(double v[3], double* red /* [4][3] */
   for (int k = 0; k < 3; ++k) v[k] = (red[k] + red[3 + k]) + (red[6 + k] + red[9 + k]);
 }
 
-template <bool L18>
-__global__ void __launch_bounds__(SAP_SPLIT) __attribute__((amdgpu_waves_per_eu(2)))
+template <typename R, bool L18>
+__global__ void __launch_bounds__(SAP_SPLIT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
 k_sap_block_split(SapArgs a) {
-  __shared__ cpx<float> lk[L18 ? 9 * SAP_L18 : SAP_LK * 8 * SAP_HALF];  // the block's links
-  __shared__ cpx<float> vb[12][SAP_HALF + 1];  // hop input; column SAP_HALF zero
-  __shared__ cpx<float> xb[L18 ? 1 : 12][SAP_HALF];  // partial sums in exchange (12-real form)
+  __shared__ cpx<R> lk[L18 ? 9 * SAP_L18 : SAP_LK * 8 * SAP_HALF];  // the block's links
+  __shared__ cpx<R> vb[12][SAP_HALF + 1];  // hop input; column SAP_HALF zero
+  __shared__ cpx<R> xb[L18 ? 1 : 12][SAP_HALF];  // partial sums in exchange (12-real form)
   __shared__ double red[12];
   const Geo& g = a.g;
   int bc[4];
@@ -515,13 +518,13 @@ k_sap_block_split(SapArgs a) {
     site_e = ge[0] + (long long)g.L[0] * (ge[1] + (long long)g.L[1] * (ge[2] + (long long)g.L[2] * ge[3]));
     site_o = go[0] + (long long)g.L[0] * (go[1] + (long long)g.L[1] * (go[2] + (long long)g.L[2] * go[3]));
   }
-  cpx<float> ro[6], re[6];  // the thread's rows of the residual (r_o kept for the reconstruction)
+  cpx<R> ro[6], re[6];  // the thread's rows of the residual (r_o kept for the reconstruction)
   sap_load_rows6(a.r, site_o, h, ro);
   sap_load_rows6(a.r, site_e, h, re);
   const int ss = blk * SAP_HALF + j;
   const int vh = g.Vh;
-  constexpr int CL_E = CLOVER_ROWS / 2;
-  const uint32_t loff = boff(ss, (L18 ? LINK_ROWS : LINK12_ROWS) / 2), coff = boff(ss, CL_E);
+  constexpr int CL_E = CLOVER_ROWS / CPE<R>;
+  const uint32_t loff = boff(ss, (L18 ? LINK_ROWS : LINK12_ROWS) / CPE<R>), coff = boff(ss, CL_E);
   // the forward links of directions 2h, 2h + 1 of both parities into LDS
   constexpr int LR = L18 ? LINK_ROWS : LINK12_ROWS;  // complex rows of a direction's field
 #pragma unroll
@@ -529,42 +532,43 @@ k_sap_block_split(SapArgs a) {
 #pragma unroll
     for (int d = 0; d < 2; ++d) {
       const int mu = 2 * h + d;
-      const Field U = bfield((const pair<float>*)a.links[q] + (size_t)mu * LR * field_vh(vh), LR / 2, vh);
+      const Field U = bfield((const pair<R>*)a.links[q] + (size_t)mu * LR * field_vh(vh), LR / CPE<R>, vh);
       if constexpr (L18) {
         int lq[4];
         sap_local(j, q, lq);
         if (mu == 0 || lq[mu] < SAP_B - 1) {  // the links a hop inside the block uses
-          cpx<float> c10[10];  // rows 0..8: U_mu(x)
-          load_rows<float, DDQ_STREAM_AUX>(U, 0, 10, loff, c10);
+          constexpr int NR = (9 + CPE<R> - 1) / CPE<R> * CPE<R>;  // whole elements
+          cpx<R> c10[NR];  // rows 0..8: U_mu(x)
+          load_rows<R, DDQ_STREAM_AUX>(U, 0, NR, loff, c10);
           const int o = sap_l18_base(mu, q) + sap_l18_c(mu, j);
 #pragma unroll
           for (int e = 0; e < 9; ++e) lk[e * SAP_L18 + o] = c10[e];
         }
       } else {
-        cpx<float> c6[SAP_LK];
-        load_rows<float, DDQ_STREAM_AUX>(U, 0, SAP_LK, loff, c6);
+        cpx<R> c6[SAP_LK];
+        load_rows<R, DDQ_STREAM_AUX>(U, 0, SAP_LK, loff, c6);
 #pragma unroll
         for (int e = 0; e < SAP_LK; ++e) lk[sap_lk_idx(e, mu, q, j)] = c6[e];
       }
     }
-  if (threadIdx.x < 12) vb[threadIdx.x][SAP_HALF] = {0.f, 0.f};
-  cpx<float> cle[18], clo[18];  // clover block h of A_ee (even site) and of A_oo^-1 (odd site)
-  load_rows<float, DDQ_STREAM_AUX>(bfield(a.clov_e, CL_E, vh), 18 * h, 18, coff, cle);
-  load_rows<float, DDQ_STREAM_AUX>(bfield(a.clov_oi, CL_E, vh), 18 * h, 18, coff, clo);
-  HopCtx<float> ce, co;
-  ce.sf = co.sf = -1.f;
-  ce.sb = co.sb = 1.f;
+  if (threadIdx.x < 12) vb[threadIdx.x][SAP_HALF] = {R(0), R(0)};
+  cpx<R> cle[18], clo[18];  // clover block h of A_ee (even site) and of A_oo^-1 (odd site)
+  load_rows<R, DDQ_STREAM_AUX>(bfield(a.clov_e, CL_E, vh), 18 * h, 18, coff, cle);
+  load_rows<R, DDQ_STREAM_AUX>(bfield(a.clov_oi, CL_E, vh), 18 * h, 18, coff, clo);
+  HopCtx<R> ce, co;
+  ce.sf = co.sf = R(-1);
+  ce.sb = co.sb = R(1);
   const bool wrap_t = g.L[3] == SAP_B && g.antiperiodic;
   ce.nb.sgn_tf = (wrap_t && le[3] == SAP_B - 1) ? -1.f : 1.f;
   ce.nb.sgn_tb = (wrap_t && le[3] == 0) ? -1.f : 1.f;
   co.nb.sgn_tf = (wrap_t && lo[3] == SAP_B - 1) ? -1.f : 1.f;
   co.nb.sgn_tb = (wrap_t && lo[3] == 0) ? -1.f : 1.f;
 
-  Spinor<float> acc;
-  cpx<float> rr[6], ex[6], t6[6], q6[6];
+  Spinor<R> acc;
+  cpx<R> rr[6], ex[6], t6[6], q6[6];
   // the partials of acc summed into the thread's rows; in the 18-real form through vb,
   // once every thread has read vb for its hops
-  auto exchange = [&](cpx<float> own[6]) {
+  auto exchange = [&](cpx<R> own[6]) {
     if constexpr (L18) {
       __syncthreads();
       sap_exchange(vb, h, j, acc, own);
@@ -573,36 +577,36 @@ k_sap_block_split(SapArgs a) {
     }
   };
   // eq. 2 on the block: b~_e = r_e + H_eo (A_oo^-1 r_o)
-  clover_block_apply<float>(clo, ro, t6);
+  clover_block_apply<R>(clo, ro, t6);
   sap_put6(vb, h, j, t6);
   __syncthreads();  // the links and vb written
-  sap_hops_half<L18>(g, le, 0, j, h, vb, lk, ce, acc);
+  sap_hops_half<L18, R>(g, le, 0, j, h, vb, lk, ce, acc);
   exchange(t6);
 #pragma unroll
   for (int k = 0; k < 6; ++k) {
-    rr[k] = re[k] + 0.5f * t6[k];
-    ex[k] = {0.f, 0.f};
+    rr[k] = re[k] + R(0.5) * t6[k];
+    ex[k] = {R(0), R(0)};
   }
   // Minimal Residual on the block Schur complement S = A_ee - H_eo A_oo^-1 H_oe
   for (int it = 0; it < a.m; ++it) {
     __syncthreads();  // every thread is done reading vb
     sap_put6(vb, h, j, rr);
     __syncthreads();
-    sap_hops_half<L18>(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
+    sap_hops_half<L18, R>(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
     exchange(q6);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) q6[k] = 0.5f * q6[k];
-    clover_block_apply<float>(clo, q6, t6);  // A_oo^-1 H_oe r
+    for (int k = 0; k < 6; ++k) q6[k] = R(0.5) * q6[k];
+    clover_block_apply<R>(clo, q6, t6);  // A_oo^-1 H_oe r
     if constexpr (L18) __syncthreads();  // every thread has read its partials from vb
     sap_put6(vb, h, j, t6);  // (12-real: vb's readers passed the exchange's barrier)
     __syncthreads();
-    sap_hops_half<L18>(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
+    sap_hops_half<L18, R>(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
     exchange(t6);
-    clover_block_apply<float>(cle, rr, q6);
+    clover_block_apply<R>(cle, rr, q6);
     double d[3] = {0.0, 0.0, 0.0};  // q^H r, |q|^2
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
-      q6[k] = q6[k] - 0.5f * t6[k];
+      q6[k] = q6[k] - R(0.5) * t6[k];
       const double qr = q6[k].r, qi = q6[k].i, rr_ = rr[k].r, ri = rr[k].i;
       d[0] += qr * rr_ + qi * ri;
       d[1] += qr * ri - qi * rr_;
@@ -610,7 +614,7 @@ k_sap_block_split(SapArgs a) {
     }
     sap_sum3_4(d, red);
     if (d[2] == 0.0) break;  // uniform: every thread holds the same sums
-    const cpx<float> alpha = {(float)(d[0] / d[2]), (float)(d[1] / d[2])};
+    const cpx<R> alpha = {(R)(d[0] / d[2]), (R)(d[1] / d[2])};
 #pragma unroll
     for (int k = 0; k < 6; ++k) {
       ex[k] = ex[k] + alpha * rr[k];
@@ -622,11 +626,11 @@ k_sap_block_split(SapArgs a) {
   sap_put6(vb, h, j, ex);
   sap_add_rows6(a.x, site_e, h, ex);
   __syncthreads();
-  sap_hops_half<L18>(g, lo, 1, j, h, vb, lk, co, acc);
+  sap_hops_half<L18, R>(g, lo, 1, j, h, vb, lk, co, acc);
   exchange(t6);
 #pragma unroll
-  for (int k = 0; k < 6; ++k) t6[k] = ro[k] + 0.5f * t6[k];
-  clover_block_apply<float>(clo, t6, q6);
+  for (int k = 0; k < 6; ++k) t6[k] = ro[k] + R(0.5) * t6[k];
+  clover_block_apply<R>(clo, t6, q6);
   sap_add_rows6(a.x, site_o, h, q6);
 }
 
@@ -807,12 +811,15 @@ hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t*
   const dim3 grid((unsigned)nblk), block(SAP_HALF);
   // the LDS kernel's grid: the blocks of one colour, (nb[0] + 1) / 2 of them per row in x
   const dim3 grid_c((unsigned)(nblk / a.nb[0] * ((a.nb[0] + 1) / 2)));
-  if (!prec_f32)
+  const bool l18_fits = g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B;  // no block spans y, z, t
+  if (!prec_f32 && l18_fits)
+    hipLaunchKernelGGL((k_sap_block_split<double, true>), grid_c, dim3(SAP_SPLIT), 0, s, a);
+  else if (!prec_f32)
     hipLaunchKernelGGL(k_sap_block<double>, grid, block, 0, s, a);
   else if (link12)
-    hipLaunchKernelGGL(k_sap_block_split<false>, grid_c, dim3(SAP_SPLIT), 0, s, a);
-  else if (g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B)  // 18-real: no block spans y, z, t
-    hipLaunchKernelGGL(k_sap_block_split<true>, grid_c, dim3(SAP_SPLIT), 0, s, a);
+    hipLaunchKernelGGL((k_sap_block_split<float, false>), grid_c, dim3(SAP_SPLIT), 0, s, a);
+  else if (l18_fits)
+    hipLaunchKernelGGL((k_sap_block_split<float, true>), grid_c, dim3(SAP_SPLIT), 0, s, a);
   else
     hipLaunchKernelGGL(k_sap_block<float>, grid, block, 0, s, a);
   return hipGetLastError();

@@ -14,14 +14,14 @@
 // a wavefront loads is one contiguous run.
 //
 // Two kernels:
-// * k_sap_block (FP64; FP32 with 18-real links): 128 threads, thread j owns the j-th
-//   even and the j-th odd site of the block (the checkerboard half index of the block's
-//   lexicographic site order); the hopping terms read the other parity's half-block
-//   vector from one LDS buffer, the links and clover blocks from memory at every use.
-// * k_sap_block_split (FP32 with 12-real links): everything the MR steps touch stays on
-//   chip -- the block's links in LDS, the clover blocks in registers -- and each site
-//   pair is split over two threads so that two workgroups give every SIMD two
-//   wavefronts (see the kernel).
+// * k_sap_block_split (no block spans y, z or t; or FP32 with 12-real links): everything
+//   the MR steps touch stays on chip -- the block's links in LDS, the clover blocks in
+//   registers -- and each site pair is split over two threads (see the kernel).
+// * k_sap_block (the other lattices: FP64, FP32 with 18-real links): 128 threads,
+//   thread j owns the j-th even and the j-th odd site of the block (the checkerboard
+//   half index of the block's lexicographic site order); the hopping terms read the
+//   other parity's half-block vector from one LDS buffer, the links and clover blocks
+//   from memory at every use.
 #include "hop_common.h"
 
 namespace ddq {

@@ -1862,9 +1862,10 @@ namespace {
 
 // SAP(n, m) of Alg. 1 on D x = b (full FP64 vectors), x updated in place: every sweep
 // recomputes r = b - D x (FP64) on the blocks of a colour before that colour's block
-// solves, which run in prec (DDQ_F64 or DDQ_F32).  ws64: the workspace of oe_workspace
-// (r uses its upper half).
-int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64) {
+// solves, which run in prec (DDQ_F64 or DDQ_F32).  x_zero: x is zero on entry, so the
+// first colour's residual is b itself and is read from b.  ws64: the workspace of
+// oe_workspace (r uses its upper half).
+int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_t* ws64, bool x_zero = false) {
   d2_t* r = ws64 + 4 * (size_t)L->nvec();
   const bool f32 = prec == DDQ_F32;
   const bool l12 = f32 && L->link12;
@@ -1906,13 +1907,15 @@ int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_
   const std::string name = "sap_block_mr" + std::to_string(m) + (f32 ? (l12 ? "_f32l12" : "_f32") : "_f64");
   for (int it = 0; it < n; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      HIPCHK(prof_launch(L, "sap_residual_f64", bytes_res, [&]() {  // r = b - D x on the colour's blocks
-        return launch_sap_residual(L->geo, b, x, r, L->sap_rlinks[0].p, L->sap_rlinks[1].p, L->sap_rclov[0].p,
-                                   L->sap_rclov[1].p, colour, L->stream);
-      }));
+      const bool from_b = x_zero && it == 0 && colour == 0;  // r = b - D 0
+      if (!from_b)
+        HIPCHK(prof_launch(L, "sap_residual_f64", bytes_res, [&]() {  // r = b - D x on the colour's blocks
+          return launch_sap_residual(L->geo, b, x, r, L->sap_rlinks[0].p, L->sap_rlinks[1].p, L->sap_rclov[0].p,
+                                     L->sap_rclov[1].p, colour, L->stream);
+        }));
       HIPCHK(prof_launch(L, name, bytes, [&]() {
-        return launch_sap_blocks(L->geo, f32, l12, r, x, L->sap_links[0].p, L->sap_links[1].p, L->sap_clov[0].p,
-                                 L->sap_clov[1].p, colour, m, L->stream);
+        return launch_sap_blocks(L->geo, f32, l12, from_b ? b : r, x, L->sap_links[0].p, L->sap_links[1].p,
+                                 L->sap_clov[0].p, L->sap_clov[1].p, colour, m, L->stream);
       }));
     }
   return DDQ_OK;
@@ -2018,7 +2021,7 @@ extern "C" int ddq_fgmres_sap_solve(ddq_lattice* L, void* x, const void* b, cons
   const long long nf = 2 * L->nvec();
   auto sap_prec = [&](const d2_t* v, d2_t* z) -> int {  // z = SAP(n, m) on D z = v from zero
     HIPCHK(hipMemsetAsync(z, 0, (size_t)nf * 16, L->stream));
-    return sap_impl(L, prec, z, v, sap_n, sap_m, ws64);
+    return sap_impl(L, prec, z, v, sap_n, sap_m, ws64, true);
   };
   return fgmres_full(L, x, b, P, info, ws64, sap_prec, nullptr, nullptr);
 }

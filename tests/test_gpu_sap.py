@@ -64,6 +64,30 @@ def test_sap_f32_with_twelve_real_links(dims, m):
     assert rel(x.cpu().numpy(), ref) < 1e-5
 
 
+def test_sap_odd_block_count():
+    """12x8x8x8: three blocks along x, so a row of blocks holds two of one colour and one
+    of the other (the on-chip block solves' grid covers both colours' rows); FP64, FP32
+    18-real and FP32 12-real block solves against one oracle run."""
+    dims = (12, 8, 8, 8)
+    c = case(dims)
+    b = c.full(506)
+    x0 = c.full(507) * 0.1
+    ref = solvers.sap(c.op, b, x0, 2, 2)
+    for prec, tol in ((api.DDQ_F64, 1e-12), (api.DDQ_F32, 1e-5)):
+        x = torch.from_numpy(x0.copy()).cuda()
+        api.sap_smooth(c.lat, torch.from_numpy(b).cuda(), x, 2, 2, prec=prec)
+        torch.cuda.synchronize()
+        assert rel(x.cpu().numpy(), ref) < tol, prec
+    lat = api.create_lattice(dims)
+    api.set_gauge(lat, torch.from_numpy(c.U).cuda(), link12=True)
+    api.set_clover(lat, 1.0, -0.2)
+    x = torch.from_numpy(x0.copy()).cuda()
+    api.sap_smooth(lat, torch.from_numpy(b).cuda(), x, 2, 2, prec=api.DDQ_F32)
+    torch.cuda.synchronize()
+    api.destroy_lattice(lat)
+    assert rel(x.cpu().numpy(), ref) < 1e-5
+
+
 def test_sap_reduces_the_residual_and_zero_sweeps():
     c = case((8, 8, 4, 8))
     b = c.full(511)

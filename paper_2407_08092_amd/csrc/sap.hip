@@ -587,9 +587,12 @@ k_sap_block_split(SapArgs a) {
     rr[k] = re[k] + R(0.5) * t6[k];
     ex[k] = {R(0), R(0)};
   }
-  // Minimal Residual on the block Schur complement S = A_ee - H_eo A_oo^-1 H_oe
+  // Minimal Residual on the block Schur complement S = A_ee - H_eo A_oo^-1 H_oe.  A
+  // thread's stores into vb (its own rows of column j) need no barrier before them:
+  // every other thread's reads of column j, in a hop, come before the barrier of the
+  // exchange that follows that hop, and after the exchange only the thread itself reads
+  // its own rows.
   for (int it = 0; it < a.m; ++it) {
-    __syncthreads();  // every thread is done reading vb
     sap_put6(vb, h, j, rr);
     __syncthreads();
     sap_hops_half<L18, R>(g, lo, 1, j, h, vb, lk, co, acc);  // H_oe r
@@ -597,8 +600,7 @@ k_sap_block_split(SapArgs a) {
 #pragma unroll
     for (int k = 0; k < 6; ++k) q6[k] = R(0.5) * q6[k];
     clover_block_apply<R>(clo, q6, t6);  // A_oo^-1 H_oe r
-    if constexpr (L18) __syncthreads();  // every thread has read its partials from vb
-    sap_put6(vb, h, j, t6);  // (12-real: vb's readers passed the exchange's barrier)
+    sap_put6(vb, h, j, t6);
     __syncthreads();
     sap_hops_half<L18, R>(g, le, 0, j, h, vb, lk, ce, acc);  // H_eo A_oo^-1 H_oe r
     exchange(t6);
@@ -622,7 +624,6 @@ k_sap_block_split(SapArgs a) {
     }
   }
   // eq. 2 on the block: e_o = A_oo^-1 (r_o + H_oe e_e)
-  __syncthreads();
   sap_put6(vb, h, j, ex);
   sap_add_rows6(a.x, site_e, h, ex);
   __syncthreads();

@@ -1900,22 +1900,26 @@ int sap_impl(ddq_lattice* L, int prec, d2_t* x, const d2_t* b, int n, int m, d2_
   // algorithmic bytes of one colour's launches, per site of that colour's blocks:
   // block solve -- the FP64 residual, the FP64 iterate (read and written), the links and
   // the clover blocks once; residual -- x (its own sites and, once, the other colour's),
-  // b, r, the FP64 links and clover blocks
+  // b, r, the FP64 links and clover blocks.  On chip the block solves form r themselves:
+  // the sum of both without r's store and load.
   const double per_site = 192 + 384 + (f32 ? (l12 ? 384 : 576) + 288 : 1152 + 576);
-  const double bytes = (double)L->V / 2 * per_site;
-  const double bytes_res = (double)L->V / 2 * (2 * 192 + 192 + 192 + 1152 + 576);
-  const std::string name = "sap_block_mr" + std::to_string(m) + (f32 ? (l12 ? "_f32l12" : "_f32") : "_f64");
+  const double per_site_res = 2 * 192 + 192 + 192 + 1152 + 576;
+  const bool on_chip = sap_on_chip(L->geo, f32, l12);
+  const std::string tag = "_mr" + std::to_string(m) + (f32 ? (l12 ? "_f32l12" : "_f32") : "_f64");
+  const SapResidualSrc src{b, x, {L->sap_rlinks[0].p, L->sap_rlinks[1].p}, {L->sap_rclov[0].p, L->sap_rclov[1].p}};
   for (int it = 0; it < n; ++it)
     for (int colour = 0; colour < 2; ++colour) {
-      const bool from_b = x_zero && it == 0 && colour == 0;  // r = b - D 0
-      if (!from_b)
-        HIPCHK(prof_launch(L, "sap_residual_f64", bytes_res, [&]() {  // r = b - D x on the colour's blocks
-          return launch_sap_residual(L->geo, b, x, r, L->sap_rlinks[0].p, L->sap_rlinks[1].p, L->sap_rclov[0].p,
-                                     L->sap_rclov[1].p, colour, L->stream);
+      const bool from_b = x_zero && it == 0 && colour == 0;  // r = b - D 0 = b
+      if (!from_b && !on_chip)
+        HIPCHK(prof_launch(L, "sap_residual_f64", (double)L->V / 2 * per_site_res, [&]() {
+          return launch_sap_residual(L->geo, src, r, colour, L->stream);  // r = b - D x on the colour's blocks
         }));
-      HIPCHK(prof_launch(L, name, bytes, [&]() {
+      const bool fused = on_chip && !from_b;
+      const double bytes = (double)L->V / 2 * (fused ? per_site + per_site_res - 2 * 192 : per_site);
+      HIPCHK(prof_launch(L, (fused ? "sap_res_block" : "sap_block") + tag, bytes, [&]() {
         return launch_sap_blocks(L->geo, f32, l12, from_b ? b : r, x, L->sap_links[0].p, L->sap_links[1].p,
-                                 L->sap_clov[0].p, L->sap_clov[1].p, colour, m, L->stream);
+                                 L->sap_clov[0].p, L->sap_clov[1].p, colour, m, fused ? &src : nullptr,
+                                 L->stream);
       }));
     }
   return DDQ_OK;

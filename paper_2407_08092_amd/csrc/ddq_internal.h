@@ -232,18 +232,26 @@ hipError_t launch_field_to_f32(const d2_t* in, void* out, int nfields, int crows
 hipError_t launch_links_to_f32_12(const d2_t* in, void* out, int vh, hipStream_t s);
 hipError_t launch_parity_to_f32(void* y, const d2_t* x, int nrhs, int vh, hipStream_t s);
 hipError_t launch_parity_to_f64(d2_t* y, const void* x, int nrhs, int vh, hipStream_t s);
+// sources of the SAP residual r = b - D x (FP64 full vectors b, x; FP64 links per parity
+// and undivided clover blocks A_ee, A_oo, in SAP order)
+struct SapResidualSrc {
+  const d2_t* b;
+  const d2_t* x;
+  const void* links[2];
+  const void* clov[2];
+};
 // SAP block solves: for every 4^4 block of `colour`, m Minimal Residual steps on the
 // block Schur complement of D_kk e = r_k, then x += e on the block (FP64 full vectors r,
 // x); the block solve in FP64, or in FP32 (prec_f32) with FP32 links (12-real: link12)
-// and clover, all in SAP order (launch_sap_reorder)
+// and clover, all in SAP order (launch_sap_reorder).  res: the block solves form r
+// themselves from these sources (only where sap_on_chip holds); null: r is read
 hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t* r, d2_t* x, const void* links_e,
                              const void* links_o, const void* clov_e, const void* clov_oi, int colour, int m,
-                             hipStream_t s);
-// r = b - D x (FP64 full vectors) at the sites of every 4^4 block of `colour`; FP64
-// links and undivided clover blocks A_ee, A_oo in SAP order
-hipError_t launch_sap_residual(const Geo& g, const d2_t* b, const d2_t* x, d2_t* r, const void* links_e,
-                               const void* links_o, const void* clov_ee, const void* clov_oo, int colour,
-                               hipStream_t s);
+                             const SapResidualSrc* res, hipStream_t s);
+// whether launch_sap_blocks solves this lattice's blocks on chip (and can form r itself)
+bool sap_on_chip(const Geo& g, int prec_f32, int link12);
+// r = b - D x (FP64 full vectors) at the sites of every 4^4 block of `colour`
+hipError_t launch_sap_residual(const Geo& g, const SapResidualSrc& src, d2_t* r, int colour, hipStream_t s);
 // copy of a blocked field of parity `parity` (erows element rows) into SAP order (the
 // 128 sites of that parity of every 4^4 block consecutive), as launch_sap_blocks reads
 // its links and clover

@@ -144,6 +144,7 @@ struct SapArgs {
   Geo g;
   const d2_t* r;  // full residual b - D x (ABI full layout)
   d2_t* x;        // full iterate, updated on the blocks of `colour`
+  SapResidualSrc res;  // the on-chip kernel's sources of r = b - D x when it forms r itself
   const void* links[2];  // links per parity, in the block solve's precision
   const void* clov_e;    // A_ee (even sites)
   const void* clov_oi;   // A_oo^-1 (odd sites)
@@ -275,6 +276,115 @@ __global__ void __launch_bounds__(SAP_HALF) k_sap_block(SapArgs a) {
 #pragma unroll
     for (int c = 0; c < 3; ++c) acc.c[s][c] = rr.c[s][c] + R(0.5) * acc.c[s][c];
   sap_add_full(a.x, site_o, clover_mul<R>(Co, cofo, acc));
+}
+
+// ---------------------------------------------------------------------------
+// The residual of Alg. 1 on the blocks of one colour: r = b - D x at every site of the
+// colour's blocks (the sites the block solves read), FP64.  D x at a site is
+// A x - 1/2 sum over the 8 hops of (1 -/+ g_mu) U x(neighbour) with the lattice's
+// boundary conditions, the neighbours anywhere in the lattice.  Links and clover blocks
+// (A_ee, A_oo: the undivided blocks) come from FP64 copies in SAP order, so each
+// wavefront reads them as contiguous runs; x, b and r are the full vectors.  The
+// on-chip block solves form it in their prologue; k_sap_residual writes it out for the
+// other block-solve kernel.
+// ---------------------------------------------------------------------------
+// r at the site (parity q, half index j) of block blk at block coordinates bc
+__device__ __forceinline__ Spinor<double> sap_residual_site(const Geo& g, const int bc[4], int blk, int q, int j,
+                                                            const d2_t* b, const d2_t* x, const void* links,
+                                                            const void* clov) {
+  int lc[4], gc[4];
+  sap_local(j, q, lc);
+  for (int mu = 0; mu < 4; ++mu) gc[mu] = SAP_B * bc[mu] + lc[mu];
+  auto lex = [&](const int c[4]) {
+    return c[0] + (long long)g.L[0] * (c[1] + (long long)g.L[1] * (c[2] + (long long)g.L[2] * c[3]));
+  };
+  const long long site = lex(gc);
+  const int ss = blk * SAP_HALF + j;
+  HopCtx<double> c;
+  c.links = (const pair<double>*)links;
+  c.lrows = LINK_ROWS;
+  c.vh = g.Vh;
+  c.loff = boff(ss, LINK_ROWS);
+  c.sf = -1.0;  // D: forward (1 - g), backward (1 + g)
+  c.sb = 1.0;
+  c.nb.sgn_tf = (g.antiperiodic && gc[3] == g.L[3] - 1) ? -1.f : 1.f;
+  c.nb.sgn_tb = (g.antiperiodic && gc[3] == 0) ? -1.f : 1.f;
+  long long nsite[8];
+#pragma unroll
+  for (int H = 0; H < 8; ++H) {
+    const int mu = H >> 1;
+    int nc[4] = {gc[0], gc[1], gc[2], gc[3]};
+    nc[mu] += (H & 1) ? -1 : 1;
+    if (nc[mu] < 0) nc[mu] += g.L[mu];
+    if (nc[mu] >= g.L[mu]) nc[mu] -= g.L[mu];
+    nsite[H] = lex(nc);
+  }
+  Spinor<double> acc;
+  zero(acc);
+#pragma unroll
+  for (int H = 0; H < 8; ++H) {
+    const Spinor<double> p = sap_load_full<double>(x, nsite[H]);
+    const Link<double> u = load_link_half<double>(link_field(c, H >> 1), H & 1, c.loff);
+    switch (H) {
+      case 0: hop_compute<0, double>(acc, p, u, c); break;
+      case 1: hop_compute<1, double>(acc, p, u, c); break;
+      case 2: hop_compute<2, double>(acc, p, u, c); break;
+      case 3: hop_compute<3, double>(acc, p, u, c); break;
+      case 4: hop_compute<4, double>(acc, p, u, c); break;
+      case 5: hop_compute<5, double>(acc, p, u, c); break;
+      case 6: hop_compute<6, double>(acc, p, u, c); break;
+      default: hop_compute<7, double>(acc, p, u, c); break;
+    }
+    hop_fence<double>(acc);
+  }
+  const Spinor<double> ax =
+      clover_mul<double>(bfield(clov, CLOVER_ROWS, g.Vh), boff(ss, CLOVER_ROWS), sap_load_full<double>(x, site));
+  const Spinor<double> bb = sap_load_full<double>(b, site);
+  Spinor<double> r;
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) r.c[sp][cc] = bb.c[sp][cc] - (ax.c[sp][cc] - 0.5 * acc.c[sp][cc]);
+  return r;
+}
+
+// the block coordinates of workgroup k of a launch over one colour's blocks (bx fastest,
+// (nb[0] + 1) / 2 a row); false for the spare workgroup of a row with an odd count
+__device__ __forceinline__ bool sap_colour_block(const int nb[4], int colour, int k, int bc[4], int& blk) {
+  const int hx = (nb[0] + 1) >> 1;
+  int row = k / hx;
+  bc[1] = row % nb[1];
+  row /= nb[1];
+  bc[2] = row % nb[2];
+  bc[3] = row / nb[2];
+  bc[0] = 2 * (k - (k / hx) * hx) + ((colour + bc[1] + bc[2] + bc[3]) & 1);
+  blk = bc[0] + nb[0] * (bc[1] + nb[1] * (bc[2] + nb[2] * bc[3]));
+  return bc[0] < nb[0];
+}
+
+struct SapResArgs {
+  Geo g;
+  d2_t* r;
+  SapResidualSrc src;
+  int nb[4];
+  int colour;
+};
+
+// one workgroup of 256 threads per block (thread t: parity t / 128, half index t mod 128)
+__global__ void __launch_bounds__(256) k_sap_residual(SapResArgs a) {
+  int bc[4], blk;
+  if (!sap_colour_block(a.nb, a.colour, (int)blockIdx.x, bc, blk)) return;  // uniform
+  // the parity is uniform over a wavefront: its links and clover through scalar descriptors
+  const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 7), j = (int)threadIdx.x & (SAP_HALF - 1);
+  const Spinor<double> r = sap_residual_site(a.g, bc, blk, q, j, a.src.b, a.src.x, a.src.links[q], a.src.clov[q]);
+  int lc[4], gc[4];
+  sap_local(j, q, lc);
+  for (int mu = 0; mu < 4; ++mu) gc[mu] = SAP_B * bc[mu] + lc[mu];
+  const long long site = gc[0] + (long long)a.g.L[0] * (gc[1] + (long long)a.g.L[1] * (gc[2] + (long long)a.g.L[2] * gc[3]));
+#pragma unroll
+  for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) a.r[site * 12 + 3 * sp + cc] = d2_t{r.c[sp][cc].r, r.c[sp][cc].i};
 }
 
 // ---------------------------------------------------------------------------
@@ -482,7 +592,9 @@ __device__ __forceinline__ void sap_sum3_4(double v[3], double* red /* [4][3] */
   for (int k = 0; k < 3; ++k) v[k] = (red[k] + red[3 + k]) + (red[6 + k] + red[9 + k]);
 }
 
-template <typename R, bool L18>
+// RES: the kernel forms r = b - D x at the block's sites itself (a.res), in a prologue
+// whose memory traffic overlaps the other resident block's arithmetic; else it reads a.r
+template <typename R, bool L18, bool RES>
 __global__ void __launch_bounds__(SAP_SPLIT) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 2 : 1)))
 k_sap_block_split(SapArgs a) {
   __shared__ cpx<R> lk[L18 ? 9 * SAP_L18 : SAP_LK * 8 * SAP_HALF];  // the block's links
@@ -490,19 +602,8 @@ k_sap_block_split(SapArgs a) {
   __shared__ cpx<R> xb[L18 ? 1 : 12][SAP_HALF];  // partial sums in exchange (12-real form)
   __shared__ double red[12];
   const Geo& g = a.g;
-  int bc[4];
-  {
-    const int hx = (a.nb[0] + 1) >> 1;
-    const int k = (int)blockIdx.x;
-    int row = k / hx;
-    bc[1] = row % a.nb[1];
-    row /= a.nb[1];
-    bc[2] = row % a.nb[2];
-    bc[3] = row / a.nb[2];
-    bc[0] = 2 * (k - (k / hx) * hx) + ((a.colour + bc[1] + bc[2] + bc[3]) & 1);
-  }
-  if (bc[0] >= a.nb[0]) return;  // uniform over the workgroup
-  const int blk = bc[0] + a.nb[0] * (bc[1] + a.nb[1] * (bc[2] + a.nb[2] * bc[3]));
+  int bc[4], blk;
+  if (!sap_colour_block(a.nb, a.colour, (int)blockIdx.x, bc, blk)) return;  // uniform
   const int j = (int)threadIdx.x & (SAP_HALF - 1);
   const int h = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 7);
   int le[4], lo[4];
@@ -519,8 +620,31 @@ k_sap_block_split(SapArgs a) {
     site_o = go[0] + (long long)g.L[0] * (go[1] + (long long)g.L[1] * (go[2] + (long long)g.L[2] * go[3]));
   }
   cpx<R> ro[6], re[6];  // the thread's rows of the residual (r_o kept for the reconstruction)
-  sap_load_rows6(a.r, site_o, h, ro);
-  sap_load_rows6(a.r, site_e, h, re);
+  if constexpr (RES) {
+    // r at the block's 256 sites (thread t: parity t / 128, half index j), passed to the
+    // threads that own its rows through the LDS that the links take afterwards
+    cpx<R>* rs = lk;  // [parity][12 rows][128 sites]
+    {
+      const int q = __builtin_amdgcn_readfirstlane((int)threadIdx.x >> 7);  // uniform over a wavefront
+      const Spinor<double> rv =
+          sap_residual_site(g, bc, blk, q, j, a.res.b, a.res.x, a.res.links[q], a.res.clov[q]);
+#pragma unroll
+      for (int sp = 0; sp < 4; ++sp)
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc)
+          rs[(q * 12 + 3 * sp + cc) * SAP_HALF + j] = {(R)rv.c[sp][cc].r, (R)rv.c[sp][cc].i};
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+      re[k] = rs[(6 * h + k) * SAP_HALF + j];
+      ro[k] = rs[(12 + 6 * h + k) * SAP_HALF + j];
+    }
+    __syncthreads();  // the links overwrite rs
+  } else {
+    sap_load_rows6(a.r, site_o, h, ro);
+    sap_load_rows6(a.r, site_e, h, re);
+  }
   const int ss = blk * SAP_HALF + j;
   const int vh = g.Vh;
   constexpr int CL_E = CLOVER_ROWS / CPE<R>;
@@ -635,111 +759,11 @@ k_sap_block_split(SapArgs a) {
   sap_add_rows6(a.x, site_o, h, q6);
 }
 
-// ---------------------------------------------------------------------------
-// The residual of Alg. 1 on the blocks of one colour: r = b - D x at every site of the
-// colour's blocks (the sites the block solves read), FP64, one workgroup of 256
-// threads per block (thread t: parity t / 128, half index t mod 128).  D x at a site
-// is A x - 1/2 sum over the 8 hops of (1 -/+ g_mu) U x(neighbour) with the lattice's
-// boundary conditions, the neighbours anywhere in the lattice.  Links and clover blocks
-// (A_ee, A_oo: the undivided blocks) come from FP64 copies in SAP order, so each
-// wavefront reads them as contiguous runs; x, b and r are the full vectors.
-// ---------------------------------------------------------------------------
-struct SapResArgs {
-  Geo g;
-  const d2_t* b;
-  const d2_t* x;
-  d2_t* r;
-  const void* links[2];  // FP64 links per parity in SAP order (LINK_ROWS rows a direction)
-  const void* clov[2];   // FP64 A_ee, A_oo in SAP order
-  int nb[4];
-  int colour;
-};
-
-__global__ void __launch_bounds__(256) k_sap_residual(SapResArgs a) {
-  const Geo& g = a.g;
-  int bc[4];
-  {
-    const int hx = (a.nb[0] + 1) >> 1;
-    const int k = (int)blockIdx.x;
-    int row = k / hx;
-    bc[1] = row % a.nb[1];
-    row /= a.nb[1];
-    bc[2] = row % a.nb[2];
-    bc[3] = row / a.nb[2];
-    bc[0] = 2 * (k - (k / hx) * hx) + ((a.colour + bc[1] + bc[2] + bc[3]) & 1);
-  }
-  if (bc[0] >= a.nb[0]) return;  // uniform over the workgroup
-  const int blk = bc[0] + a.nb[0] * (bc[1] + a.nb[1] * (bc[2] + a.nb[2] * bc[3]));
-  const int q = (int)threadIdx.x >> 7, j = (int)threadIdx.x & (SAP_HALF - 1);
-  int lc[4], gc[4];
-  sap_local(j, q, lc);
-  for (int mu = 0; mu < 4; ++mu) gc[mu] = SAP_B * bc[mu] + lc[mu];
-  auto lex = [&](const int c[4]) {
-    return c[0] + (long long)g.L[0] * (c[1] + (long long)g.L[1] * (c[2] + (long long)g.L[2] * c[3]));
-  };
-  const long long site = lex(gc);
-  const int ss = blk * SAP_HALF + j;
-  HopCtx<double> c;
-  c.links = (const pair<double>*)a.links[q];
-  c.lrows = LINK_ROWS;
-  c.vh = g.Vh;
-  c.loff = boff(ss, LINK_ROWS);
-  c.sf = -1.0;  // D: forward (1 - g), backward (1 + g)
-  c.sb = 1.0;
-  c.nb.sgn_tf = (g.antiperiodic && gc[3] == g.L[3] - 1) ? -1.f : 1.f;
-  c.nb.sgn_tb = (g.antiperiodic && gc[3] == 0) ? -1.f : 1.f;
-  long long nsite[8];
-#pragma unroll
-  for (int H = 0; H < 8; ++H) {
-    const int mu = H >> 1;
-    int nc[4] = {gc[0], gc[1], gc[2], gc[3]};
-    nc[mu] += (H & 1) ? -1 : 1;
-    if (nc[mu] < 0) nc[mu] += g.L[mu];
-    if (nc[mu] >= g.L[mu]) nc[mu] -= g.L[mu];
-    nsite[H] = lex(nc);
-  }
-  Spinor<double> acc;
-  zero(acc);
-#pragma unroll
-  for (int H = 0; H < 8; ++H) {
-    const Spinor<double> p = sap_load_full<double>(a.x, nsite[H]);
-    const Link<double> u = load_link_half<double>(link_field(c, H >> 1), H & 1, c.loff);
-    switch (H) {
-      case 0: hop_compute<0, double>(acc, p, u, c); break;
-      case 1: hop_compute<1, double>(acc, p, u, c); break;
-      case 2: hop_compute<2, double>(acc, p, u, c); break;
-      case 3: hop_compute<3, double>(acc, p, u, c); break;
-      case 4: hop_compute<4, double>(acc, p, u, c); break;
-      case 5: hop_compute<5, double>(acc, p, u, c); break;
-      case 6: hop_compute<6, double>(acc, p, u, c); break;
-      default: hop_compute<7, double>(acc, p, u, c); break;
-    }
-    hop_fence<double>(acc);
-  }
-  const Spinor<double> ax = clover_mul<double>(bfield(a.clov[q], CLOVER_ROWS, g.Vh), boff(ss, CLOVER_ROWS),
-                                               sap_load_full<double>(a.x, site));
-  const Spinor<double> bb = sap_load_full<double>(a.b, site);
-#pragma unroll
-  for (int sp = 0; sp < 4; ++sp)
-#pragma unroll
-    for (int cc = 0; cc < 3; ++cc) {
-      const cpx<double> v = bb.c[sp][cc] - (ax.c[sp][cc] - 0.5 * acc.c[sp][cc]);
-      a.r[site * 12 + 3 * sp + cc] = d2_t{v.r, v.i};
-    }
-}
-
-hipError_t launch_sap_residual(const Geo& g, const d2_t* b, const d2_t* x, d2_t* r, const void* links_e,
-                               const void* links_o, const void* clov_ee, const void* clov_oo, int colour,
-                               hipStream_t s) {
+hipError_t launch_sap_residual(const Geo& g, const SapResidualSrc& src, d2_t* r, int colour, hipStream_t s) {
   SapResArgs a;
   a.g = g;
-  a.b = b;
-  a.x = x;
   a.r = r;
-  a.links[0] = links_e;
-  a.links[1] = links_o;
-  a.clov[0] = clov_ee;
-  a.clov[1] = clov_oo;
+  a.src = src;
   long long rows = 1;
   for (int mu = 0; mu < 4; ++mu) {
     if (g.L[mu] % SAP_B != 0) return hipErrorInvalidValue;
@@ -789,13 +813,31 @@ hipError_t launch_sap_reorder(const Geo& g, int parity, const void* src, void* d
   return hipGetLastError();
 }
 
+bool sap_on_chip(const Geo& g, int prec_f32, int link12) {
+  return (prec_f32 && link12) || (g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B);
+}
+
+template <typename R, bool L18>
+static void launch_split(const SapArgs& a, bool res, dim3 grid, hipStream_t s) {
+  if (res)
+    hipLaunchKernelGGL((k_sap_block_split<R, L18, true>), grid, dim3(SAP_SPLIT), 0, s, a);
+  else
+    hipLaunchKernelGGL((k_sap_block_split<R, L18, false>), grid, dim3(SAP_SPLIT), 0, s, a);
+}
+
 hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t* r, d2_t* x, const void* links_e,
                              const void* links_o, const void* clov_e, const void* clov_oi, int colour, int m,
-                             hipStream_t s) {
+                             const SapResidualSrc* res, hipStream_t s) {
   SapArgs a;
   a.g = g;
   a.r = r;
   a.x = x;
+  if (res) {
+    if (!sap_on_chip(g, prec_f32, link12)) return hipErrorInvalidValue;
+    a.res = *res;
+  } else {
+    a.res = SapResidualSrc{};
+  }
   a.links[0] = links_e;
   a.links[1] = links_o;
   a.clov_e = clov_e;
@@ -813,14 +855,15 @@ hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t*
   // the LDS kernel's grid: the blocks of one colour, (nb[0] + 1) / 2 of them per row in x
   const dim3 grid_c((unsigned)(nblk / a.nb[0] * ((a.nb[0] + 1) / 2)));
   const bool l18_fits = g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B;  // no block spans y, z, t
+  const bool rs = res != nullptr;
   if (!prec_f32 && l18_fits)
-    hipLaunchKernelGGL((k_sap_block_split<double, true>), grid_c, dim3(SAP_SPLIT), 0, s, a);
+    launch_split<double, true>(a, rs, grid_c, s);
   else if (!prec_f32)
     hipLaunchKernelGGL(k_sap_block<double>, grid, block, 0, s, a);
   else if (link12)
-    hipLaunchKernelGGL((k_sap_block_split<float, false>), grid_c, dim3(SAP_SPLIT), 0, s, a);
+    launch_split<float, false>(a, rs, grid_c, s);
   else if (l18_fits)
-    hipLaunchKernelGGL((k_sap_block_split<float, true>), grid_c, dim3(SAP_SPLIT), 0, s, a);
+    launch_split<float, true>(a, rs, grid_c, s);
   else
     hipLaunchKernelGGL(k_sap_block<float>, grid, block, 0, s, a);
   return hipGetLastError();

@@ -1,7 +1,7 @@
 """The boundary's resource and multi-right-hand-side contract, through the raw C ABI
 where it matters:
 
-* apply, smooth and solve allocate nothing: past the reservation they return
+* apply, smooth, SAP and solve allocate nothing: past the reservation they return
   DDQ_ERR_STATE and do nothing; after ddq_reserve they run, leave the device's free
   memory unchanged and give the results of the per-right-hand-side calls;
 * ddq_oe_gmres_solve with several right-hand sides: every system meets the full
@@ -161,3 +161,29 @@ def test_autotune_cache_round_trip(tmp_path):
     assert any(n.endswith("_x4_nb2g4x8") for n in names), names
     ref = np.stack([c.op.schur(v) for v in c.vec(42, 4)])
     assert rel(to_host(y), ref) < 1e-5
+
+
+def test_sap_allocates_nothing_after_its_reservation():
+    """DDQ_RESERVE_SAP covers the SAP-order copies of the block solves (FP64, FP32
+    12-real) and of the residual (FP64 links, A_ee, A_oo): the first calls after the
+    reservation build them there, so no SAP call changes the device's free memory."""
+    L = _lib.lib()
+    dims = (8, 8, 8, 8)
+    c = Case(dims, 0.5, 1.0, -0.2, 41)
+    # the HIP runtime loads sap.hip's code object on the first launch of one of its
+    # kernels (device memory of its own): a SAP call on another lattice does that first
+    warm = torch.from_numpy(c.full(43)).cuda()
+    api.sap_smooth(c.lat, warm, torch.zeros_like(warm), 1, 1, prec=api.DDQ_F64)
+    lat = api.create_lattice(dims)
+    api.set_gauge(lat, torch.from_numpy(c.U).cuda(), link12=True)
+    api.set_clover(lat, 1.0, -0.2)
+    b = torch.from_numpy(c.full(42)).cuda()
+    x = torch.zeros_like(b)
+    assert L.ddq_sap_smooth(lat.handle, api.DDQ_F64, _p(x), _p(b), 1, 2) == ERR_STATE
+    assert L.ddq_reserve(lat.handle, 1, 0, api.DDQ_RESERVE_SAP) == 0
+    free0 = _free_bytes()
+    for prec in (api.DDQ_F64, api.DDQ_F32, api.DDQ_F64):
+        assert L.ddq_sap_smooth(lat.handle, prec, _p(x), _p(b), 1, 2) == 0
+        assert _free_bytes() == free0
+    assert torch.isfinite(torch.view_as_real(x)).all()
+    api.destroy_lattice(lat)

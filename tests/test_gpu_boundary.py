@@ -3,7 +3,10 @@ where it matters:
 
 * apply, smooth, SAP and solve allocate nothing: past the reservation they return
   DDQ_ERR_STATE and do nothing; after ddq_reserve they run, leave the device's free
-  memory unchanged and give the results of the per-right-hand-side calls;
+  memory unchanged and give the results of the per-right-hand-side calls (the HIP
+  runtime takes device memory of its own when it first loads a source file's code
+  object or instantiates graphs; in the suite's order the earlier tests have done that,
+  and the SAP test does it itself);
 * ddq_oe_gmres_solve with several right-hand sides: every system meets the full
   residual bar |b - D x| <= 1e-10 |b| with the oracle's D and equals its one-system
   solve;

@@ -825,8 +825,24 @@ def batched(api, synth, torch, dev, solve=True):
     gbs = bytes_multi / (fast["apply_ms"] * 1e-3) / 1e9
     fast.update({"apply_GBs": round(gbs, 1), "frac_of_8TBs": round(gbs / HBM_PEAK_GBS, 4),
                  "speedup_vs_single_loop": round(n * t_one / fast["apply_ms"], 3)})
+    # the same 12 right-hand sides in FP16 storage (16-bit spinors and 12-real links, FP32
+    # arithmetic; up to three right-hand sides per thread): 240 B of spinor passes per
+    # right-hand side, 384 B of links and 320 B of 16-bit clover slots per site
+    x16 = api.convert_parity(lat, api.convert_parity(lat, x, torch.complex128), torch.float16)
+    y16 = torch.empty_like(x16)
+    t16 = timed(lambda: api.apply_schur(lat, x16, y16))
+    bytes16 = (240 * n + 384 + 320) * vh
+    api.apply_schur(lat, x, y)  # the FP32 result to compare with
+    ref = api.convert_parity(lat, y, torch.complex128)
+    got = api.convert_parity(lat, y16, torch.complex128)
+    fp16 = {"apply_ms": round(t16, 4), "apply_GBs": round(bytes16 / (t16 * 1e-3) / 1e9, 1),
+            "bytes_per_apply": bytes16, "speedup_vs_fastest_fp32": round(fast["apply_ms"] / t16, 3),
+            "rel_diff_vs_fp32": float((got - ref).norm() / ref.norm())}
+    log(f"multi-rhs FP16 storage: {fp16['apply_ms']} ms = {fp16['apply_GBs']} GB/s")
+    del x16, y16, ref, got
     multi = {"workload": "24^3x48, 12 right-hand sides, FP32 Schur apply", "bytes_per_apply": bytes_multi,
-             "single_apply_ms": round(t_one, 4), "best": fast, "planar": planar, "mrhs_layout": inter}
+             "single_apply_ms": round(t_one, 4), "best": fast, "planar": planar, "mrhs_layout": inter,
+             "fp16_storage": fp16}
     del x, y, x1, y1
     if not solve:
         for lat in lats:

@@ -16,7 +16,8 @@
 // Two kernels:
 // * k_sap_block_split (no block spans y, z or t; or FP32 with 12-real links): everything
 //   the MR steps touch stays on chip -- the block's links in LDS, the clover blocks in
-//   registers -- and each site pair is split over two threads (see the kernel).
+//   registers -- each site pair is split over two threads, and the colour's residual is
+//   formed in the kernel's prologue (see the kernel).
 // * k_sap_block (the other lattices: FP64, FP32 with 18-real links): 128 threads,
 //   thread j owns the j-th even and the j-th odd site of the block (the checkerboard
 //   half index of the block's lexicographic site order); the hopping terms read the
@@ -388,16 +389,17 @@ __global__ void __launch_bounds__(256) k_sap_residual(SapResArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// FP32 block solves with the block's links in LDS across the MR steps: the forward hop
-// of site x reads U_mu(x), the backward hop the neighbour's U_mu(x - mu) and applies
-// its adjoint.  Two LDS forms of the links:
-// * 12-real storage: rows 0 and 1 of all 1,024 forward links (48 KB), the third row
+// Block solves with the block's links in LDS across the MR steps: the forward hop of
+// site x reads U_mu(x), the backward hop the neighbour's U_mu(x - mu) and applies its
+// adjoint.  Two LDS forms of the links:
+// * 12-real FP32 storage: rows 0 and 1 of all 1,024 forward links (48 KB), the third row
 //   rebuilt at each hop; entry e of (direction mu, parity q, half index j) at
 //   (e * 8 + 2 mu + q) * 128 + j;
-// * 18-real storage (L18; no block spans y, z or t): the whole matrices of the 832
-//   links a hop can use (59 KB) -- all of x, and of y, z, t those whose site is not at
-//   the block's last coordinate in the direction (that link leaves the block); entry e
-//   of (mu, q, compact index c) at e * SAP_L18 + sap_l18_base(mu, q) + c.
+// * 18-real storage (L18; FP32 or FP64; no block spans y, z or t): the whole matrices
+//   of the 832 links a hop can use (59 KB in FP32, 120 KB in FP64) -- all of x, and of
+//   y, z, t those whose site is not at the block's last coordinate in the direction
+//   (that link leaves the block); entry e of (mu, q, compact index c) at
+//   e * SAP_L18 + sap_l18_base(mu, q) + c.
 // ---------------------------------------------------------------------------
 constexpr int SAP_LK = 6;                        // entries of a link in the 12-real form
 constexpr int SAP_L18 = 2 * (SAP_HALF + 3 * 96);  // links of the 18-real form
@@ -503,10 +505,11 @@ __device__ __forceinline__ void sap_lds_steps(const Geo& g, const int lc[4], int
 // h = threadIdx / 128 (uniform over a wavefront) and j = threadIdx mod 128.  Thread h
 // sums the hops of directions 2h and 2h + 1 into a partial spinor; the partials meet in
 // LDS, after which thread h owns spins 2h, 2h + 1 of its two sites: the rows clover
-// block h acts on, the rows of the Minimal Residual vectors it updates.  Per workgroup
-// 72 KB of LDS (12-real: links, the hop input, an exchange buffer; 18-real: links and
-// the hop input, which then also carries the exchange): two blocks share a compute
-// unit with two wavefronts per SIMD.
+// block h acts on, the rows of the Minimal Residual vectors it updates.  In FP32 a
+// workgroup takes 72 KB of LDS (12-real: links, the hop input, an exchange buffer;
+// 18-real: links and the hop input, which then also carries the exchange), so two
+// blocks share a compute unit with two wavefronts per SIMD; in FP64 145 KB, one block
+// per compute unit.
 // ---------------------------------------------------------------------------
 constexpr int SAP_SPLIT = 2 * SAP_HALF;  // threads of a workgroup
 
@@ -852,7 +855,7 @@ hipError_t launch_sap_blocks(const Geo& g, int prec_f32, int link12, const d2_t*
   a.colour = colour & 1;
   a.m = m;
   const dim3 grid((unsigned)nblk), block(SAP_HALF);
-  // the LDS kernel's grid: the blocks of one colour, (nb[0] + 1) / 2 of them per row in x
+  // the on-chip kernel's grid: the blocks of one colour, (nb[0] + 1) / 2 of them a row in x
   const dim3 grid_c((unsigned)(nblk / a.nb[0] * ((a.nb[0] + 1) / 2)));
   const bool l18_fits = g.L[1] > SAP_B && g.L[2] > SAP_B && g.L[3] > SAP_B;  // no block spans y, z, t
   const bool rs = res != nullptr;

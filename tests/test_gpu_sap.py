@@ -64,11 +64,13 @@ def test_sap_f32_with_twelve_real_links(dims, m):
     assert rel(x.cpu().numpy(), ref) < 1e-5
 
 
-def test_sap_odd_block_count():
-    """12x8x8x8: three blocks along x, so a row of blocks holds two of one colour and one
-    of the other (the on-chip block solves' grid covers both colours' rows); FP64, FP32
-    18-real and FP32 12-real block solves against one oracle run."""
-    dims = (12, 8, 8, 8)
+@pytest.mark.parametrize("dims", [(12, 8, 8, 8), (8, 12, 8, 8), (4, 8, 8, 8)], ids=lambda d: "x".join(map(str, d)))
+def test_sap_odd_block_count(dims):
+    """Three blocks along x (a row of blocks holds two of one colour and one of the other:
+    the on-chip block solves' grid covers both colours' rows) or along y (neighbouring
+    blocks across the boundary share a colour), and one block along x (the x hops wrap
+    inside the block, all in LDS); FP64, FP32 18-real and FP32 12-real block solves, all
+    on chip, against one oracle run."""
     c = case(dims)
     b = c.full(506)
     x0 = c.full(507) * 0.1

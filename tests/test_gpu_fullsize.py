@@ -186,28 +186,30 @@ def test_sap_gauge_covariance_fullsize():
     Residual coefficients transform with the site field Om, so SAP on
     (U' = Om U Om(+mu)^H, Om b) returns Om x.  Checks the colour-restricted residual and
     the on-chip block solves over all 20,736 blocks of a colour: FP64 blocks (whole
-    18-real links in LDS; 1e-12) and FP32 blocks with 12-real links (1e-5, and 1e-5 from
-    FP64)."""
+    18-real links in LDS; 1e-12) and FP32 blocks with 12-real and with 18-real links
+    (1e-5, and 1e-5 from FP64)."""
     dev = "cuda"
     U = synth.gauge_field(DIMS, 0.5, 311, device=dev)
     b = torch.from_numpy(synth.gaussian_spinor(DIMS, 312)).to(dev)
 
     def sap(U_, b_):
-        lat = api.create_lattice(DIMS)
-        api.set_gauge(lat, U_, link12=True)
-        api.set_clover(lat, 1.2, M0)
         out = []
-        for prec in (api.DDQ_F64, api.DDQ_F32):
-            x = torch.zeros_like(b_)
-            api.sap_smooth(lat, b_, x, 1, 2, prec=prec)
-            out.append(x)
-        torch.cuda.synchronize()
-        api.destroy_lattice(lat)
-        torch.cuda.empty_cache()
+        for link12 in (True, False):  # FP32 blocks with 12-real, then 18-real links
+            lat = api.create_lattice(DIMS)
+            api.set_gauge(lat, U_, link12=link12)
+            api.set_clover(lat, 1.2, M0)
+            for prec in ((api.DDQ_F64, api.DDQ_F32) if link12 else (api.DDQ_F32,)):
+                x = torch.zeros_like(b_)
+                api.sap_smooth(lat, b_, x, 1, 2, prec=prec)
+                out.append(x)
+            torch.cuda.synchronize()
+            api.destroy_lattice(lat)
+            torch.cuda.empty_cache()
         return out
 
-    x64, x32 = sap(U, b)
+    x64, x32, x18 = sap(U, b)
     assert relerr(x32, x64) < 1e-5
+    assert relerr(x18, x64) < 1e-5
     Om = synth.random_su3_sites(DIMS, 313, device=dev)
     for mu, axis in enumerate((3, 2, 1, 0)):
         U[..., mu, :, :] = Om @ U[..., mu, :, :] @ torch.roll(Om, -1, dims=axis).conj().transpose(-1, -2)
@@ -215,7 +217,8 @@ def test_sap_gauge_covariance_fullsize():
     def rot(v):  # Om(x) on the colour index of a full vector [t][z][y][x][4][3]
         return (Om.unsqueeze(-3) @ v.unsqueeze(-1)).squeeze(-1)
 
-    y64, y32 = sap(U, rot(b))
+    y64, y32, y18 = sap(U, rot(b))
     del U
     assert relerr(y64, rot(x64)) < 1e-12
     assert relerr(y32, rot(x32)) < 1e-5
+    assert relerr(y18, rot(x18)) < 1e-5

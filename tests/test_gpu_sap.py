@@ -90,14 +90,39 @@ def test_sap_odd_block_count(dims):
     assert rel(x.cpu().numpy(), ref) < 1e-5
 
 
+@pytest.mark.parametrize("dims", [(8, 8, 4, 8), (8, 8, 8, 8)], ids=lambda d: "x".join(map(str, d)))
+def test_sap_without_mr_steps(dims):
+    """m = 0: every block solve leaves the even sites alone and solves the block's odd rows
+    (e_o = A_oo^-1 r_o); 8x8x4x8 takes the block kernel that reads links from memory for
+    FP64 and FP32 18-real, 8^4 the on-chip one; FP32 12-real on both."""
+    c = case(dims)
+    b = c.full(512)
+    x0 = c.full(513) * 0.1
+    ref = solvers.sap(c.op, b, x0, 2, 0)
+    for prec, tol in ((api.DDQ_F64, 1e-12), (api.DDQ_F32, 1e-5)):
+        x = torch.from_numpy(x0.copy()).cuda()
+        api.sap_smooth(c.lat, torch.from_numpy(b).cuda(), x, 2, 0, prec=prec)
+        torch.cuda.synchronize()
+        assert rel(x.cpu().numpy(), ref) < tol, prec
+    lat = api.create_lattice(dims)
+    api.set_gauge(lat, torch.from_numpy(c.U).cuda(), link12=True)
+    api.set_clover(lat, 1.0, -0.2)
+    x = torch.from_numpy(x0.copy()).cuda()
+    api.sap_smooth(lat, torch.from_numpy(b).cuda(), x, 2, 0, prec=api.DDQ_F32)
+    torch.cuda.synchronize()
+    api.destroy_lattice(lat)
+    assert rel(x.cpu().numpy(), ref) < 1e-5
+
+
 def test_sap_reduces_the_residual_and_zero_sweeps():
     c = case((8, 8, 4, 8))
     b = c.full(511)
     bd = torch.from_numpy(b).cuda()
-    x = torch.zeros_like(bd)
+    x0 = torch.from_numpy(c.full(514)).cuda()
+    x = x0.clone()
     api.sap_smooth(c.lat, bd, x, 0, 4)
     torch.cuda.synchronize()
-    assert torch.count_nonzero(x) == 0  # n = 0: x unchanged
+    assert torch.equal(x, x0)  # n = 0: x unchanged
     res = []
     for n in (1, 2, 4):
         x = torch.zeros_like(bd)

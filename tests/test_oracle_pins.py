@@ -684,6 +684,24 @@ def _block_parity_dofs(lat, in_block):
     return _block_dofs(lat, in_block & (par == 0)), _block_dofs(lat, in_block & (par == 1))
 
 
+@pytest.mark.parametrize("block", [(2, 2, 2, 2), (4, 4, 2, 2)])
+def test_block_solve_without_mr_steps_solves_only_the_odd_rows(block):
+    """m = 0, the degenerate block solve of Alg. 1 with odd-even inside the blocks (Sect.
+    2.4.5): no Minimal Residual step leaves e_e = 0, and the reconstruction of eq. 2 gives
+    e_o = (D_oo^k)^-1 r_o, from the dense D of the lattice; zero outside the block."""
+    lat = Lattice((4, 4, 2, 2))
+    op = WilsonClover(lat, synth.gauge_field(lat.dims, 0.3, 151), 1.0, -0.1)
+    D = sparse_D(op).toarray()
+    idx, colour, nblk = solvers.sap_blocks(lat, block)
+    r = _full_vec(lat, 152)
+    rv = r.ravel()
+    for k in range(nblk):
+        e_d, o_d = _block_parity_dofs(lat, idx == k)
+        e = solvers.block_solve(op, idx == k, r, 0)
+        assert np.all(e.ravel()[e_d] == 0) and np.all(e[~(idx == k)] == 0)
+        assert rel_err(e.ravel()[o_d], np.linalg.solve(D[np.ix_(o_d, o_d)], rv[o_d])) < 1e-12
+
+
 @pytest.mark.parametrize("block,m", [((2, 2, 2, 2), 1), ((2, 2, 2, 2), 2), ((4, 4, 2, 2), 1),
                                      ((4, 4, 2, 2), 2), ((4, 4, 2, 2), 3)])
 def test_block_solve_at_few_mr_steps_is_block_odd_even_mr(block, m):

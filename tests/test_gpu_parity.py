@@ -253,6 +253,21 @@ def test_gmres_not_converged_status():
     assert info["cycles"] == 1 and info["iters"] == 2
 
 
+def test_zero_rhs_is_converged_before_any_step():
+    """b = 0 from x = 0: |b - D x| = 0 <= tol |b| holds before the first Arnoldi step (Alg. 2
+    stops on the initial residual), for odd-even GMRES, FGMRES with M_nu and FGMRES with
+    SAP; x stays zero."""
+    c = case((4, 4, 4, 4))
+    b = torch.zeros(c.lat.full_shape, dtype=torch.complex128, device="cuda")
+    runs = [(api.oe_gmres_solve, {}), (api.fgmres_solve, {"omega": 0.1}), (api.fgmres_sap_solve, {})]
+    for solve, kw in runs:
+        x, info, ok = solve(c.lat, b, m=8, **kw)
+        torch.cuda.synchronize()
+        assert ok, solve.__name__
+        assert info["iters"] == 0 and info["true_relres"] == 0.0, (solve.__name__, info)
+        assert torch.count_nonzero(x) == 0, solve.__name__
+
+
 def test_gmres_nonfinite_rhs_rejected():
     c = case((4, 4, 4, 4))
     b = synth.gaussian_spinor((4, 4, 4, 4), 62)

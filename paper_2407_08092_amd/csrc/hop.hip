@@ -11,20 +11,27 @@
 
 namespace ddq {
 
-// register budget: waves per SIMD the scheduler must keep resident
+// register budget: waves per SIMD the scheduler must keep resident.  FP32 with 12-real
+// links asks for 3: under the budget of 4 those kernels spill 8 bytes a lane, under that of 3
+// they are scheduled into 127 registers without spills and still run 4 waves per SIMD.
 #ifndef DDQ_WAVES_F64
 #define DDQ_WAVES_F64 2
 #endif
 #ifndef DDQ_WAVES_F32
 #define DDQ_WAVES_F32 4
 #endif
+#ifndef DDQ_WAVES_F32_L12
+#define DDQ_WAVES_F32_L12 3
+#endif
 // workgroup order of the one-right-hand-side kernels: 0 = the dispatcher's, 1 = slab
 // order (slab_group)
 #ifndef DDQ_SITE_ORDER
 #define DDQ_SITE_ORDER 1
 #endif
-template <typename R> struct HOP_WAVES { static constexpr int value = DDQ_WAVES_F32; };
-template <> struct HOP_WAVES<double> { static constexpr int value = DDQ_WAVES_F64; };
+template <typename R, bool L12> struct HOP_WAVES {
+  static constexpr int value = L12 ? DDQ_WAVES_F32_L12 : DDQ_WAVES_F32;
+};
+template <bool L12> struct HOP_WAVES<double, L12> { static constexpr int value = DDQ_WAVES_F64; };
 
 // site of this thread in a one-right-hand-side launch (grid: one_rhs_grid); false if none.
 // t_cnt > 0 restricts the launch to the output sites of slices [t_lo, t_lo + t_cnt).
@@ -59,7 +66,7 @@ static int one_rhs_grid(const Geo& g, int t_cnt = 0) {
 }
 
 template <typename R, int MODE, bool DAG, bool L12, bool MR>
-__global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(HOP_WAVES<R>::value)))
+__global__ void __launch_bounds__(HOP_BLOCK) __attribute__((amdgpu_waves_per_eu(HOP_WAVES<R, L12>::value)))
 hop_kernel(HopArgs<R> a) {
   const int vh = a.g.Vh;
   int i, rhs;
